@@ -1,0 +1,28 @@
+"""FP64 CPU oracle for the periodized Coulomb sum of Gumerov & Duraiswami
+("A method to compute periodic sums").
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call, link
+or execute anything in this package; only the test-suite, the smoke check and
+the benchmark's CPU-baseline leg use it.  It shares no code with the HIP library.
+
+Parts:
+  * ``method``  -- the method's "set" and "get" algorithms (Sec. 2.3), for the
+    Laplace kernel with the renormalized solid-harmonic basis (Sec. 3.1,
+    eqs. (1.6)-(1.8)), Gauss spherical check points (Sec. 2.2), SVD
+    pseudo-inverse (eq. (10)), box integrals (App. B) and the zero-mean
+    constant via the face/edge reduction of App. C;
+  * ``ewald``   -- an independent classical Ewald sum (App. D);
+  * ``adjoint`` -- the exact gradient of the method's energy with respect to
+    positions and charges (derived from eqs. (3), (8), (10), (pfx3)-(pfx4));
+  * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
+
+Pins (tests/test_oracle_*.py): the basis against an independent assembly from
+associated Legendre functions (eq. (1.1)-(1.4.1)), harmonicity and finite
+differences; the Gauss grid counts L = 2p^2 - p against the N+2L columns of
+Tables 2-3; near-set sizes against A_gf lambda^3 N (eq. (o2.1), Table 5); box
+integrals against closed forms; Phi0 against the textbook prism potential,
+quadrature and its Laplacian; Ewald against its splitting-parameter
+independence and the NaCl Madelung constant (eq. (st1)); the method against
+the Madelung constant, Table 1's Gauss-grid errors, Ewald, periodicity and
+translation invariance; the adjoint against central finite differences.
+"""

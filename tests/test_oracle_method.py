@@ -1,0 +1,143 @@
+"""Pins for the oracle's implementation of the method (Sec. 2.3, Sec. 3) against
+the Madelung constant, Table 1, Ewald, periodicity and translation invariance."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.ewald import Ewald, MADELUNG_NACL
+from oracle.method import Plan
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def _eps_M(p, R_b=1.5):
+    c = W.nacl_cell()
+    phi, _ = Plan(c["box"], p, R_b=R_b).solve(c["x"], c["q"])
+    return np.max(np.abs(phi * 0.5 / (-c["q"] * MADELUNG_NACL) - 1))
+
+
+@pytest.mark.parametrize("p", [8, 12, 16])
+def test_table1_gauss_grid_order_of_magnitude(p):
+    """Table 1, Gauss column (lambda = sqrt 3): same order of magnitude (the
+    paper's azimuth placement and partner rule are not stated)."""
+    ref = GOLD["table1_gauss"]["eps_M"][str(p)]
+    e = _eps_M(p)
+    assert ref / 10 < e < ref * 10
+
+
+def test_madelung_high_accuracy():
+    """Sec. 4.1: p = 35, R_b = 1.5 gives eps_M ~ 6e-14."""
+    assert _eps_M(35) < 5 * GOLD["nacl_small_test"]["eps_M"]["35"]
+
+
+def test_error_decays_like_lambda_power():
+    """Fig. 3 text / eq. (errb1): eps ~ C (R0/R_b)^p; the slope of log eps_M over p
+    is close to -ln lambda (lambda = sqrt 3)."""
+    ps = np.array([8, 12, 16, 20, 24])
+    e = np.array([_eps_M(p) for p in ps])
+    slope = np.polyfit(ps, np.log(e), 1)[0]
+    assert -1.6 * np.log(np.sqrt(3)) < slope < -0.6 * np.log(np.sqrt(3))
+
+
+@pytest.mark.parametrize("box,p,tol", [((1.0, 1.0, 1.0), 12, 3e-5), ((1.0, 1.0, 1.0), 24, 5e-9),
+                                       ((1.0, 1.3, 2.1), 16, 3e-6), ((2.0, 1.0, 1.0), 20, 3e-7)])
+def test_method_matches_ewald(box, p, tol):
+    x, q = W.uniform_box(150, box, charges="gauss", seed=p)
+    R0 = 0.5 * np.linalg.norm(box)
+    phi, E = Plan(box, p, lam=np.sqrt(3)).solve(x, q)
+    phe, Ee = Ewald(box).solve(x, q)
+    assert _rel(phi, phe) < tol
+    assert _rel(E, Ee) < tol
+
+
+def test_method_matches_ewald_with_dipole_at_generic_targets():
+    """Charges with a large dipole moment: the periodicity fit reproduces the
+    conducting-boundary Ewald field with no extra side condition."""
+    box = (1.0, 1.0, 1.0)
+    g = np.random.default_rng(8)
+    x = (g.random((40, 3)) - 0.5) * 0.9
+    q = np.where(x[:, 0] > 0, 1.0, -1.0)
+    q -= q.mean()
+    y = (g.random((30, 3)) - 0.5)
+    phi, E = Plan(box, 20, R_b=1.5).solve(x, q, targets=y)
+    phe, Ee = Ewald(box).solve(x, q, targets=y)
+    assert _rel(phi, phe) < 1e-7 and _rel(E, Ee) < 1e-7
+
+
+def test_periodicity_on_faces():
+    """phi(y + d_k e_k) = phi(y) (eq. (7)) at points on the faces."""
+    box = np.array([1.0, 1.2, 0.9])
+    x, q = W.uniform_box(100, box, charges="gauss", seed=2)
+    g = np.random.default_rng(1)
+    ys, ys2 = [], []
+    for k in range(3):
+        y = (g.random((10, 3)) - 0.5) * box
+        y[:, k] = -box[k] / 2
+        ys.append(y)
+        y2 = y.copy()
+        y2[:, k] += box[k]
+        ys2.append(y2)
+    pl = Plan(box, 24, lam=np.sqrt(3))
+    a = pl.solve(x, q, targets=np.concatenate(ys))
+    b = pl.solve(x, q, targets=np.concatenate(ys2))
+    # truncation error at p = 24, lambda = sqrt 3 is ~1e-8 (it matches the error against Ewald)
+    assert _rel(a[0], b[0]) < 1e-7 and _rel(a[1], b[1]) < 1e-7
+
+
+def test_translation_invariance():
+    """Shifting every particle by s (wrapped) changes the near/far split entirely
+    but not the periodic solution."""
+    box = np.array([1.0, 1.0, 1.3])
+    x, q = W.uniform_box(120, box, charges="gauss", seed=3)
+    pl = Plan(box, 24, lam=np.sqrt(3))
+    a = pl.solve(x, q)
+    xs = W.wrap(x + np.array([0.31, -0.17, 0.52]), box)
+    b = pl.solve(xs, q)
+    assert _rel(a[0], b[0]) < 1e-7 and _rel(a[1], b[1]) < 1e-7
+
+
+def test_least_squares_normal_equations():
+    x, q = W.uniform_box(200, (1, 1, 1), seed=6)
+    pl = Plan((1, 1, 1), 12, R_b=1.5)
+    parts = pl.solve(x, q, return_parts=True)
+    r = pl.A @ parts["C"][1:] - parts["f"]
+    assert np.abs(pl.A.T @ r).max() < 1e-10 * np.abs(pl.A.T @ parts["f"]).max()
+    C2 = np.linalg.lstsq(pl.A, parts["f"], rcond=None)[0]
+    np.testing.assert_allclose(parts["C"][1:], C2, rtol=1e-11, atol=1e-12 * np.abs(C2).max())
+    assert pl.rank == pl.P - 1
+
+
+def test_zero_mean_constant_only_shifts():
+    x, q = W.uniform_box(100, (1, 1, 1), charges="gauss", seed=7)
+    pl = Plan((1, 1, 1), 12, R_b=1.5)
+    a = pl.solve(x, q, with_mean=True)
+    b = pl.solve(x, q, with_mean=False)
+    dd = a[0] - b[0]
+    assert np.ptp(dd) < 1e-12 * np.abs(a[0]).max()
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_target_on_particle_uses_K0_zero():
+    x, q = W.uniform_box(50, (1, 1, 1), charges="gauss", seed=8)
+    pl = Plan((1, 1, 1), 12, R_b=1.5)
+    a = pl.solve(x, q)
+    b = pl.solve(x, q, targets=x[:7])
+    np.testing.assert_allclose(b[0], a[0][:7], rtol=1e-14)
+    np.testing.assert_allclose(b[1], a[1][:7], rtol=1e-14)
+
+
+def test_rocksalt_lattice_madelung():
+    """An 8^3-site rock-salt lattice (the small-cell analogue of the 32^3 lattice
+    workload): every site's potential times the spacing is -q M (eq. (st1))."""
+    r = W.rocksalt(8)
+    # the truncation error grows with N (eq. (errb4.1)): 4e-6 at p = 16, 1.5e-7 at p = 20
+    phi, E = Plan(r["box"], 20, R_b=1.5).solve(r["x"], r["q"])
+    assert np.max(np.abs(phi * r["spacing"] / (-r["q"] * MADELUNG_NACL) - 1)) < 5e-7
+    assert np.abs(E).max() * r["spacing"] ** 2 < 2e-6

@@ -1,0 +1,132 @@
+"""Seeded synthetic inputs for the periodic Coulomb sum.
+
+This module only draws random numbers and lays them out; it holds none of the
+method's arithmetic, so both the FP64 oracle and the HIP path can consume the
+same inputs without sharing any code of the method.
+
+Every generator uses numpy's PCG64 with seed ``20131015 + k`` (k = the
+workload number below) unless a seed is passed.  Positions are wrapped into the
+half-open box [-d/2, d/2) per axis; charges are exactly neutral in the sense the
+method needs (sum below 1e-12 of the sum of magnitudes).
+
+Workloads (the paper's test systems are synthetic: a rock-salt cell in the
+small-size tests, random charges in a unit cube in the large-scale tests, and
+boxes of several aspect ratios):
+
+1. cube 1x1x1, N=1000 uniform, q=+-1 (500 each, shuffled)
+2. cube 1x1x1, N=100,000 uniform, q ~ N(0,1) minus its mean, with a seeded
+   2,000-particle subset for sampled comparisons
+3. box 1x1x2.5, N=1,000,000 in 64 Gaussian blobs (sigma = 0.03 d_k per axis,
+   wrapped), q=+-1 balanced
+4. 512 independent boxes, d_k ~ U[1,2], N ~ log-uniform[200, 20000], uniform
+   positions, q ~ N(0,1) minus the mean
+5. rock-salt lattice of 32^3 sites (spacing 1/32 in a unit cube), q=(-1)^(i+j+k),
+   positions jittered by N(0, 0.002^2) per coordinate
+"""
+import numpy as np
+
+BASE_SEED = 20131015
+
+
+def rng(k, seed=None):
+    return np.random.Generator(np.random.PCG64(BASE_SEED + k if seed is None else seed))
+
+
+def wrap(x, d):
+    """Map coordinates into [-d/2, d/2) per axis (x: (N,3), d: (3,))."""
+    d = np.asarray(d, dtype=np.float64)
+    x = x - d * np.floor(x / d + 0.5)
+    # guard the half-open upper edge against rounding
+    x = np.where(x >= d / 2, x - d, x)
+    x = np.where(x < -d / 2, x + d, x)
+    return np.ascontiguousarray(x)
+
+
+def _neutral_pm1(g, n):
+    q = np.concatenate([np.ones(n // 2), -np.ones(n - n // 2)])
+    g.shuffle(q)
+    return q
+
+
+def _neutral_gauss(g, n):
+    q = g.standard_normal(n)
+    return q - q.mean()
+
+
+def uniform_box(n, box, charges="pm1", seed=0):
+    g = np.random.Generator(np.random.PCG64(seed))
+    d = np.asarray(box, dtype=np.float64)
+    x = wrap((g.random((n, 3)) - 0.5) * d, d)
+    q = _neutral_pm1(g, n) if charges == "pm1" else _neutral_gauss(g, n)
+    return x, q
+
+
+def config1():
+    g = rng(1)
+    d = np.array([1.0, 1.0, 1.0])
+    x = wrap((g.random((1000, 3)) - 0.5) * d, d)
+    return dict(box=d, x=x, q=_neutral_pm1(g, 1000), p=12, R_b=1.5)
+
+
+def config2(n=100_000, nsub=2000):
+    g = rng(2)
+    d = np.array([1.0, 1.0, 1.0])
+    x = wrap((g.random((n, 3)) - 0.5) * d, d)
+    q = _neutral_gauss(g, n)
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    return dict(box=d, x=x, q=q, p=16, R_b=1.5, subset=sub)
+
+
+def config3(n=1_000_000, nblob=64, nsub=2000):
+    g = rng(3)
+    d = np.array([1.0, 1.0, 2.5])
+    centres = (g.random((nblob, 3)) - 0.5) * d
+    per = n // nblob
+    counts = np.full(nblob, per)
+    counts[: n - per * nblob] += 1
+    lab = np.repeat(np.arange(nblob), counts)
+    x = centres[lab] + g.standard_normal((n, 3)) * (0.03 * d)
+    x = wrap(x, d)
+    q = _neutral_pm1(g, n)
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    return dict(box=d, x=x, q=q, p=20, lam=1.5, subset=sub)
+
+
+def config4(nsys=512, nmin=200, nmax=20000):
+    g = rng(4)
+    systems = []
+    for _ in range(nsys):
+        d = g.uniform(1.0, 2.0, size=3)
+        n = int(round(np.exp(g.uniform(np.log(nmin), np.log(nmax)))))
+        x = wrap((g.random((n, 3)) - 0.5) * d, d)
+        q = _neutral_gauss(g, n)
+        systems.append(dict(box=d, x=x, q=q))
+    return dict(systems=systems, p=12, lam=float(np.sqrt(3.0)))
+
+
+def rocksalt(m=32, jitter=0.0, seed=None):
+    """m^3 sites -1/2 + (i+1/2)/m of a unit cube, q = (-1)^(i+j+k)."""
+    g = rng(5, seed)
+    i = np.arange(m)
+    I, J, K = np.meshgrid(i, i, i, indexing="ij")
+    s = (np.stack([I, J, K], axis=-1).reshape(-1, 3) + 0.5) / m - 0.5
+    q = np.where(((I + J + K).reshape(-1) % 2) == 0, 1.0, -1.0)
+    d = np.array([1.0, 1.0, 1.0])
+    if jitter > 0:
+        s = s + g.normal(0.0, jitter, size=s.shape)
+    return dict(box=d, x=wrap(s, d), q=q, spacing=1.0 / m)
+
+
+def config5(jitter=0.002):
+    r = rocksalt(32, jitter=jitter)
+    r.update(p=16, R_b=1.5)
+    return r
+
+
+def nacl_cell(d=1.0):
+    """Eight charges at (+-d/4, +-d/4, +-d/4) with q = s1*s2*s3: one rock-salt
+    cell of period d, nearest-neighbour distance d/2."""
+    s = np.array([[a, b, c] for a in (-1, 1) for b in (-1, 1) for c in (-1, 1)], dtype=np.float64)
+    x = s * (d / 4.0)
+    q = s[:, 0] * s[:, 1] * s[:, 2]
+    return dict(box=np.array([d, d, d]), x=x, q=q)
