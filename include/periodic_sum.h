@@ -1,0 +1,208 @@
+/*
+ * periodic_sum.h -- C ABI of libperiodic_sum.so, an MI355X (gfx950) implementation
+ * of the periodized sum of Gumerov & Duraiswami, "A method to compute periodic sums"
+ * (arXiv:1310.4374), for the Coulomb kernel K(r) = 1/|r|, K(0) = 0 (eq. (1)).
+ *
+ * Problem (Sec. 1, eqs. (1)-(2)): N charges q_i at x_i in the box
+ * Omega0 = [-d1/2,d1/2) x [-d2/2,d2/2) x [-d3/2,d3/2), sum q_i = 0, replicated on the
+ * lattice p = (i1 d1, i2 d2, i3 d3).  Outputs, at the particles (Y0 = X0, the
+ * molecular-dynamics case of Sec. 2.3) or at M separate targets in the box:
+ * the periodic potential phi and the field -grad phi (Gaussian units).
+ *
+ * Method (Sec. 2.3, "set" and "get"; Sec. 3 for the Laplace kernel):
+ *   phi = phi_near + phi_far + C1, where phi_near sums the sources x_j + p with
+ *   |x_j + p| <= R_b directly (eq. (3)); phi_far = sum_{t>=2} C_t R_t(y) over the
+ *   renormalized regular solid harmonics (eqs. (1.6)-(1.8)), here evaluated at
+ *   y/R0; C = A^+ f is the least-squares fit of periodicity at L check points on
+ *   the circumsphere and their periodic partners (eqs. (7)-(10)); C1 makes the
+ *   box mean of phi zero (eqs. (pfx2)-(pfx4), App. B, App. C), the convention of
+ *   Ewald summation (App. D).
+ *
+ * Conventions for every call:
+ *   - Status: every call returns ps_status; PS_OK = 0.  No C++ exception crosses
+ *     the ABI.  periodic_sum_last_error() returns a thread-local message for the
+ *     last failure on the calling thread.
+ *   - Memory: arrays marked "device" are device pointers on the plan's device;
+ *     the caller owns them.  The library never frees, retains or writes past the
+ *     documented extent of a caller's array.  The plan owns all of its workspace,
+ *     which is allocated by the plan call and sized by n_max/m_max, so the eval
+ *     calls never allocate device memory.
+ *   - Layout: structure of arrays, FP64: x[n], y[n], z[n], q[n]; outputs phi[n]
+ *     (or [m]), ex/ey/ez[n] (the three field components).
+ *   - Streams: `stream` is a hipStream_t (NULL = the default stream).  Eval calls
+ *     are asynchronous: they only enqueue work on that stream.  Argument errors
+ *     are reported synchronously; data errors (non-neutral charges, particles
+ *     outside the box) are detected on the device and returned by
+ *     periodic_sum_status(), which synchronizes the stream.
+ *   - Concurrency: one plan serves one eval at a time (its workspace is shared);
+ *     different plans are independent.  Results are bitwise reproducible for
+ *     identical inputs and plan.
+ */
+#ifndef PERIODIC_SUM_H
+#define PERIODIC_SUM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ps_plan_s* ps_plan;
+
+typedef enum {
+    PS_OK = 0,
+    PS_E_INVALID = 1,      /* bad argument (null pointer, size, parameter range) */
+    PS_E_NOT_NEUTRAL = 2,  /* |sum q| > 1e-12 sum |q| (eq. (1) requires neutrality) */
+    PS_E_OUT_OF_BOX = 3,   /* a particle or target outside [-d/2, d/2) */
+    PS_E_RANK = 4,         /* fitting matrix numerically rank deficient beyond rcond */
+    PS_E_NOMEM = 5,        /* device or host allocation failed */
+    PS_E_HIP = 6,          /* a HIP runtime call failed */
+    PS_E_UNSUPPORTED = 7   /* request outside what this build supports */
+} ps_status;
+
+typedef enum {
+    PS_FP64 = 0,        /* every step in FP64 */
+    PS_FP32_ACC64 = 1   /* particle near sums with FP32 pair arithmetic on
+                           block-relative coordinates (two-float near tiles) and
+                           FP64 accumulation; every other step in FP64 */
+} ps_precision;
+
+typedef enum {
+    PS_MEAN_ZERO = 0,   /* C1 from the zero box-mean condition, eq. (pfx3) */
+    PS_MEAN_NONE = 1    /* C1 = 0 (remark after algorithm "get") */
+} ps_mean;
+
+typedef struct {
+    double  box[3];       /* d1, d2, d3 > 0 */
+    int32_t p;            /* truncation number: degrees 0..p-1, P = p*p basis terms; 2 <= p <= 40 */
+    double  R_b;          /* near radius; if <= 0, lambda * R0 is used, R0 = |d|/2 */
+    double  lambda;       /* used only when R_b <= 0; must give R_b > R0 */
+    int32_t precision;    /* ps_precision */
+    int32_t mean;         /* ps_mean */
+    double  rcond;        /* singular values below rcond * sigma_max are dropped from A^+; <= 0 -> 1e-13 */
+    int64_t n_max;        /* largest particle count an eval may pass (workspace size) */
+    int64_t m_max;        /* largest separate-target count an eval may pass (0: particles only) */
+    int32_t tile_targets; /* targets per workgroup in the particle sums: 0 (default), 64, 128 or 256 */
+    int32_t n_split;      /* source splits of the particle sums: 0 = automatic */
+} ps_params;
+
+typedef struct {
+    int32_t p, P, L;          /* truncation number, basis size, check points */
+    int32_t n_images;         /* lattice images whose box meets the ball |x| <= R_b */
+    int32_t rank;             /* numerical rank of A (P-1 when full) */
+    double  R0, R_b, cond;    /* circumradius, near radius, sigma_max/sigma_min(kept) */
+    int64_t n_near_last;      /* N_b of the last completed eval (synchronizes) */
+    int32_t tile_targets, n_split;
+    int32_t nsys;             /* 1, or the number of systems of a batched plan */
+} ps_plan_info;
+
+/* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
+ * near radius, the Gauss spherical grid of L = 2p^2 - p check points on the
+ * circumsphere (Sec. 2.2), their partners shifted by one box period along the
+ * coordinate that moves them deepest into the sphere, the L x (P-1) fitting
+ * matrix A (eq. (8); the constant basis function is dropped, Sec. 3), its
+ * pseudo-inverse by Householder QR + one-sided Jacobi SVD with cut-off rcond
+ * (eq. (10)), and the box integrals R_t^(0) by tensor Gauss-Legendre (App. B).
+ * Uploads these and allocates all device workspace on `device`.
+ * prm: host pointer, read during the call only.  *out receives the plan. */
+ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out);
+
+/* Algorithm "get" (Sec. 2.3, steps 1-8) on the device, one system:
+ * near-set build (steps 1-2), FP64 near sums at the 2L check points (step 3),
+ * f and C = A^+ f (steps 4-5), the zero-mean constant C1 (step 6, eq. (pfx3)-(pfx4)),
+ * near sums and the far-field expansion with its gradient at the targets
+ * (steps 3 and 7), and the combination (step 8).
+ *   n, x, y, z, q : particle count (1 <= n <= n_max) and device arrays [n].
+ *   m, tx, ty, tz : m = 0 and NULL pointers: targets are the particles, and the
+ *                   pair of a particle with itself is excluded (K(0) = 0);
+ *                   m > 0: m <= m_max separate device targets in the box.
+ *   phi           : device [n] (or [m]) potential.
+ *   ex, ey, ez    : device [n] (or [m]) field -grad phi; all three NULL to skip
+ *                   nothing (the field is always computed) but not store it.
+ * Enqueued on `stream`; returns before the work completes. */
+ps_status periodic_sum_eval(ps_plan plan, int64_t n,
+                            const double* x, const double* y, const double* z, const double* q,
+                            int64_t m, const double* tx, const double* ty, const double* tz,
+                            double* phi, double* ex, double* ey, double* ez, void* stream);
+
+/* Energy E = (1/2) sum_i q_i phi(x_i) at the particles, with phi and the field
+ * as in periodic_sum_eval (outputs may be NULL).  energy: device pointer to one
+ * double, written by a deterministic reduction. */
+ps_status periodic_sum_energy(ps_plan plan, int64_t n,
+                              const double* x, const double* y, const double* z, const double* q,
+                              double* energy, double* phi, double* ex, double* ey, double* ez,
+                              void* stream);
+
+/* Vector-Jacobian product of the energy: dEdx/dEdy/dEdz/dEdq [n] (device) receive
+ * gE * dE/dx_i etc., gE read from a device scalar.
+ *   exact = 1: the exact derivative of the discrete method.  With
+ *     u = sum_k q_k R(x_k), w = (A^+)^T u and
+ *     psi(z) = sum_k q_k K(z - x_k) + sum_l w_l [K(z - y~_l) - K(z - y_l)],
+ *     dE/dx_i = q_i/2 [grad phi(x_i) + sum_{p: (i,p) near} grad psi(x_i + p)],
+ *     dE/dq_i = 1/2 [phi(x_i) + sum_{p: (i,p) near} psi(x_i + p)],
+ *     derived from eqs. (3), (8), (10), (pfx3)-(pfx4) (the paper gives no adjoint).
+ *   exact = 0: the physical approximation dE/dx_i = -q_i field_i, dE/dq_i = phi_i.
+ * dE/dq is returned projected onto sum dq = 0 (mean removed): the energy is only
+ * defined for neutral charges.  Must follow a periodic_sum_energy (or eval at the
+ * particles) with the same inputs on the same stream: it reuses that forward
+ * pass's near set, coefficients and outputs kept in the plan. */
+ps_status periodic_sum_energy_vjp(ps_plan plan, int64_t n,
+                                  const double* x, const double* y, const double* z, const double* q,
+                                  const double* gE, double* dEdx, double* dEdy, double* dEdz,
+                                  double* dEdq, int32_t exact, void* stream);
+
+/* Batched "set": nsys independent systems, each with its own box and charges
+ * (prm[k].box, p, R_b/lambda, n_max as the largest N of system k; precision,
+ * mean and rcond are taken from prm[0]).  Same host steps as periodic_sum_plan
+ * per system; device tables are packed per system. */
+ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int device, ps_plan* out);
+
+/* Batched "get": all systems in one hipGraph launch on `stream`.  offsets: host
+ * array [nsys+1], system k owns particles offsets[k] .. offsets[k+1]-1 of the
+ * packed device arrays x, y, z, q and of the outputs (targets = particles).
+ * Work over (system, target block, source chunk) is ordered largest first. */
+ps_status periodic_sum_eval_batched(ps_plan plan, const int64_t* offsets,
+                                    const double* x, const double* y, const double* z, const double* q,
+                                    double* phi, double* ex, double* ey, double* ez, void* stream);
+
+/* Synchronizes `stream` and returns the data-dependent status of the last eval
+ * (PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX) or PS_OK, then clears it. */
+ps_status periodic_sum_status(ps_plan plan, void* stream);
+
+/* Plan facts; n_near_last synchronizes the device. */
+ps_status periodic_sum_plan_info(ps_plan plan, ps_plan_info* out);
+
+/* Copies the plan's check points (host buffers [3*L] each, xyz interleaved),
+ * the pseudo-inverse [(P-1)*L] row-major and the box integrals [P]; any pointer
+ * may be NULL.  Sizes from periodic_sum_plan_info.  Single-system plans only. */
+ps_status periodic_sum_plan_tables(ps_plan plan, double* check_points, double* partners,
+                                   double* pinv, double* box_means);
+
+/* Coefficients C_1..C_P of the last completed eval (host buffer [P]; synchronizes). */
+ps_status periodic_sum_last_coefficients(ps_plan plan, double* C);
+
+/* Stage timing with HIP events recorded on the eval stream between the stages
+ * of algorithm "get" (single-system evals; not inside the batched graph).
+ * enable != 0 turns it on for the following evals. */
+ps_status periodic_sum_set_profiling(ps_plan plan, int32_t enable);
+
+/* Durations in milliseconds of the last profiled eval's stages, in this order
+ * (PS_N_STAGES values): 0 validation + spatial ordering, 1 near-set build
+ * (steps 1-2), 2 tile bounds and target blocks, 3 FP64 check-point sums
+ * (step 3 at Y_c1, Y_c2), 4 least-squares solve (steps 4-5), 5 zero-mean
+ * constant (step 6), 6 particle pair sums (step 3 at Y0), 7 far field and
+ * combination (steps 7-8).  Synchronizes on the last event.  ms: host [n],
+ * n >= PS_N_STAGES. */
+#define PS_N_STAGES 8
+ps_status periodic_sum_stage_times(ps_plan plan, double* ms, int32_t n);
+
+/* Releases the plan and its device workspace (synchronizes its device). */
+void periodic_sum_destroy(ps_plan plan);
+
+const char* periodic_sum_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERIODIC_SUM_H */

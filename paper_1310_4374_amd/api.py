@@ -1,0 +1,221 @@
+"""Python front end of the C ABI (torch tensors in, torch tensors out).
+
+Positions are passed structure-of-arrays: a (3, N) float64 tensor on the plan's
+device (rows x, y, z); charges an (N,) float64 tensor.  Calls enqueue work on
+torch's current stream of that device and return at once.
+"""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib, ps_params, ps_plan_info
+
+_PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
+_MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
+
+
+def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
+            tile_targets=0, n_split=0):
+    prm = ps_params()
+    for k in range(3):
+        prm.box[k] = float(box[k])
+    prm.p = int(p)
+    prm.R_b = float(R_b) if R_b is not None else 0.0
+    prm.lambda_ = float(lam) if lam is not None else 0.0
+    prm.precision = _PREC[precision] if isinstance(precision, str) else int(precision)
+    prm.mean = _MEAN[mean] if isinstance(mean, str) else int(mean)
+    prm.rcond = float(rcond)
+    prm.n_max = int(n_max)
+    prm.m_max = int(m_max)
+    prm.tile_targets = int(tile_targets)
+    prm.n_split = int(n_split)
+    return prm
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _soa(x, device):
+    """(3, N) or (N, 3) float64 positions -> contiguous (3, N) on the device."""
+    if x.dim() != 2 or 3 not in x.shape:
+        raise ValueError("positions must be (3, N) or (N, 3)")
+    if x.shape[0] != 3 or (x.shape[1] == 3 and not x.is_contiguous()):
+        x = x.t()
+    if x.dtype != torch.float64 or x.device != device:
+        raise ValueError("positions must be float64 on %s" % device)
+    return x.contiguous()
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Plan:
+    """One periodic box: algorithm "set" at construction, "get" on each eval."""
+
+    def __init__(self, box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
+                 tile_targets=0, n_split=0, device=0):
+        self.device = torch.device("cuda", device)
+        self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split)
+        h = ctypes.c_void_p()
+        check(lib().periodic_sum_plan(ctypes.byref(self._prm), int(device), ctypes.byref(h)))
+        self._h = h
+        self.n_max = int(n_max)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().periodic_sum_destroy(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        inf = ps_plan_info()
+        check(lib().periodic_sum_plan_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
+
+    def tables(self):
+        """Check points (L,3), partners (L,3), pseudo-inverse (P-1,L), box means (P,) as CPU float64 tensors."""
+        inf = self.info()
+        L, P = inf["L"], inf["P"]
+        yc = torch.empty(L, 3, dtype=torch.float64)
+        yt = torch.empty(L, 3, dtype=torch.float64)
+        pinv = torch.empty(P - 1, L, dtype=torch.float64)
+        bm = torch.empty(P, dtype=torch.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        check(lib().periodic_sum_plan_tables(self._h, *(ctypes.cast(t.data_ptr(), dp) for t in (yc, yt, pinv, bm))))
+        return yc, yt, pinv, bm
+
+    def coefficients(self):
+        P = self.info()["P"]
+        C = torch.empty(P, dtype=torch.float64)
+        check(lib().periodic_sum_last_coefficients(self._h, ctypes.cast(C.data_ptr(), ctypes.POINTER(ctypes.c_double))))
+        return C
+
+    def eval(self, x, q, targets=None, out=None):
+        """phi (N,) and field -grad phi (3, N) at the particles, or at separate
+        targets (3, M).  Returns device tensors; enqueued on the current stream."""
+        x = _soa(x, self.device)
+        q = q.contiguous()
+        n = x.shape[1]
+        if targets is not None:
+            t = _soa(targets, self.device)
+            m = t.shape[1]
+            tp = [_ptr(t[0]), _ptr(t[1]), _ptr(t[2])]
+        else:
+            m = 0
+            tp = [None, None, None]
+        cnt = m if m else n
+        if out is None:
+            phi = torch.empty(cnt, dtype=torch.float64, device=self.device)
+            field = torch.empty(3, cnt, dtype=torch.float64, device=self.device)
+        else:
+            phi, field = out
+        check(lib().periodic_sum_eval(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), m, *tp,
+                                      _ptr(phi), _ptr(field[0]), _ptr(field[1]), _ptr(field[2]),
+                                      _stream(self.device)))
+        return phi, field
+
+    def set_profiling(self, enable=True):
+        check(lib().periodic_sum_set_profiling(self._h, int(bool(enable))))
+
+    def stage_times(self):
+        """Milliseconds per stage of the last profiled eval (synchronizes)."""
+        arr = (ctypes.c_double * len(_lib.STAGES))()
+        check(lib().periodic_sum_stage_times(self._h, arr, len(_lib.STAGES)))
+        return dict(zip(_lib.STAGES, list(arr)))
+
+    def status(self):
+        """Synchronize and raise on a data error of the last eval."""
+        check(lib().periodic_sum_status(self._h, _stream(self.device)))
+
+    def energy(self, x, q, phi=None, field=None):
+        x = _soa(x, self.device)
+        q = q.contiguous()
+        n = x.shape[1]
+        e = torch.empty(1, dtype=torch.float64, device=self.device)
+        f = field if field is not None else None
+        check(lib().periodic_sum_energy(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(e), _ptr(phi),
+                                        _ptr(f[0]) if f is not None else None, _ptr(f[1]) if f is not None else None,
+                                        _ptr(f[2]) if f is not None else None, _stream(self.device)))
+        return e
+
+    def energy_vjp(self, x, q, gE, exact=True):
+        x = _soa(x, self.device)
+        q = q.contiguous()
+        n = x.shape[1]
+        dx = torch.empty(3, n, dtype=torch.float64, device=self.device)
+        dq = torch.empty(n, dtype=torch.float64, device=self.device)
+        gE = gE.reshape(1).to(torch.float64).contiguous()
+        check(lib().periodic_sum_energy_vjp(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(gE),
+                                            _ptr(dx[0]), _ptr(dx[1]), _ptr(dx[2]), _ptr(dq), int(bool(exact)),
+                                            _stream(self.device)))
+        return dx, dq
+
+
+class BatchedPlan:
+    """Many independent boxes solved by one graph launch per eval."""
+
+    def __init__(self, systems, p, lam=None, R_b=None, precision="fp32", mean="zero", rcond=1e-13, tile_targets=0,
+                 n_split=0, device=0):
+        """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam')."""
+        self.device = torch.device("cuda", device)
+        arr = (ps_params * len(systems))()
+        for k, s in enumerate(systems):
+            arr[k] = _params(s["box"], s.get("p", p), s.get("R_b", R_b), s.get("lam", lam), precision, mean, rcond,
+                             s["n_max"], 0, tile_targets, n_split)
+        h = ctypes.c_void_p()
+        check(lib().periodic_sum_plan_batched(len(systems), arr, int(device), ctypes.byref(h)))
+        self._h = h
+        self._arr = arr
+        self.nsys = len(systems)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().periodic_sum_destroy(h)
+            self._h = None
+
+    def eval(self, x, q, offsets, out=None):
+        """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints."""
+        x = _soa(x, self.device)
+        q = q.contiguous()
+        off = (ctypes.c_int64 * (self.nsys + 1))(*[int(v) for v in offsets])
+        n = x.shape[1]
+        if out is None:
+            phi = torch.empty(n, dtype=torch.float64, device=self.device)
+            field = torch.empty(3, n, dtype=torch.float64, device=self.device)
+        else:
+            phi, field = out
+        check(lib().periodic_sum_eval_batched(self._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
+                                              _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), _stream(self.device)))
+        return phi, field
+
+    def status(self):
+        check(lib().periodic_sum_status(self._h, _stream(self.device)))
+
+
+class PeriodicEnergy(torch.autograd.Function):
+    """E = (1/2) sum q_i phi(x_i) with a hand-written adjoint (exact derivative of
+    the discrete method, or the physical -q E / phi approximation)."""
+
+    @staticmethod
+    def forward(ctx, x, q, plan, exact=True):
+        e = plan.energy(x, q)
+        ctx.save_for_backward(x, q)
+        ctx.plan = plan
+        ctx.exact = exact
+        return e[0]
+
+    @staticmethod
+    def backward(ctx, gE):
+        x, q = ctx.saved_tensors
+        dx, dq = ctx.plan.energy_vjp(x, q, gE, exact=ctx.exact)
+        if x.shape[0] != 3:
+            dx = dx.t()
+        return dx, dq, None, None

@@ -1,0 +1,983 @@
+// C ABI of the periodized Coulomb sum (include/periodic_sum.h): plan ("set",
+// Sec. 2.3) on the host, eval ("get") as a sequence of HIP kernels on the
+// caller's stream.  One code path serves a single box and a batch of boxes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/periodic_sum.h"
+#include "ps_device.h"
+#include "ps_kernels.h"
+#include "ps_setup.h"
+
+using namespace ps;
+
+namespace {
+
+thread_local std::string g_err;
+
+ps_status fail(ps_status s, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIPCHK(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess) return fail(PS_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
+constexpr int kCheckItemTarget = 4096;
+constexpr int kMaxSplit = 256;
+constexpr int kMaxCheckSplit = 2048;
+
+template <typename T>
+struct DBuf {
+    T* p = nullptr;
+    size_t n = 0;
+};
+
+struct Tables {                     // per-shape item tables (depend on the particle counts)
+    std::vector<int64_t> key;       // particle counts (and target count) they were built for
+    std::vector<CItem> sort_items, far_items;
+    std::vector<NItem> near_items;
+    std::vector<TItem> t_items;
+    std::vector<PItem> chk_items, p_items;
+    std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs
+    std::vector<SysDev> sys;
+    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0;
+};
+
+}  // namespace
+
+struct ps_plan_s {
+    int device = 0;
+    int nsys = 1;
+    int precision = 0;
+    int mean = 0;
+    int bt = 256;
+    int n_split_req = 0;
+    int maxP = 0, maxp = 0, maxL = 0;
+    int64_t m_max = 0;
+    std::vector<SystemSetup> setups;
+    std::vector<int64_t> n_max;      // per system
+    std::vector<SysDev> base;        // per system, static part
+    // device tables
+    SysDev* d_sys = nullptr;
+    double *d_img = nullptr, *d_chk = nullptr, *d_pinv = nullptr, *d_bm = nullptr, *d_rec = nullptr;
+    double *d_coef = nullptr, *d_f = nullptr;
+    // workspace
+    int64_t ntot_max = 0, near_tot = 0, cell_tot = 0, tiles_tot = 0, chk_tot = 0, inv_tot = 0;
+    double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
+    int *d_perm = nullptr, *d_keys = nullptr, *d_slots = nullptr, *d_cnt = nullptr, *d_start = nullptr;
+    double *d_nx = nullptr, *d_ny = nullptr, *d_nz = nullptr, *d_nq = nullptr;
+    int *d_nbase = nullptr, *d_inv = nullptr;
+    int64_t* d_nnear = nullptr;
+    int* d_ncount = nullptr;
+    int64_t* d_ioff = nullptr;
+    double* d_tile_bb = nullptr;
+    double *d_tblk_chk = nullptr, *d_tblk_p = nullptr;
+    double *d_part_chk = nullptr, *d_part_p = nullptr;
+    int64_t part_chk_cap = 0, part_p_cap = 0, tblk_p_cap = 0, tblk_chk_cap = 0;
+    double* d_mean_part = nullptr;
+    double* d_val_part = nullptr;
+    int64_t* d_scan_tot = nullptr;
+    int mean_blocks = 32, val_blocks = 8, scan_blocks = 4;
+    int64_t capacity = 2048;            // resident pair-sum workgroups on the device
+    double* d_osort = nullptr;
+    int* d_status = nullptr;
+    // item tables on the device
+    CItem *d_sort_items = nullptr, *d_far_items = nullptr;
+    NItem* d_near_items = nullptr;
+    TItem* d_t_items = nullptr;
+    PItem *d_chk_items = nullptr, *d_p_items = nullptr;
+    PJob* d_jobs = nullptr;
+    int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0;
+    Tables tab;
+    bool tab_valid = false;
+    int64_t last_n = 0;
+    std::vector<void*> allocs;
+    // adjoint workspace (allocated by the first exact energy_vjp call)
+    bool adj_ready = false;
+    double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr, *d_aq = nullptr;
+    double *d_adj_bb = nullptr, *d_adj_tblk = nullptr, *d_adj_part = nullptr, *d_mom = nullptr;
+    double *d_dq = nullptr, *d_dx = nullptr, *d_energy = nullptr;
+    TItem* d_adj_t = nullptr;
+    PItem* d_adj_p = nullptr;
+    PJob* d_adj_job = nullptr;
+    int64_t adj_part_cap = 0, adj_tb_cap = 0, adj_p_cap = 0;
+    std::vector<TItem> adj_t;
+    std::vector<PItem> adj_p;
+    PJob adj_job{};
+    // stage timing
+    bool prof = false;
+    hipEvent_t ev[PS_N_STAGES + 1] = {};
+    bool ev_recorded = false;
+    // batched graph
+    hipGraphExec_t graph = nullptr;
+    std::vector<const void*> graph_key;
+    hipStream_t cap_stream = nullptr;
+
+    ~ps_plan_s()
+    {
+        if (device >= 0) (void)hipSetDevice(device);
+        if (graph) (void)hipGraphExecDestroy(graph);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
+        for (void* p : allocs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T** p, int64_t count)
+    {
+        if (count < 1) count = 1;
+        hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * static_cast<size_t>(count));
+        if (e == hipSuccess) allocs.push_back(*p);
+        return e;
+    }
+};
+
+namespace {
+
+int ceil_log2(int64_t v)
+{
+    int b = 0;
+    while ((int64_t(1) << b) < v) ++b;
+    return b;
+}
+
+// Cell grid for the spatial ordering: cubic cells of side d_max / 2^gbits with
+// about two to four particles each (at most 128 per axis), so that the Morton
+// key space 2^(3 gbits) stays close to the number of occupied cells.
+void choose_grid(const double box[3], int64_t nmax, int g[3], int& gbits)
+{
+    const double V = box[0] * box[1] * box[2];
+    const double dmax = std::max(box[0], std::max(box[1], box[2]));
+    const double h = std::cbrt(V / std::max<double>(1.0, nmax / 2.0));
+    const double graw = std::max(1.0, std::ceil(dmax / h));
+    gbits = std::min(7, ceil_log2(static_cast<int64_t>(graw)));
+    if (gbits > 0 && (double)(1 << gbits) > 1.5 * graw) --gbits;
+    const double hc = dmax / (1 << gbits);
+    for (int k = 0; k < 3; ++k) g[k] = static_cast<int>(std::min<double>(1 << gbits, std::max(1.0, std::ceil(box[k] / hc))));
+}
+
+ps_status check_params(const ps_params* prm)
+{
+    if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
+    if (prm->precision != PS_FP64 && prm->precision != PS_FP32_ACC64) return fail(PS_E_INVALID, "unknown precision %d", prm->precision);
+    if (prm->mean != PS_MEAN_ZERO && prm->mean != PS_MEAN_NONE) return fail(PS_E_INVALID, "unknown mean mode %d", prm->mean);
+    if (prm->n_max < 1 || prm->n_max > (int64_t(1) << 30)) return fail(PS_E_INVALID, "n_max must be in [1, 2^30]");
+    if (prm->m_max < 0 || prm->m_max > (int64_t(1) << 30)) return fail(PS_E_INVALID, "m_max must be in [0, 2^30]");
+    if (prm->tile_targets != 0 && prm->tile_targets != 64 && prm->tile_targets != 128 && prm->tile_targets != 256)
+        return fail(PS_E_INVALID, "tile_targets must be 0, 64, 128 or 256");
+    if (prm->n_split < 0 || prm->n_split > kMaxSplit) return fail(PS_E_INVALID, "n_split must be in [0, %d]", kMaxSplit);
+    if (prm->p < 2 || prm->p > 40) return fail(PS_E_INVALID, "p must be in [2, 40]");
+    for (int k = 0; k < 3; ++k)
+        if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
+    const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + prm->box[2] * prm->box[2]);
+    const double Rb = prm->R_b > 0 ? prm->R_b : prm->lambda * R0;
+    if (!(Rb > R0) || !std::isfinite(Rb)) return fail(PS_E_INVALID, "near radius must exceed the circumradius (lambda > 1)");
+    return PS_OK;
+}
+
+// Source splits for one system's pair sum: the workgroup count ntb * S should
+// fill whole rounds of the device's resident capacity (at least four rounds
+// when the sources allow), so that the last round is not mostly idle.
+int split_for_capacity(int64_t ntb, int64_t capacity, int64_t ntiles_exp, int64_t max_split)
+{
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(max_split, std::max<int64_t>(1, ntiles_exp / 8)));
+    int best = 1;
+    double best_score = -1.0;
+    for (int64_t sp = 1; sp <= smax; ++sp) {
+        const int64_t items = ntb * sp;
+        const int64_t rounds = (items + capacity - 1) / capacity;
+        const double eff = static_cast<double>(items) / (rounds * capacity);
+        const double score = eff * (rounds >= 4 ? 1.0 : 0.9 + 0.025 * rounds);
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = static_cast<int>(sp);
+        }
+        if (rounds >= 12) break;
+    }
+    return best;
+}
+
+int split_for(int64_t ntb, int64_t target)
+{
+    int64_t s = (target + ntb - 1) / ntb;
+    if (s >= 8) s = (s + 7) / 8 * 8;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, s)));
+}
+
+// Build every per-shape table for particle counts n[k] (and m separate targets
+// for a single system).  Returns false if a workspace capacity is exceeded.
+bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const double* tx, const double* ty,
+                  const double* tz, std::string& why)
+{
+    Tables& T = pl->tab;
+    T = Tables();
+    const int nsys = pl->nsys;
+    T.sys = pl->base;
+    int64_t off = 0, coff = 0;
+    for (int s = 0; s < nsys; ++s) {
+        SysDev& S = T.sys[s];
+        if (n[s] > pl->n_max[s]) { why = "particle count exceeds n_max"; return false; }
+        S.n_off = off;
+        S.n = n[s];
+        off += n[s];
+        (void)coff;
+    }
+    // per-particle chunks (sort) and near-build items
+    for (int s = 0; s < nsys; ++s) {
+        SysDev& S = T.sys[s];
+        for (int64_t b = 0; b < S.n; b += kChunk)
+            T.sort_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(kChunk, S.n - b)), b});
+        S.nitem_begin = static_cast<int64_t>(T.near_items.size());
+        for (int mi = 0; mi < S.nimg; ++mi)
+            for (int64_t b = 0; b < S.n; b += kChunk)
+                T.near_items.push_back(NItem{s, mi, b, static_cast<int>(std::min<int64_t>(kChunk, S.n - b)), 0});
+        S.nitem_end = static_cast<int64_t>(T.near_items.size());
+    }
+    const bool separate = m > 0;
+    const int bt = pl->bt;
+    // jobs: check sums (FP64, potential) then particle sums
+    T.jobs.resize(2 * nsys);
+    int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
+    struct Est { int64_t ntb, nbexp; };
+    std::vector<Est> est(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        const SysDev& S = T.sys[s];
+        const SystemSetup& su = pl->setups[s];
+        PJob& C = T.jobs[s];
+        C = PJob{};
+        C.tx = pl->d_chk + S.chk_off;
+        C.ty = pl->d_chk + pl->chk_tot + S.chk_off;
+        C.tz = pl->d_chk + 2 * pl->chk_tot + S.chk_off;
+        C.nt = 2 * S.L;
+        C.sx = pl->d_nx + S.near_off;
+        C.sy = pl->d_ny + S.near_off;
+        C.sz = pl->d_nz + S.near_off;
+        C.sq = pl->d_nq + S.near_off;
+        C.ns_dev = pl->d_nnear + s;
+        C.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * 6;
+        C.tblk = pl->d_tblk_chk + tb_c_off * 4;
+        const int64_t ntb_c = (C.nt + 255) / 256;
+        // expected near-set size: the ball's volume fraction of the lattice (eq. (o2.1))
+        const double nb_exp = std::max<double>(1.0, 4.18879020478639 * su.R_b * su.R_b * su.R_b / su.V0 * S.n);
+        const int64_t ntiles_exp = static_cast<int64_t>(nb_exp / kTile) + 1;
+        C.nsplit = static_cast<int>(std::min<int64_t>(std::min<int64_t>(kMaxCheckSplit, (kCheckItemTarget + ntb_c - 1) / ntb_c),
+                                                      std::max<int64_t>(1, ntiles_exp / 2)));
+        C.ncomp = 1;
+        C.bt = 256;
+        C.part = pl->d_part_chk + pc_off;
+        pc_off += static_cast<int64_t>(C.nsplit) * C.nt;
+        for (int64_t tb = 0; tb < ntb_c; ++tb) {
+            T.t_items.push_back(TItem{s, static_cast<int>(tb)});
+            for (int sp = 0; sp < C.nsplit; ++sp) T.chk_items.push_back(PItem{s, static_cast<int>(tb), sp, 0});
+        }
+        tb_c_off += ntb_c;
+
+        PJob& Pj = T.jobs[nsys + s];
+        Pj = PJob{};
+        if (separate) {
+            Pj.tx = tx;
+            Pj.ty = ty;
+            Pj.tz = tz;
+            Pj.nt = m;
+        } else {
+            Pj.tx = pl->d_sx + S.n_off;
+            Pj.ty = pl->d_sy + S.n_off;
+            Pj.tz = pl->d_sz + S.n_off;
+            Pj.nt = S.n;
+        }
+        Pj.sx = C.sx;
+        Pj.sy = C.sy;
+        Pj.sz = C.sz;
+        Pj.sq = C.sq;
+        Pj.ns_dev = C.ns_dev;
+        Pj.tile_bb = C.tile_bb;
+        Pj.tblk = pl->d_tblk_p + tb_p_off * 4;
+        const int64_t ntb = (Pj.nt + bt - 1) / bt;
+        est[s] = Est{ntb, static_cast<int64_t>(nb_exp)};
+        tb_p_off += ntb;
+        Pj.ncomp = 4;
+        Pj.bt = bt;
+    }
+    // splits of the particle sums: aim for kItemTarget workgroups over the batch
+    int64_t ntb_all = 0;
+    for (int s = 0; s < nsys; ++s) ntb_all += est[s].ntb;
+    for (int s = 0; s < nsys; ++s) {
+        PJob& Pj = T.jobs[nsys + s];
+        int sp;
+        if (pl->n_split_req > 0) sp = pl->n_split_req;
+        else if (nsys == 1) {
+            const int64_t cap_split = std::max<int64_t>(1, (pl->part_p_cap / std::max<int64_t>(1, 4 * Pj.nt)));
+            sp = split_for_capacity(est[s].ntb, pl->capacity, est[s].nbexp / kTile + 1, std::min<int64_t>(kMaxSplit, cap_split));
+        }
+        else {
+            // batch: split large systems so their work items match the typical one
+            const double cost = static_cast<double>(est[s].nbexp) * bt;
+            double total = 0.0;
+            for (int r = 0; r < nsys; ++r) total += static_cast<double>(est[r].nbexp) * std::min<int64_t>(bt, T.sys[r].n) * est[r].ntb;
+            const double item_cost = std::max(1.0, total / kItemTarget);
+            sp = static_cast<int>(std::max(1.0, std::min<double>(kMaxSplit, std::ceil(cost / item_cost))));
+        }
+        const int64_t ntiles_exp = est[s].nbexp / kTile + 1;
+        sp = static_cast<int>(std::min<int64_t>(sp, std::max<int64_t>(1, ntiles_exp)));
+        Pj.nsplit = sp;
+        Pj.part = pl->d_part_p + pp_off;
+        pp_off += static_cast<int64_t>(sp) * 4 * Pj.nt;
+    }
+    if (pc_off > pl->part_chk_cap) { why = "check partial workspace too small"; return false; }
+    if (pp_off > pl->part_p_cap) { why = "pair partial workspace too small"; return false; }
+    if (tb_p_off > pl->tblk_p_cap || tb_c_off > pl->tblk_chk_cap) { why = "target block workspace too small"; return false; }
+    // particle pair items, largest systems first; splits of one target block are
+    // consecutive so that workgroups sharing a source split land on the same XCD
+    std::vector<int> order(nsys);
+    for (int s = 0; s < nsys; ++s) order[s] = s;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const PJob& A = T.jobs[nsys + a];
+        const PJob& B = T.jobs[nsys + b];
+        return static_cast<double>(est[a].nbexp) / A.nsplit > static_cast<double>(est[b].nbexp) / B.nsplit;
+    });
+    for (int s : order) {
+        const PJob& Pj = T.jobs[nsys + s];
+        for (int64_t tb = 0; tb < est[s].ntb; ++tb) {
+            T.t_items.push_back(TItem{nsys + s, static_cast<int>(tb)});
+            for (int sp = 0; sp < Pj.nsplit; ++sp) T.p_items.push_back(PItem{s, static_cast<int>(tb), sp, 0});
+        }
+    }
+    // far-field/combine chunks of 256 targets
+    for (int s = 0; s < nsys; ++s) {
+        const int64_t nt = T.jobs[nsys + s].nt;
+        for (int64_t b = 0; b < nt; b += 256)
+            T.far_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(256, nt - b)), b});
+    }
+    T.nsort = T.sort_items.size();
+    T.nfar = T.far_items.size();
+    T.nnear_items = T.near_items.size();
+    T.nt_items = T.t_items.size();
+    T.nchk = T.chk_items.size();
+    T.np = T.p_items.size();
+    if (T.nsort > pl->cap_sort || T.nfar > pl->cap_far || T.nnear_items > pl->cap_near_items || T.nt_items > pl->cap_t ||
+        T.nchk > pl->cap_chk || T.np > pl->cap_p) {
+        why = "item table capacity exceeded";
+        return false;
+    }
+    return true;
+}
+
+hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
+{
+    Tables& T = pl->tab;
+    hipError_t e;
+#define UP(dst, vec)                                                                                               \
+    if (!(vec).empty()) {                                                                                          \
+        e = hipMemcpyAsync(dst, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice, st);         \
+        if (e != hipSuccess) return e;                                                                             \
+    }
+    UP(pl->d_sys, T.sys)
+    UP(pl->d_sort_items, T.sort_items)
+    UP(pl->d_far_items, T.far_items)
+    UP(pl->d_near_items, T.near_items)
+    UP(pl->d_t_items, T.t_items)
+    UP(pl->d_chk_items, T.chk_items)
+    UP(pl->d_p_items, T.p_items)
+    UP(pl->d_jobs, T.jobs)
+#undef UP
+    return hipStreamSynchronize(st);
+}
+
+// Enqueue algorithm "get" for the current tables.
+void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* z, const double* q, bool separate,
+                 double* phi, double* ex, double* ey, double* ez, hipStream_t st)
+{
+    const Tables& T = pl->tab;
+    const int nsys = pl->nsys;
+    const bool prof = pl->prof && nsys == 1;
+    auto mark = [&](int k) {
+        if (prof) (void)hipEventRecord(pl->ev[k], st);
+    };
+    mark(0);
+    launch_validate(nsys, pl->val_blocks, pl->d_sys, x, y, z, q, pl->d_status, pl->d_val_part, st);
+    int64_t max_ncell = 0;
+    for (const SysDev& S : T.sys) max_ncell = std::max<int64_t>(max_ncell, S.ncell);
+    launch_sort(nsys, T.nsort, max_ncell, pl->d_sys, pl->d_sort_items, x, y, z, q, pl->d_keys, pl->d_slots, pl->d_cnt,
+                pl->d_start, pl->cell_tot, pl->scan_blocks, pl->d_scan_tot, pl->d_perm, pl->d_sx, pl->d_sy, pl->d_sz,
+                pl->d_sq, st);
+    mark(1);
+    launch_near(nsys, T.nnear_items, pl->d_sys, pl->d_near_items, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq,
+                pl->d_ncount, pl->d_ioff, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_nbase, pl->d_inv,
+                st);
+    const PJob* cjobs = pl->d_jobs;
+    const PJob* pjobs = pl->d_jobs + nsys;
+    mark(2);
+    launch_tile_bounds(nsys, nsys == 1 ? 1024 : 64, pjobs, st);
+    launch_tblock(T.nt_items, pl->d_jobs, pl->d_t_items, st);
+    mark(3);
+    launch_p2p(0, 256, false, T.nchk, cjobs, pl->d_chk_items, st);                      // step 3 at the check points
+    mark(4);
+    launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
+    mark(5);
+    launch_mean(nsys, pl->mean_blocks, pl->d_sys, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part, pl->d_bm,
+                pl->d_coef, st);                                                          // step 6
+    mark(6);
+    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
+    mark(7);
+    launch_far(T.nfar, pl->maxP, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, pl->d_coef, pl->d_rec,
+               separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
+    mark(8);
+    if (prof) pl->ev_recorded = true;
+}
+
+ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
+{
+    if (!out) return fail(PS_E_INVALID, "output plan pointer is NULL");
+    *out = nullptr;
+    if (nsys < 1) return fail(PS_E_INVALID, "nsys must be >= 1");
+    if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
+    for (int s = 0; s < nsys; ++s) {
+        ps_status st = check_params(&prm[s]);
+        if (st != PS_OK) return st;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PS_E_HIP, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(PS_E_INVALID, "device %d out of range [0, %d)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    ps_plan_s* pl = new (std::nothrow) ps_plan_s();
+    if (!pl) return fail(PS_E_NOMEM, "host allocation failed");
+    pl->device = device;
+    pl->nsys = nsys;
+    pl->precision = prm[0].precision;
+    pl->mean = prm[0].mean;
+    pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
+    pl->n_split_req = prm[0].n_split;
+    pl->m_max = nsys == 1 ? prm[0].m_max : 0;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+            pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
+                           p2p_blocks_per_cu(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt);
+    }
+    pl->setups.resize(nsys);
+    pl->n_max.resize(nsys);
+    pl->base.resize(nsys);
+    // host "set" per system
+    std::vector<std::string> errs(nsys);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int s = 0; s < nsys; ++s)
+        errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond);
+    for (int s = 0; s < nsys; ++s)
+        if (!errs[s].empty()) {
+            delete pl;
+            return fail(PS_E_INVALID, "system %d: %s", s, errs[s].c_str());
+        }
+    // pack offsets
+    int64_t img_tot = 0, pinv_tot = 0, coef_tot = 0, rec_tot = 0, f_tot = 0;
+    int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const SystemSetup& su = pl->setups[s];
+        SysDev& S = pl->base[s];
+        S = SysDev{};
+        pl->n_max[s] = prm[s].n_max;
+        for (int k = 0; k < 3; ++k) {
+            S.box[k] = su.box[k];
+            S.half[k] = 0.5 * su.box[k];
+        }
+        S.R0 = su.R0;
+        S.inv_R0 = 1.0 / su.R0;
+        S.thr = su.thr;
+        S.V0 = su.V0;
+        S.p = su.p;
+        S.P = su.P;
+        S.L = su.L;
+        S.nimg = static_cast<int>(su.images.size() / 3);
+        S.mean_mode = prm[0].mean;
+        choose_grid(su.box, prm[s].n_max, S.g, S.gbits);
+        for (int k = 0; k < 3; ++k) S.inv_cell[k] = S.g[k] / su.box[k];
+        S.ncell = int64_t(1) << (3 * S.gbits);
+        S.cell_off = cell_tot;
+        cell_tot += S.ncell + 1;
+        S.near_off = near_tot;
+        S.near_cap = prm[s].n_max * S.nimg;
+        near_tot += (S.near_cap + kTile - 1) / kTile * kTile;  // tiles never straddle systems
+        S.img_off = img_tot;
+        img_tot += S.nimg;
+        S.chk_off = chk_tot;
+        chk_tot += 2 * S.L;
+        S.pinv_off = pinv_tot;
+        pinv_tot += static_cast<int64_t>(S.P - 1) * S.L;
+        S.coef_off = coef_tot;
+        S.bm_off = coef_tot;
+        coef_tot += S.P;
+        S.rec_off = rec_tot;
+        rec_tot += 2 * S.P + S.p;
+        S.f_off = f_tot;
+        f_tot += S.L;
+        S.inv_off = inv_tot;
+        inv_tot += prm[s].n_max * S.nimg;
+        n_tot += prm[s].n_max;
+        pl->maxP = std::max(pl->maxP, S.P);
+        pl->maxp = std::max(pl->maxp, S.p);
+        pl->maxL = std::max(pl->maxL, S.L);
+    }
+    pl->ntot_max = n_tot;
+    pl->near_tot = near_tot;
+    pl->cell_tot = cell_tot;
+    pl->chk_tot = chk_tot;
+    pl->inv_tot = inv_tot;
+    pl->tiles_tot = near_tot / kTile + 1;
+    // host tables
+    std::vector<double> h_img(img_tot * 3), h_chk(chk_tot * 3), h_pinv(pinv_tot), h_bm(coef_tot), h_rec(rec_tot);
+    for (int s = 0; s < nsys; ++s) {
+        const SystemSetup& su = pl->setups[s];
+        const SysDev& S = pl->base[s];
+        for (int mi = 0; mi < S.nimg; ++mi)
+            for (int k = 0; k < 3; ++k) h_img[(S.img_off + mi) * 3 + k] = su.images[mi * 3 + k] * su.box[k];
+        for (int l = 0; l < S.L; ++l)
+            for (int k = 0; k < 3; ++k) {
+                h_chk[k * chk_tot + S.chk_off + l] = su.yc[l * 3 + k];
+                h_chk[k * chk_tot + S.chk_off + S.L + l] = su.yt[l * 3 + k];
+            }
+        std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
+        std::copy(su.box_means.begin(), su.box_means.end(), h_bm.begin() + S.bm_off);
+        std::copy(su.rec.a.begin(), su.rec.a.end(), h_rec.begin() + S.rec_off);
+        std::copy(su.rec.b.begin(), su.rec.b.end(), h_rec.begin() + S.rec_off + S.P);
+        std::copy(su.rec.c.begin(), su.rec.c.end(), h_rec.begin() + S.rec_off + 2 * S.P);
+    }
+    // capacities of the per-shape tables
+    int64_t sort_cap = 0, near_items_cap = 0, far_cap = 0, tb_p = 0, tb_c = 0;
+    int64_t nt_sum = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const SysDev& S = pl->base[s];
+        const int64_t nt = std::max<int64_t>(prm[s].n_max, nsys == 1 ? prm[0].m_max : 0);
+        sort_cap += (prm[s].n_max + kChunk - 1) / kChunk;
+        near_items_cap += S.nimg * ((prm[s].n_max + kChunk - 1) / kChunk);
+        far_cap += (nt + 255) / 256;
+        tb_p += (nt + 63) / 64;
+        tb_c += (2 * S.L + 255) / 256;
+        nt_sum += nt;
+    }
+    pl->cap_sort = sort_cap;
+    pl->cap_near_items = near_items_cap;
+    pl->cap_far = far_cap;
+    pl->cap_t = tb_p + tb_c;
+    pl->tblk_p_cap = tb_p;
+    pl->tblk_chk_cap = tb_c;
+    pl->cap_chk = tb_c * kMaxCheckSplit + 16;
+    pl->cap_p = std::max<int64_t>(tb_p * kMaxSplit, 1);
+    pl->part_chk_cap = chk_tot * kMaxCheckSplit + 16;
+    pl->part_p_cap = std::max<int64_t>(4 * nt_sum * 16, 4 * (int64_t)kItemTarget * 256 * 2) + 4 * nt_sum * 8;
+    if (pl->n_split_req > 0) pl->part_p_cap = std::max<int64_t>(pl->part_p_cap, 4 * nt_sum * pl->n_split_req);
+    hipError_t e = hipSuccess;
+#define AL(ptr, cnt) \
+    if (e == hipSuccess) e = pl->alloc(&(ptr), (cnt));
+    AL(pl->d_sys, nsys)
+    AL(pl->d_img, img_tot * 3)
+    AL(pl->d_chk, chk_tot * 3)
+    AL(pl->d_pinv, pinv_tot)
+    AL(pl->d_bm, coef_tot)
+    AL(pl->d_rec, rec_tot)
+    AL(pl->d_coef, coef_tot)
+    AL(pl->d_f, f_tot)
+    AL(pl->d_sx, n_tot)
+    AL(pl->d_sy, n_tot)
+    AL(pl->d_sz, n_tot)
+    AL(pl->d_sq, n_tot)
+    AL(pl->d_perm, n_tot)
+    AL(pl->d_keys, n_tot)
+    AL(pl->d_slots, n_tot)
+    AL(pl->d_osort, 4 * n_tot)
+    AL(pl->d_cnt, cell_tot)
+    AL(pl->d_start, cell_tot)
+    AL(pl->d_nx, near_tot)
+    AL(pl->d_ny, near_tot)
+    AL(pl->d_nz, near_tot)
+    AL(pl->d_nq, near_tot)
+    AL(pl->d_nbase, near_tot)
+    AL(pl->d_inv, inv_tot)
+    AL(pl->d_nnear, nsys)
+    AL(pl->d_ncount, near_items_cap)
+    AL(pl->d_ioff, near_items_cap)
+    AL(pl->d_tile_bb, pl->tiles_tot * 6)
+    AL(pl->d_tblk_chk, tb_c * 4)
+    AL(pl->d_tblk_p, tb_p * 4)
+    AL(pl->d_part_chk, pl->part_chk_cap)
+    AL(pl->d_part_p, pl->part_p_cap)
+    pl->mean_blocks = nsys == 1 ? 1024 : 32;
+    pl->val_blocks = nsys == 1 ? 256 : 8;
+    pl->scan_blocks = nsys == 1 ? 256 : 4;
+    AL(pl->d_mean_part, (int64_t)nsys * pl->mean_blocks)
+    AL(pl->d_val_part, (int64_t)2 * nsys * pl->val_blocks)
+    AL(pl->d_scan_tot, (int64_t)nsys * pl->scan_blocks)
+    AL(pl->d_status, 1)
+    AL(pl->d_sort_items, sort_cap)
+    AL(pl->d_far_items, far_cap)
+    AL(pl->d_near_items, near_items_cap)
+    AL(pl->d_t_items, pl->cap_t)
+    AL(pl->d_chk_items, pl->cap_chk)
+    AL(pl->d_p_items, pl->cap_p)
+    AL(pl->d_jobs, 2 * nsys)
+#undef AL
+    if (e != hipSuccess) {
+        delete pl;
+        return fail(PS_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+#define UPS(dst, vec) \
+    if (e == hipSuccess && !(vec).empty()) e = hipMemcpy(dst, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice);
+    UPS(pl->d_img, h_img)
+    UPS(pl->d_chk, h_chk)
+    UPS(pl->d_pinv, h_pinv)
+    UPS(pl->d_bm, h_bm)
+    UPS(pl->d_rec, h_rec)
+#undef UPS
+    if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int));
+    if (e == hipSuccess) e = hipMemset(pl->d_coef, 0, sizeof(double) * coef_tot);
+    if (e == hipSuccess) e = hipMemset(pl->d_nnear, 0, sizeof(int64_t) * nsys);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        delete pl;
+        return fail(PS_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
+    }
+    *out = pl;
+    return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* periodic_sum_last_error(void) { return g_err.c_str(); }
+
+ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out) { return make_plan(1, prm, device, out); }
+
+ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int device, ps_plan* out)
+{
+    return make_plan(nsys, prm, device, out);
+}
+
+void periodic_sum_destroy(ps_plan plan) { delete plan; }
+
+ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double* y, const double* z, const double* q,
+                            int64_t m, const double* tx, const double* ty, const double* tz, double* phi, double* ex,
+                            double* ey, double* ez, void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (pl->nsys != 1) return fail(PS_E_INVALID, "batched plan: use periodic_sum_eval_batched");
+    if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max=%lld]", (long long)n, (long long)pl->n_max[0]);
+    if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
+    if (m < 0 || m > pl->m_max) return fail(PS_E_INVALID, "m=%lld outside [0, m_max=%lld]", (long long)m, (long long)pl->m_max);
+    if (m > 0 && (!tx || !ty || !tz)) return fail(PS_E_INVALID, "target arrays must not be NULL when m > 0");
+    if (!phi && !ex && !ey && !ez) return fail(PS_E_INVALID, "no output array given");
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::vector<int64_t> key = {n, m, reinterpret_cast<int64_t>(tx), reinterpret_cast<int64_t>(ty),
+                                      reinterpret_cast<int64_t>(tz)};
+    if (!pl->tab_valid || pl->tab.key != key) {
+        std::string why;
+        pl->tab_valid = false;
+        if (!build_tables(pl, std::vector<int64_t>{n}, m, tx, ty, tz, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
+        pl->tab.key = key;
+        HIPCHK(upload_tables(pl, st));
+        pl->tab_valid = true;
+    }
+    pl->last_n = n;
+    enqueue_get(pl, x, y, z, q, m > 0, phi, ex, ey, ez, st);
+    HIPCHK(hipGetLastError());
+    return PS_OK;
+}
+
+ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const double* x, const double* y,
+                                    const double* z, const double* q, double* phi, double* ex, double* ey, double* ez,
+                                    void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (!offsets) return fail(PS_E_INVALID, "offsets is NULL");
+    if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
+    if (!phi && !ex && !ey && !ez) return fail(PS_E_INVALID, "no output array given");
+    std::vector<int64_t> n(pl->nsys);
+    if (offsets[0] != 0) return fail(PS_E_INVALID, "offsets[0] must be 0");
+    for (int s = 0; s < pl->nsys; ++s) {
+        n[s] = offsets[s + 1] - offsets[s];
+        if (n[s] < 1 || n[s] > pl->n_max[s])
+            return fail(PS_E_INVALID, "system %d: n=%lld outside [1, n_max=%lld]", s, (long long)n[s], (long long)pl->n_max[s]);
+    }
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool same_shape = pl->tab_valid && pl->tab.key == n;
+    if (!same_shape) {
+        std::string why;
+        if (!build_tables(pl, n, 0, nullptr, nullptr, nullptr, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
+        pl->tab.key = n;
+        HIPCHK(upload_tables(pl, st));
+        pl->tab_valid = true;
+        if (pl->graph) {
+            (void)hipGraphExecDestroy(pl->graph);
+            pl->graph = nullptr;
+        }
+    }
+    // one graph per (shape, buffers): captured on a private stream, launched on the caller's
+    std::vector<const void*> key = {x, y, z, q, phi, ex, ey, ez};
+    if (!pl->graph || pl->graph_key != key) {
+        if (pl->graph) {
+            (void)hipGraphExecDestroy(pl->graph);
+            pl->graph = nullptr;
+        }
+        if (!pl->cap_stream) HIPCHK(hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking));
+        HIPCHK(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+        enqueue_get(pl, x, y, z, q, false, phi, ex, ey, ez, pl->cap_stream);
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamEndCapture(pl->cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&pl->graph, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(PS_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+        pl->graph_key = key;
+    }
+    HIPCHK(hipGraphLaunch(pl->graph, st));
+    return PS_OK;
+}
+
+ps_status periodic_sum_status(ps_plan pl, void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, pl->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipMemsetAsync(pl->d_status, 0, sizeof(int), st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (h & 1) return fail(PS_E_NOT_NEUTRAL, "charges are not neutral (|sum q| > 1e-12 sum |q|)");
+    if (h & 2) return fail(PS_E_OUT_OF_BOX, "a particle lies outside [-d/2, d/2) or has a NaN coordinate/charge");
+    return PS_OK;
+}
+
+ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
+{
+    if (!pl || !out) return fail(PS_E_INVALID, "NULL argument");
+    const SystemSetup& su = pl->setups[0];
+    out->p = su.p;
+    out->P = su.P;
+    out->L = su.L;
+    out->n_images = static_cast<int32_t>(su.images.size() / 3);
+    out->rank = su.rank;
+    out->R0 = su.R0;
+    out->R_b = su.R_b;
+    out->cond = su.cond;
+    out->tile_targets = pl->bt;
+    out->n_split = pl->tab.jobs.size() > static_cast<size_t>(pl->nsys) ? pl->tab.jobs[pl->nsys].nsplit : 0;
+    out->nsys = pl->nsys;
+    HIPCHK(hipSetDevice(pl->device));
+    HIPCHK(hipDeviceSynchronize());
+    int64_t nb = 0;
+    HIPCHK(hipMemcpy(&nb, pl->d_nnear, sizeof(int64_t), hipMemcpyDeviceToHost));
+    out->n_near_last = nb;
+    return PS_OK;
+}
+
+ps_status periodic_sum_plan_tables(ps_plan pl, double* check_points, double* partners, double* pinv, double* box_means)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (pl->nsys != 1) return fail(PS_E_INVALID, "single-system plans only");
+    const SystemSetup& su = pl->setups[0];
+    if (check_points) std::copy(su.yc.begin(), su.yc.end(), check_points);
+    if (partners) std::copy(su.yt.begin(), su.yt.end(), partners);
+    if (pinv) std::copy(su.pinv.begin(), su.pinv.end(), pinv);
+    if (box_means) std::copy(su.box_means.begin(), su.box_means.end(), box_means);
+    return PS_OK;
+}
+
+ps_status periodic_sum_set_profiling(ps_plan pl, int32_t enable)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    HIPCHK(hipSetDevice(pl->device));
+    if (enable && !pl->ev[0])
+        for (hipEvent_t& e : pl->ev) HIPCHK(hipEventCreate(&e));
+    pl->prof = enable != 0;
+    pl->ev_recorded = false;
+    return PS_OK;
+}
+
+ps_status periodic_sum_stage_times(ps_plan pl, double* ms, int32_t n)
+{
+    if (!pl || !ms) return fail(PS_E_INVALID, "NULL argument");
+    if (n < PS_N_STAGES) return fail(PS_E_INVALID, "need room for %d stages", PS_N_STAGES);
+    if (!pl->ev_recorded) return fail(PS_E_INVALID, "no profiled eval has been enqueued");
+    HIPCHK(hipSetDevice(pl->device));
+    HIPCHK(hipEventSynchronize(pl->ev[PS_N_STAGES]));
+    for (int k = 0; k < PS_N_STAGES; ++k) {
+        float t = 0.f;
+        HIPCHK(hipEventElapsedTime(&t, pl->ev[k], pl->ev[k + 1]));
+        ms[k] = t;
+    }
+    return PS_OK;
+}
+
+ps_status periodic_sum_last_coefficients(ps_plan pl, double* C)
+{
+    if (!pl || !C) return fail(PS_E_INVALID, "NULL argument");
+    HIPCHK(hipSetDevice(pl->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(C, pl->d_coef, sizeof(double) * pl->setups[0].P, hipMemcpyDeviceToHost));
+    return PS_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+constexpr int kMomBlocks = 64;
+
+ps_status ensure_forward_tables(ps_plan_s* pl, int64_t n, hipStream_t st)
+{
+    const std::vector<int64_t> key = {n, 0, 0, 0, 0};
+    if (!pl->tab_valid || pl->tab.key != key) {
+        std::string why;
+        pl->tab_valid = false;
+        if (!build_tables(pl, std::vector<int64_t>{n}, 0, nullptr, nullptr, nullptr, why))
+            return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
+        pl->tab.key = key;
+        HIPCHK(upload_tables(pl, st));
+        pl->tab_valid = true;
+    }
+    return PS_OK;
+}
+
+ps_status ensure_adjoint_workspace(ps_plan_s* pl)
+{
+    if (pl->adj_ready) return PS_OK;
+    const SysDev& S = pl->base[0];
+    const int64_t ns = pl->n_max[0] + 2 * S.L;
+    const int64_t ncap = S.near_cap;
+    pl->adj_tb_cap = (ncap + 63) / 64 + 1;
+    pl->adj_p_cap = pl->adj_tb_cap * 64 + kItemTarget * 2;
+    pl->adj_part_cap = 4 * (static_cast<int64_t>(kItemTarget) * 256 * 2 + 9 * ncap);
+    hipError_t e = hipSuccess;
+#define AL(ptr, cnt) \
+    if (e == hipSuccess) e = pl->alloc(&(ptr), (cnt));
+    AL(pl->d_ax, ns)
+    AL(pl->d_ay, ns)
+    AL(pl->d_az, ns)
+    AL(pl->d_aq, ns)
+    AL(pl->d_adj_bb, (ns / kTile + 1) * 6)
+    AL(pl->d_adj_tblk, pl->adj_tb_cap * 4)
+    AL(pl->d_adj_part, pl->adj_part_cap)
+    AL(pl->d_mom, (int64_t)kMomBlocks * S.P)
+    AL(pl->d_dq, pl->n_max[0])
+    AL(pl->d_dx, 3 * pl->n_max[0])
+    AL(pl->d_adj_t, pl->adj_tb_cap)
+    AL(pl->d_adj_p, pl->adj_p_cap)
+    AL(pl->d_adj_job, 1)
+#undef AL
+    if (e != hipSuccess) return fail(PS_E_NOMEM, "adjoint workspace allocation failed: %s", hipGetErrorString(e));
+    pl->adj_ready = true;
+    return PS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status periodic_sum_energy(ps_plan pl, int64_t n, const double* x, const double* y, const double* z,
+                              const double* q, double* energy, double* phi, double* ex, double* ey, double* ez,
+                              void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy is available for single-system plans");
+    if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max]", (long long)n);
+    if (!x || !y || !z || !q || !energy) return fail(PS_E_INVALID, "NULL argument");
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    ps_status s = ensure_forward_tables(pl, n, st);
+    if (s != PS_OK) return s;
+    pl->last_n = n;
+    enqueue_get(pl, x, y, z, q, false, phi, ex, ey, ez, st);
+    launch_energy(1, pl->d_sys, pl->d_sq, pl->d_osort, energy, st);
+    HIPCHK(hipGetLastError());
+    return PS_OK;
+}
+
+ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const double* y, const double* z,
+                                  const double* q, const double* gE, double* dEdx, double* dEdy, double* dEdz,
+                                  double* dEdq, int32_t exact, void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy_vjp is available for single-system plans");
+    if (!x || !y || !z || !q || !gE) return fail(PS_E_INVALID, "NULL argument");
+    const std::vector<int64_t> key = {n, 0, 0, 0, 0};
+    if (!pl->tab_valid || pl->tab.key != key || pl->last_n != n)
+        return fail(PS_E_INVALID, "energy_vjp must follow a forward pass at the same particles");
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const SysDev& S = pl->tab.sys[0];
+    if (exact) {
+        ps_status s = ensure_adjoint_workspace(pl);
+        if (s != PS_OK) return s;
+        int64_t nb = 0;
+        HIPCHK(hipMemcpyAsync(&nb, pl->d_nnear, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const int64_t ns = n + 2 * S.L;
+        const int bt = pl->bt;
+        PJob& J = pl->adj_job;
+        J = PJob{};
+        J.tx = pl->d_nx + S.near_off;
+        J.ty = pl->d_ny + S.near_off;
+        J.tz = pl->d_nz + S.near_off;
+        J.nt = nb;
+        J.sx = pl->d_ax;
+        J.sy = pl->d_ay;
+        J.sz = pl->d_az;
+        J.sq = pl->d_aq;
+        J.ns_dev = nullptr;
+        J.ns_host = ns;
+        J.tile_bb = pl->d_adj_bb;
+        J.tblk = pl->d_adj_tblk;
+        J.part = pl->d_adj_part;
+        J.ncomp = 4;
+        J.bt = bt;
+        const int64_t ntb = (nb + bt - 1) / bt;
+        J.nsplit = static_cast<int>(std::min<int64_t>(split_for(ntb, kItemTarget), ns / kTile + 1));
+        if (ntb > pl->adj_tb_cap || static_cast<int64_t>(J.nsplit) * 4 * nb > pl->adj_part_cap ||
+            ntb * J.nsplit > pl->adj_p_cap)
+            return fail(PS_E_UNSUPPORTED, "adjoint workspace too small");
+        pl->adj_t.clear();
+        pl->adj_p.clear();
+        for (int64_t tb = 0; tb < ntb; ++tb) {
+            pl->adj_t.push_back(TItem{0, static_cast<int>(tb)});
+            for (int sp = 0; sp < J.nsplit; ++sp) pl->adj_p.push_back(PItem{0, static_cast<int>(tb), sp, 0});
+        }
+        HIPCHK(hipMemcpyAsync(pl->d_adj_job, &J, sizeof(PJob), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pl->d_adj_t, pl->adj_t.data(), sizeof(TItem) * pl->adj_t.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipMemcpyAsync(pl->d_adj_p, pl->adj_p.data(), sizeof(PItem) * pl->adj_p.size(), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        launch_adjoint_sources(S.P, S.p, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec,
+                               pl->d_mom, kMomBlocks, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az,
+                               pl->d_aq, st);
+        launch_tile_bounds(1, 256, pl->d_adj_job, st);
+        launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
+        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, static_cast<int64_t>(pl->adj_p.size()),
+                   pl->d_adj_job, pl->d_adj_p, st);
+    } else {
+        ps_status s = ensure_adjoint_workspace(pl);
+        if (s != PS_OK) return s;
+    }
+    launch_adjoint_finish(n, pl->d_sys, pl->d_adj_job, pl->d_inv, pl->d_sq, pl->d_osort, exact ? 1 : 0, pl->d_dq,
+                          pl->d_dx, pl->d_perm, gE, dEdq, dEdx, dEdy, dEdz, st);
+    HIPCHK(hipGetLastError());
+    return PS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Device-side descriptors shared by the kernels and the host orchestration.
+#pragma once
+#include <cstdint>
+
+namespace ps {
+
+constexpr int kTile = 256;         // sources staged per LDS tile
+constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
+
+// One periodic system (a box with its particles).  Offsets index packed arrays.
+struct SysDev {
+    double box[3], half[3], inv_cell[3];
+    double R0, inv_R0, thr, V0;
+    int g[3], gbits;
+    int p, P, L, nimg;
+    int mean_mode, pad0;
+    int64_t n_off, n;            // particles in the packed input / sorted arrays
+    int64_t cell_off, ncell;     // cell counters (ncell + 1 entries)
+    int64_t near_off, near_cap;  // near list
+    int64_t img_off;             // images, 3 doubles each
+    int64_t chk_off;             // 2L check targets (first L: y_l, then y~_l)
+    int64_t pinv_off;            // (P-1) x L
+    int64_t coef_off;            // P coefficients; coef[0] holds C1
+    int64_t bm_off;              // P box means R_t^(0)
+    int64_t rec_off;             // recurrence tables: a[P], b[P], c[p]
+    int64_t inv_off;             // inverse near map: nimg x n (entry index or -1)
+    int64_t nitem_begin, nitem_end;  // near-build items of this system
+    int64_t f_off;               // L right-hand-side values
+};
+
+// A pair-sum job: every target of a set against every source of another.
+struct PJob {
+    const double* tx;
+    const double* ty;
+    const double* tz;
+    int64_t nt;
+    const double* sx;
+    const double* sy;
+    const double* sz;
+    const double* sq;
+    const int64_t* ns_dev;  // device source count (or null)
+    int64_t ns_host;        // host source count when ns_dev is null
+    const double* tile_bb;  // 6 doubles per tile of kTile sources: lo xyz, hi xyz
+    double* tblk;           // 4 doubles per target block: centre xyz, radius
+    double* part;           // partial sums [nsplit][ncomp][nt]
+    int nsplit, ncomp, bt, pad;
+};
+
+struct PItem { int job, tb, split, pad; };           // one workgroup of a pair sum
+struct TItem { int job, tb; };                       // one target block
+struct CItem { int sys, count; int64_t start; };     // a chunk of a system's particles
+struct NItem { int sys, img; int64_t start; int count, pad; };  // near-build item
+
+}  // namespace ps

@@ -1,0 +1,44 @@
+// Host launchers of the HIP kernels (ps_kernels.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "ps_device.h"
+
+namespace ps {
+
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st);
+void launch_validate(int nsys, int nblk, const SysDev* sys, const double* X, const double* Y, const double* Z,
+                     const double* Q, int* status, double* part, hipStream_t st);
+void launch_sort(int nsys, int64_t ncitems, int64_t max_ncell, const SysDev* sys, const CItem* citems, const double* X,
+                 const double* Y, const double* Z, const double* Q, int* keys, int* slots, int* cnt, int* start,
+                 int64_t ncnt_total, int scan_blocks, int64_t* scan_tot, int* perm, double* sx, double* sy, double* sz,
+                 double* sq, hipStream_t st);
+void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nitems, const double* img,
+                 const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
+                 int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st);
+void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st);
+void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st);
+void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
+void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
+                  double* coef, double* f, hipStream_t st);
+void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
+                 const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st);
+void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
+                const double* coef, const double* rec, const int* perm, double* phi, double* ex, double* ey,
+                double* ez, double* osort, hipStream_t st);
+
+}  // namespace ps
+
+namespace ps {
+void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* osort, double* energy, hipStream_t st);
+void launch_adjoint_sources(int P, int p, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
+                            const double* sz, const double* sq, const double* rec, double* mom_part, int mom_blocks,
+                            const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
+                            double* az, double* aq, hipStream_t st);
+void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
+                           const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,
+                           double* oq, double* ox, double* oy, double* oz, hipStream_t st);
+}  // namespace ps
+namespace ps {
+int p2p_blocks_per_cu(int prec, int bt);
+}

@@ -1,0 +1,1226 @@
+// HIP kernels (gfx950) of the periodized Coulomb sum, algorithm "get" (Sec. 2.3).
+//
+// Data layout in HBM: structure-of-arrays FP64 for positions, charges, the near
+// list and all outputs; partial sums of the pair kernels as [split][component][target].
+// Every kernel takes its work from small descriptor tables (SysDev, PJob, items),
+// so one launch serves one box or a batch of boxes.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "ps_device.h"
+#include "ps_kernels.h"
+
+namespace ps {
+
+// ----------------------------------------------------------------------------
+// deterministic reductions (fixed order for a given launch shape)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int64_t wave_sum_i64(int64_t v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide reductions; the result is valid in every thread.  `sh` needs
+// blockDim/64 entries.  All threads of the block must call them.
+template <int OP>
+__device__ double block_reduce(double v, double* sh)
+{
+    v = OP == 0 ? wave_sum(v) : (OP == 1 ? wave_min(v) : wave_max(v));
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int i = 1; i < nw; ++i) r = OP == 0 ? r + sh[i] : (OP == 1 ? fmin(r, sh[i]) : fmax(r, sh[i]));
+    return r;
+}
+
+// Exclusive block scan of one int64 per thread (blockDim <= 1024); returns the
+// exclusive prefix, and the block total in *total.
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    __syncthreads();
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int64_t base = 0, tot = 0;
+    for (int i = 0; i < nw; ++i) {
+        if (i < w) base += sh[i];
+        tot += sh[i];
+    }
+    *total = tot;
+    return base + x - v;
+}
+
+// ----------------------------------------------------------------------------
+// utilities
+// ----------------------------------------------------------------------------
+__global__ void k_fill_i32(int* p, int64_t n, int v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Neutrality (eq. (1)) and box membership of every particle: partial sums of
+// q and |q| per workgroup (grid: blocks x systems), then a per-system check.
+__global__ __launch_bounds__(256) void k_validate(const SysDev* __restrict__ sys, const double* __restrict__ X,
+                                                  const double* __restrict__ Y, const double* __restrict__ Z,
+                                                  const double* __restrict__ Q, int* status, double* __restrict__ part)
+{
+    __shared__ double sh[4];
+    const SysDev& S = sys[blockIdx.y];
+    double sq = 0.0, sa = 0.0, bad = 0.0;
+    for (int64_t i = blockIdx.x * 256ll + threadIdx.x; i < S.n; i += (int64_t)gridDim.x * 256) {
+        const int64_t k = S.n_off + i;
+        const double q = Q[k];
+        sq += q;
+        sa += fabs(q);
+        const double x = X[k], y = Y[k], z = Z[k];
+        const bool in = x >= -S.half[0] && x < S.half[0] && y >= -S.half[1] && y < S.half[1] && z >= -S.half[2] &&
+                        z < S.half[2] && q == q;
+        if (!in) bad = 1.0;
+    }
+    sq = block_reduce<0>(sq, sh);
+    sa = block_reduce<0>(sa, sh);
+    bad = block_reduce<2>(bad, sh);
+    if (threadIdx.x == 0) {
+        double* o = part + 2 * ((int64_t)blockIdx.y * gridDim.x + blockIdx.x);
+        o[0] = sq;
+        o[1] = sa;
+        if (bad > 0.0) atomicOr(status, 2);
+    }
+}
+
+__global__ void k_validate_final(const double* __restrict__ part, int nblk, int* status)
+{
+    if (threadIdx.x != 0) return;
+    double sq = 0.0, sa = 0.0;
+    const double* o = part + 2 * (int64_t)blockIdx.x * nblk;
+    for (int b = 0; b < nblk; ++b) {
+        sq += o[2 * b];
+        sa += o[2 * b + 1];
+    }
+    if (!(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
+}
+
+// ----------------------------------------------------------------------------
+// spatial ordering: counting sort of particles by Morton-ordered cell, with
+// each cell's entries put back in index order (deterministic result)
+// ----------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_cell_keys(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
+                                                   const double* __restrict__ X, const double* __restrict__ Y,
+                                                   const double* __restrict__ Z, int* __restrict__ keys,
+                                                   int* __restrict__ slots, int* __restrict__ cnt)
+{
+    const CItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    for (int k = threadIdx.x; k < it.count; k += 256) {
+        const int64_t g = S.n_off + it.start + k;
+        const double v[3] = {X[g], Y[g], Z[g]};
+        uint32_t c[3];
+        for (int d = 0; d < 3; ++d) {
+            double u = floor((v[d] + S.half[d]) * S.inv_cell[d]);
+            u = fmin(fmax(u, 0.0), (double)(S.g[d] - 1));  // also maps NaN to 0
+            c[d] = (uint32_t)u;
+        }
+        const int key = (int)(spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+        keys[g] = key;
+        slots[g] = atomicAdd(&cnt[S.cell_off + key], 1);
+    }
+}
+
+// Exclusive scan of each system's ncell+1 counters in three phases: block
+// totals over contiguous chunks, a scan of those totals, and the chunk rescan.
+__device__ __forceinline__ void scan_chunk(int64_t len, int nblk, int b, int64_t* lo, int64_t* hi)
+{
+    const int64_t per = (len + nblk - 1) / nblk;
+    *lo = (int64_t)b * per < len ? (int64_t)b * per : len;
+    *hi = *lo + per < len ? *lo + per : len;
+}
+
+__global__ __launch_bounds__(256) void k_scan_totals(const SysDev* __restrict__ sys, const int* __restrict__ cnt,
+                                                     int64_t* __restrict__ btot)
+{
+    __shared__ double sh[4];
+    const SysDev& S = sys[blockIdx.y];
+    int64_t lo, hi;
+    scan_chunk(S.ncell + 1, gridDim.x, blockIdx.x, &lo, &hi);
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += (double)cnt[S.cell_off + i];
+    acc = block_reduce<0>(acc, sh);
+    if (threadIdx.x == 0) btot[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = (int64_t)acc;
+}
+
+__global__ __launch_bounds__(256) void k_scan_chunks(const SysDev* __restrict__ sys, const int* __restrict__ cnt,
+                                                     const int64_t* __restrict__ btot, int* __restrict__ start)
+{
+    __shared__ int64_t sh[4];
+    const SysDev& S = sys[blockIdx.y];
+    int64_t base = 0;
+    for (int b = 0; b < (int)blockIdx.x; ++b) base += btot[(int64_t)blockIdx.y * gridDim.x + b];
+    int64_t lo, hi;
+    scan_chunk(S.ncell + 1, gridDim.x, blockIdx.x, &lo, &hi);
+    for (int64_t c0 = lo; c0 < hi; c0 += 256) {
+        const int64_t i = c0 + threadIdx.x;
+        const int64_t v = i < hi ? cnt[S.cell_off + i] : 0;
+        int64_t tot;
+        const int64_t ex = block_exclusive_scan(v, sh, &tot);
+        if (i < hi) start[S.cell_off + i] = (int)(base + ex);
+        base += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cell_scatter(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
+                                                      const int* __restrict__ keys, const int* __restrict__ slots,
+                                                      const int* __restrict__ start, int* __restrict__ perm)
+{
+    const CItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    for (int k = threadIdx.x; k < it.count; k += 256) {
+        const int64_t i = it.start + k;
+        const int64_t g = S.n_off + i;
+        const int64_t pos = (int64_t)start[S.cell_off + keys[g]] + slots[g];
+        perm[S.n_off + pos] = (int)i;
+    }
+}
+
+// Put each cell's particles in increasing index order (insertion sort; cells are small).
+__global__ __launch_bounds__(256) void k_cell_fixup(const SysDev* __restrict__ sys, const int* __restrict__ start,
+                                                    int* __restrict__ perm)
+{
+    const SysDev& S = sys[blockIdx.y];
+    const int64_t c = blockIdx.x * 256ll + threadIdx.x;
+    if (c >= S.ncell) return;
+    const int64_t b = start[S.cell_off + c], e = start[S.cell_off + c + 1];
+    int* p = perm + S.n_off;
+    for (int64_t i = b + 1; i < e; ++i) {
+        const int v = p[i];
+        int64_t j = i - 1;
+        while (j >= b && p[j] > v) {
+            p[j + 1] = p[j];
+            --j;
+        }
+        p[j + 1] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
+                                                const int* __restrict__ perm, const double* __restrict__ X,
+                                                const double* __restrict__ Y, const double* __restrict__ Z,
+                                                const double* __restrict__ Q, double* __restrict__ sx,
+                                                double* __restrict__ sy, double* __restrict__ sz,
+                                                double* __restrict__ sq)
+{
+    const CItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    for (int k = threadIdx.x; k < it.count; k += 256) {
+        const int64_t j = S.n_off + it.start + k;
+        const int64_t o = S.n_off + perm[j];
+        sx[j] = X[o];
+        sy[j] = Y[o];
+        sz[j] = Z[o];
+        sq[j] = Q[o];
+    }
+}
+
+// ----------------------------------------------------------------------------
+// near set (algorithm "get", steps 1-2): x_j + p with |x_j + p| <= R_b
+// ----------------------------------------------------------------------------
+// The membership test is evaluated exactly as ((X*X + Y*Y) + Z*Z) <= R_b^2 (1 + 1e-12)
+// with X = x + p_x, without fused multiply-add, so that ties on the sphere are
+// decided the same way by any FP64 implementation of the rule.
+struct BallTest {
+    double X, Y, Z;
+    bool in;
+};
+__device__ __forceinline__ BallTest in_ball(double x, double y, double z, double px, double py, double pz, double thr)
+{
+#pragma clang fp contract(off)
+    BallTest b;
+    b.X = x + px;
+    b.Y = y + py;
+    b.Z = z + pz;
+    const double s = b.X * b.X + b.Y * b.Y;
+    b.in = s + b.Z * b.Z <= thr;
+    return b;
+}
+
+__global__ __launch_bounds__(256) void k_near_count(const SysDev* __restrict__ sys, const NItem* __restrict__ items,
+                                                    const double* __restrict__ img, const double* __restrict__ sx,
+                                                    const double* __restrict__ sy, const double* __restrict__ sz,
+                                                    int* __restrict__ ncount)
+{
+    __shared__ double sh[4];
+    const NItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    const double* pv = img + (S.img_off + it.img) * 3;
+    const double px = pv[0], py = pv[1], pz = pv[2];
+    double c = 0.0;
+    for (int e = 0; e < 4; ++e) {
+        const int k = threadIdx.x * 4 + e;
+        if (k < it.count) {
+            const int64_t g = S.n_off + it.start + k;
+            if (in_ball(sx[g], sy[g], sz[g], px, py, pz, S.thr).in) c += 1.0;
+        }
+    }
+    c = block_reduce<0>(c, sh);
+    if (threadIdx.x == 0) ncount[blockIdx.x] = (int)c;
+}
+
+// Per system: exclusive scan of the item counts -> item offsets and N_b.
+__global__ __launch_bounds__(1024) void k_near_scan(const SysDev* __restrict__ sys, const int* __restrict__ ncount,
+                                                    int64_t* __restrict__ ioff, int64_t* __restrict__ nnear)
+{
+    __shared__ int64_t sh[16];
+    const SysDev& S = sys[blockIdx.x];
+    const int64_t len = S.nitem_end - S.nitem_begin;
+    const int64_t seg = (len + 1023) / 1024;
+    const int64_t b = threadIdx.x * seg, e = b + seg < len ? b + seg : len;
+    int64_t loc = 0;
+    for (int64_t i = b; i < e; ++i) loc += ncount[S.nitem_begin + i];
+    int64_t tot;
+    int64_t run = block_exclusive_scan(loc, sh, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        ioff[S.nitem_begin + i] = run;
+        run += ncount[S.nitem_begin + i];
+    }
+    if (threadIdx.x == 0) nnear[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_near_write(const SysDev* __restrict__ sys, const NItem* __restrict__ items,
+                                                    const int64_t* __restrict__ ioff, const double* __restrict__ img,
+                                                    const double* __restrict__ sx, const double* __restrict__ sy,
+                                                    const double* __restrict__ sz, const double* __restrict__ sq,
+                                                    double* __restrict__ nx, double* __restrict__ ny,
+                                                    double* __restrict__ nz, double* __restrict__ nq,
+                                                    int* __restrict__ nbase, int* __restrict__ inv)
+{
+    __shared__ int64_t sh[4];
+    const NItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    const double* pv = img + (S.img_off + it.img) * 3;
+    const double px = pv[0], py = pv[1], pz = pv[2];
+    bool f[4];
+    double X[4], Y[4], Z[4];
+    int64_t cnt = 0;
+    for (int e = 0; e < 4; ++e) {
+        const int k = threadIdx.x * 4 + e;
+        f[e] = false;
+        if (k < it.count) {
+            const int64_t g = S.n_off + it.start + k;
+            const BallTest b = in_ball(sx[g], sy[g], sz[g], px, py, pz, S.thr);
+            f[e] = b.in;
+            X[e] = b.X;
+            Y[e] = b.Y;
+            Z[e] = b.Z;
+        }
+        cnt += f[e] ? 1 : 0;
+    }
+    int64_t tot;
+    int64_t pos = block_exclusive_scan(cnt, sh, &tot) + ioff[blockIdx.x];
+    for (int e = 0; e < 4; ++e) {
+        const int k = threadIdx.x * 4 + e;
+        if (k >= it.count) continue;
+        const int64_t j = it.start + k;
+        int* iv = inv + S.inv_off + (int64_t)it.img * S.n;
+        if (f[e]) {
+            const int64_t o = S.near_off + pos;
+            nx[o] = X[e];
+            ny[o] = Y[e];
+            nz[o] = Z[e];
+            nq[o] = sq[S.n_off + j];
+            nbase[o] = (int)j;
+            iv[j] = (int)pos;
+            ++pos;
+        } else {
+            iv[j] = -1;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// tile bounds of a source set and centre/radius of each target block
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jobs)
+{
+    __shared__ double sh[4];
+    const PJob& J = jobs[blockIdx.y];
+    const int64_t ns = J.ns_dev ? *J.ns_dev : J.ns_host;
+    const int64_t ntiles = (ns + kTile - 1) / kTile;
+    double* bb = const_cast<double*>(J.tile_bb);
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int64_t j = t * kTile + threadIdx.x;
+        const bool v = j < ns;
+        const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
+        const double lx = block_reduce<1>(v ? x : 1e300, sh), ly = block_reduce<1>(v ? y : 1e300, sh),
+                     lz = block_reduce<1>(v ? z : 1e300, sh);
+        const double hx = block_reduce<2>(v ? x : -1e300, sh), hy = block_reduce<2>(v ? y : -1e300, sh),
+                     hz = block_reduce<2>(v ? z : -1e300, sh);
+        if (threadIdx.x == 0) {
+            double* o = bb + t * 6;
+            o[0] = lx;
+            o[1] = ly;
+            o[2] = lz;
+            o[3] = hx;
+            o[4] = hy;
+            o[5] = hz;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, const TItem* __restrict__ items)
+{
+    __shared__ double sh[4];
+    const TItem it = items[blockIdx.x];
+    const PJob& J = jobs[it.job];
+    const int64_t i = (int64_t)it.tb * J.bt + threadIdx.x;
+    const bool v = (int)threadIdx.x < J.bt && i < J.nt;
+    const double x = v ? J.tx[i] : 0.0, y = v ? J.ty[i] : 0.0, z = v ? J.tz[i] : 0.0;
+    const double lx = block_reduce<1>(v ? x : 1e300, sh), ly = block_reduce<1>(v ? y : 1e300, sh),
+                 lz = block_reduce<1>(v ? z : 1e300, sh);
+    const double hx = block_reduce<2>(v ? x : -1e300, sh), hy = block_reduce<2>(v ? y : -1e300, sh),
+                 hz = block_reduce<2>(v ? z : -1e300, sh);
+    const double cx = 0.5 * (lx + hx), cy = 0.5 * (ly + hy), cz = 0.5 * (lz + hz);
+    const double d = v ? sqrt((x - cx) * (x - cx) + (y - cy) * (y - cy) + (z - cz) * (z - cz)) : 0.0;
+    const double r = block_reduce<2>(d, sh);
+    if (threadIdx.x == 0) {
+        double* o = J.tblk + (int64_t)it.tb * 4;
+        o[0] = cx;
+        o[1] = cy;
+        o[2] = cz;
+        o[3] = r * (1.0 + 1e-12);
+    }
+}
+
+// ----------------------------------------------------------------------------
+// pair sums (the free-space finite sum of eq. (r2) over the near set)
+// ----------------------------------------------------------------------------
+// A workgroup owns BT consecutive targets (one per lane) and one split of the
+// source tiles.  Sources are staged kTile at a time in LDS and read as
+// broadcasts.  A tile whose bounding box is farther than 4 x (target-block
+// radius) from the block centre is "far": it cannot hold a source coinciding
+// with a target, so its loop has no K(0) = 0 test; other tiles are "near" and
+// apply K(0) = 0.  Accumulation (FP32 kernel): the potential of every 8 pairs
+// is summed as a balanced FP32 tree and added to an FP64 accumulator; the field
+// runs in FP32 chains flushed to FP64 every 32 pairs.  (A serial FP32 sum over a
+// whole tile would add an error growing like sqrt(tile) times the per-pair
+// rounding.)  The FP64 kernel accumulates every pair in FP64.  Splits are
+// combined later in a fixed order.
+struct SourceSplit {
+    int64_t ns, t0, t1;
+};
+__device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
+{
+    SourceSplit s;
+    s.ns = J.ns_dev ? *J.ns_dev : J.ns_host;
+    const int64_t ntiles = (s.ns + kTile - 1) / kTile;
+    const int64_t per = (ntiles + J.nsplit - 1) / J.nsplit;
+    s.t0 = (int64_t)split * per;
+    s.t1 = s.t0 + per < ntiles ? s.t0 + per : ntiles;
+    return s;
+}
+
+__device__ __forceinline__ bool tile_is_far(const double* bb, double cx, double cy, double cz, double far2)
+{
+    const double gx = fmax(0.0, fmax(bb[0] - cx, cx - bb[3]));
+    const double gy = fmax(0.0, fmax(bb[1] - cy, cy - bb[4]));
+    const double gz = fmax(0.0, fmax(bb[2] - cz, cz - bb[5]));
+    return gx * gx + gy * gy + gz * gz > far2;
+}
+
+// FP32 pair arithmetic on coordinates relative to the target-block centre.
+// Far tiles: one-float relative coordinates (their rounding error is a fixed
+// fraction of the pair distance there).  Near tiles: two-float (hi + lo)
+// relative coordinates, d = (t_hi - s_hi) + (t_lo - s_lo), so close pairs keep
+// their full FP64-derived separation.
+template <int BT, bool FIELD>
+__global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
+{
+    __shared__ float4 sA[kTile];
+    __shared__ float4 sB[kTile];
+    const PItem it = items[blockIdx.x];
+    const PJob& J = jobs[it.job];
+    const SourceSplit sp = split_range(J, it.split);
+    const int64_t i = (int64_t)it.tb * BT + threadIdx.x;
+    const bool active = i < J.nt;
+    const double* tb = J.tblk + (int64_t)it.tb * 4;
+    const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
+    const double far2 = 16.0 * rT * rT;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (active) {
+        rx = J.tx[i] - cx;
+        ry = J.ty[i] - cy;
+        rz = J.tz[i] - cz;
+    }
+    const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
+    const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
+    double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
+    for (int64_t t = sp.t0; t < sp.t1; ++t) {
+        const bool far = tile_is_far(J.tile_bb + t * 6, cx, cy, cz, far2);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTile; k += BT) {
+            const int64_t j = t * kTile + k;
+            float4 a = make_float4(4096.f, 4096.f, 4096.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (j < sp.ns) {
+                const double ux = J.sx[j] - cx, uy = J.sy[j] - cy, uz = J.sz[j] - cz;
+                const float ax = (float)ux, ay = (float)uy, az = (float)uz;
+                a = make_float4(ax, ay, az, (float)J.sq[j]);
+                b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az), 0.f);
+            }
+            sA[k] = a;
+            sB[k] = b;
+        }
+        __syncthreads();
+        if (far) {
+            for (int k0 = 0; k0 < kTile; k0 += 32) {
+                float fX = 0.f, fY = 0.f, fZ = 0.f;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    float qv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float4 s = sA[k0 + g * 8 + u];
+                        const float dx = hx - s.x, dy = hy - s.y, dz = hz - s.z;
+                        float r2 = dx * dx;
+                        r2 = __builtin_fmaf(dy, dy, r2);
+                        r2 = __builtin_fmaf(dz, dz, r2);
+                        const float ri = __builtin_amdgcn_rsqf(r2);
+                        qv[u] = s.w * ri;
+                        if (FIELD) {
+                            const float qr3 = qv[u] * (ri * ri);
+                            fX = __builtin_fmaf(qr3, dx, fX);
+                            fY = __builtin_fmaf(qr3, dy, fY);
+                            fZ = __builtin_fmaf(qr3, dz, fZ);
+                        }
+                    }
+                    aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
+                }
+                if (FIELD) {
+                    aX += (double)fX;
+                    aY += (double)fY;
+                    aZ += (double)fZ;
+                }
+            }
+        } else {
+            for (int k0 = 0; k0 < kTile; k0 += 32) {
+                float fX = 0.f, fY = 0.f, fZ = 0.f;
+#pragma unroll
+                for (int g = 0; g < 4; ++g) {
+                    float qv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float4 s = sA[k0 + g * 8 + u];
+                        const float4 l = sB[k0 + g * 8 + u];
+                        const float dx = (hx - s.x) + (lx - l.x), dy = (hy - s.y) + (ly - l.y),
+                                    dz = (hz - s.z) + (lz - l.z);
+                        float r2 = dx * dx;
+                        r2 = __builtin_fmaf(dy, dy, r2);
+                        r2 = __builtin_fmaf(dz, dz, r2);
+                        float ri = __builtin_amdgcn_rsqf(r2);
+                        ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
+                        qv[u] = s.w * ri;
+                        if (FIELD) {
+                            const float qr3 = qv[u] * (ri * ri);
+                            fX = __builtin_fmaf(qr3, dx, fX);
+                            fY = __builtin_fmaf(qr3, dy, fY);
+                            fZ = __builtin_fmaf(qr3, dz, fZ);
+                        }
+                    }
+                    aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
+                }
+                if (FIELD) {
+                    aX += (double)fX;
+                    aY += (double)fY;
+                    aZ += (double)fZ;
+                }
+            }
+        }
+    }
+    if (active) {
+        double* P_ = J.part + (int64_t)it.split * J.ncomp * J.nt;
+        P_[i] = aP;
+        if (FIELD) {
+            P_[J.nt + i] = aX;
+            P_[2 * J.nt + i] = aY;
+            P_[3 * J.nt + i] = aZ;
+        }
+    }
+}
+
+// FP64 reciprocal square root: the hardware estimate (relative error ~5e-8)
+// refined by one Newton step y <- y + y/2 (1 - r2 y^2).
+__device__ __forceinline__ double rsqrt64(double r2)
+{
+    double y = __builtin_amdgcn_rsq(r2);
+    const double h = r2 * y;
+    const double e = __builtin_fma(-h, y, 1.0);
+    return __builtin_fma(0.5 * y, e, y);
+}
+
+struct Src64 {
+    double x, y, z, q;
+};
+
+template <int BT, bool FIELD>
+__global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
+{
+    __shared__ Src64 sS[kTile];
+    const PItem it = items[blockIdx.x];
+    const PJob& J = jobs[it.job];
+    const SourceSplit sp = split_range(J, it.split);
+    const int64_t i = (int64_t)it.tb * BT + threadIdx.x;
+    const bool active = i < J.nt;
+    const double* tb = J.tblk + (int64_t)it.tb * 4;
+    const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
+    const double far2 = 16.0 * rT * rT;
+    double tx = 0.0, ty = 0.0, tz = 0.0;
+    if (active) {
+        tx = J.tx[i];
+        ty = J.ty[i];
+        tz = J.tz[i];
+    }
+    double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
+    for (int64_t t = sp.t0; t < sp.t1; ++t) {
+        const bool far = tile_is_far(J.tile_bb + t * 6, cx, cy, cz, far2);
+        __syncthreads();
+        for (int k = threadIdx.x; k < kTile; k += BT) {
+            const int64_t j = t * kTile + k;
+            Src64 s = {1e6, 1e6, 1e6, 0.0};
+            if (j < sp.ns) s = Src64{J.sx[j], J.sy[j], J.sz[j], J.sq[j]};
+            sS[k] = s;
+        }
+        __syncthreads();
+        if (far) {
+#pragma unroll 4
+            for (int k = 0; k < kTile; ++k) {
+                const Src64 s = sS[k];
+                const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+                double r2 = dx * dx;
+                r2 = __builtin_fma(dy, dy, r2);
+                r2 = __builtin_fma(dz, dz, r2);
+                const double ri = rsqrt64(r2);
+                const double qr = s.q * ri;
+                aP += qr;
+                if (FIELD) {
+                    const double qr3 = qr * (ri * ri);
+                    aX = __builtin_fma(qr3, dx, aX);
+                    aY = __builtin_fma(qr3, dy, aY);
+                    aZ = __builtin_fma(qr3, dz, aZ);
+                }
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 0; k < kTile; ++k) {
+                const Src64 s = sS[k];
+                const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+                double r2 = dx * dx;
+                r2 = __builtin_fma(dy, dy, r2);
+                r2 = __builtin_fma(dz, dz, r2);
+                double ri = rsqrt64(r2);
+                ri = r2 > 0.0 ? ri : 0.0;  // K(0) = 0
+                const double qr = s.q * ri;
+                aP += qr;
+                if (FIELD) {
+                    const double qr3 = qr * (ri * ri);
+                    aX = __builtin_fma(qr3, dx, aX);
+                    aY = __builtin_fma(qr3, dy, aY);
+                    aZ = __builtin_fma(qr3, dz, aZ);
+                }
+            }
+        }
+    }
+    if (active) {
+        double* P_ = J.part + (int64_t)it.split * J.ncomp * J.nt;
+        P_[i] = aP;
+        if (FIELD) {
+            P_[J.nt + i] = aX;
+            P_[2 * J.nt + i] = aY;
+            P_[3 * J.nt + i] = aZ;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------
+// least-squares solve (steps 4-5): f = phi_near(Y_c2) - phi_near(Y_c1), C = A^+ f
+// ----------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ cjobs,
+                                             double* __restrict__ fout)
+{
+    const SysDev& S = sys[blockIdx.y];
+    const PJob& J = cjobs[blockIdx.y];
+    const int l = blockIdx.x * 256 + threadIdx.x;
+    if (l >= S.L) return;
+    double a = 0.0, b = 0.0;
+    for (int s = 0; s < J.nsplit; ++s) {
+        a += J.part[(int64_t)s * J.nt + l];
+        b += J.part[(int64_t)s * J.nt + S.L + l];
+    }
+    fout[S.f_off + l] = b - a;
+}
+
+__global__ __launch_bounds__(256) void k_gemv(const SysDev* __restrict__ sys, const double* __restrict__ pinv,
+                                              const double* __restrict__ f, double* __restrict__ coef)
+{
+    const SysDev& S = sys[blockIdx.y];
+    const int lane = threadIdx.x & 63;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (r >= S.P - 1) return;
+    const double* row = pinv + S.pinv_off + (int64_t)r * S.L;
+    const double* fs = f + S.f_off;
+    double acc = 0.0;
+    for (int l = lane; l < S.L; l += 64) acc = __builtin_fma(row[l], fs[l], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) coef[S.coef_off + 1 + r] = acc;
+}
+
+// ----------------------------------------------------------------------------
+// zero-mean constant (step 6, eqs. (pfx3)-(pfx4))
+// ----------------------------------------------------------------------------
+// Phi0(x) = (1/V0) int_box dV/|y - x| by the closed-form potential of a uniform
+// rectangular prism: the alternating sum over the eight corners of
+// F(a,b,c) = ab ln(c+r) + bc ln(a+r) + ca ln(b+r)
+//            - a^2/2 atan(bc/(ar)) - b^2/2 atan(ca/(br)) - c^2/2 atan(ab/(cr)),
+// (a,b,c) = corner - x.  Each term is taken as zero where its prefactor
+// vanishes (its limit), and c + r is formed as (a^2+b^2)/(r-c) when c < 0.
+__device__ __forceinline__ double log_c_plus_r(double c, double r, double s)
+{
+    return log(c >= 0.0 ? c + r : s / (r - c));
+}
+
+__device__ double prism_corner(double a, double b, double c)
+{
+    const double a2 = a * a, b2 = b * b, c2 = c * c;
+    const double r = sqrt(a2 + b2 + c2);
+    if (r == 0.0) return 0.0;
+    double F = 0.0;
+    if (a * b != 0.0) F += a * b * log_c_plus_r(c, r, a2 + b2);
+    if (b * c != 0.0) F += b * c * log_c_plus_r(a, r, b2 + c2);
+    if (c * a != 0.0) F += c * a * log_c_plus_r(b, r, c2 + a2);
+    if (a != 0.0) F -= 0.5 * a2 * atan(b * c / (a * r));
+    if (b != 0.0) F -= 0.5 * b2 * atan(c * a / (b * r));
+    if (c != 0.0) F -= 0.5 * c2 * atan(a * b / (c * r));
+    return F;
+}
+
+__device__ double box_mean_potential(const SysDev& S, double x, double y, double z)
+{
+    double tot = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
+        tot += sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z);
+    }
+    return tot / S.V0;
+}
+
+__global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, const int64_t* __restrict__ nnear,
+                                              const double* __restrict__ nx, const double* __restrict__ ny,
+                                              const double* __restrict__ nz, const double* __restrict__ nq,
+                                              double* __restrict__ part)
+{
+    __shared__ double sh[4];
+    const SysDev& S = sys[blockIdx.y];
+    const int64_t nb = nnear[blockIdx.y];
+    double acc = 0.0;
+    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < nb; e += (int64_t)gridDim.x * 256) {
+        const int64_t o = S.near_off + e;
+        acc += nq[o] * box_mean_potential(S, nx[o], ny[o], nz[o]);
+    }
+    acc = block_reduce<0>(acc, sh);
+    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
+__global__ void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part, int nblk,
+                     const double* __restrict__ bm, double* __restrict__ coef)
+{
+    const SysDev& S = sys[blockIdx.x];
+    if (threadIdx.x != 0) return;
+    if (S.mean_mode != 0) {
+        coef[S.coef_off] = 0.0;
+        return;
+    }
+    double s = 0.0;
+    for (int b = 0; b < nblk; ++b) s += part[(int64_t)blockIdx.x * nblk + b];
+    double d = 0.0;
+    for (int t = 1; t < S.P; ++t) d += coef[S.coef_off + t] * bm[S.bm_off + t];
+    coef[S.coef_off] = -s - d;
+}
+
+// ----------------------------------------------------------------------------
+// far field (step 7) and combination (step 8)
+// ----------------------------------------------------------------------------
+// phi_far = sum_{t>=2} C_t R^_t(u), u = y/R0, with the renormalized recurrence
+// (coefficients a, b, c in LDS) differentiated in forward mode: every value is
+// carried with its gradient, which gives grad phi_far without separate
+// gradient coefficients.
+__device__ void far_field(int p, const double* __restrict__ C, const double* __restrict__ A,
+                          const double* __restrict__ B, const double* __restrict__ Cd, double x, double y, double z,
+                          double& phi, double& gx, double& gy, double& gz)
+{
+    const double r2 = x * x + y * y + z * z;
+    double dA = 1.0, dAx = 0.0, dAy = 0.0, dAz = 0.0;
+    double dB = 0.0, dBx = 0.0, dBy = 0.0, dBz = 0.0;
+    double P0 = 0.0, X0 = 0.0, Y0 = 0.0, Z0 = 0.0;
+    for (int m = 0; m < p; ++m) {
+        if (m > 0) {
+            const double c = Cd[m];
+            const double nA = -c * (x * dA + y * dB);
+            const double nAx = -c * (dA + x * dAx + y * dBx);
+            const double nAy = -c * (x * dAy + dB + y * dBy);
+            const double nAz = -c * (x * dAz + y * dBz);
+            const double nB = c * (y * dA - x * dB);
+            const double nBx = c * (y * dAx - dB - x * dBx);
+            const double nBy = c * (dA + y * dAy - x * dBy);
+            const double nBz = c * (y * dAz - x * dBz);
+            dA = nA; dAx = nAx; dAy = nAy; dAz = nAz;
+            dB = nB; dBx = nBx; dBy = nBy; dBz = nBz;
+        }
+        for (int s = 0; s < (m ? 2 : 1); ++s) {
+            const int mm = s ? -m : m;
+            double v1 = s ? dB : dA, v1x = s ? dBx : dAx, v1y = s ? dBy : dAy, v1z = s ? dBz : dAz;
+            double v2 = 0.0, v2x = 0.0, v2y = 0.0, v2z = 0.0;
+            const int t0 = m * m + m + mm;
+            if (t0 > 0) {
+                const double ct = C[t0];
+                P0 = __builtin_fma(ct, v1, P0);
+                X0 = __builtin_fma(ct, v1x, X0);
+                Y0 = __builtin_fma(ct, v1y, Y0);
+                Z0 = __builtin_fma(ct, v1z, Z0);
+            }
+            for (int n = m + 1; n < p; ++n) {
+                const int t = n * n + n + mm;
+                const double a = A[t], b = B[t];
+                const double v = -a * z * v1 - b * r2 * v2;
+                const double vx = -a * z * v1x - b * (2.0 * x * v2 + r2 * v2x);
+                const double vy = -a * z * v1y - b * (2.0 * y * v2 + r2 * v2y);
+                const double vz = -a * (v1 + z * v1z) - b * (2.0 * z * v2 + r2 * v2z);
+                const double ct = C[t];
+                P0 = __builtin_fma(ct, v, P0);
+                X0 = __builtin_fma(ct, vx, X0);
+                Y0 = __builtin_fma(ct, vy, Y0);
+                Z0 = __builtin_fma(ct, vz, Z0);
+                v2 = v1; v2x = v1x; v2y = v1y; v2z = v1z;
+                v1 = v; v1x = vx; v1y = vy; v1z = vz;
+            }
+        }
+    }
+    phi = P0;
+    gx = X0;
+    gy = Y0;
+    gz = Z0;
+}
+
+// One workgroup per chunk of a system's targets: fixed-order sum of the pair
+// partials, far field and constant, store (to the original particle order when
+// perm is given; `osort` keeps a copy in sorted order: phi, ex, ey, ez).
+__global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
+                                                     const PJob* __restrict__ pjobs, const double* __restrict__ coef,
+                                                     const double* __restrict__ rec, const int* __restrict__ perm,
+                                                     double* __restrict__ phi, double* __restrict__ ex,
+                                                     double* __restrict__ ey, double* __restrict__ ez,
+                                                     double* __restrict__ osort)
+{
+    extern __shared__ double lds[];
+    const CItem it = items[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    const PJob& J = pjobs[it.sys];
+    const int P = S.P, p = S.p;
+    double* C = lds;
+    double* A = lds + P;
+    double* B = lds + 2 * P;
+    double* Cd = lds + 3 * P;
+    for (int t = threadIdx.x; t < P; t += 256) {
+        C[t] = coef[S.coef_off + t];
+        A[t] = rec[S.rec_off + t];
+        B[t] = rec[S.rec_off + P + t];
+    }
+    for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k >= it.count) return;
+    const int64_t i = it.start + k;
+    double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int s = 0; s < J.nsplit; ++s) {
+        const double* P_ = J.part + (int64_t)s * 4 * J.nt;
+        ph += P_[i];
+        fx += P_[J.nt + i];
+        fy += P_[2 * J.nt + i];
+        fz += P_[3 * J.nt + i];
+    }
+    double pf, gx, gy, gz;
+    far_field(p, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy, gz);
+    ph += pf + C[0];
+    fx -= gx * S.inv_R0;
+    fy -= gy * S.inv_R0;
+    fz -= gz * S.inv_R0;
+    const int64_t o = perm ? S.n_off + perm[S.n_off + i] : S.n_off + i;
+    if (phi) phi[o] = ph;
+    if (ex) ex[o] = fx;
+    if (ey) ey[o] = fy;
+    if (ez) ez[o] = fz;
+    if (osort) {
+        const int64_t g = S.n_off + i;
+        osort[4 * g + 0] = ph;
+        osort[4 * g + 1] = fx;
+        osort[4 * g + 2] = fy;
+        osort[4 * g + 3] = fz;
+    }
+}
+
+// ----------------------------------------------------------------------------
+// host launchers
+// ----------------------------------------------------------------------------
+#define PS_LAUNCH(...) hipLaunchKernelGGL(__VA_ARGS__)
+
+void launch_fill_i32(int* p, int64_t n, int v, hipStream_t st)
+{
+    if (n <= 0) return;
+    int64_t g = (n + 255) / 256;
+    if (g > 4096) g = 4096;
+    PS_LAUNCH(k_fill_i32, dim3((unsigned)g), dim3(256), 0, st, p, n, v);
+}
+void launch_validate(int nsys, int nblk, const SysDev* sys, const double* X, const double* Y, const double* Z,
+                     const double* Q, int* status, double* part, hipStream_t st)
+{
+    PS_LAUNCH(k_validate, dim3(nblk, nsys), dim3(256), 0, st, sys, X, Y, Z, Q, status, part);
+    PS_LAUNCH(k_validate_final, dim3(nsys), dim3(64), 0, st, part, nblk, status);
+}
+void launch_sort(int nsys, int64_t ncitems, int64_t max_ncell, const SysDev* sys, const CItem* citems, const double* X,
+                 const double* Y, const double* Z, const double* Q, int* keys, int* slots, int* cnt, int* start,
+                 int64_t ncnt_total, int scan_blocks, int64_t* scan_tot, int* perm, double* sx, double* sy, double* sz,
+                 double* sq, hipStream_t st)
+{
+    launch_fill_i32(cnt, ncnt_total, 0, st);
+    PS_LAUNCH(k_cell_keys, dim3((unsigned)ncitems), dim3(256), 0, st, sys, citems, X, Y, Z, keys, slots, cnt);
+    PS_LAUNCH(k_scan_totals, dim3(scan_blocks, nsys), dim3(256), 0, st, sys, cnt, scan_tot);
+    PS_LAUNCH(k_scan_chunks, dim3(scan_blocks, nsys), dim3(256), 0, st, sys, cnt, scan_tot, start);
+    PS_LAUNCH(k_cell_scatter, dim3((unsigned)ncitems), dim3(256), 0, st, sys, citems, keys, slots, start, perm);
+    PS_LAUNCH(k_cell_fixup, dim3((unsigned)((max_ncell + 255) / 256), nsys), dim3(256), 0, st, sys, start, perm);
+    PS_LAUNCH(k_gather, dim3((unsigned)ncitems), dim3(256), 0, st, sys, citems, perm, X, Y, Z, Q, sx, sy, sz, sq);
+}
+void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nitems, const double* img,
+                 const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
+                 int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st)
+{
+    PS_LAUNCH(k_near_count, dim3((unsigned)nnitems), dim3(256), 0, st, sys, nitems, img, sx, sy, sz, ncount);
+    PS_LAUNCH(k_near_scan, dim3(nsys), dim3(1024), 0, st, sys, ncount, ioff, nnear);
+    PS_LAUNCH(k_near_write, dim3((unsigned)nnitems), dim3(256), 0, st, sys, nitems, ioff, img, sx, sy, sz, sq, nx, ny,
+              nz, nq, nbase, inv);
+}
+void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st)
+{
+    PS_LAUNCH(k_tile_bounds, dim3(blocks_per_job, njobs), dim3(256), 0, st, jobs);
+}
+void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st)
+{
+    if (nitems <= 0) return;
+    PS_LAUNCH(k_tblock, dim3((unsigned)nitems), dim3(256), 0, st, jobs, items);
+}
+void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
+{
+    if (nitems <= 0) return;
+    const dim3 g((unsigned)nitems);
+#define P2P_CASE(BT)                                                                                       \
+    if (bt == BT) {                                                                                        \
+        if (prec == 1) {                                                                                   \
+            if (field) PS_LAUNCH((k_p2p_f32<BT, true>), g, dim3(BT), 0, st, jobs, items);                  \
+            else PS_LAUNCH((k_p2p_f32<BT, false>), g, dim3(BT), 0, st, jobs, items);                       \
+        } else {                                                                                           \
+            if (field) PS_LAUNCH((k_p2p_f64<BT, true>), g, dim3(BT), 0, st, jobs, items);                  \
+            else PS_LAUNCH((k_p2p_f64<BT, false>), g, dim3(BT), 0, st, jobs, items);                       \
+        }                                                                                                  \
+        return;                                                                                            \
+    }
+    P2P_CASE(64)
+    P2P_CASE(128)
+    P2P_CASE(256)
+#undef P2P_CASE
+}
+void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
+                  double* coef, double* f, hipStream_t st)
+{
+    PS_LAUNCH(k_rhs, dim3((maxL + 255) / 256, nsys), dim3(256), 0, st, sys, cjobs, f);
+    PS_LAUNCH(k_gemv, dim3((maxP - 1 + 3) / 4, nsys), dim3(256), 0, st, sys, pinv, f, coef);
+}
+void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
+                 const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st)
+{
+    PS_LAUNCH(k_mean, dim3(nblk, nsys), dim3(256), 0, st, sys, nnear, nx, ny, nz, nq, part);
+    PS_LAUNCH(k_c1, dim3(nsys), dim3(64), 0, st, sys, part, nblk, bm, coef);
+}
+void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
+                const double* coef, const double* rec, const int* perm, double* phi, double* ex, double* ey,
+                double* ez, double* osort, hipStream_t st)
+{
+    if (nitems <= 0) return;
+    PS_LAUNCH(k_far_combine, dim3((unsigned)nitems), dim3(256), (3 * maxP + maxp) * sizeof(double), st, sys, items,
+              pjobs, coef, rec, perm, phi, ex, ey, ez, osort);
+}
+
+}  // namespace ps
+
+// ----------------------------------------------------------------------------
+// energy and its gradient (adjoint of the discrete method)
+// ----------------------------------------------------------------------------
+namespace ps {
+
+// E = (1/2) sum_i q_i phi_i over a system's particles (sorted order).
+__global__ __launch_bounds__(256) void k_energy(const SysDev* __restrict__ sys, const double* __restrict__ sq,
+                                                const double* __restrict__ osort, double* __restrict__ energy)
+{
+    __shared__ double sh[4];
+    const SysDev& S = sys[blockIdx.x];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < S.n; i += 256) acc += sq[S.n_off + i] * osort[4 * (S.n_off + i)];
+    acc = block_reduce<0>(acc, sh);
+    if (threadIdx.x == 0) energy[blockIdx.x] = 0.5 * acc;
+}
+
+// Partial moments u_t = sum_k q_k R^_t(x_k / R0), t >= 1, over a slice of the
+// particles: each wave evaluates the basis recurrence for 64 particles and
+// reduces every term across its lanes; part[block][t].
+__global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, const double* __restrict__ sx,
+                                                const double* __restrict__ sy, const double* __restrict__ sz,
+                                                const double* __restrict__ sq, const double* __restrict__ rec,
+                                                double* __restrict__ part)
+{
+    extern __shared__ double lds[];
+    const SysDev& S = sys[0];
+    const int P = S.P, p = S.p;
+    double* A = lds;
+    double* B = lds + P;
+    double* Cd = lds + 2 * P;
+    double* acc = lds + 2 * P + p;  // [4][P]
+    for (int t = threadIdx.x; t < P; t += 256) {
+        A[t] = rec[S.rec_off + t];
+        B[t] = rec[S.rec_off + P + t];
+        for (int w = 0; w < 4; ++w) acc[w * P + t] = 0.0;
+    }
+    for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double* aw = acc + w * P;
+    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64; base < S.n; base += (int64_t)gridDim.x * 256) {
+        const int64_t i = base + lane;
+        const bool v = i < S.n;
+        const double x = v ? sx[S.n_off + i] * S.inv_R0 : 0.0, y = v ? sy[S.n_off + i] * S.inv_R0 : 0.0,
+                     z = v ? sz[S.n_off + i] * S.inv_R0 : 0.0, q = v ? sq[S.n_off + i] : 0.0;
+        const double r2 = x * x + y * y + z * z;
+        double dA = 1.0, dB = 0.0;
+        for (int m = 0; m < p; ++m) {
+            if (m > 0) {
+                const double c = Cd[m];
+                const double nA = -c * (x * dA + y * dB);
+                const double nB = c * (y * dA - x * dB);
+                dA = nA;
+                dB = nB;
+            }
+            for (int s = 0; s < (m ? 2 : 1); ++s) {
+                const int mm = s ? -m : m;
+                double v1 = s ? dB : dA, v2 = 0.0;
+                const int t0 = m * m + m + mm;
+                if (t0 > 0) {
+                    const double r = wave_sum(q * v1);
+                    if (lane == 0) aw[t0] += r;
+                }
+                for (int n = m + 1; n < p; ++n) {
+                    const int t = n * n + n + mm;
+                    const double vv = -A[t] * z * v1 - B[t] * r2 * v2;
+                    const double r = wave_sum(q * vv);
+                    if (lane == 0) aw[t] += r;
+                    v2 = v1;
+                    v1 = vv;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += 256)
+        part[(int64_t)blockIdx.x * P + t] = ((acc[t] + acc[P + t]) + acc[2 * P + t]) + acc[3 * P + t];
+}
+
+// u = sum of the moment partials; w = (A^+)^T u; adjoint sources: the sorted
+// particles, then +w_l at the partners y~_l, then -w_l at the check points y_l.
+__global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ sys, const double* __restrict__ part,
+                                                     int nblk, const double* __restrict__ pinv,
+                                                     const double* __restrict__ chk, int64_t chk_tot,
+                                                     double* __restrict__ ax, double* __restrict__ ay,
+                                                     double* __restrict__ az, double* __restrict__ aq)
+{
+    extern __shared__ double u[];
+    const SysDev& S = sys[0];
+    const int P = S.P, L = S.L;
+    for (int t = threadIdx.x; t < P; t += 256) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * P + t];
+        u[t] = s;
+    }
+    __syncthreads();
+    for (int l = threadIdx.x; l < L; l += 256) {
+        double w = 0.0;
+        for (int t = 1; t < P; ++t) w = __builtin_fma(pinv[S.pinv_off + (int64_t)(t - 1) * L + l], u[t], w);
+        const int64_t o1 = S.n + l, o2 = S.n + L + l;
+        const double* cx = chk + S.chk_off;
+        const double* cy = chk + chk_tot + S.chk_off;
+        const double* cz = chk + 2 * chk_tot + S.chk_off;
+        ax[o1] = cx[L + l];
+        ay[o1] = cy[L + l];
+        az[o1] = cz[L + l];
+        aq[o1] = w;
+        ax[o2] = cx[l];
+        ay[o2] = cy[l];
+        az[o2] = cz[l];
+        aq[o2] = -w;
+    }
+}
+
+__global__ void k_copy4(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
+                        const double* __restrict__ c, const double* __restrict__ d, double* __restrict__ A,
+                        double* __restrict__ B, double* __restrict__ C, double* __restrict__ D)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        A[i] = a[i];
+        B[i] = b[i];
+        C[i] = c[i];
+        D[i] = d[i];
+    }
+}
+
+// Gather psi and grad psi from every near image of each particle (inverse map,
+// image order) and form the unprojected gradients in sorted order:
+// dq[i] = (phi_i + sum psi)/2,  dx[k][i] = q_i/2 (grad phi_i + sum grad psi).
+// The pair kernel returned the field of psi, i.e. -grad psi.
+__global__ __launch_bounds__(256) void k_adj_gather(const SysDev* __restrict__ sys, const PJob* __restrict__ ajob,
+                                                    const int* __restrict__ inv, const double* __restrict__ sq,
+                                                    const double* __restrict__ osort, int exact,
+                                                    double* __restrict__ dq, double* __restrict__ dx)
+{
+    const SysDev& S = sys[0];
+    const int64_t i = blockIdx.x * 256ll + threadIdx.x;
+    if (i >= S.n) return;
+    const double* o = osort + 4 * (S.n_off + i);
+    const double q = sq[S.n_off + i];
+    if (!exact) {
+        dq[i] = o[0];
+        dx[i] = -q * o[1];
+        dx[S.n + i] = -q * o[2];
+        dx[2 * S.n + i] = -q * o[3];
+        return;
+    }
+    const PJob& J = ajob[0];
+    double ps = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
+    for (int m = 0; m < S.nimg; ++m) {
+        const int e = inv[S.inv_off + (int64_t)m * S.n + i];
+        if (e < 0) continue;
+        for (int s = 0; s < J.nsplit; ++s) {
+            const double* P_ = J.part + (int64_t)s * 4 * J.nt;
+            ps += P_[e];
+            fx += P_[J.nt + e];
+            fy += P_[2 * J.nt + e];
+            fz += P_[3 * J.nt + e];
+        }
+    }
+    dq[i] = 0.5 * (o[0] + ps);
+    dx[i] = 0.5 * q * (-o[1] - fx);
+    dx[S.n + i] = 0.5 * q * (-o[2] - fy);
+    dx[2 * S.n + i] = 0.5 * q * (-o[3] - fz);
+}
+
+// Remove the mean of dq (neutral charges), scale by gE and store in the
+// original particle order.
+__global__ __launch_bounds__(1024) void k_adj_finish(const SysDev* __restrict__ sys, const int* __restrict__ perm,
+                                                     const double* __restrict__ dq, const double* __restrict__ dx,
+                                                     const double* __restrict__ gE, double* __restrict__ oq,
+                                                     double* __restrict__ ox, double* __restrict__ oy,
+                                                     double* __restrict__ oz)
+{
+    __shared__ double sh[16];
+    const SysDev& S = sys[0];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < S.n; i += 1024) acc += dq[i];
+    acc = block_reduce<0>(acc, sh);
+    const double mean = acc / (double)S.n;
+    const double g = gE[0];
+    for (int64_t i = threadIdx.x; i < S.n; i += 1024) {
+        const int64_t o = perm[S.n_off + i];
+        if (oq) oq[o] = g * (dq[i] - mean);
+        if (ox) ox[o] = g * dx[i];
+        if (oy) oy[o] = g * dx[S.n + i];
+        if (oz) oz[o] = g * dx[2 * S.n + i];
+    }
+}
+
+void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* osort, double* energy, hipStream_t st)
+{
+    PS_LAUNCH(k_energy, dim3(nsys), dim3(256), 0, st, sys, sq, osort, energy);
+}
+void launch_adjoint_sources(int P, int p, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
+                            const double* sz, const double* sq, const double* rec, double* mom_part, int mom_blocks,
+                            const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
+                            double* az, double* aq, hipStream_t st)
+{
+    PS_LAUNCH(k_moment, dim3(mom_blocks), dim3(256), (2 * P + p + 4 * P) * sizeof(double), st, sys, sx, sy, sz, sq,
+              rec, mom_part);
+    PS_LAUNCH(k_copy4, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, n, sx, sy, sz, sq,
+              ax, ay, az, aq);
+    PS_LAUNCH(k_adj_weights, dim3(1), dim3(256), P * sizeof(double), st, sys, mom_part, mom_blocks, pinv, chk, chk_tot,
+              ax, ay, az, aq);
+}
+void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
+                           const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,
+                           double* oq, double* ox, double* oy, double* oz, hipStream_t st)
+{
+    PS_LAUNCH(k_adj_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sys, ajob, inv, sq, osort, exact, dq,
+              dx);
+    PS_LAUNCH(k_adj_finish, dim3(1), dim3(1024), 0, st, sys, perm, dq, dx, gE, oq, ox, oy, oz);
+}
+
+}  // namespace ps
+
+namespace ps {
+// Resident workgroups per compute unit of the pair kernels (occupancy query).
+int p2p_blocks_per_cu(int prec, int bt)
+{
+    int nb = 0;
+    hipError_t e = hipErrorInvalidValue;
+#define OCC(BT)                                                                                         \
+    if (bt == BT)                                                                                       \
+        e = prec == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f32<BT, true>, BT, 0)   \
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f64<BT, true>, BT, 0);
+    OCC(64)
+    OCC(128)
+    OCC(256)
+#undef OCC
+    return e == hipSuccess && nb > 0 ? nb : 1;
+}
+}  // namespace ps

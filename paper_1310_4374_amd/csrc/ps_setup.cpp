@@ -1,0 +1,303 @@
+// Host FP64 "set" phase (Sec. 2.3, algorithm "set", steps 1-6; Sec. 3; App. B).
+#include "ps_setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+namespace ps {
+
+void Recurrence::build(int p_)
+{
+    p = p_;
+    a.assign(p * p, 0.0);
+    b.assign(p * p, 0.0);
+    c.assign(p, 0.0);
+    for (int m = 1; m < p; ++m) c[m] = std::sqrt((2.0 * m - 1.0) / (2.0 * m));
+    for (int n = 1; n < p; ++n)
+        for (int m = -n + 1; m <= n - 1; ++m) {
+            const double am = std::abs(m);
+            const double lo = n - am, hi = n + am;
+            const int t = n * n + n + m;
+            a[t] = (2.0 * n - 1.0) / std::sqrt(lo * hi);
+            b[t] = (n - am >= 2) ? std::sqrt((lo - 1.0) * (hi - 1.0) / (lo * hi)) : 0.0;
+        }
+}
+
+void Recurrence::eval(double x, double y, double z, double* out) const
+{
+    const double r2 = x * x + y * y + z * z;
+    double dA = 1.0, dB = 0.0;  // R^_m^{m}, R^_m^{-m} on the diagonal
+    for (int m = 0; m < p; ++m) {
+        if (m > 0) {
+            const double nA = -c[m] * (x * dA + y * dB);
+            const double nB = c[m] * (y * dA - x * dB);
+            dA = nA;
+            dB = nB;
+        }
+        for (int s = 0; s < (m ? 2 : 1); ++s) {
+            const int mm = s ? -m : m;
+            double prev2 = 0.0, prev1 = s ? dB : dA;
+            out[m * m + m + mm] = prev1;
+            for (int n = m + 1; n < p; ++n) {
+                const int t = n * n + n + mm;
+                const double v = -a[t] * z * prev1 - b[t] * r2 * prev2;
+                out[t] = v;
+                prev2 = prev1;
+                prev1 = v;
+            }
+        }
+    }
+}
+
+// Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1], ascending:
+// Newton's method on P_n evaluated by the three-term recurrence.
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int i = 0; i < (n + 1) / 2; ++i) {
+        double zr = std::cos(M_PI * (i + 0.75) / (n + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = zr;
+            for (int k = 2; k <= n; ++k) {
+                const double p2 = ((2.0 * k - 1.0) * zr * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = zr; p0 = 1.0; }
+            dp = n * (zr * p1 - p0) / (zr * zr - 1.0);
+            const double dz = p1 / dp;
+            zr -= dz;
+            if (std::fabs(dz) <= 1e-17 && it > 2) break;
+        }
+        // final derivative at the converged node
+        double p0 = 1.0, p1 = zr;
+        for (int k = 2; k <= n; ++k) {
+            const double p2 = ((2.0 * k - 1.0) * zr * p1 - (k - 1.0) * p0) / k;
+            p0 = p1;
+            p1 = p2;
+        }
+        dp = (n == 1) ? 1.0 : n * (zr * p1 - p0) / (zr * zr - 1.0);
+        if ((n & 1) && i == (n - 1) / 2) zr = 0.0;
+        const double wt = 2.0 / ((1.0 - zr * zr) * dp * dp);
+        x[i] = -zr;
+        x[n - 1 - i] = zr;
+        w[i] = wt;
+        w[n - 1 - i] = wt;
+    }
+}
+
+namespace {
+
+// Pseudo-inverse of the L x n matrix A (column-major) by Householder QR
+// followed by a one-sided (Hestenes) Jacobi SVD of the n x n factor R:
+// A = Q R, R = U S V^T, A^+ = V S^+ U^T Q^T with singular values below
+// rcond * s_max dropped.  Returns A^+ row-major (n x L).
+void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vector<double>& pinv,
+                    int& rank, double& cond)
+{
+    std::vector<double> vs(static_cast<size_t>(L) * n, 0.0), beta(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        double* col = &A[static_cast<size_t>(k) * L];
+        double nrm = 0.0;
+        for (int i = k; i < L; ++i) nrm += col[i] * col[i];
+        nrm = std::sqrt(nrm);
+        double* v = &vs[static_cast<size_t>(k) * L];
+        if (nrm == 0.0) { beta[k] = 0.0; continue; }
+        const double alpha = col[k] >= 0 ? -nrm : nrm;
+        for (int i = k; i < L; ++i) v[i] = col[i];
+        v[k] -= alpha;
+        double vv = 0.0;
+        for (int i = k; i < L; ++i) vv += v[i] * v[i];
+        beta[k] = vv > 0 ? 2.0 / vv : 0.0;
+        for (int j = k; j < n; ++j) {
+            double* cj = &A[static_cast<size_t>(j) * L];
+            double s = 0.0;
+            for (int i = k; i < L; ++i) s += v[i] * cj[i];
+            s *= beta[k];
+            for (int i = k; i < L; ++i) cj[i] -= s * v[i];
+        }
+    }
+    // R (n x n, column-major) and V = I
+    std::vector<double> R(static_cast<size_t>(n) * n, 0.0), V(static_cast<size_t>(n) * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        for (int i = 0; i <= j; ++i) R[static_cast<size_t>(j) * n + i] = A[static_cast<size_t>(j) * L + i];
+        V[static_cast<size_t>(j) * n + j] = 1.0;
+    }
+    for (int sweep = 0; sweep < 80; ++sweep) {
+        double off = 0.0;
+        for (int i = 0; i < n - 1; ++i)
+            for (int j = i + 1; j < n; ++j) {
+                double* ci = &R[static_cast<size_t>(i) * n];
+                double* cj = &R[static_cast<size_t>(j) * n];
+                double al = 0, be = 0, ga = 0;
+                for (int k = 0; k < n; ++k) {
+                    al += ci[k] * ci[k];
+                    be += cj[k] * cj[k];
+                    ga += ci[k] * cj[k];
+                }
+                if (ga == 0.0) continue;
+                const double o = std::fabs(ga) / std::sqrt(al * be);
+                off = std::max(off, o);
+                if (o < 1e-15) continue;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                for (int k = 0; k < n; ++k) {
+                    const double xi = ci[k], xj = cj[k];
+                    ci[k] = c * xi - s * xj;
+                    cj[k] = s * xi + c * xj;
+                }
+                double* vi = &V[static_cast<size_t>(i) * n];
+                double* vj = &V[static_cast<size_t>(j) * n];
+                for (int k = 0; k < n; ++k) {
+                    const double xi = vi[k], xj = vj[k];
+                    vi[k] = c * xi - s * xj;
+                    vj[k] = s * xi + c * xj;
+                }
+            }
+        if (off < 1e-15) break;
+    }
+    std::vector<double> sig(n);
+    double smax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += R[static_cast<size_t>(j) * n + k] * R[static_cast<size_t>(j) * n + k];
+        sig[j] = std::sqrt(s);
+        smax = std::max(smax, sig[j]);
+    }
+    rank = 0;
+    double smin = smax;
+    std::vector<double> inv2(n, 0.0);
+    for (int j = 0; j < n; ++j)
+        if (sig[j] > rcond * smax) {
+            ++rank;
+            smin = std::min(smin, sig[j]);
+            inv2[j] = 1.0 / (sig[j] * sig[j]);
+        }
+    cond = smax / smin;
+    // B = R^+ = V S^-2 (R V)^T  (columns of R now hold R V = U S); M = [B^T; 0] (L x n)
+    std::vector<double> M(static_cast<size_t>(L) * n, 0.0);  // column-major
+    for (int a = 0; a < n; ++a)        // row a of B
+        for (int r = 0; r < n; ++r) {  // column r of B
+            double s = 0.0;
+            for (int j = 0; j < n; ++j)
+                if (inv2[j] != 0.0) s += V[static_cast<size_t>(j) * n + a] * inv2[j] * R[static_cast<size_t>(j) * n + r];
+            M[static_cast<size_t>(a) * L + r] = s;  // M[r][a] = B[a][r]
+        }
+    // A^+T = H_0 H_1 ... H_{n-1} M
+    for (int k = n - 1; k >= 0; --k) {
+        if (beta[k] == 0.0) continue;
+        const double* v = &vs[static_cast<size_t>(k) * L];
+        for (int j = 0; j < n; ++j) {
+            double* cj = &M[static_cast<size_t>(j) * L];
+            double s = 0.0;
+            for (int i = k; i < L; ++i) s += v[i] * cj[i];
+            s *= beta[k];
+            for (int i = k; i < L; ++i) cj[i] -= s * v[i];
+        }
+    }
+    pinv.assign(static_cast<size_t>(n) * L, 0.0);
+    for (int a = 0; a < n; ++a)
+        for (int l = 0; l < L; ++l) pinv[static_cast<size_t>(a) * L + l] = M[static_cast<size_t>(a) * L + l];
+}
+
+}  // namespace
+
+std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond)
+{
+    for (int k = 0; k < 3; ++k) {
+        if (!(bx[k] > 0.0) || !std::isfinite(bx[k])) return "box lengths must be positive and finite";
+        box[k] = bx[k];
+    }
+    if (p_ < 2 || p_ > 40) return "p must be in [2, 40]";
+    p = p_;
+    P = p * p;
+    V0 = box[0] * box[1] * box[2];
+    R0 = 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1] + box[2] * box[2]);   // step 1
+    R_b = Rb > 0 ? Rb : lambda * R0;
+    if (!(R_b > R0) || !std::isfinite(R_b)) return "the near radius must exceed the circumradius (lambda > 1)";
+    thr = R_b * R_b * (1.0 + 1e-12);
+    if (rcond <= 0) rcond = 1e-13;
+
+    // lattice images whose box [i d - d/2, i d + d/2] comes within R_b of the centre
+    images.clear();
+    images.insert(images.end(), {0, 0, 0});
+    int K[3];
+    for (int k = 0; k < 3; ++k) K[k] = static_cast<int>(std::floor(R_b / box[k] + 0.5));
+    for (int i = -K[0]; i <= K[0]; ++i)
+        for (int j = -K[1]; j <= K[1]; ++j)
+            for (int l = -K[2]; l <= K[2]; ++l) {
+                if (i == 0 && j == 0 && l == 0) continue;
+                const int ii[3] = {i, j, l};
+                double dmin2 = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    const double g = std::max(0.0, std::abs(ii[k]) * box[k] - 0.5 * box[k]);
+                    dmin2 += g * g;
+                }
+                if (dmin2 <= thr * (1.0 + 1e-9)) images.insert(images.end(), {i, j, l});
+            }
+
+    // step 2: Gauss spherical grid on the circumsphere, L = p (2p - 1)
+    std::vector<double> mu, wq;
+    gauss_legendre(p, mu, wq);
+    const int nphi = 2 * p - 1;
+    L = p * nphi;
+    yc.assign(static_cast<size_t>(L) * 3, 0.0);
+    yt.assign(static_cast<size_t>(L) * 3, 0.0);
+    for (int a = 0; a < p; ++a) {
+        const double st = std::sqrt(1.0 - mu[a] * mu[a]);
+        for (int bph = 0; bph < nphi; ++bph) {
+            const double ph = 2.0 * M_PI * bph / nphi;
+            double* y = &yc[(static_cast<size_t>(a) * nphi + bph) * 3];
+            y[0] = R0 * st * std::cos(ph);
+            y[1] = R0 * st * std::sin(ph);
+            y[2] = R0 * mu[a];
+        }
+    }
+    // step 3: partner = one coordinate shifted by its period, the coordinate that
+    // brings the point deepest into S0 (largest d_k (2|y_k| - d_k)), towards the centre
+    for (int l = 0; l < L; ++l) {
+        const double* y = &yc[static_cast<size_t>(l) * 3];
+        int kb = 0;
+        double best = -1e300;
+        for (int k = 0; k < 3; ++k) {
+            const double g = box[k] * (2.0 * std::fabs(y[k]) - box[k]);
+            if (g > best) { best = g; kb = k; }
+        }
+        double* t = &yt[static_cast<size_t>(l) * 3];
+        for (int k = 0; k < 3; ++k) t[k] = y[k];
+        t[kb] = y[kb] - (y[kb] > 0 ? 1.0 : (y[kb] < 0 ? -1.0 : 0.0)) * box[kb];
+    }
+    // step 4: A_lt = R_t(y_l/R0) - R_t(y~_l/R0), t = 2..P  (column-major L x (P-1))
+    rec.build(p);
+    const int n = P - 1;
+    std::vector<double> A(static_cast<size_t>(L) * n), r1(P), r2(P);
+    for (int l = 0; l < L; ++l) {
+        const double* y = &yc[static_cast<size_t>(l) * 3];
+        const double* t = &yt[static_cast<size_t>(l) * 3];
+        rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
+        rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
+        for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * L + l] = r1[j + 1] - r2[j + 1];
+    }
+    // step 5: decomposition -> pseudo-inverse
+    pseudo_inverse(L, n, std::move(A), rcond, pinv, rank, cond);
+    if (rank < 1) return "fitting matrix has numerical rank zero";
+    // step 6: box integrals of the basis (App. B), N_q = floor((p-1)/2) + 1 nodes per axis
+    const int nq = (p - 1) / 2 + 1;
+    std::vector<double> xg, wg;
+    gauss_legendre(nq, xg, wg);
+    box_means.assign(P, 0.0);
+    for (int i = 0; i < nq; ++i)
+        for (int j = 0; j < nq; ++j)
+            for (int k = 0; k < nq; ++k) {
+                rec.eval(0.5 * box[0] * xg[i] / R0, 0.5 * box[1] * xg[j] / R0, 0.5 * box[2] * xg[k] / R0, r1.data());
+                const double w = wg[i] * wg[j] * wg[k] / 8.0;
+                for (int t = 0; t < P; ++t) box_means[t] += w * r1[t];
+            }
+    return std::string();
+}
+
+}  // namespace ps

@@ -1,0 +1,43 @@
+// Host-side FP64 "set" phase of the periodized sum (Sec. 2.3, algorithm "set").
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ps {
+
+// Coefficients of the renormalized solid-harmonic recurrence, obtained by
+// folding the scale factors sqrt((n-|m|)!(n+|m|)!) of eq. (1.7) into the
+// Cartesian recurrence of eq. (1.6):
+//   R^_m^{+m} = -c_m (x R^_{m-1}^{m-1} + y R^_{m-1}^{-(m-1)}),
+//   R^_m^{-m} =  c_m (y R^_{m-1}^{m-1} - x R^_{m-1}^{-(m-1)}),   c_m = sqrt((2m-1)/(2m)),
+//   R^_n^m    = -a_nm z R^_{n-1}^m - b_nm r^2 R^_{n-2}^m          (n > |m|),
+//   a_nm = (2n-1)/sqrt((n-|m|)(n+|m|)),  b_nm = sqrt((n-|m|-1)(n+|m|-1)/((n-|m|)(n+|m|))),
+// with R^_0^0 = 1 and R^_0^{-0} = 0.  Index t = n^2 + n + m (eq. (1.8), 0-based).
+struct Recurrence {
+    int p = 0;
+    std::vector<double> a, b;  // [p*p], indexed by t
+    std::vector<double> c;     // [p], c[0] unused
+    void build(int p_);
+    // R^_t at (x, y, z) for t < p*p.
+    void eval(double x, double y, double z, double* out) const;
+};
+
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
+
+struct SystemSetup {
+    double box[3] = {0, 0, 0};
+    double R0 = 0, R_b = 0, thr = 0, V0 = 0;
+    int p = 0, P = 0, L = 0;
+    int rank = 0;
+    double cond = 0;
+    std::vector<double> yc, yt;        // [L*3] check points and partners
+    std::vector<double> pinv;          // (P-1) x L, row-major: C_{t+1} = sum_l pinv[t*L+l] f_l
+    std::vector<double> box_means;     // [P]: R_t^(0), App. B
+    std::vector<int> images;           // [nimg*3] lattice integers, (0,0,0) first
+    Recurrence rec;
+    // Returns an empty string on success, or the reason for failure.
+    std::string build(const double box[3], int p, double R_b, double lambda, double rcond);
+};
+
+}  // namespace ps

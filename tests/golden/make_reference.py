@@ -1,0 +1,79 @@
+"""Write the oracle's reference values for the full-size workloads.
+
+Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
+nothing here comes from the HIP library.  The outputs let GPU tests and the
+benchmark compare sampled particles at full size without re-running the slow
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5]
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import workloads as W  # noqa: E402
+from oracle.method import Plan  # noqa: E402
+
+OUT = os.path.dirname(os.path.abspath(__file__))
+
+
+def _save(name, **arrs):
+    path = os.path.join(OUT, name)
+    np.savez_compressed(path, **arrs)
+    print("wrote", path, flush=True)
+
+
+def cfg2():
+    c = W.config2()
+    pl = Plan(c["box"], c["p"], R_b=c["R_b"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save("ref_cfg2.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
+
+
+def cfg3():
+    c = W.config3()
+    pl = Plan(c["box"], c["p"], lam=c["lam"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save("ref_cfg3.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
+
+
+def cfg4(nsample=300):
+    c = W.config4()
+    n = np.array([len(s["q"]) for s in c["systems"]])
+    order = np.argsort(n)
+    pick = np.unique(np.concatenate([order[:2], order[len(n) // 2 - 1: len(n) // 2 + 1], order[-2:]]))
+    out = {"systems": pick}
+    for k in pick:
+        s = c["systems"][k]
+        g = np.random.Generator(np.random.PCG64(1000 + int(k)))
+        sub = np.sort(g.choice(len(s["q"]), size=min(nsample, len(s["q"])), replace=False))
+        pl = Plan(s["box"], c["p"], lam=c["lam"])
+        phi, field = pl.solve(s["x"], s["q"], targets=s["x"][sub])
+        out["sub_%d" % k] = sub
+        out["phi_%d" % k] = phi
+        out["field_%d" % k] = field
+    _save("ref_cfg4.npz", **out)
+
+
+def cfg5(nsample=200):
+    c = W.config5()
+    g = np.random.Generator(np.random.PCG64(555))
+    sub = np.sort(g.choice(len(c["q"]), size=nsample, replace=False))
+    pl = Plan(c["box"], c["p"], R_b=c["R_b"])
+    phi, field = pl.solve(c["x"], c["q"], targets=c["x"][sub])
+    # unjittered lattice: every site is equivalent, so two sites (one per sign) suffice
+    r = W.rocksalt(32)
+    lphi, lfield = pl.solve(r["x"], r["q"], targets=r["x"][:2])
+    _save("ref_cfg5.npz", subset=sub, phi=phi, field=field, lattice_phi=lphi, lattice_q=r["q"][:2])
+
+
+if __name__ == "__main__":
+    for name in sys.argv[1:] or ["cfg2"]:
+        t = time.time()
+        globals()[name]()
+        print(name, "%.1fs" % (time.time() - t), flush=True)

@@ -1,0 +1,78 @@
+"""The C-ABI library loads and exports every function include/periodic_sum.h
+declares; argument errors are reported without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1310_4374_amd import _lib
+
+HDR = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "periodic_sum.h")
+
+
+def _declared():
+    src = open(HDR).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(periodic_sum_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "periodic_sum_energy_vjp",
+                     "periodic_sum_plan_batched", "periodic_sum_eval_batched", "periodic_sum_status",
+                     "periodic_sum_destroy", "periodic_sum_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert sorted(_declared()) == sorted(_lib.EXPORTS)
+
+
+def test_struct_layout_matches_header():
+    """The ctypes mirror of ps_params has the C layout (no torch types cross)."""
+    assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
+    assert _lib.ps_params.n_max.offset == 64
+
+
+def _params(**kw):
+    prm = _lib.ps_params()
+    for k in range(3):
+        prm.box[k] = 1.0
+    prm.p = 8
+    prm.R_b = 1.5
+    prm.n_max = 100
+    for k, v in kw.items():
+        setattr(prm, k, v)
+    return prm
+
+
+@pytest.mark.parametrize("kw", [dict(p=1), dict(p=41), dict(n_max=0), dict(precision=7), dict(mean=3),
+                                dict(tile_targets=100), dict(n_split=-1), dict(m_max=-5)])
+def test_invalid_parameters_rejected_on_host(kw):
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    st = L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h))
+    assert st == _lib.PS_E_INVALID
+    assert not h.value
+    assert L.periodic_sum_last_error()
+
+
+def test_null_arguments_rejected():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.periodic_sum_plan(None, 0, ctypes.byref(h)) == _lib.PS_E_INVALID
+    assert L.periodic_sum_plan(ctypes.byref(_params()), 0, None) == _lib.PS_E_INVALID
+    assert L.periodic_sum_eval(None, 10, *([None] * 4), 0, *([None] * 3), *([None] * 4), None) == _lib.PS_E_INVALID
+    assert L.periodic_sum_status(None, None) == _lib.PS_E_INVALID
+    L.periodic_sum_destroy(None)
+
+
+@pytest.mark.parametrize("kw", [dict(R_b=0.5), dict(R_b=0.0, lambda_=0.9)])
+def test_near_radius_must_exceed_circumradius(kw):
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == _lib.PS_E_INVALID

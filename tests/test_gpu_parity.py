@@ -1,0 +1,350 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Bars: FP64 path rel-L2 <= 1e-12 for the potential and the field; FP32 path
+(FP32 pair arithmetic, FP64 accumulation) rel-L2 <= 1e-6.  Integer work (the
+near-set size) must match exactly.  Sizes span several tiles and ragged tails.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.adjoint import energy_gradients, physics_gradients
+from oracle.method import Plan as OPlan
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def _dev(a):
+    return torch.tensor(np.ascontiguousarray(a), device="cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ps():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1310_4374_amd as m
+    m.lib()
+    return m
+
+
+def _run(ps, box, p, x, q, prec, R_b=None, lam=None, targets=None, **kw):
+    pl = ps.Plan(box, p, R_b=R_b, lam=lam, precision=prec, n_max=len(q),
+                 m_max=0 if targets is None else len(targets), **kw)
+    phi, field = pl.eval(_dev(x.T), _dev(q), targets=None if targets is None else _dev(targets.T))
+    pl.status()
+    return pl, phi.cpu().numpy(), field.cpu().numpy().T
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_small_cube_config(ps, prec):
+    """Cube 1^3, N=1000 uniform, q=+-1, p=12, R_b=1.5 (the small workload)."""
+    c = W.config1()
+    op = OPlan(c["box"], c["p"], R_b=c["R_b"])
+    ref = op.solve(c["x"], c["q"], return_parts=True)
+    pl, phi, field = _run(ps, c["box"], c["p"], c["x"], c["q"], prec, R_b=c["R_b"])
+    print(prec, "rel-L2 phi %.3e field %.3e" % (_rel(phi, ref["phi"]), _rel(field, ref["field"])))
+    assert _rel(phi, ref["phi"]) <= TOL[prec]
+    assert _rel(field, ref["field"]) <= TOL[prec]
+    info = pl.info()
+    assert info["n_near_last"] == ref["n_near"]
+    assert info["L"] == 2 * c["p"] ** 2 - c["p"] and info["rank"] == c["p"] ** 2 - 1
+    C = pl.coefficients().numpy()
+    assert _rel(C[1:], ref["C"][1:]) < 1e-12
+    assert abs(C[0] - ref["C"][0]) < 1e-12 * max(1.0, abs(ref["C"][0]))
+
+
+def test_plan_tables_match_oracle(ps):
+    for box, p, kw in [((1, 1, 1), 12, dict(R_b=1.5)), ((1, 1, 2.5), 20, dict(lam=1.5)), ((1.3, 1.9, 1.1), 9, dict(lam=1.7))]:
+        pl = ps.Plan(box, p, n_max=10, **kw)
+        op = OPlan(box, p, R_b=kw.get("R_b"), lam=kw.get("lam"))
+        yc, yt, pinv, bm = (t.numpy() for t in pl.tables())
+        np.testing.assert_allclose(yc, op.yc, atol=1e-15 * op.R0 * 4)
+        np.testing.assert_allclose(yt, op.yt, atol=1e-15 * op.R0 * 4)
+        assert _rel(pinv, op.Apinv) < 1e-12
+        np.testing.assert_allclose(bm, op.R0mean, atol=1e-14)
+        inf = pl.info()
+        assert inf["rank"] == op.rank and abs(inf["cond"] / op.cond - 1) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("box,lam,p,n", [((1.0, 1.3, 2.1), 1.73, 10, 700), ((2.0, 1.0, 1.0), 1.5, 12, 1500)])
+def test_non_cubic_boxes(ps, prec, box, lam, p, n):
+    x, q = W.uniform_box(n, box, charges="gauss", seed=n)
+    ref = OPlan(box, p, lam=lam).solve(x, q)
+    _, phi, field = _run(ps, box, p, x, q, prec, lam=lam)
+    assert _rel(phi, ref[0]) <= TOL[prec]
+    assert _rel(field, ref[1]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,bt,split", [(2, 0, 0), (63, 64, 0), (257, 128, 3), (1025, 256, 1), (3001, 64, 0)])
+def test_ragged_sizes_and_launch_shapes(ps, prec, n, bt, split):
+    box = (1.0, 1.0, 1.0)
+    if n == 2:
+        x = np.array([[0.1, 0.2, -0.3], [-0.25, 0.05, 0.4]])
+        q = np.array([1.0, -1.0])
+    else:
+        x, q = W.uniform_box(n, box, charges="gauss", seed=n)
+    ref = OPlan(box, 8, R_b=1.5).solve(x, q)
+    _, phi, field = _run(ps, box, 8, x, q, prec, R_b=1.5, tile_targets=bt, n_split=split)
+    assert _rel(phi, ref[0]) <= TOL[prec]
+    assert _rel(field, ref[1]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_separate_targets_and_coincident_points(ps, prec):
+    """M evaluation points in the box (Sec. 1); targets placed exactly on
+    particles take K(0) = 0 for that pair."""
+    box = (1.0, 1.2, 0.9)
+    x, q = W.uniform_box(500, box, charges="gauss", seed=3)
+    g = np.random.default_rng(4)
+    y = (g.random((300, 3)) - 0.5) * np.asarray(box)
+    y[:20] = x[100:120]
+    ref = OPlan(box, 10, lam=1.7).solve(x, q, targets=y)
+    _, phi, field = _run(ps, box, 10, x, q, prec, lam=1.7, targets=y)
+    assert _rel(phi, ref[0]) <= TOL[prec]
+    assert _rel(field, ref[1]) <= TOL[prec]
+
+
+def test_mean_none_shifts_by_constant(ps):
+    c = W.config1()
+    _, a, fa = _run(ps, c["box"], 10, c["x"], c["q"], "fp64", R_b=1.5)
+    pl = ps.Plan(c["box"], 10, R_b=1.5, n_max=1000, mean="none")
+    b, fb = pl.eval(_dev(c["x"].T), _dev(c["q"]))
+    d = a - b.cpu().numpy()
+    assert np.ptp(d) < 1e-12 * np.abs(a).max()
+    np.testing.assert_array_equal(fa, fb.cpu().numpy().T)
+    assert pl.coefficients().numpy()[0] == 0.0
+
+
+def test_rocksalt_madelung(ps):
+    """Unjittered rock-salt lattice (32^3 sites, spacing 1/32, p = 16, R_b = 1.5):
+    the potential at the sites equals the oracle's (which, like the method,
+    carries the truncation error at these parameters), all sites are
+    equivalent up to that error, and phi * spacing approaches -q M (eq. (st1))."""
+    from oracle.ewald import MADELUNG_NACL
+    r = W.rocksalt(32)
+    ref = _golden("ref_cfg5.npz")
+    _, phi, field = _run(ps, r["box"], 16, r["x"], r["q"], "fp64", R_b=1.5)
+    np.testing.assert_allclose(phi[:2], ref["lattice_phi"], rtol=1e-12)
+    err = np.abs(phi * r["spacing"] / (-r["q"] * MADELUNG_NACL) - 1)
+    print("Madelung max rel err %.3e (oracle %.3e)" % (err.max(), np.abs(ref["lattice_phi"] * r["spacing"] / (-ref["lattice_q"] * MADELUNG_NACL) - 1).max()))
+    assert err.max() < 2e-4
+    # the sites are physically equivalent; the method's truncation error varies
+    # with the position in the box, so their spread is at that error's level
+    assert np.ptp(phi * r["spacing"] * r["q"]) < 4e-4 * MADELUNG_NACL
+
+
+def test_status_reports_data_errors(ps):
+    from paper_1310_4374_amd import PeriodicSumError
+    c = W.config1()
+    pl = ps.Plan(c["box"], 8, R_b=1.5, n_max=1000)
+    q = c["q"].copy()
+    q[0] += 0.5
+    pl.eval(_dev(c["x"].T), _dev(q))
+    with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
+        pl.status()
+    x = c["x"].copy()
+    x[5, 1] = 0.5  # upper face is outside the half-open box
+    pl.eval(_dev(x.T), _dev(c["q"]))
+    with pytest.raises(PeriodicSumError, match="OUT_OF_BOX"):
+        pl.status()
+    pl.eval(_dev(c["x"].T), _dev(c["q"]))
+    pl.status()
+    with pytest.raises(PeriodicSumError, match="INVALID"):
+        pl.eval(_dev(np.zeros((3, 2000))), _dev(np.zeros(2000)))
+
+
+def test_bitwise_reproducible(ps):
+    c = W.config1()
+    for prec in ("fp64", "fp32"):
+        pl = ps.Plan(c["box"], 12, R_b=1.5, n_max=1000, precision=prec)
+        a = pl.eval(_dev(c["x"].T), _dev(c["q"]))
+        b = pl.eval(_dev(c["x"].T), _dev(c["q"]))
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
+def test_energy_and_exact_adjoint(ps, prec, tol):
+    box = (1.0, 1.1, 0.9)
+    x, q = W.uniform_box(800, box, charges="gauss", seed=12)
+    op = OPlan(box, 10, lam=1.7)
+    E, dx, dq, _ = energy_gradients(op, x, q)
+    pl = ps.Plan(box, 10, lam=1.7, n_max=800, precision=prec)
+    xt, qt = _dev(x.T), _dev(q)
+    e = pl.energy(xt, qt)
+    g = torch.full((1,), 2.0, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(xt, qt, g, exact=True)
+    assert abs(float(e.cpu()[0]) - E) <= tol * abs(E)
+    assert _rel(gx.cpu().numpy().T, 2 * dx) <= tol
+    assert _rel(gq.cpu().numpy(), 2 * dq) <= tol
+    px, pq = physics_gradients(op, x, q)
+    hx, hq = pl.energy_vjp(xt, qt, g, exact=False)
+    assert _rel(hx.cpu().numpy().T, 2 * px) <= tol
+    assert _rel(hq.cpu().numpy(), 2 * pq) <= tol
+
+
+def test_autograd_matches_finite_differences(ps):
+    """The autograd.Function's backward (exact adjoint, FP64) against central
+    differences h = 1e-5 of the library's own energy."""
+    box = (1.0, 1.0, 1.0)
+    x, q = W.uniform_box(400, box, charges="gauss", seed=21)
+    pl = ps.Plan(box, 10, R_b=1.5, n_max=400)
+    xt = _dev(x.T).requires_grad_(True)
+    qt = _dev(q).requires_grad_(True)
+    E = ps.PeriodicEnergy.apply(xt, qt, pl, True)
+    E.backward()
+    gx, gq = xt.grad.cpu().numpy(), qt.grad.cpu().numpy()
+    h = 1e-5
+
+    def energy(xx, qq):
+        return float(pl.energy(_dev(xx.T), _dev(qq)).cpu()[0])
+
+    from oracle.geometry import lattice_vectors
+    P = lattice_vectors(box, 1.5)
+    dist = np.abs(np.linalg.norm(x[:, None, :] + P[None], axis=2) - 1.5).min(1)
+    for i in np.nonzero(dist > 1e-3)[0][:4]:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (energy(xp, q) - energy(xm, q)) / (2 * h)
+            assert abs(gx[k, i] - fd) < 1e-6 * max(1.0, abs(fd))
+    for i, j in [(0, 1), (7, 300)]:
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qp[j] -= h
+        qm[i] -= h
+        qm[j] += h
+        fd = (energy(x, qp) - energy(x, qm)) / (2 * h)
+        assert abs((gq[i] - gq[j]) - fd) < 1e-6 * max(1.0, abs(fd))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batched_matches_oracle_and_single(ps, prec):
+    g = np.random.default_rng(5)
+    systems, xs, qs = [], [], []
+    for k in range(7):
+        box = g.uniform(1.0, 2.0, size=3)
+        n = int(g.integers(50, 1500))
+        x, q = W.uniform_box(n, box, charges="gauss", seed=100 + k)
+        systems.append(dict(box=box, n_max=n))
+        xs.append(x)
+        qs.append(q)
+    lam = float(np.sqrt(3))
+    bp = ps.BatchedPlan(systems, p=10, lam=lam, precision=prec)
+    off = np.concatenate([[0], np.cumsum([len(q) for q in qs])])
+    X = np.concatenate(xs)
+    Q = np.concatenate(qs)
+    phi, field = bp.eval(_dev(X.T), _dev(Q), off)
+    phi2, field2 = bp.eval(_dev(X.T), _dev(Q), off)   # second launch of the same graph
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    assert np.array_equal(phi, phi2.cpu().numpy())
+    for k in range(7):
+        sl = slice(off[k], off[k + 1])
+        ref = OPlan(systems[k]["box"], 10, lam=lam).solve(xs[k], qs[k])
+        assert _rel(phi[sl], ref[0]) <= TOL[prec]
+        assert _rel(field[sl], ref[1]) <= TOL[prec]
+
+
+# --------------------------------------------------------------------------
+# full-size workloads: sampled particles against stored oracle values
+# (tests/golden/make_reference.py, oracle only)
+# --------------------------------------------------------------------------
+def _golden(name):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", name)
+    if not os.path.exists(path):
+        pytest.skip("reference %s not generated" % name)
+    return np.load(path)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_full_size_uniform_cube(ps, prec):
+    """N = 100,000 uniform in the unit cube, q ~ N(0,1) minus mean, p = 16,
+    in the launch configuration the benchmark times; 2,000 sampled particles."""
+    c = W.config2()
+    ref = _golden("ref_cfg2.npz")
+    pl, phi, field = _run(ps, c["box"], c["p"], c["x"], c["q"], prec, R_b=c["R_b"])
+    sub = ref["subset"]
+    assert pl.info()["n_near_last"] == int(ref["n_near"])
+    e1, e2 = _rel(phi[sub], ref["phi"]), _rel(field[sub], ref["field"])
+    print(prec, "cfg2 rel-L2 phi %.3e field %.3e" % (e1, e2))
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]
+
+
+def test_full_size_clustered_anisotropic(ps):
+    """N = 1,000,000 in 64 Gaussian blobs, box 1x1x2.5, p = 20, lambda = 1.5,
+    FP32 pairs with FP64 accumulation; 2,000 sampled particles."""
+    c = W.config3()
+    ref = _golden("ref_cfg3.npz")
+    pl, phi, field = _run(ps, c["box"], c["p"], c["x"], c["q"], "fp32", lam=c["lam"])
+    sub = ref["subset"]
+    assert pl.info()["n_near_last"] == int(ref["n_near"])
+    e1, e2 = _rel(phi[sub], ref["phi"]), _rel(field[sub], ref["field"])
+    print("cfg3 rel-L2 phi %.3e field %.3e" % (e1, e2))
+    assert e1 <= 1e-6 and e2 <= 1e-6
+
+
+def test_full_size_batch(ps):
+    """512 boxes, d_k ~ U[1,2], N ~ log-uniform[200, 20000], p = 12, lambda = sqrt 3,
+    FP32 pairs, one graph launch; sampled particles of six systems."""
+    c = W.config4()
+    ref = _golden("ref_cfg4.npz")
+    systems = [dict(box=s["box"], n_max=len(s["q"])) for s in c["systems"]]
+    bp = ps.BatchedPlan(systems, p=c["p"], lam=c["lam"], precision="fp32")
+    off = np.concatenate([[0], np.cumsum([len(s["q"]) for s in c["systems"]])])
+    X = np.concatenate([s["x"] for s in c["systems"]])
+    Q = np.concatenate([s["q"] for s in c["systems"]])
+    phi, field = bp.eval(_dev(X.T), _dev(Q), off)
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    for k in ref["systems"]:
+        sub = ref["sub_%d" % k] + off[k]
+        assert _rel(phi[sub], ref["phi_%d" % k]) <= 1e-6
+        assert _rel(field[sub], ref["field_%d" % k]) <= 1e-6
+
+
+def test_full_size_rocksalt_energy_gradient(ps):
+    """Jittered 32^3 rock-salt lattice, p = 16: sampled potentials and fields
+    against the oracle; the physical gradient is -q field; the exact adjoint
+    agrees with central differences on sampled coordinates."""
+    c = W.config5()
+    ref = _golden("ref_cfg5.npz")
+    n = len(c["q"])
+    pl = ps.Plan(c["box"], c["p"], R_b=c["R_b"], n_max=n)
+    xt, qt = _dev(c["x"].T), _dev(c["q"])
+    phi, field = pl.eval(xt, qt)
+    sub = ref["subset"]
+    assert _rel(phi.cpu().numpy()[sub], ref["phi"]) <= 1e-12
+    assert _rel(field.cpu().numpy().T[sub], ref["field"]) <= 1e-12
+    e = pl.energy(xt, qt)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(xt, qt, one, exact=True)
+    px, _ = pl.energy_vjp(xt, qt, one, exact=False)
+    gx = gx.cpu().numpy()
+    assert _rel(px.cpu().numpy()[:, sub].T, -c["q"][sub, None] * ref["field"]) <= 1e-12
+    # exact adjoint vs physical gradient: method truncation level
+    assert _rel(gx, px.cpu().numpy()) < 1e-3
+    h = 1e-5
+
+    def energy(xx):
+        return float(pl.energy(_dev(xx.T), qt).cpu()[0])
+
+    x = c["x"]
+    for i in sub[:3]:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (energy(xp) - energy(xm)) / (2 * h)
+            assert abs(gx[k, i] - fd) < 1e-5 * max(1.0, abs(fd)), (i, k, gx[k, i], fd)
+    del e
