@@ -30,7 +30,24 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(c, ntarget=400):
+def measured_traffic(precision):
+    """HBM bytes per launch of the pair kernel from the committed rocprofv3
+    counter record, or None if the kernel source has changed since."""
+    import hashlib
+    if precision != "fp32":
+        return None
+    rec = os.path.join(ROOT, "profiles", "p2p_f32_uniform_cube_N100k_hbm_counters.json")
+    if not os.path.exists(rec):
+        return None
+    src = open(os.path.join(ROOT, "paper_1310_4374_amd", "csrc", "ps_kernels.hip")).read()
+    a = src.index("template <int BT, bool FIELD>\n__global__ __launch_bounds__(BT) void k_p2p_f32")
+    b = src.index("// FP64 reciprocal square root", a)
+    h = hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    d = json.load(open(rec))
+    return d["traffic_bytes"] if d.get("source_sha256_16") == h else None
+
+
+def cpu_baseline(c, ntarget=4000):
     """The FP64 oracle as it stands, on a bounded sample: its full "get" with the
     check points and `ntarget` particles as targets."""
     from oracle.method import Plan as OPlan
@@ -53,6 +70,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this implementation has no multi-GPU path "
@@ -66,6 +85,13 @@ def main():
     c = W.config2()
     n = len(c["q"])
     dev = torch.device("cuda", 0)
+    if args.copy_calibration_mib:
+        a = torch.ones(args.copy_calibration_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("calibration copy: %d MiB read, %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
+        del a, b
     x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
     q = torch.tensor(c["q"], device=dev)
     plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n)
@@ -116,7 +142,7 @@ def main():
         t_pairs = stage_ms["pairs"] * 1e-3
         achieved = FLOP_PER_PAIR * n * nb / t_pairs / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.precision),
                 "kernel": "k_p2p_%s<256,field> (particle near sums)" % ("f32" if args.precision == "fp32" else "f64"),
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,
                 "pair_rate": n * nb / t_pairs}

@@ -674,19 +674,33 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
 // ----------------------------------------------------------------------------
 // least-squares solve (steps 4-5): f = phi_near(Y_c2) - phi_near(Y_c1), C = A^+ f
 // ----------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ cjobs,
-                                             double* __restrict__ fout)
+// f_l = phi_near(y~_l) - phi_near(y_l) from the split partials: 64 check
+// points per workgroup, 16 lane groups over the splits, combined in fixed order.
+__global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ cjobs,
+                                              double* __restrict__ fout)
 {
+    __shared__ double sa[16][64], sb[16][64];
     const SysDev& S = sys[blockIdx.y];
     const PJob& J = cjobs[blockIdx.y];
-    const int l = blockIdx.x * 256 + threadIdx.x;
-    if (l >= S.L) return;
+    const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int l = blockIdx.x * 64 + lane;
     double a = 0.0, b = 0.0;
-    for (int s = 0; s < J.nsplit; ++s) {
-        a += J.part[(int64_t)s * J.nt + l];
-        b += J.part[(int64_t)s * J.nt + S.L + l];
+    if (l < S.L)
+        for (int s = g; s < J.nsplit; s += 16) {
+            a += J.part[(int64_t)s * J.nt + l];
+            b += J.part[(int64_t)s * J.nt + S.L + l];
+        }
+    sa[g][lane] = a;
+    sb[g][lane] = b;
+    __syncthreads();
+    if (g == 0 && l < S.L) {
+        double A = 0.0, B = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            A += sa[k][lane];
+            B += sb[k][lane];
+        }
+        fout[S.f_off + l] = B - A;
     }
-    fout[S.f_off + l] = b - a;
 }
 
 __global__ __launch_bounds__(256) void k_gemv(const SysDev* __restrict__ sys, const double* __restrict__ pinv,
@@ -760,20 +774,17 @@ __global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, co
     if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
 
-__global__ void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part, int nblk,
-                     const double* __restrict__ bm, double* __restrict__ coef)
+__global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part, int nblk,
+                                            const double* __restrict__ bm, double* __restrict__ coef)
 {
+    __shared__ double sh[4];
     const SysDev& S = sys[blockIdx.x];
-    if (threadIdx.x != 0) return;
-    if (S.mean_mode != 0) {
-        coef[S.coef_off] = 0.0;
-        return;
-    }
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)blockIdx.x * nblk + b];
-    double d = 0.0;
-    for (int t = 1; t < S.P; ++t) d += coef[S.coef_off + t] * bm[S.bm_off + t];
-    coef[S.coef_off] = -s - d;
+    double sm = 0.0, d = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) sm += part[(int64_t)blockIdx.x * nblk + b];
+    for (int t = 1 + threadIdx.x; t < S.P; t += 256) d += coef[S.coef_off + t] * bm[S.bm_off + t];
+    sm = block_reduce<0>(sm, sh);
+    d = block_reduce<0>(d, sh);
+    if (threadIdx.x == 0) coef[S.coef_off] = S.mean_mode == 0 ? -sm - d : 0.0;
 }
 
 // ----------------------------------------------------------------------------
@@ -969,14 +980,14 @@ void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, 
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
                   double* coef, double* f, hipStream_t st)
 {
-    PS_LAUNCH(k_rhs, dim3((maxL + 255) / 256, nsys), dim3(256), 0, st, sys, cjobs, f);
+    PS_LAUNCH(k_rhs, dim3((maxL + 63) / 64, nsys), dim3(1024), 0, st, sys, cjobs, f);
     PS_LAUNCH(k_gemv, dim3((maxP - 1 + 3) / 4, nsys), dim3(256), 0, st, sys, pinv, f, coef);
 }
 void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
                  const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st)
 {
     PS_LAUNCH(k_mean, dim3(nblk, nsys), dim3(256), 0, st, sys, nnear, nx, ny, nz, nq, part);
-    PS_LAUNCH(k_c1, dim3(nsys), dim3(64), 0, st, sys, part, nblk, bm, coef);
+    PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, nblk, bm, coef);
 }
 void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
                 const double* coef, const double* rec, const int* perm, double* phi, double* ex, double* ey,
