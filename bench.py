@@ -22,12 +22,30 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-FP32_PEAK_TFLOPS = 157.3   # MI355X FP32 vector (packed), published
+# Peaks of the ALU-bound pair kernel.  The published FP32 vector figure (157.3
+# TFLOP/s) counts packed FP32 (two lanes' worth of FMA per instruction); packed
+# FP32 is not used by these kernels, so their ceiling from the unit counts is
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
+FP32_PUBLISHED_TFLOPS = 157.3
+FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+FP64_TFLOPS = 78.6
 FLOP_PER_PAIR = 20         # potential + field: 3 sub, r^2 (mul + 2 FMA), rsqrt, 3 mul, add, 3 FMA
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def pair_kernel_hash():
+    """sha256 (16 hex digits) of the FP32 pair kernel's source text, between the
+    comment that opens it and the FP64 reciprocal square root that follows."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_1310_4374_amd", "csrc", "ps_kernels.hip")).read()
+    a = src.find("// FP32 pair arithmetic on coordinates relative to the target-block centre.")
+    b = src.find("// FP64 reciprocal square root", a)
+    if a < 0 or b < 0:
+        return None
+    return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
 def measured_traffic(precision):
@@ -39,10 +57,9 @@ def measured_traffic(precision):
     rec = os.path.join(ROOT, "profiles", "p2p_f32_uniform_cube_N100k_hbm_counters.json")
     if not os.path.exists(rec):
         return None
-    src = open(os.path.join(ROOT, "paper_1310_4374_amd", "csrc", "ps_kernels.hip")).read()
-    a = src.index("template <int BT, bool FIELD>\n__global__ __launch_bounds__(BT) void k_p2p_f32")
-    b = src.index("// FP64 reciprocal square root", a)
-    h = hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
+    h = pair_kernel_hash()
+    if h is None:
+        return None
     d = json.load(open(rec))
     return d["traffic_bytes"] if d.get("source_sha256_16") == h else None
 
@@ -70,6 +87,11 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
+    ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
+    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
+    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt"],
+                    help="cube (default): the headline solve; the others measure the batched, clustered and "
+                         "differentiated workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -81,6 +103,11 @@ def main():
     import torch
     import paper_1310_4374_amd as ps
     import workloads as W
+
+    if args.workload != "cube":
+        out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
 
     c = W.config2()
     n = len(c["q"])
@@ -94,9 +121,12 @@ def main():
         del a, b
     x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
     q = torch.tensor(c["q"], device=dev)
-    plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n)
+    plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n,
+                   tile_targets=args.tile_targets)
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    if args.autotune:
+        log("autotune: best %.3f ms" % plan.autotune(x, q))
     log("plan ready:", plan.info())
     for _ in range(args.warmup):
         plan.eval(x, q, out=(phi, field))
@@ -141,9 +171,14 @@ def main():
         stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
         t_pairs = stage_ms["pairs"] * 1e-3
         achieved = FLOP_PER_PAIR * n * nb / t_pairs / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / FP32_PEAK_TFLOPS, "traffic": measured_traffic(args.precision),
-                "kernel": "k_p2p_%s<256,field> (particle near sums)" % ("f32" if args.precision == "fp32" else "f64"),
+        peak = FP32_NONPACKED_TFLOPS if args.precision == "fp32" else FP64_TFLOPS
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak, "traffic": measured_traffic(args.precision),
+                "peak_basis": ("non-packed FP32 VALU: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz"
+                               if args.precision == "fp32" else "FP64 vector, published"),
+                "frac_of_published_fp32_157_3": achieved / FP32_PUBLISHED_TFLOPS,
+                "kernel": "k_p2p_%s<%d,field> (particle near sums)" % ("f32" if args.precision == "fp32" else "f64",
+                                                                    info["tile_targets"]),
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,
                 "pair_rate": n * nb / t_pairs}
     out = {
@@ -172,6 +207,140 @@ def main():
         log("timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(out), flush=True)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _time(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def bench_batch(args):
+    """512 boxes (d_k ~ U[1,2], N ~ log-uniform[200, 20000]), p = 12, lambda = sqrt 3:
+    one graph launch of the batched FP32 path (autotuned) against the per-box
+    FP64 path run box after box."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config4()
+    dev = torch.device("cuda", 0)
+    systems = [dict(box=s["box"], n_max=len(s["q"])) for s in c["systems"]]
+    off = np.concatenate([[0], np.cumsum([len(s["q"]) for s in c["systems"]])])
+    X = torch.tensor(np.ascontiguousarray(np.concatenate([s["x"] for s in c["systems"]]).T), device=dev)
+    Q = torch.tensor(np.concatenate([s["q"] for s in c["systems"]]), device=dev)
+    t = time.perf_counter()
+    bp = ps.BatchedPlan(systems, p=c["p"], lam=c["lam"], precision="fp32")
+    t_plan = time.perf_counter() - t
+    tuned_ms = bp.autotune(X, Q, off)
+    info = bp.info()
+    phi = torch.empty(X.shape[1], dtype=torch.float64, device=dev)
+    field = torch.empty(3, X.shape[1], dtype=torch.float64, device=dev)
+    ms = _time(lambda: bp.eval(X, Q, off, out=(phi, field)), args.steps, args.warmup)
+    bp.status()
+    nb = np.array(bp.near_counts())
+    n = np.diff(off)
+    L = 2 * c["p"] ** 2 - c["p"]
+    pairs = float(np.sum((n + 2 * L) * nb))
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "ref_cfg4.npz"))
+    ph, fd = phi.cpu().numpy(), field.cpu().numpy().T
+    err32 = max(max(_rel(ph[ref["sub_%d" % k] + off[k]], ref["phi_%d" % k]),
+                    _rel(fd[ref["sub_%d" % k] + off[k]], ref["field_%d" % k])) for k in ref["systems"])
+    # per-box FP64 form: one plan and one eval per system, box after box
+    plans = [ps.Plan(s["box"], c["p"], lam=c["lam"], precision="fp64", n_max=len(s["q"])) for s in c["systems"]]
+    xs = [X[:, off[k]:off[k + 1]].contiguous() for k in range(len(plans))]
+    qs = [Q[off[k]:off[k + 1]].contiguous() for k in range(len(plans))]
+    outs = [(torch.empty(len(q_), dtype=torch.float64, device=dev), torch.empty(3, len(q_), dtype=torch.float64, device=dev)) for q_ in qs]
+
+    def loop():
+        for k, pl in enumerate(plans):
+            pl.eval(xs[k], qs[k], out=outs[k])
+    ms64 = _time(loop, max(1, args.steps // 4), 1)
+    err64 = max(max(_rel(outs[k][0].cpu().numpy()[ref["sub_%d" % k]], ref["phi_%d" % k]),
+                    _rel(outs[k][1].cpu().numpy().T[ref["sub_%d" % k]], ref["field_%d" % k])) for k in ref["systems"])
+    nsys = len(plans)
+    return {"metric": "periodic solves/s (batched boxes)", "value": nsys / (ms * 1e-3), "unit": "solves/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "512 boxes d_k~U[1,2], N~logU[200,20000] (sum %d), q~N(0,1)-mean, p=12, "
+                                   "lambda=sqrt3, FP32 pairs, one graph launch" % int(off[-1]),
+                       "pairs_per_batch": pairs, "tile_targets": info["tile_targets"]},
+            "pair_rate": pairs / (ms * 1e-3), "max_rel_l2_sampled": err32, "autotune_best_ms": tuned_ms,
+            "plan_seconds": t_plan,
+            "per_box_fp64": {"solves_per_s": nsys / (ms64 * 1e-3), "ms_per_batch": ms64, "max_rel_l2_sampled": err64},
+            "speedup_vs_per_box_fp64": ms64 / ms}
+
+
+def bench_clustered(args):
+    """1,000,000 particles in 64 Gaussian blobs, box 1 x 1 x 2.5, p = 20, lambda = 1.5, FP32 pairs."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config3()
+    dev = torch.device("cuda", 0)
+    n = len(c["q"])
+    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
+    q = torch.tensor(c["q"], device=dev)
+    pl = ps.Plan(c["box"], c["p"], lam=c["lam"], precision="fp32", n_max=n)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    pl.set_profiling(True)
+    ms = _time(lambda: pl.eval(x, q, out=(phi, field)), max(1, args.steps), 1)
+    st = pl.stage_times()
+    pl.status()
+    inf = pl.info()
+    nb = inf["n_near_last"]
+    pairs = (n + 2 * inf["L"]) * nb
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "ref_cfg3.npz"))
+    sub = ref["subset"]
+    return {"metric": "pair interactions/s (clustered, anisotropic)", "value": pairs / (ms * 1e-3),
+            "unit": "pair interactions/s", "n_gpus": 1, "steps": max(1, args.steps), "ms_per_step": ms,
+            "solves_per_s": 1e3 / ms, "dtype": "f32", "higher_is_better": True,
+            "config": {"workload": "box 1x1x2.5, N=1e6 in 64 Gaussian blobs, p=20, lambda=1.5", "n_near": nb},
+            "rel_l2_phi": _rel(phi.cpu().numpy()[sub], ref["phi"]),
+            "rel_l2_field": _rel(field.cpu().numpy().T[sub], ref["field"]), "stage_ms": st,
+            "pair_kernel_rate": n * nb / (st["pairs"] * 1e-3)}
+
+
+def bench_rocksalt(args):
+    """Jittered rock-salt lattice 32^3 (N = 32,768), p = 16: energy plus the exact
+    adjoint (dE/dx, dE/dq) as one forward + backward step, FP64 and FP32."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config5()
+    dev = torch.device("cuda", 0)
+    n = len(c["q"])
+    out = {"metric": "energy + exact gradient steps/s (rock-salt lattice)", "unit": "steps/s", "n_gpus": 1,
+           "config": {"workload": "rock-salt 32^3 sites jittered N(0,0.002^2), p=16, R_b=1.5"}}
+    for prec in ("fp64", "fp32"):
+        pl = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=prec, n_max=n)
+        x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev, requires_grad=True)
+        q = torch.tensor(c["q"], device=dev, requires_grad=True)
+
+        def step():
+            x.grad = None
+            q.grad = None
+            E = ps.PeriodicEnergy.apply(x, q, pl, True)
+            E.backward()
+        ms = _time(step, max(2, args.steps // 2), 1)
+        fwd = _time(lambda: pl.energy(x.detach(), q.detach()), max(2, args.steps // 2), 1)
+        out[prec] = {"ms_per_step": ms, "forward_ms": fwd, "steps_per_s": 1e3 / ms,
+                     "n_near": pl.info()["n_near_last"]}
+    out["value"] = out["fp32"]["steps_per_s"]
+    out["ms_per_step"] = out["fp32"]["ms_per_step"]
+    return out
 
 
 if __name__ == "__main__":

@@ -165,6 +165,22 @@ ps_status periodic_sum_eval_batched(ps_plan plan, const int64_t* offsets,
                                     const double* x, const double* y, const double* z, const double* q,
                                     double* phi, double* ex, double* ey, double* ez, void* stream);
 
+/* Autotuner for the particle pair sums: times each candidate of targets per
+ * workgroup {64, 128, 256} x source-split scale {1/2, 1, 2} (relative to the
+ * occupancy-based choice) on the given inputs, with HIP events on `stream`,
+ * and keeps the fastest in the plan (reported by periodic_sum_plan_info).
+ * offsets: host [nsys+1] as in periodic_sum_eval_batched ({0, n} for a
+ * single-system plan); the outputs receive the last candidate's result.
+ * Synchronizes the stream.  best_ms (host, may be NULL) receives the best
+ * time per eval. */
+ps_status periodic_sum_autotune(ps_plan plan, const int64_t* offsets,
+                                const double* x, const double* y, const double* z, const double* q,
+                                double* phi, double* ex, double* ey, double* ez, double* best_ms, void* stream);
+
+/* Near-set sizes N_b of every system after the last completed eval
+ * (host [nsys]; synchronizes the device). */
+ps_status periodic_sum_near_counts(ps_plan plan, int64_t* out, int32_t nsys);
+
 /* Synchronizes `stream` and returns the data-dependent status of the last eval
  * (PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX) or PS_OK, then clears it. */
 ps_status periodic_sum_status(ps_plan plan, void* stream);

@@ -20,7 +20,8 @@ STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID", 2: "PS_E_NOT_NEUTRAL", 3: "PS_E_O
 EXPORTS = ["periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "periodic_sum_energy_vjp",
            "periodic_sum_plan_batched", "periodic_sum_eval_batched", "periodic_sum_status", "periodic_sum_plan_info",
            "periodic_sum_plan_tables", "periodic_sum_last_coefficients", "periodic_sum_set_profiling",
-           "periodic_sum_stage_times", "periodic_sum_destroy", "periodic_sum_last_error"]
+           "periodic_sum_stage_times", "periodic_sum_autotune", "periodic_sum_near_counts", "periodic_sum_destroy",
+           "periodic_sum_last_error"]
 STAGES = ["sort", "near", "bounds", "check", "solve", "mean", "pairs", "far"]
 
 
@@ -83,6 +84,10 @@ def lib():
         L.periodic_sum_set_profiling.restype = st
         L.periodic_sum_stage_times.argtypes = [vp, dp, ctypes.c_int32]
         L.periodic_sum_stage_times.restype = st
+        L.periodic_sum_autotune.argtypes = [vp, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp, vp, vp, dp, vp]
+        L.periodic_sum_autotune.restype = st
+        L.periodic_sum_near_counts.argtypes = [vp, ctypes.POINTER(i64), ctypes.c_int32]
+        L.periodic_sum_near_counts.restype = st
         L.periodic_sum_destroy.argtypes = [vp]
         L.periodic_sum_destroy.restype = None
         L.periodic_sum_last_error.argtypes = []

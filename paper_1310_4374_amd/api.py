@@ -130,6 +130,13 @@ class Plan:
         check(lib().periodic_sum_stage_times(self._h, arr, len(_lib.STAGES)))
         return dict(zip(_lib.STAGES, list(arr)))
 
+    def autotune(self, x, q):
+        """Pick targets per workgroup and the split scale by timing them on these inputs; returns ms per eval."""
+        return _autotune(self, x, q, [0, _soa(x, self.device).shape[1]])
+
+    def near_counts(self):
+        return _near_counts(self, 1)
+
     def status(self):
         """Synchronize and raise on a data error of the last eval."""
         check(lib().periodic_sum_status(self._h, _stream(self.device)))
@@ -156,6 +163,26 @@ class Plan:
                                             _ptr(dx[0]), _ptr(dx[1]), _ptr(dx[2]), _ptr(dq), int(bool(exact)),
                                             _stream(self.device)))
         return dx, dq
+
+
+def _autotune(obj, x, q, offsets):
+    x = _soa(x, obj.device)
+    q = q.contiguous()
+    n = x.shape[1]
+    off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
+    phi = torch.empty(n, dtype=torch.float64, device=obj.device)
+    field = torch.empty(3, n, dtype=torch.float64, device=obj.device)
+    best = ctypes.c_double()
+    check(lib().periodic_sum_autotune(obj._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
+                                      _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), ctypes.byref(best),
+                                      _stream(obj.device)))
+    return best.value
+
+
+def _near_counts(obj, nsys):
+    out = (ctypes.c_int64 * nsys)()
+    check(lib().periodic_sum_near_counts(obj._h, out, nsys))
+    return list(out)
 
 
 class BatchedPlan:
@@ -195,6 +222,18 @@ class BatchedPlan:
         check(lib().periodic_sum_eval_batched(self._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
                                               _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), _stream(self.device)))
         return phi, field
+
+    def autotune(self, x, q, offsets):
+        """Pick targets per workgroup and the split scale by timing them on these inputs; returns ms per batch."""
+        return _autotune(self, x, q, offsets)
+
+    def near_counts(self):
+        return _near_counts(self, self.nsys)
+
+    def info(self):
+        inf = ps_plan_info()
+        check(lib().periodic_sum_plan_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in inf._fields_}
 
     def status(self):
         check(lib().periodic_sum_status(self._h, _stream(self.device)))

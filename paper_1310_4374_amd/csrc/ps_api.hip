@@ -70,6 +70,7 @@ struct ps_plan_s {
     int mean = 0;
     int bt = 256;
     int n_split_req = 0;
+    double split_scale = 1.0;          // autotuned factor on the automatic split count
     int maxP = 0, maxp = 0, maxL = 0;
     int64_t m_max = 0;
     std::vector<SystemSetup> setups;
@@ -184,6 +185,7 @@ ps_status check_params(const ps_params* prm)
     if (prm->tile_targets != 0 && prm->tile_targets != 64 && prm->tile_targets != 128 && prm->tile_targets != 256)
         return fail(PS_E_INVALID, "tile_targets must be 0, 64, 128 or 256");
     if (prm->n_split < 0 || prm->n_split > kMaxSplit) return fail(PS_E_INVALID, "n_split must be in [0, %d]", kMaxSplit);
+
     if (prm->p < 2 || prm->p > 40) return fail(PS_E_INVALID, "p must be in [2, 40]");
     for (int k = 0; k < 3; ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
@@ -272,7 +274,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         C.sz = pl->d_nz + S.near_off;
         C.sq = pl->d_nq + S.near_off;
         C.ns_dev = pl->d_nnear + s;
-        C.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * 6;
+        C.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * (kTile / kGroup) * 6;
         C.tblk = pl->d_tblk_chk + tb_c_off * 4;
         const int64_t ntb_c = (C.nt + 255) / 256;
         // expected near-set size: the ball's volume fraction of the lattice (eq. (o2.1))
@@ -326,13 +328,14 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         else if (nsys == 1) {
             const int64_t cap_split = std::max<int64_t>(1, (pl->part_p_cap / std::max<int64_t>(1, 4 * Pj.nt)));
             sp = split_for_capacity(est[s].ntb, pl->capacity, est[s].nbexp / kTile + 1, std::min<int64_t>(kMaxSplit, cap_split));
+            sp = static_cast<int>(std::max(1.0, std::min<double>(cap_split, std::round(sp * pl->split_scale))));
         }
         else {
             // batch: split large systems so their work items match the typical one
             const double cost = static_cast<double>(est[s].nbexp) * bt;
             double total = 0.0;
             for (int r = 0; r < nsys; ++r) total += static_cast<double>(est[r].nbexp) * std::min<int64_t>(bt, T.sys[r].n) * est[r].ntb;
-            const double item_cost = std::max(1.0, total / kItemTarget);
+            const double item_cost = std::max(1.0, total / (kItemTarget * pl->split_scale));
             sp = static_cast<int>(std::max(1.0, std::min<double>(kMaxSplit, std::ceil(cost / item_cost))));
         }
         const int64_t ntiles_exp = est[s].nbexp / kTile + 1;
@@ -464,6 +467,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     pl->precision = prm[0].precision;
     pl->mean = prm[0].mean;
     pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
+
     pl->n_split_req = prm[0].n_split;
     pl->m_max = nsys == 1 ? prm[0].m_max : 0;
     {
@@ -612,7 +616,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     AL(pl->d_nnear, nsys)
     AL(pl->d_ncount, near_items_cap)
     AL(pl->d_ioff, near_items_cap)
-    AL(pl->d_tile_bb, pl->tiles_tot * 6)
+    AL(pl->d_tile_bb, pl->tiles_tot * (kTile / kGroup) * 6)
     AL(pl->d_tblk_chk, tb_c * 4)
     AL(pl->d_tblk_p, tb_p * 4)
     AL(pl->d_part_chk, pl->part_chk_cap)
@@ -800,6 +804,92 @@ ps_status periodic_sum_plan_tables(ps_plan pl, double* check_points, double* par
     return PS_OK;
 }
 
+ps_status periodic_sum_near_counts(ps_plan pl, int64_t* out, int32_t nsys)
+{
+    if (!pl || !out) return fail(PS_E_INVALID, "NULL argument");
+    if (nsys != pl->nsys) return fail(PS_E_INVALID, "nsys %d does not match the plan's %d", nsys, pl->nsys);
+    HIPCHK(hipSetDevice(pl->device));
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(out, pl->d_nnear, sizeof(int64_t) * nsys, hipMemcpyDeviceToHost));
+    return PS_OK;
+}
+
+ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double* x, const double* y, const double* z,
+                                const double* q, double* phi, double* ex, double* ey, double* ez, double* best_ms,
+                                void* stream)
+{
+    if (!pl || !offsets) return fail(PS_E_INVALID, "NULL argument");
+    HIPCHK(hipSetDevice(pl->device));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const bool f32 = pl->precision == PS_FP32_ACC64;
+    const int cand[3] = {64, 128, 256};
+    const double scales[3] = {0.5, 1.0, 2.0};
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    const int keep_bt = pl->bt;
+    const double keep_scale = pl->split_scale;
+    const int keep_req = pl->n_split_req;
+    pl->n_split_req = 0;
+    float best = 1e30f;
+    int best_bt = keep_bt;
+    double best_scale = keep_scale;
+    ps_status rs = PS_OK;
+    for (const int bt : cand)
+        for (double sc : scales) {
+            pl->bt = bt;
+            pl->split_scale = sc;
+            pl->tab_valid = false;
+            {
+                hipDeviceProp_t prop;
+                if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess)
+                    pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
+                                   p2p_blocks_per_cu(f32 ? 1 : 0, bt);
+            }
+            auto run = [&]() -> ps_status {
+                if (pl->nsys == 1)
+                    return periodic_sum_eval(pl, offsets[1] - offsets[0], x, y, z, q, 0, nullptr, nullptr, nullptr, phi,
+                                             ex, ey, ez, stream);
+                return periodic_sum_eval_batched(pl, offsets, x, y, z, q, phi, ex, ey, ez, stream);
+            };
+            rs = run();  // warm-up (builds tables / the graph)
+            if (rs == PS_E_UNSUPPORTED) {  // candidate does not fit the workspace
+                rs = PS_OK;
+                continue;
+            }
+            if (rs != PS_OK) break;
+            HIPCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < 2 && rs == PS_OK; ++r) rs = run();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            if (rs != PS_OK) break;
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            ms *= 0.5f;
+            if (ms < best) {
+                best = ms;
+                best_bt = bt;
+                best_scale = sc;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    pl->bt = best_bt;
+    pl->split_scale = best_scale;
+    pl->n_split_req = keep_req;
+    pl->tab_valid = false;
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, pl->device) == hipSuccess)
+            pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
+                           p2p_blocks_per_cu(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt);
+    }
+    if (rs != PS_OK) return rs;
+    if (best > 1e29f) return fail(PS_E_UNSUPPORTED, "no tuning candidate fits the plan's workspace");
+    if (best_ms) *best_ms = best;
+    return PS_OK;
+}
+
 ps_status periodic_sum_set_profiling(ps_plan pl, int32_t enable)
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
@@ -872,7 +962,7 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_ay, ns)
     AL(pl->d_az, ns)
     AL(pl->d_aq, ns)
-    AL(pl->d_adj_bb, (ns / kTile + 1) * 6)
+    AL(pl->d_adj_bb, (ns / kTile + 1) * (kTile / kGroup) * 6)
     AL(pl->d_adj_tblk, pl->adj_tb_cap * 4)
     AL(pl->d_adj_part, pl->adj_part_cap)
     AL(pl->d_mom, (int64_t)kMomBlocks * S.P)

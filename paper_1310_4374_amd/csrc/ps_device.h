@@ -5,6 +5,12 @@
 namespace ps {
 
 constexpr int kTile = 256;         // sources staged per LDS tile
+constexpr int kGroup = 32;         // sources per near/far decision (one bounding box each)
+// A group is "far" for a target block of radius rT (about its centre c) when
+// its bounding box is farther than kFarFactor * rT from c.  In FP32 the
+// coordinate rounding error of a far pair relative to its separation is then
+// at most u (1 + 2/(kFarFactor - 1)), u = 2^-24.
+constexpr double kFarFactor = 2.0;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.

@@ -372,9 +372,21 @@ __global__ __launch_bounds__(256) void k_near_write(const SysDev* __restrict__ s
 // ----------------------------------------------------------------------------
 // tile bounds of a source set and centre/radius of each target block
 // ----------------------------------------------------------------------------
+// Bounding boxes of every group of kGroup consecutive sources (the unit of the
+// pair kernels' near/far decision): one workgroup per tile, one half-wave per group.
+__device__ __forceinline__ double half_min(double v)
+{
+    for (int o = 16; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double half_max(double v)
+{
+    for (int o = 16; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 __global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jobs)
 {
-    __shared__ double sh[4];
     const PJob& J = jobs[blockIdx.y];
     const int64_t ns = J.ns_dev ? *J.ns_dev : J.ns_host;
     const int64_t ntiles = (ns + kTile - 1) / kTile;
@@ -383,12 +395,10 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jo
         const int64_t j = t * kTile + threadIdx.x;
         const bool v = j < ns;
         const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
-        const double lx = block_reduce<1>(v ? x : 1e300, sh), ly = block_reduce<1>(v ? y : 1e300, sh),
-                     lz = block_reduce<1>(v ? z : 1e300, sh);
-        const double hx = block_reduce<2>(v ? x : -1e300, sh), hy = block_reduce<2>(v ? y : -1e300, sh),
-                     hz = block_reduce<2>(v ? z : -1e300, sh);
-        if (threadIdx.x == 0) {
-            double* o = bb + t * 6;
+        const double lx = half_min(v ? x : 1e300), ly = half_min(v ? y : 1e300), lz = half_min(v ? z : 1e300);
+        const double hx = half_max(v ? x : -1e300), hy = half_max(v ? y : -1e300), hz = half_max(v ? z : -1e300);
+        if ((threadIdx.x & (kGroup - 1)) == 0) {
+            double* o = bb + (t * (kTile / kGroup) + threadIdx.x / kGroup) * 6;
             o[0] = lx;
             o[1] = ly;
             o[2] = lz;
@@ -460,10 +470,55 @@ __device__ __forceinline__ bool tile_is_far(const double* bb, double cx, double 
 }
 
 // FP32 pair arithmetic on coordinates relative to the target-block centre.
-// Far tiles: one-float relative coordinates (their rounding error is a fixed
-// fraction of the pair distance there).  Near tiles: two-float (hi + lo)
+// Far groups: one-float relative coordinates (their rounding error is a fixed
+// fraction of the pair distance there).  Near groups: two-float (hi + lo)
 // relative coordinates, d = (t_hi - s_hi) + (t_lo - s_lo), so close pairs keep
-// their full FP64-derived separation.
+// their full FP64-derived separation, and K(0) = 0 is applied.
+template <bool NEAR, bool FIELD>
+__device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
+                                            float hy, float hz, float lx, float ly, float lz, double& aP, double& aX,
+                                            double& aY, double& aZ)
+{
+    float fX = 0.f, fY = 0.f, fZ = 0.f;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        float qv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float4 s = sA[g * 8 + u];
+            float dx, dy, dz;
+            if (NEAR) {
+                const float4 l = sB[g * 8 + u];
+                dx = (hx - s.x) + (lx - l.x);
+                dy = (hy - s.y) + (ly - l.y);
+                dz = (hz - s.z) + (lz - l.z);
+            } else {
+                dx = hx - s.x;
+                dy = hy - s.y;
+                dz = hz - s.z;
+            }
+            float r2 = dx * dx;
+            r2 = __builtin_fmaf(dy, dy, r2);
+            r2 = __builtin_fmaf(dz, dz, r2);
+            float ri = __builtin_amdgcn_rsqf(r2);
+            if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
+            qv[u] = s.w * ri;
+            if (FIELD) {
+                const float qr3 = qv[u] * (ri * ri);
+                fX = __builtin_fmaf(qr3, dx, fX);
+                fY = __builtin_fmaf(qr3, dy, fY);
+                fZ = __builtin_fmaf(qr3, dz, fZ);
+            }
+        }
+        aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
+    }
+    if (FIELD) {
+        aX += (double)fX;
+        aY += (double)fY;
+        aZ += (double)fZ;
+    }
+}
+
 template <int BT, bool FIELD>
 __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
@@ -476,7 +531,7 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     const bool active = i < J.nt;
     const double* tb = J.tblk + (int64_t)it.tb * 4;
     const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
-    const double far2 = 16.0 * rT * rT;
+    const double far2 = kFarFactor * kFarFactor * rT * rT;
     double rx = 0.0, ry = 0.0, rz = 0.0;
     if (active) {
         rx = J.tx[i] - cx;
@@ -487,7 +542,6 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
     double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
     for (int64_t t = sp.t0; t < sp.t1; ++t) {
-        const bool far = tile_is_far(J.tile_bb + t * 6, cx, cy, cz, far2);
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
             const int64_t j = t * kTile + k;
@@ -502,69 +556,13 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
             sB[k] = b;
         }
         __syncthreads();
-        if (far) {
-            for (int k0 = 0; k0 < kTile; k0 += 32) {
-                float fX = 0.f, fY = 0.f, fZ = 0.f;
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    float qv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const float4 s = sA[k0 + g * 8 + u];
-                        const float dx = hx - s.x, dy = hy - s.y, dz = hz - s.z;
-                        float r2 = dx * dx;
-                        r2 = __builtin_fmaf(dy, dy, r2);
-                        r2 = __builtin_fmaf(dz, dz, r2);
-                        const float ri = __builtin_amdgcn_rsqf(r2);
-                        qv[u] = s.w * ri;
-                        if (FIELD) {
-                            const float qr3 = qv[u] * (ri * ri);
-                            fX = __builtin_fmaf(qr3, dx, fX);
-                            fY = __builtin_fmaf(qr3, dy, fY);
-                            fZ = __builtin_fmaf(qr3, dz, fZ);
-                        }
-                    }
-                    aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
-                }
-                if (FIELD) {
-                    aX += (double)fX;
-                    aY += (double)fY;
-                    aZ += (double)fZ;
-                }
-            }
-        } else {
-            for (int k0 = 0; k0 < kTile; k0 += 32) {
-                float fX = 0.f, fY = 0.f, fZ = 0.f;
-#pragma unroll
-                for (int g = 0; g < 4; ++g) {
-                    float qv[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const float4 s = sA[k0 + g * 8 + u];
-                        const float4 l = sB[k0 + g * 8 + u];
-                        const float dx = (hx - s.x) + (lx - l.x), dy = (hy - s.y) + (ly - l.y),
-                                    dz = (hz - s.z) + (lz - l.z);
-                        float r2 = dx * dx;
-                        r2 = __builtin_fmaf(dy, dy, r2);
-                        r2 = __builtin_fmaf(dz, dz, r2);
-                        float ri = __builtin_amdgcn_rsqf(r2);
-                        ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
-                        qv[u] = s.w * ri;
-                        if (FIELD) {
-                            const float qr3 = qv[u] * (ri * ri);
-                            fX = __builtin_fmaf(qr3, dx, fX);
-                            fY = __builtin_fmaf(qr3, dy, fY);
-                            fZ = __builtin_fmaf(qr3, dz, fZ);
-                        }
-                    }
-                    aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
-                }
-                if (FIELD) {
-                    aX += (double)fX;
-                    aY += (double)fY;
-                    aZ += (double)fZ;
-                }
-            }
+        const double* bb = J.tile_bb + t * (kTile / kGroup) * 6;
+#pragma unroll 1
+        for (int gq = 0; gq < kTile / kGroup; ++gq) {
+            if (tile_is_far(bb + gq * 6, cx, cy, cz, far2))
+                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
+            else
+                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
         }
     }
     if (active) {
@@ -592,6 +590,30 @@ struct Src64 {
     double x, y, z, q;
 };
 
+template <bool NEAR, bool FIELD>
+__device__ __forceinline__ void group32_f64(const Src64* __restrict__ sS, double tx, double ty, double tz, double& aP,
+                                            double& aX, double& aY, double& aZ)
+{
+#pragma unroll 8
+    for (int k = 0; k < kGroup; ++k) {
+        const Src64 s = sS[k];
+        const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
+        double r2 = dx * dx;
+        r2 = __builtin_fma(dy, dy, r2);
+        r2 = __builtin_fma(dz, dz, r2);
+        double ri = rsqrt64(r2);
+        if (NEAR) ri = r2 > 0.0 ? ri : 0.0;  // K(0) = 0
+        const double qr = s.q * ri;
+        aP += qr;
+        if (FIELD) {
+            const double qr3 = qr * (ri * ri);
+            aX = __builtin_fma(qr3, dx, aX);
+            aY = __builtin_fma(qr3, dy, aY);
+            aZ = __builtin_fma(qr3, dz, aZ);
+        }
+    }
+}
+
 template <int BT, bool FIELD>
 __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
@@ -603,7 +625,9 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
     const bool active = i < J.nt;
     const double* tb = J.tblk + (int64_t)it.tb * 4;
     const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
-    const double far2 = 16.0 * rT * rT;
+    // FP64 coordinates need no precision margin: a group is far as soon as it
+    // cannot hold a source coinciding with a target
+    const double far2 = rT * rT;
     double tx = 0.0, ty = 0.0, tz = 0.0;
     if (active) {
         tx = J.tx[i];
@@ -612,7 +636,6 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
     }
     double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
     for (int64_t t = sp.t0; t < sp.t1; ++t) {
-        const bool far = tile_is_far(J.tile_bb + t * 6, cx, cy, cz, far2);
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
             const int64_t j = t * kTile + k;
@@ -621,43 +644,13 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
             sS[k] = s;
         }
         __syncthreads();
-        if (far) {
-#pragma unroll 4
-            for (int k = 0; k < kTile; ++k) {
-                const Src64 s = sS[k];
-                const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-                double r2 = dx * dx;
-                r2 = __builtin_fma(dy, dy, r2);
-                r2 = __builtin_fma(dz, dz, r2);
-                const double ri = rsqrt64(r2);
-                const double qr = s.q * ri;
-                aP += qr;
-                if (FIELD) {
-                    const double qr3 = qr * (ri * ri);
-                    aX = __builtin_fma(qr3, dx, aX);
-                    aY = __builtin_fma(qr3, dy, aY);
-                    aZ = __builtin_fma(qr3, dz, aZ);
-                }
-            }
-        } else {
-#pragma unroll 4
-            for (int k = 0; k < kTile; ++k) {
-                const Src64 s = sS[k];
-                const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-                double r2 = dx * dx;
-                r2 = __builtin_fma(dy, dy, r2);
-                r2 = __builtin_fma(dz, dz, r2);
-                double ri = rsqrt64(r2);
-                ri = r2 > 0.0 ? ri : 0.0;  // K(0) = 0
-                const double qr = s.q * ri;
-                aP += qr;
-                if (FIELD) {
-                    const double qr3 = qr * (ri * ri);
-                    aX = __builtin_fma(qr3, dx, aX);
-                    aY = __builtin_fma(qr3, dy, aY);
-                    aZ = __builtin_fma(qr3, dz, aZ);
-                }
-            }
+        const double* bb = J.tile_bb + t * (kTile / kGroup) * 6;
+#pragma unroll 1
+        for (int gq = 0; gq < kTile / kGroup; ++gq) {
+            if (tile_is_far(bb + gq * 6, cx, cy, cz, far2))
+                group32_f64<false, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);
+            else
+                group32_f64<true, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);
         }
     }
     if (active) {
@@ -1224,8 +1217,8 @@ int p2p_blocks_per_cu(int prec, int bt)
 {
     int nb = 0;
     hipError_t e = hipErrorInvalidValue;
-#define OCC(BT)                                                                                         \
-    if (bt == BT)                                                                                       \
+#define OCC(BT)                                                                                               \
+    if (bt == BT)                                                                                             \
         e = prec == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f32<BT, true>, BT, 0)   \
                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f64<BT, true>, BT, 0);
     OCC(64)

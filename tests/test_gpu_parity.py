@@ -348,3 +348,33 @@ def test_full_size_rocksalt_energy_gradient(ps):
             fd = (energy(xp) - energy(xm)) / (2 * h)
             assert abs(gx[k, i] - fd) < 1e-5 * max(1.0, abs(fd)), (i, k, gx[k, i], fd)
     del e
+
+
+def test_autotuned_batch_still_matches_oracle(ps):
+    """The autotuner only changes the launch shape: results stay at the bar."""
+    g = np.random.default_rng(9)
+    systems, xs, qs = [], [], []
+    for k in range(5):
+        box = g.uniform(1.0, 2.0, size=3)
+        n = int(g.integers(100, 2500))
+        x, q = W.uniform_box(n, box, charges="gauss", seed=200 + k)
+        systems.append(dict(box=box, n_max=n))
+        xs.append(x)
+        qs.append(q)
+    lam = float(np.sqrt(3))
+    bp = ps.BatchedPlan(systems, p=9, lam=lam, precision="fp32")
+    off = np.concatenate([[0], np.cumsum([len(q) for q in qs])])
+    X, Q = _dev(np.concatenate(xs).T), _dev(np.concatenate(qs))
+    ms = bp.autotune(X, Q, off)
+    assert ms > 0 and bp.info()["tile_targets"] in (64, 128, 256)
+    phi, field = bp.eval(X, Q, off)
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    nb = bp.near_counts()
+    for k in range(5):
+        sl = slice(off[k], off[k + 1])
+        op = OPlan(systems[k]["box"], 9, lam=lam)
+        parts = op.solve(xs[k], qs[k], return_parts=True)
+        assert nb[k] == parts["n_near"]
+        assert _rel(phi[sl], parts["phi"]) <= 1e-6
+        assert _rel(field[sl], parts["field"]) <= 1e-6
