@@ -68,6 +68,11 @@ typedef enum {
 } ps_precision;
 
 typedef enum {
+    PS_BASIS_SPHERICAL = 0,  /* renormalized regular solid harmonics, eqs. (1.6)-(1.8) */
+    PS_BASIS_RBF = 1         /* the kernel at M given centres outside the box, eq. (5) */
+} ps_basis;
+
+typedef enum {
     PS_MEAN_ZERO = 0,   /* C1 from the zero box-mean condition, eq. (pfx3) */
     PS_MEAN_NONE = 1    /* C1 = 0 (remark after algorithm "get") */
 } ps_mean;
@@ -84,10 +89,18 @@ typedef struct {
     int64_t m_max;        /* largest separate-target count an eval may pass (0: particles only) */
     int32_t tile_targets; /* targets per workgroup in the particle sums: 0 (default), 64, 128 or 256 */
     int32_t n_split;      /* source splits of the particle sums: 0 = automatic */
+    int32_t basis;        /* ps_basis */
+    int32_t n_centres;    /* PS_BASIS_RBF: number of centres M (1..4096) */
+    const double* centres;      /* PS_BASIS_RBF: host [3*M], xyz interleaved, each with |x| > R0;
+                                   the far field is sum_t C_t / |y - x_t| (an M-source pair sum) */
+    int32_t n_check;      /* 0: Gauss spherical grid of L = 2p^2 - p points (Sec. 2.2);
+                             > 0: that many caller-given check points */
+    const double* check_points; /* host [3*n_check], xyz interleaved, |y| <= R0 and outside the box
+                                   along at least one axis (so a partner exists, Sec. 2.3 step 3) */
 } ps_params;
 
 typedef struct {
-    int32_t p, P, L;          /* truncation number, basis size, check points */
+    int32_t p, P, L;          /* truncation number, basis size (M + 1 for RBF), check points */
     int32_t n_images;         /* lattice images whose box meets the ball |x| <= R_b */
     int32_t rank;             /* numerical rank of A (P-1 when full) */
     double  R0, R_b, cond;    /* circumradius, near radius, sigma_max/sigma_min(kept) */
@@ -98,11 +111,14 @@ typedef struct {
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
  * near radius, the Gauss spherical grid of L = 2p^2 - p check points on the
- * circumsphere (Sec. 2.2), their partners shifted by one box period along the
- * coordinate that moves them deepest into the sphere, the L x (P-1) fitting
- * matrix A (eq. (8); the constant basis function is dropped, Sec. 3), its
+ * circumsphere (Sec. 2.2) or the caller's points, their partners shifted by one
+ * box period along the coordinate that moves them deepest into the sphere, the
+ * fitting matrix A (eq. (8); for the spherical basis the constant function is
+ * dropped, Sec. 3; for the RBF basis A_lt = K(y_l - x_t) - K(y~_l - x_t)), its
  * pseudo-inverse by Householder QR + one-sided Jacobi SVD with cut-off rcond
- * (eq. (10)), and the box integrals R_t^(0) by tensor Gauss-Legendre (App. B).
+ * (eq. (10)), and the box integrals R_t^(0): tensor Gauss-Legendre for the
+ * spherical basis (App. B), the box-mean potential at each centre for the RBF
+ * basis (App. C).  Host arrays in prm are read during the call only.
  * Uploads these and allocates all device workspace on `device`.
  * prm: host pointer, read during the call only.  *out receives the plan. */
 ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out);

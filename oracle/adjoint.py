@@ -27,7 +27,6 @@ are not part of the derivative.
 import numpy as np
 
 from . import _native
-from .basis import basis
 
 
 def energy_gradients(plan, x, q):
@@ -38,7 +37,7 @@ def energy_gradients(plan, x, q):
     phi = parts["phi"]
     grad = -parts["field"]
     E = 0.5 * float(np.sum(q * phi))
-    u = basis(*(x.T / plan.R0), plan.p)[1:] @ q                     # (P-1,)
+    u = plan.moments(x, q)                                          # (P-1,)
     w = plan.Apinv.T @ u                                            # (L,)
     xs, qs, base, _ = plan.near(x, q)
     src = np.concatenate([x, plan.yt, plan.yc])

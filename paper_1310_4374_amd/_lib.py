@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "_lib", "libperiodic_sum.so")
 PS_OK, PS_E_INVALID, PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX, PS_E_RANK, PS_E_NOMEM, PS_E_HIP, PS_E_UNSUPPORTED = range(8)
 PS_FP64, PS_FP32_ACC64 = 0, 1
 PS_MEAN_ZERO, PS_MEAN_NONE = 0, 1
+PS_BASIS_SPHERICAL, PS_BASIS_RBF = 0, 1
 
 STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID", 2: "PS_E_NOT_NEUTRAL", 3: "PS_E_OUT_OF_BOX", 4: "PS_E_RANK",
                 5: "PS_E_NOMEM", 6: "PS_E_HIP", 7: "PS_E_UNSUPPORTED"}
@@ -29,7 +30,9 @@ class ps_params(ctypes.Structure):
     _fields_ = [("box", ctypes.c_double * 3), ("p", ctypes.c_int32), ("R_b", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("precision", ctypes.c_int32), ("mean", ctypes.c_int32),
                 ("rcond", ctypes.c_double), ("n_max", ctypes.c_int64), ("m_max", ctypes.c_int64),
-                ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32)]
+                ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32), ("basis", ctypes.c_int32),
+                ("n_centres", ctypes.c_int32), ("centres", ctypes.POINTER(ctypes.c_double)),
+                ("n_check", ctypes.c_int32), ("check_points", ctypes.POINTER(ctypes.c_double))]
 
 
 class ps_plan_info(ctypes.Structure):

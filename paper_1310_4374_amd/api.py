@@ -15,8 +15,18 @@ _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
 
 
+def _host_points(a):
+    """(k, 3) float64 C-contiguous host array (kept alive by the caller)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(a.cpu() if hasattr(a, "cpu") else a, dtype=np.float64))
+    if a.ndim != 2 or a.shape[1] != 3:
+        raise ValueError("points must be (k, 3)")
+    return a
+
+
 def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-            tile_targets=0, n_split=0):
+            tile_targets=0, n_split=0, centres=None, check_points=None, keep=None):
+    """keep: a list that receives the host arrays the struct points to."""
     prm = ps_params()
     for k in range(3):
         prm.box[k] = float(box[k])
@@ -30,6 +40,18 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
     prm.m_max = int(m_max)
     prm.tile_targets = int(tile_targets)
     prm.n_split = int(n_split)
+    dp = ctypes.POINTER(ctypes.c_double)
+    if centres is not None:
+        c = _host_points(centres)
+        keep.append(c)
+        prm.basis = _lib.PS_BASIS_RBF
+        prm.n_centres = c.shape[0]
+        prm.centres = c.ctypes.data_as(dp)
+    if check_points is not None:
+        y = _host_points(check_points)
+        keep.append(y)
+        prm.n_check = y.shape[0]
+        prm.check_points = y.ctypes.data_as(dp)
     return prm
 
 
@@ -56,9 +78,14 @@ class Plan:
     """One periodic box: algorithm "set" at construction, "get" on each eval."""
 
     def __init__(self, box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-                 tile_targets=0, n_split=0, device=0):
+                 tile_targets=0, n_split=0, centres=None, check_points=None, device=0):
+        """centres: (M, 3) RBF centres outside the box (eq. (5)); None for the
+        spherical-harmonic basis.  check_points: (L, 3) points on the
+        circumsphere; None for the Gauss spherical grid."""
         self.device = torch.device("cuda", device)
-        self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split)
+        keep = []
+        self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split,
+                            centres, check_points, keep)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan(ctypes.byref(self._prm), int(device), ctypes.byref(h)))
         self._h = h
@@ -190,12 +217,14 @@ class BatchedPlan:
 
     def __init__(self, systems, p, lam=None, R_b=None, precision="fp32", mean="zero", rcond=1e-13, tile_targets=0,
                  n_split=0, device=0):
-        """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam')."""
+        """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam',
+        'centres', 'check_points')."""
         self.device = torch.device("cuda", device)
         arr = (ps_params * len(systems))()
+        keep = []
         for k, s in enumerate(systems):
             arr[k] = _params(s["box"], s.get("p", p), s.get("R_b", R_b), s.get("lam", lam), precision, mean, rcond,
-                             s["n_max"], 0, tile_targets, n_split)
+                             s["n_max"], 0, tile_targets, n_split, s.get("centres"), s.get("check_points"), keep)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan_batched(len(systems), arr, int(device), ctypes.byref(h)))
         self._h = h

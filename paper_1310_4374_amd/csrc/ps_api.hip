@@ -55,10 +55,10 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<CItem> sort_items, far_items;
     std::vector<NItem> near_items;
     std::vector<TItem> t_items;
-    std::vector<PItem> chk_items, p_items;
-    std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs
+    std::vector<PItem> chk_items, p_items, f_items;
+    std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
     std::vector<SysDev> sys;
-    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0;
+    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0;
 };
 
 }  // namespace
@@ -80,6 +80,12 @@ struct ps_plan_s {
     SysDev* d_sys = nullptr;
     double *d_img = nullptr, *d_chk = nullptr, *d_pinv = nullptr, *d_bm = nullptr, *d_rec = nullptr;
     double *d_coef = nullptr, *d_f = nullptr;
+    double* d_cen = nullptr;            // RBF centres, SoA over all systems
+    double* d_cen_bb = nullptr;         // their group bounding boxes
+    double* d_part_far = nullptr;       // RBF far-field partials [4][nt] per system
+    int64_t cen_tot = 0, part_far_cap = 0;
+    bool any_rbf = false;
+    int maxP_sph = 1;                   // largest spherical basis (LDS of the combine kernel)
     // workspace
     int64_t ntot_max = 0, near_tot = 0, cell_tot = 0, tiles_tot = 0, chk_tot = 0, inv_tot = 0;
     double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
@@ -104,7 +110,7 @@ struct ps_plan_s {
     CItem *d_sort_items = nullptr, *d_far_items = nullptr;
     NItem* d_near_items = nullptr;
     TItem* d_t_items = nullptr;
-    PItem *d_chk_items = nullptr, *d_p_items = nullptr;
+    PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
     PJob* d_jobs = nullptr;
     int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0;
     Tables tab;
@@ -120,9 +126,13 @@ struct ps_plan_s {
     PItem* d_adj_p = nullptr;
     PJob* d_adj_job = nullptr;
     int64_t adj_part_cap = 0, adj_tb_cap = 0, adj_p_cap = 0;
-    std::vector<TItem> adj_t;
-    std::vector<PItem> adj_p;
-    PJob adj_job{};
+    std::vector<TItem> adj_t, mom_t;
+    std::vector<PItem> adj_p, mom_p;
+    PJob adj_job{}, mom_job{};
+    PJob* d_mom_job = nullptr;
+    TItem* d_mom_t = nullptr;
+    PItem* d_mom_p = nullptr;
+    double* d_mom_tblk = nullptr;
     // stage timing
     bool prof = false;
     hipEvent_t ev[PS_N_STAGES + 1] = {};
@@ -187,6 +197,10 @@ ps_status check_params(const ps_params* prm)
     if (prm->n_split < 0 || prm->n_split > kMaxSplit) return fail(PS_E_INVALID, "n_split must be in [0, %d]", kMaxSplit);
 
     if (prm->p < 2 || prm->p > 40) return fail(PS_E_INVALID, "p must be in [2, 40]");
+    if (prm->basis != PS_BASIS_SPHERICAL && prm->basis != PS_BASIS_RBF) return fail(PS_E_INVALID, "unknown basis %d", prm->basis);
+    if (prm->basis == PS_BASIS_RBF && (prm->n_centres < 1 || prm->n_centres > 4096 || !prm->centres))
+        return fail(PS_E_INVALID, "the RBF basis needs 1..4096 centres");
+    if (prm->n_check < 0 || (prm->n_check > 0 && !prm->check_points)) return fail(PS_E_INVALID, "bad check-point arguments");
     for (int k = 0; k < 3; ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
     const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + prm->box[2] * prm->box[2]);
@@ -256,7 +270,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     const bool separate = m > 0;
     const int bt = pl->bt;
     // jobs: check sums (FP64, potential) then particle sums
-    T.jobs.resize(2 * nsys);
+    T.jobs.resize(3 * nsys);
     int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
     struct Est { int64_t ntb, nbexp; };
     std::vector<Est> est(nsys);
@@ -363,6 +377,39 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
             for (int sp = 0; sp < Pj.nsplit; ++sp) T.p_items.push_back(PItem{s, static_cast<int>(tb), sp, 0});
         }
     }
+    // RBF far field: the M centres with charges C_2..C_{M+1} against the particle targets
+    int64_t pf_off = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const SysDev& S = T.sys[s];
+        const PJob& Pj = T.jobs[nsys + s];
+        PJob& F = T.jobs[2 * nsys + s];
+        F = PJob{};
+        F.tx = Pj.tx;
+        F.ty = Pj.ty;
+        F.tz = Pj.tz;
+        F.nt = Pj.nt;
+        F.tblk = Pj.tblk;
+        F.bt = Pj.bt;
+        F.ncomp = 4;
+        F.nsplit = 1;
+        if (S.basis == 1) {
+            F.sx = pl->d_cen + S.cen_off;
+            F.sy = pl->d_cen + pl->cen_tot + S.cen_off;
+            F.sz = pl->d_cen + 2 * pl->cen_tot + S.cen_off;
+            F.sq = pl->d_coef + S.coef_off + 1;
+            F.ns_host = S.M;
+            F.tile_bb = pl->d_cen_bb + (S.cen_off / kTile) * (kTile / kGroup) * 6;
+            F.part = pl->d_part_far + pf_off;
+            pf_off += 4 * F.nt;
+            for (int64_t tb = 0; tb < est[s].ntb; ++tb) T.f_items.push_back(PItem{s, static_cast<int>(tb), 0, 0});
+        } else {
+            F.sx = F.sy = F.sz = F.sq = Pj.sx;
+            F.ns_host = 0;
+            F.tile_bb = Pj.tile_bb;
+            F.part = nullptr;
+        }
+    }
+    if (pf_off > pl->part_far_cap) { why = "far-field partial workspace too small"; return false; }
     // far-field/combine chunks of 256 targets
     for (int s = 0; s < nsys; ++s) {
         const int64_t nt = T.jobs[nsys + s].nt;
@@ -375,8 +422,9 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T.nt_items = T.t_items.size();
     T.nchk = T.chk_items.size();
     T.np = T.p_items.size();
+    T.nf = T.f_items.size();
     if (T.nsort > pl->cap_sort || T.nfar > pl->cap_far || T.nnear_items > pl->cap_near_items || T.nt_items > pl->cap_t ||
-        T.nchk > pl->cap_chk || T.np > pl->cap_p) {
+        T.nchk > pl->cap_chk || T.np > pl->cap_p || T.nf > pl->cap_t) {
         why = "item table capacity exceeded";
         return false;
     }
@@ -399,6 +447,7 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     UP(pl->d_t_items, T.t_items)
     UP(pl->d_chk_items, T.chk_items)
     UP(pl->d_p_items, T.p_items)
+    UP(pl->d_f_items, T.f_items)
     UP(pl->d_jobs, T.jobs)
 #undef UP
     return hipStreamSynchronize(st);
@@ -440,7 +489,12 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(6);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
     mark(7);
-    launch_far(T.nfar, pl->maxP, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, pl->d_coef, pl->d_rec,
+    const PJob* fjobs = pl->d_jobs + 2 * nsys;
+    if (pl->any_rbf) {  // step 7 for the RBF basis: sum over the M centres
+        launch_tile_bounds(nsys, 16, fjobs, st);
+        launch_p2p(0, pl->bt, true, T.nf, fjobs, pl->d_f_items, st);
+    }
+    launch_far(T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
                separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
     mark(8);
     if (prof) pl->ev_recorded = true;
@@ -483,7 +537,8 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     std::vector<std::string> errs(nsys);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int s = 0; s < nsys; ++s)
-        errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond);
+        errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
+                                      prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points);
     for (int s = 0; s < nsys; ++s)
         if (!errs[s].empty()) {
             delete pl;
@@ -491,7 +546,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
         }
     // pack offsets
     int64_t img_tot = 0, pinv_tot = 0, coef_tot = 0, rec_tot = 0, f_tot = 0;
-    int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0;
+    int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0, cen_tot = 0, pfar = 0;
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         SysDev& S = pl->base[s];
@@ -510,6 +565,16 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
         S.L = su.L;
         S.nimg = static_cast<int>(su.images.size() / 3);
         S.mean_mode = prm[0].mean;
+        S.basis = su.basis;
+        S.M = su.basis == 1 ? static_cast<int>(su.centres.size() / 3) : 0;
+        S.cen_off = cen_tot;
+        if (su.basis == 1) {
+            cen_tot += (S.M + kTile - 1) / kTile * kTile;
+            pfar += 4 * std::max<int64_t>(prm[s].n_max, nsys == 1 ? prm[0].m_max : 0);
+            pl->any_rbf = true;
+        } else {
+            pl->maxP_sph = std::max(pl->maxP_sph, su.P);
+        }
         choose_grid(su.box, prm[s].n_max, S.g, S.gbits);
         for (int k = 0; k < 3; ++k) S.inv_cell[k] = S.g[k] / su.box[k];
         S.ncell = int64_t(1) << (3 * S.gbits);
@@ -528,7 +593,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
         S.bm_off = coef_tot;
         coef_tot += S.P;
         S.rec_off = rec_tot;
-        rec_tot += 2 * S.P + S.p;
+        rec_tot += su.basis == 1 ? 0 : 2 * S.P + S.p;
         S.f_off = f_tot;
         f_tot += S.L;
         S.inv_off = inv_tot;
@@ -544,8 +609,11 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     pl->chk_tot = chk_tot;
     pl->inv_tot = inv_tot;
     pl->tiles_tot = near_tot / kTile + 1;
+    pl->cen_tot = cen_tot;
+    pl->part_far_cap = pfar;
     // host tables
     std::vector<double> h_img(img_tot * 3), h_chk(chk_tot * 3), h_pinv(pinv_tot), h_bm(coef_tot), h_rec(rec_tot);
+    std::vector<double> h_cen(std::max<int64_t>(1, 3 * cen_tot), 1e3);  // padding: far from every box
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         const SysDev& S = pl->base[s];
@@ -558,9 +626,14 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
             }
         std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
         std::copy(su.box_means.begin(), su.box_means.end(), h_bm.begin() + S.bm_off);
-        std::copy(su.rec.a.begin(), su.rec.a.end(), h_rec.begin() + S.rec_off);
-        std::copy(su.rec.b.begin(), su.rec.b.end(), h_rec.begin() + S.rec_off + S.P);
-        std::copy(su.rec.c.begin(), su.rec.c.end(), h_rec.begin() + S.rec_off + 2 * S.P);
+        if (su.basis == 1) {
+            for (int t = 0; t < S.M; ++t)
+                for (int k = 0; k < 3; ++k) h_cen[k * cen_tot + S.cen_off + t] = su.centres[t * 3 + k];
+        } else {
+            std::copy(su.rec.a.begin(), su.rec.a.end(), h_rec.begin() + S.rec_off);
+            std::copy(su.rec.b.begin(), su.rec.b.end(), h_rec.begin() + S.rec_off + S.P);
+            std::copy(su.rec.c.begin(), su.rec.c.end(), h_rec.begin() + S.rec_off + 2 * S.P);
+        }
     }
     // capacities of the per-shape tables
     int64_t sort_cap = 0, near_items_cap = 0, far_cap = 0, tb_p = 0, tb_c = 0;
@@ -634,7 +707,11 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     AL(pl->d_t_items, pl->cap_t)
     AL(pl->d_chk_items, pl->cap_chk)
     AL(pl->d_p_items, pl->cap_p)
-    AL(pl->d_jobs, 2 * nsys)
+    AL(pl->d_jobs, 3 * nsys)
+    AL(pl->d_f_items, pl->cap_t)
+    AL(pl->d_cen, 3 * std::max<int64_t>(1, cen_tot))
+    AL(pl->d_cen_bb, (cen_tot / kTile + 1) * (kTile / kGroup) * 6)
+    AL(pl->d_part_far, pfar)
 #undef AL
     if (e != hipSuccess) {
         delete pl;
@@ -647,6 +724,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     UPS(pl->d_pinv, h_pinv)
     UPS(pl->d_bm, h_bm)
     UPS(pl->d_rec, h_rec)
+    UPS(pl->d_cen, h_cen)
 #undef UPS
     if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(pl->d_coef, 0, sizeof(double) * coef_tot);
@@ -971,6 +1049,10 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_adj_t, pl->adj_tb_cap)
     AL(pl->d_adj_p, pl->adj_p_cap)
     AL(pl->d_adj_job, 1)
+    AL(pl->d_mom_job, 1)
+    AL(pl->d_mom_t, 4096 / 256 + 1)
+    AL(pl->d_mom_p, (4096 / 256 + 1) * kMomBlocks)
+    AL(pl->d_mom_tblk, (4096 / 256 + 1) * 4)
 #undef AL
     if (e != hipSuccess) return fail(PS_E_NOMEM, "adjoint workspace allocation failed: %s", hipGetErrorString(e));
     pl->adj_ready = true;
@@ -1049,13 +1131,54 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
             pl->adj_t.push_back(TItem{0, static_cast<int>(tb)});
             for (int sp = 0; sp < J.nsplit; ++sp) pl->adj_p.push_back(PItem{0, static_cast<int>(tb), sp, 0});
         }
+        // moments u_t = sum_k q_k R_t(x_k): the basis recurrence (spherical) or the
+        // potential of the particles at the M centres (RBF, a pair sum)
+        PJob& Mj = pl->mom_job;
+        Mj = PJob{};
+        int mom_blocks = kMomBlocks, stride = S.P, toff = 0;
+        if (S.basis == 1) {
+            Mj.tx = pl->d_cen + S.cen_off;
+            Mj.ty = pl->d_cen + pl->cen_tot + S.cen_off;
+            Mj.tz = pl->d_cen + 2 * pl->cen_tot + S.cen_off;
+            Mj.nt = S.M;
+            Mj.sx = pl->d_nx + S.near_off;  // the first n near entries are the sorted particles
+            Mj.sy = pl->d_ny + S.near_off;
+            Mj.sz = pl->d_nz + S.near_off;
+            Mj.sq = pl->d_nq + S.near_off;
+            Mj.ns_host = n;
+            Mj.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * (kTile / kGroup) * 6;
+            Mj.tblk = pl->d_mom_tblk;
+            Mj.part = pl->d_mom;
+            Mj.ncomp = 1;
+            Mj.bt = 256;
+            Mj.nsplit = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMomBlocks, (n + kTile - 1) / kTile)));
+            mom_blocks = Mj.nsplit;
+            stride = S.M;
+            toff = 1;
+            pl->mom_t.clear();
+            pl->mom_p.clear();
+            for (int tb = 0; tb < (S.M + 255) / 256; ++tb) {
+                pl->mom_t.push_back(TItem{0, tb});
+                for (int sp = 0; sp < Mj.nsplit; ++sp) pl->mom_p.push_back(PItem{0, tb, sp, 0});
+            }
+            HIPCHK(hipMemcpyAsync(pl->d_mom_job, &Mj, sizeof(PJob), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(pl->d_mom_t, pl->mom_t.data(), sizeof(TItem) * pl->mom_t.size(), hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(pl->d_mom_p, pl->mom_p.data(), sizeof(PItem) * pl->mom_p.size(), hipMemcpyHostToDevice, st));
+        }
         HIPCHK(hipMemcpyAsync(pl->d_adj_job, &J, sizeof(PJob), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(pl->d_adj_t, pl->adj_t.data(), sizeof(TItem) * pl->adj_t.size(), hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(pl->d_adj_p, pl->adj_p.data(), sizeof(PItem) * pl->adj_p.size(), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
-        launch_adjoint_sources(S.P, S.p, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec,
-                               pl->d_mom, kMomBlocks, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az,
-                               pl->d_aq, st);
+        if (S.basis == 1) {
+            launch_tblock(static_cast<int64_t>(pl->mom_t.size()), pl->d_mom_job, pl->d_mom_t, st);
+            launch_p2p(0, 256, false, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p, st);
+        } else {
+            launch_moments(S.P, S.p, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec, pl->d_mom, kMomBlocks,
+                           st);
+        }
+        launch_adjoint_sources(S.P, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mom, mom_blocks,
+                               stride, toff, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az, pl->d_aq,
+                               st);
         launch_tile_bounds(1, 256, pl->d_adj_job, st);
         launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, static_cast<int64_t>(pl->adj_p.size()),

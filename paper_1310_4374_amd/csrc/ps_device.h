@@ -19,7 +19,9 @@ struct SysDev {
     double R0, inv_R0, thr, V0;
     int g[3], gbits;
     int p, P, L, nimg;
-    int mean_mode, pad0;
+    int mean_mode, basis;        // basis: 0 spherical harmonics, 1 RBF centres
+    int M, pad1;                 // RBF: number of centres (P = M + 1)
+    int64_t cen_off;             // RBF: centres in the packed SoA arrays
     int64_t n_off, n;            // particles in the packed input / sorted arrays
     int64_t cell_off, ncell;     // cell counters (ncell + 1 entries)
     int64_t near_off, near_cap;  // near list

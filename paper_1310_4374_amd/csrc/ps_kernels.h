@@ -24,16 +24,18 @@ void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* c
 void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
                  const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st);
 void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
-                const double* coef, const double* rec, const int* perm, double* phi, double* ex, double* ey,
-                double* ez, double* osort, hipStream_t st);
+                const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
+                double* ey, double* ez, double* osort, hipStream_t st);
 
 }  // namespace ps
 
 namespace ps {
 void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* osort, double* energy, hipStream_t st);
-void launch_adjoint_sources(int P, int p, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
-                            const double* sz, const double* sq, const double* rec, double* mom_part, int mom_blocks,
-                            const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
+void launch_moments(int P, int p, const SysDev* sys, const double* sx, const double* sy, const double* sz,
+                    const double* sq, const double* rec, double* mom_part, int mom_blocks, hipStream_t st);
+void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
+                            const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,
+                            int toff, const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
                             double* az, double* aq, hipStream_t st);
 void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
                            const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,

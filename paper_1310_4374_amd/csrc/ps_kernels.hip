@@ -847,28 +847,34 @@ __device__ void far_field(int p, const double* __restrict__ C, const double* __r
 // One workgroup per chunk of a system's targets: fixed-order sum of the pair
 // partials, far field and constant, store (to the original particle order when
 // perm is given; `osort` keeps a copy in sorted order: phi, ex, ey, ez).
+// Spherical basis: the far field is evaluated here from the coefficients.  RBF
+// basis: it was summed by the far pair job (fjobs), whose partials hold
+// sum_t C_t K(y - x_t) and its field.
 __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
-                                                     const PJob* __restrict__ pjobs, const double* __restrict__ coef,
-                                                     const double* __restrict__ rec, const int* __restrict__ perm,
-                                                     double* __restrict__ phi, double* __restrict__ ex,
-                                                     double* __restrict__ ey, double* __restrict__ ez,
-                                                     double* __restrict__ osort)
+                                                     const PJob* __restrict__ pjobs, const PJob* __restrict__ fjobs,
+                                                     const double* __restrict__ coef, const double* __restrict__ rec,
+                                                     const int* __restrict__ perm, double* __restrict__ phi,
+                                                     double* __restrict__ ex, double* __restrict__ ey,
+                                                     double* __restrict__ ez, double* __restrict__ osort)
 {
     extern __shared__ double lds[];
     const CItem it = items[blockIdx.x];
     const SysDev& S = sys[it.sys];
     const PJob& J = pjobs[it.sys];
     const int P = S.P, p = S.p;
+    const bool rbf = S.basis == 1;
     double* C = lds;
     double* A = lds + P;
     double* B = lds + 2 * P;
     double* Cd = lds + 3 * P;
-    for (int t = threadIdx.x; t < P; t += 256) {
-        C[t] = coef[S.coef_off + t];
-        A[t] = rec[S.rec_off + t];
-        B[t] = rec[S.rec_off + P + t];
+    if (!rbf) {
+        for (int t = threadIdx.x; t < P; t += 256) {
+            C[t] = coef[S.coef_off + t];
+            A[t] = rec[S.rec_off + t];
+            B[t] = rec[S.rec_off + P + t];
+        }
+        for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
     }
-    for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
     __syncthreads();
     const int k = threadIdx.x;
     if (k >= it.count) return;
@@ -881,12 +887,20 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
         fy += P_[2 * J.nt + i];
         fz += P_[3 * J.nt + i];
     }
-    double pf, gx, gy, gz;
-    far_field(p, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy, gz);
-    ph += pf + C[0];
-    fx -= gx * S.inv_R0;
-    fy -= gy * S.inv_R0;
-    fz -= gz * S.inv_R0;
+    if (rbf) {
+        const PJob& F = fjobs[it.sys];
+        ph += F.part[i] + coef[S.coef_off];
+        fx += F.part[F.nt + i];
+        fy += F.part[2 * F.nt + i];
+        fz += F.part[3 * F.nt + i];
+    } else {
+        double pf, gx, gy, gz;
+        far_field(p, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy, gz);
+        ph += pf + C[0];
+        fx -= gx * S.inv_R0;
+        fy -= gy * S.inv_R0;
+        fz -= gz * S.inv_R0;
+    }
     const int64_t o = perm ? S.n_off + perm[S.n_off + i] : S.n_off + i;
     if (phi) phi[o] = ph;
     if (ex) ex[o] = fx;
@@ -983,12 +997,12 @@ void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, co
     PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, nblk, bm, coef);
 }
 void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
-                const double* coef, const double* rec, const int* perm, double* phi, double* ex, double* ey,
-                double* ez, double* osort, hipStream_t st)
+                const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
+                double* ey, double* ez, double* osort, hipStream_t st)
 {
     if (nitems <= 0) return;
     PS_LAUNCH(k_far_combine, dim3((unsigned)nitems), dim3(256), (3 * maxP + maxp) * sizeof(double), st, sys, items,
-              pjobs, coef, rec, perm, phi, ex, ey, ez, osort);
+              pjobs, fjobs, coef, rec, perm, phi, ex, ey, ez, osort);
 }
 
 }  // namespace ps
@@ -1075,8 +1089,9 @@ __global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, 
 
 // u = sum of the moment partials; w = (A^+)^T u; adjoint sources: the sorted
 // particles, then +w_l at the partners y~_l, then -w_l at the check points y_l.
+// (the moment partials hold u_t at part[b * stride + t - toff] for t >= 1)
 __global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ sys, const double* __restrict__ part,
-                                                     int nblk, const double* __restrict__ pinv,
+                                                     int nblk, int stride, int toff, const double* __restrict__ pinv,
                                                      const double* __restrict__ chk, int64_t chk_tot,
                                                      double* __restrict__ ax, double* __restrict__ ay,
                                                      double* __restrict__ az, double* __restrict__ aq)
@@ -1086,7 +1101,8 @@ __global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ 
     const int P = S.P, L = S.L;
     for (int t = threadIdx.x; t < P; t += 256) {
         double s = 0.0;
-        for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * P + t];
+        if (t >= 1)
+            for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * stride + t - toff];
         u[t] = s;
     }
     __syncthreads();
@@ -1188,17 +1204,21 @@ void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* 
 {
     PS_LAUNCH(k_energy, dim3(nsys), dim3(256), 0, st, sys, sq, osort, energy);
 }
-void launch_adjoint_sources(int P, int p, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
-                            const double* sz, const double* sq, const double* rec, double* mom_part, int mom_blocks,
-                            const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
-                            double* az, double* aq, hipStream_t st)
+void launch_moments(int P, int p, const SysDev* sys, const double* sx, const double* sy, const double* sz,
+                    const double* sq, const double* rec, double* mom_part, int mom_blocks, hipStream_t st)
 {
     PS_LAUNCH(k_moment, dim3(mom_blocks), dim3(256), (2 * P + p + 4 * P) * sizeof(double), st, sys, sx, sy, sz, sq,
               rec, mom_part);
+}
+void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
+                            const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,
+                            int toff, const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
+                            double* az, double* aq, hipStream_t st)
+{
     PS_LAUNCH(k_copy4, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, n, sx, sy, sz, sq,
               ax, ay, az, aq);
-    PS_LAUNCH(k_adj_weights, dim3(1), dim3(256), P * sizeof(double), st, sys, mom_part, mom_blocks, pinv, chk, chk_tot,
-              ax, ay, az, aq);
+    PS_LAUNCH(k_adj_weights, dim3(1), dim3(256), P * sizeof(double), st, sys, mom_part, mom_blocks, stride, toff, pinv,
+              chk, chk_tot, ax, ay, az, aq);
 }
 void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
                            const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,

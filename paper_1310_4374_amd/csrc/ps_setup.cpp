@@ -91,6 +91,40 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
 
 namespace {
 
+// Corner term of the prism potential: F(a,b,c) = ab ln(c+r) + bc ln(a+r) + ca ln(b+r)
+// - a^2/2 atan(bc/(ar)) - b^2/2 atan(ca/(br)) - c^2/2 atan(ab/(cr)), with each
+// term zero where its prefactor vanishes and c + r formed stably for c < 0.
+double log_c_plus_r(double c, double r, double s) { return std::log(c >= 0.0 ? c + r : s / (r - c)); }
+
+double prism_corner(double a, double b, double c)
+{
+    const double a2 = a * a, b2 = b * b, c2 = c * c;
+    const double r = std::sqrt(a2 + b2 + c2);
+    if (r == 0.0) return 0.0;
+    double F = 0.0;
+    if (a * b != 0.0) F += a * b * log_c_plus_r(c, r, a2 + b2);
+    if (b * c != 0.0) F += b * c * log_c_plus_r(a, r, b2 + c2);
+    if (c * a != 0.0) F += c * a * log_c_plus_r(b, r, c2 + a2);
+    if (a != 0.0) F -= 0.5 * a2 * std::atan(b * c / (a * r));
+    if (b != 0.0) F -= 0.5 * b2 * std::atan(c * a / (b * r));
+    if (c != 0.0) F -= 0.5 * c2 * std::atan(a * b / (c * r));
+    return F;
+}
+
+}  // namespace
+
+double box_mean_potential(const double box[3], double x, double y, double z)
+{
+    double tot = 0.0;
+    for (int k = 0; k < 8; ++k) {
+        const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
+        tot += sx * sy * sz * prism_corner(sx * 0.5 * box[0] - x, sy * 0.5 * box[1] - y, sz * 0.5 * box[2] - z);
+    }
+    return tot / (box[0] * box[1] * box[2]);
+}
+
+namespace {
+
 // Pseudo-inverse of the L x n matrix A (column-major) by Householder QR
 // followed by a one-sided (Hestenes) Jacobi SVD of the n x n factor R:
 // A = Q R, R = U S V^T, A^+ = V S^+ U^T Q^T with singular values below
@@ -206,8 +240,10 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
 
 }  // namespace
 
-std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond)
+std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond, int basis_,
+                               int n_centres, const double* cen, int n_check, const double* chk)
 {
+    basis = basis_;
     for (int k = 0; k < 3; ++k) {
         if (!(bx[k] > 0.0) || !std::isfinite(bx[k])) return "box lengths must be positive and finite";
         box[k] = bx[k];
@@ -240,23 +276,36 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 if (dmin2 <= thr * (1.0 + 1e-9)) images.insert(images.end(), {i, j, l});
             }
 
-    // step 2: Gauss spherical grid on the circumsphere, L = p (2p - 1)
-    std::vector<double> mu, wq;
-    gauss_legendre(p, mu, wq);
-    const int nphi = 2 * p - 1;
-    L = p * nphi;
-    yc.assign(static_cast<size_t>(L) * 3, 0.0);
-    yt.assign(static_cast<size_t>(L) * 3, 0.0);
-    for (int a = 0; a < p; ++a) {
-        const double st = std::sqrt(1.0 - mu[a] * mu[a]);
-        for (int bph = 0; bph < nphi; ++bph) {
-            const double ph = 2.0 * M_PI * bph / nphi;
-            double* y = &yc[(static_cast<size_t>(a) * nphi + bph) * 3];
-            y[0] = R0 * st * std::cos(ph);
-            y[1] = R0 * st * std::sin(ph);
-            y[2] = R0 * mu[a];
+    // step 2: Gauss spherical grid on the circumsphere, L = p (2p - 1), or the caller's points
+    if (n_check > 0) {
+        if (!chk) return "check_points is NULL";
+        L = n_check;
+        yc.assign(chk, chk + static_cast<size_t>(L) * 3);
+        for (int l = 0; l < L; ++l) {
+            const double* y = &yc[static_cast<size_t>(l) * 3];
+            const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
+            bool outside = false;
+            for (int k = 0; k < 3; ++k) outside = outside || std::fabs(y[k]) > 0.5 * box[k];
+            if (!(r2 <= R0 * R0 * (1.0 + 1e-9)) || !outside) return "a check point is outside S0 or inside the box";
+        }
+    } else {
+        std::vector<double> mu, wq;
+        gauss_legendre(p, mu, wq);
+        const int nphi = 2 * p - 1;
+        L = p * nphi;
+        yc.assign(static_cast<size_t>(L) * 3, 0.0);
+        for (int a = 0; a < p; ++a) {
+            const double st = std::sqrt(1.0 - mu[a] * mu[a]);
+            for (int bph = 0; bph < nphi; ++bph) {
+                const double ph = 2.0 * M_PI * bph / nphi;
+                double* y = &yc[(static_cast<size_t>(a) * nphi + bph) * 3];
+                y[0] = R0 * st * std::cos(ph);
+                y[1] = R0 * st * std::sin(ph);
+                y[2] = R0 * mu[a];
+            }
         }
     }
+    yt.assign(static_cast<size_t>(L) * 3, 0.0);
     // step 3: partner = one coordinate shifted by its period, the coordinate that
     // brings the point deepest into S0 (largest d_k (2|y_k| - d_k)), towards the centre
     for (int l = 0; l < L; ++l) {
@@ -271,21 +320,50 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
         for (int k = 0; k < 3; ++k) t[k] = y[k];
         t[kb] = y[kb] - (y[kb] > 0 ? 1.0 : (y[kb] < 0 ? -1.0 : 0.0)) * box[kb];
     }
-    // step 4: A_lt = R_t(y_l/R0) - R_t(y~_l/R0), t = 2..P  (column-major L x (P-1))
+    // step 4: A_lt = R_t(y_l) - R_t(y~_l) for the basis functions t = 2..P (column-major L x (P-1))
     rec.build(p);
+    if (basis == 1) {
+        if (n_centres < 1 || n_centres > 4096 || !cen) return "RBF basis needs 1..4096 centres";
+        centres.assign(cen, cen + static_cast<size_t>(n_centres) * 3);
+        for (int t = 0; t < n_centres; ++t) {
+            const double* c = &centres[static_cast<size_t>(t) * 3];
+            if (!(c[0] * c[0] + c[1] * c[1] + c[2] * c[2] > R0 * R0 * (1.0 + 1e-9))) return "an RBF centre lies inside S0";
+        }
+        P = n_centres + 1;
+    }
     const int n = P - 1;
-    std::vector<double> A(static_cast<size_t>(L) * n), r1(P), r2(P);
+    std::vector<double> A(static_cast<size_t>(L) * n), r1(std::max(P, p * p)), r2(std::max(P, p * p));
     for (int l = 0; l < L; ++l) {
         const double* y = &yc[static_cast<size_t>(l) * 3];
         const double* t = &yt[static_cast<size_t>(l) * 3];
-        rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
-        rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
-        for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * L + l] = r1[j + 1] - r2[j + 1];
+        if (basis == 1) {
+            for (int j = 0; j < n; ++j) {
+                const double* c = &centres[static_cast<size_t>(j) * 3];
+                const double a0 = y[0] - c[0], a1 = y[1] - c[1], a2 = y[2] - c[2];
+                const double b0 = t[0] - c[0], b1 = t[1] - c[1], b2 = t[2] - c[2];
+                A[static_cast<size_t>(j) * L + l] =
+                    1.0 / std::sqrt(a0 * a0 + a1 * a1 + a2 * a2) - 1.0 / std::sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+            }
+        } else {
+            rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
+            rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * L + l] = r1[j + 1] - r2[j + 1];
+        }
     }
     // step 5: decomposition -> pseudo-inverse
     pseudo_inverse(L, n, std::move(A), rcond, pinv, rank, cond);
     if (rank < 1) return "fitting matrix has numerical rank zero";
-    // step 6: box integrals of the basis (App. B), N_q = floor((p-1)/2) + 1 nodes per axis
+    // step 6: box integrals of the basis: the box-mean potential at each RBF centre
+    // (App. C), or tensor Gauss-Legendre with N_q = floor((p-1)/2) + 1 nodes (App. B)
+    if (basis == 1) {
+        box_means.assign(P, 0.0);
+        box_means[0] = 1.0;
+        for (int t = 1; t < P; ++t) {
+            const double* c = &centres[static_cast<size_t>(t - 1) * 3];
+            box_means[t] = box_mean_potential(box, c[0], c[1], c[2]);
+        }
+        return std::string();
+    }
     const int nq = (p - 1) / 2 + 1;
     std::vector<double> xg, wg;
     gauss_legendre(nq, xg, wg);

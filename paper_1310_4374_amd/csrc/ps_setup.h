@@ -25,8 +25,14 @@ struct Recurrence {
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
+// Mean of 1/|y - x| over the box [-d/2, d/2]^3 (divided by its volume): the
+// closed-form potential of a uniform rectangular prism, summed over corners.
+double box_mean_potential(const double box[3], double x, double y, double z);
+
 struct SystemSetup {
     double box[3] = {0, 0, 0};
+    int basis = 0;                     // 0 spherical, 1 RBF
+    std::vector<double> centres;       // RBF: [M*3]
     double R0 = 0, R_b = 0, thr = 0, V0 = 0;
     int p = 0, P = 0, L = 0;
     int rank = 0;
@@ -37,7 +43,9 @@ struct SystemSetup {
     std::vector<int> images;           // [nimg*3] lattice integers, (0,0,0) first
     Recurrence rec;
     // Returns an empty string on success, or the reason for failure.
-    std::string build(const double box[3], int p, double R_b, double lambda, double rcond);
+    std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
+                      int n_centres = 0, const double* centres = nullptr, int n_check = 0,
+                      const double* check_points = nullptr);
 };
 
 }  // namespace ps

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     """The ctypes mirror of ps_params has the C layout (no torch types cross)."""
-    assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4
+    assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8
     assert _lib.ps_params.n_max.offset == 64
 
 
@@ -51,7 +51,8 @@ def _params(**kw):
 
 
 @pytest.mark.parametrize("kw", [dict(p=1), dict(p=41), dict(n_max=0), dict(precision=7), dict(mean=3),
-                                dict(tile_targets=100), dict(n_split=-1), dict(m_max=-5)])
+                                dict(tile_targets=100), dict(n_split=-1), dict(m_max=-5), dict(basis=2),
+                                dict(basis=1, n_centres=0), dict(basis=1, n_centres=10), dict(n_check=5)])
 def test_invalid_parameters_rejected_on_host(kw):
     L = _lib.lib()
     h = ctypes.c_void_p()

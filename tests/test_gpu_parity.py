@@ -378,3 +378,87 @@ def test_autotuned_batch_still_matches_oracle(ps):
         assert nb[k] == parts["n_near"]
         assert _rel(phi[sl], parts["phi"]) <= 1e-6
         assert _rel(field[sl], parts["field"]) <= 1e-6
+
+
+# --------------------------------------------------------------------------
+# RBF basis (eq. (5)) and caller-given check points
+# --------------------------------------------------------------------------
+# The RBF fitting matrix is far less well conditioned (cond(A) ~ 1e6 for 256
+# centres at p = 16) than the renormalized spherical basis (~10).  Two correct
+# FP64 pseudo-inverses may then differ by up to ~cond(A) x 1e-16 in the
+# coefficients; the potentials at the particles agree much better (measured
+# 1.3e-13), and the FP64 bar for this variant is set at 1e-11.
+TOL_RBF = {"fp64": 1e-11, "fp32": 1e-6}
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_rbf_basis_matches_oracle(ps, prec):
+    c = W.config1()
+    cen = W.fibonacci_sphere(256, 1.5)
+    op = OPlan(c["box"], 16, R_b=1.5, basis="rbf", centres=cen)
+    ref = op.solve(c["x"], c["q"], return_parts=True)
+    pl = ps.Plan(c["box"], 16, R_b=1.5, precision=prec, n_max=1000, centres=cen)
+    phi, field = pl.eval(_dev(c["x"].T), _dev(c["q"]))
+    pl.status()
+    e1, e2 = _rel(phi.cpu().numpy(), ref["phi"]), _rel(field.cpu().numpy().T, ref["field"])
+    print(prec, "rbf rel-L2 phi %.3e field %.3e cond %.3e" % (e1, e2, op.cond))
+    assert e1 <= TOL_RBF[prec] and e2 <= TOL_RBF[prec]
+    inf = pl.info()
+    assert inf["P"] == 257 and inf["rank"] == op.rank
+    _, _, pinv, bm = (t.numpy() for t in pl.tables())
+    np.testing.assert_allclose(bm, op.R0mean, rtol=1e-13)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_random_check_points_match_oracle(ps, prec):
+    box = (1.0, 1.2, 0.9)
+    R0 = 0.5 * np.linalg.norm(box)
+    yc = W.random_sphere(3 * 12 * 12, R0, seed=7)
+    x, q = W.uniform_box(900, box, charges="gauss", seed=77)
+    ref = OPlan(box, 12, lam=1.6, check_points=yc).solve(x, q)
+    pl = ps.Plan(box, 12, lam=1.6, precision=prec, n_max=900, check_points=yc)
+    phi, field = pl.eval(_dev(x.T), _dev(q))
+    pl.status()
+    assert pl.info()["L"] == 432
+    assert _rel(phi.cpu().numpy(), ref[0]) <= TOL[prec]
+    assert _rel(field.cpu().numpy().T, ref[1]) <= TOL[prec]
+
+
+def test_rbf_energy_adjoint_matches_oracle(ps):
+    box = (1.0, 1.0, 1.0)
+    x, q = W.uniform_box(500, box, charges="gauss", seed=5)
+    cen = W.fibonacci_sphere(120, 1.5)
+    op = OPlan(box, 10, R_b=1.5, basis="rbf", centres=cen)
+    E, dx, dq, _ = energy_gradients(op, x, q)
+    pl = ps.Plan(box, 10, R_b=1.5, n_max=500, centres=cen)
+    xt, qt = _dev(x.T), _dev(q)
+    e = pl.energy(xt, qt)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(xt, qt, one, exact=True)
+    assert abs(float(e.cpu()[0]) - E) <= 1e-9 * abs(E)
+    assert _rel(gx.cpu().numpy().T, dx) <= 1e-9
+    assert _rel(gq.cpu().numpy(), dq) <= 1e-9
+
+
+def test_batched_mixed_bases(ps):
+    """One batch holding a spherical-basis box and an RBF-basis box."""
+    g = np.random.default_rng(3)
+    boxes = [np.array([1.0, 1.3, 1.1]), np.array([1.2, 1.0, 1.0])]
+    xs, qs = [], []
+    for k, b in enumerate(boxes):
+        x, q = W.uniform_box(700 + 300 * k, b, charges="gauss", seed=300 + k)
+        xs.append(x)
+        qs.append(q)
+    lam = 1.7
+    R0 = [0.5 * np.linalg.norm(b) for b in boxes]
+    cen = W.fibonacci_sphere(200, lam * R0[1])
+    systems = [dict(box=boxes[0], n_max=len(qs[0])), dict(box=boxes[1], n_max=len(qs[1]), centres=cen)]
+    bp = ps.BatchedPlan(systems, p=12, lam=lam, precision="fp64")
+    off = np.concatenate([[0], np.cumsum([len(q) for q in qs])])
+    phi, field = bp.eval(_dev(np.concatenate(xs).T), _dev(np.concatenate(qs)), off)
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    r0 = OPlan(boxes[0], 12, lam=lam).solve(xs[0], qs[0])
+    r1 = OPlan(boxes[1], 12, lam=lam, basis="rbf", centres=cen).solve(xs[1], qs[1])
+    assert _rel(phi[off[0]:off[1]], r0[0]) <= 1e-12 and _rel(field[off[0]:off[1]], r0[1]) <= 1e-12
+    assert _rel(phi[off[1]:off[2]], r1[0]) <= 1e-9 and _rel(field[off[1]:off[2]], r1[1]) <= 1e-9

@@ -59,3 +59,27 @@ def test_exact_and_physical_gradients_agree_to_method_error():
     px, pq = physics_gradients(pl, x, q)
     assert np.linalg.norm(dx - px) / np.linalg.norm(dx) < 1e-5
     assert np.linalg.norm(dq - pq) / np.linalg.norm(dq) < 1e-5
+
+
+def test_rbf_adjoint_matches_finite_differences():
+    import workloads
+    box = (1.0, 1.0, 1.0)
+    x, q = W.uniform_box(30, box, charges="gauss", seed=41)
+    pl = Plan(box, 10, R_b=1.5, basis="rbf", centres=workloads.fibonacci_sphere(100, 1.5))
+    _, dEdx, dEdq, _ = energy_gradients(pl, x, q)
+    h = 1e-5
+    for i in _safe_particles(pl, x, 3):
+        for k in range(3):
+            xp = x.copy()
+            xp[i, k] += h
+            xm = x.copy()
+            xm[i, k] -= h
+            fd = (energy(pl, xp, q) - energy(pl, xm, q)) / (2 * h)
+            assert abs(dEdx[i, k] - fd) < 1e-6 * max(1.0, abs(fd))
+    qp, qm = q.copy(), q.copy()
+    qp[0] += h
+    qp[1] -= h
+    qm[0] -= h
+    qm[1] += h
+    fd = (energy(pl, x, qp) - energy(pl, x, qm)) / (2 * h)
+    assert abs((dEdq[0] - dEdq[1]) - fd) < 1e-7 * max(1.0, abs(fd))

@@ -141,3 +141,53 @@ def test_rocksalt_lattice_madelung():
     phi, E = Plan(r["box"], 20, R_b=1.5).solve(r["x"], r["q"])
     assert np.max(np.abs(phi * r["spacing"] / (-r["q"] * MADELUNG_NACL) - 1)) < 5e-7
     assert np.abs(E).max() * r["spacing"] ** 2 < 2e-6
+
+
+def test_random_check_points_table1_order_of_magnitude():
+    """Table 1, random columns (lambda = sqrt 3): the largest error over a few
+    random sets is of the order of the paper's maximum over 100 sets."""
+    GOLD_R = GOLD["table1_random"]["eps_M"]
+    c = W.nacl_cell()
+    for p, col, f in [(12, 1, 3), (16, 1, 3), (12, 2, 5)]:
+        errs = []
+        for seed in range(3):
+            yc = W.random_sphere(f * p * p, np.sqrt(3) / 2, seed)
+            phi, _ = Plan(c["box"], p, R_b=1.5, check_points=yc).solve(c["x"], c["q"])
+            errs.append(np.max(np.abs(phi * 0.5 / (-c["q"] * MADELUNG_NACL) - 1)))
+        ref = GOLD_R[str(p)][col]
+        assert ref / 10 < max(errs) < ref * 10
+
+
+def test_rbf_basis_madelung_and_ewald():
+    """Sec. 4.1, RBF basis (eq. (5)) with 256 sources on the sphere S_b: eps_M of
+    the order of the paper's 1.32e-7 (Fibonacci-lattice sources stand in for the
+    Thomson points); random charges match Ewald to the method's accuracy."""
+    ref = GOLD["rbf_basis"]
+    c = W.nacl_cell()
+    cen = W.fibonacci_sphere(ref["M"], 1.5)
+    pl = Plan(c["box"], ref["p"], R_b=1.5, basis="rbf", centres=cen)
+    phi, E = pl.solve(c["x"], c["q"])
+    e = np.max(np.abs(phi * 0.5 / (-c["q"] * MADELUNG_NACL) - 1))
+    assert ref["eps_M"] / 10 < e < ref["eps_M"] * 10
+    assert pl.rank == ref["M"]
+    box = (1.0, 1.2, 0.9)
+    x, q = W.uniform_box(120, box, charges="gauss", seed=31)
+    R0 = 0.5 * np.linalg.norm(box)
+    pl = Plan(box, 16, lam=np.sqrt(3), basis="rbf", centres=W.fibonacci_sphere(256, np.sqrt(3) * R0))
+    a = pl.solve(x, q)
+    b = Ewald(box).solve(x, q)
+    assert _rel(a[0], b[0]) < 3e-5 and _rel(a[1], b[1]) < 3e-5
+
+
+def test_rbf_box_means_are_phi0_at_centres():
+    """For the RBF basis the box integral of R_t is Phi0 at the centre (App. C,
+    as Sec. 3.4 notes): check one against direct quadrature."""
+    box = (1.0, 1.0, 1.0)
+    cen = W.fibonacci_sphere(8, 1.5)
+    pl = Plan(box, 6, R_b=1.5, basis="rbf", centres=cen)
+    g, w = np.polynomial.legendre.leggauss(20)
+    X, Y, Z = np.meshgrid(g / 2, g / 2, g / 2, indexing="ij")
+    Wt = (w[:, None, None] * w[None, :, None] * w[None, None, :]) / 8
+    for t in range(3):
+        r = np.sqrt((X - cen[t, 0]) ** 2 + (Y - cen[t, 1]) ** 2 + (Z - cen[t, 2]) ** 2)
+        assert abs(pl.R0mean[1 + t] - np.sum(Wt / r)) < 1e-12

@@ -130,3 +130,21 @@ def nacl_cell(d=1.0):
     x = s * (d / 4.0)
     q = s[:, 0] * s[:, 1] * s[:, 2]
     return dict(box=np.array([d, d, d]), x=x, q=q)
+
+
+def fibonacci_sphere(m, radius):
+    """m nearly uniform points on a sphere (spherical Fibonacci lattice):
+    z_t = 1 - (2t + 1)/m, azimuth t * pi (3 - sqrt 5).  A deterministic stand-in
+    for the Thomson points, whose database is not available."""
+    t = np.arange(m, dtype=np.float64)
+    z = 1.0 - (2.0 * t + 1.0) / m
+    ph = t * np.pi * (3.0 - np.sqrt(5.0))
+    r = np.sqrt(1.0 - z * z)
+    return np.ascontiguousarray(radius * np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1))
+
+
+def random_sphere(m, radius, seed):
+    """m points uniform on a sphere (seeded), for random check-point sets."""
+    g = np.random.Generator(np.random.PCG64(seed))
+    v = g.standard_normal((m, 3))
+    return np.ascontiguousarray(radius * v / np.linalg.norm(v, axis=1)[:, None])
