@@ -480,6 +480,7 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                                             double& aY, double& aZ)
 {
     float fX = 0.f, fY = 0.f, fZ = 0.f;
+    float p32 = 0.f;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         float qv[8];
@@ -510,13 +511,24 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                 fZ = __builtin_fmaf(qr3, dz, fZ);
             }
         }
-        aP += (double)(((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7])));
+        p32 += ((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7]));
     }
+    aP += (double)p32;
     if (FIELD) {
         aX += (double)fX;
         aY += (double)fY;
         aZ += (double)fZ;
     }
+}
+
+// Near/far decisions of the kTile/kGroup groups of a staged tile, made once per
+// tile by one lane per group and shared through a ballot, so that the group
+// branch is wave-uniform.
+__device__ __forceinline__ uint64_t far_group_mask(const double* bb, double cx, double cy, double cz, double far2)
+{
+    const int lane = threadIdx.x & 63;
+    const bool far = lane < kTile / kGroup && tile_is_far(bb + (lane & (kTile / kGroup - 1)) * 6, cx, cy, cz, far2);
+    return __ballot(far);
 }
 
 template <int BT, bool FIELD>
@@ -556,10 +568,10 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
             sB[k] = b;
         }
         __syncthreads();
-        const double* bb = J.tile_bb + t * (kTile / kGroup) * 6;
+        const uint64_t farm = far_group_mask(J.tile_bb + t * (kTile / kGroup) * 6, cx, cy, cz, far2);
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
-            if (tile_is_far(bb + gq * 6, cx, cy, cz, far2))
+            if ((farm >> gq) & 1)
                 group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
             else
                 group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
@@ -644,10 +656,10 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
             sS[k] = s;
         }
         __syncthreads();
-        const double* bb = J.tile_bb + t * (kTile / kGroup) * 6;
+        const uint64_t farm = far_group_mask(J.tile_bb + t * (kTile / kGroup) * 6, cx, cy, cz, far2);
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
-            if (tile_is_far(bb + gq * 6, cx, cy, cz, far2))
+            if ((farm >> gq) & 1)
                 group32_f64<false, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);
             else
                 group32_f64<true, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);

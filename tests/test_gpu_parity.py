@@ -255,6 +255,53 @@ def test_batched_matches_oracle_and_single(ps, prec):
         assert _rel(field[sl], ref[1]) <= TOL[prec]
 
 
+def test_batched_graph_replays_with_eager_work_between(ps):
+    """The batched path replays one captured graph while the caller's buffers
+    stay put; new particle data written into those buffers between replays,
+    with unrelated eager work and synchronizations in between, must give that
+    data's sums on every replay (each replay checked against the oracle)."""
+    g = np.random.default_rng(17)
+    boxes = [g.uniform(1.0, 2.0, size=3) for _ in range(3)]
+    ns = [700, 260, 1100]
+    systems = [dict(box=b, n_max=n) for b, n in zip(boxes, ns)]
+    off = np.concatenate([[0], np.cumsum(ns)])
+    lam = float(np.sqrt(3))
+    bp = ps.BatchedPlan(systems, p=10, lam=lam, precision="fp64")
+    X = torch.empty(3, off[-1], dtype=torch.float64, device="cuda:0")
+    Q = torch.empty(off[-1], dtype=torch.float64, device="cuda:0")
+    phi = torch.empty(off[-1], dtype=torch.float64, device="cuda:0")
+    field = torch.empty(3, off[-1], dtype=torch.float64, device="cuda:0")
+    single = ps.Plan(boxes[0], 10, lam=lam, precision="fp64", n_max=ns[0])
+    first = None
+    for rep in range(4):
+        data = [W.uniform_box(n, b, charges="gauss", seed=300 + 10 * rep + k) for k, (n, b) in enumerate(zip(ns, boxes))]
+        X.copy_(_dev(np.concatenate([d[0] for d in data]).T))
+        Q.copy_(_dev(np.concatenate([d[1] for d in data])))
+        bp.eval(X, Q, off, out=(phi, field))
+        torch.cuda.synchronize()
+        # eager work between replays: a single-box solve and a torch reduction
+        sp, _ = single.eval(_dev(data[0][0].T), _dev(data[0][1]))
+        junk = torch.randn(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        bp.status()
+        ph, fl = phi.cpu().numpy(), field.cpu().numpy().T
+        assert np.isfinite(float(junk))
+        assert _rel(ph[off[0]:off[1]], sp.cpu().numpy()) <= 1e-13
+        for k in range(3):
+            sl = slice(off[k], off[k + 1])
+            ref = OPlan(boxes[k], 10, lam=lam).solve(data[k][0], data[k][1])
+            assert _rel(ph[sl], ref[0]) <= TOL["fp64"], (rep, k)
+            assert _rel(fl[sl], ref[1]) <= TOL["fp64"], (rep, k)
+        if first is None:
+            first = (data, ph.copy())
+    # replaying the first data again reproduces the first replay bit for bit
+    data, ph0 = first
+    X.copy_(_dev(np.concatenate([d[0] for d in data]).T))
+    Q.copy_(_dev(np.concatenate([d[1] for d in data])))
+    bp.eval(X, Q, off, out=(phi, field))
+    assert np.array_equal(phi.cpu().numpy(), ph0)
+
+
 # --------------------------------------------------------------------------
 # full-size workloads: sampled particles against stored oracle values
 # (tests/golden/make_reference.py, oracle only)
