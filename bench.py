@@ -22,12 +22,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Peaks of the ALU-bound pair kernel.  The published FP32 vector figure (157.3
-# TFLOP/s) counts packed FP32 (two lanes' worth of FMA per instruction); packed
-# FP32 is not used by these kernels, so their ceiling from the unit counts is
-# 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz = 78.6 TFLOP/s.
-FP32_PUBLISHED_TFLOPS = 157.3
-FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# Peaks of the ALU-bound pair kernel: MI355X's published FP32 and FP64 vector
+# figures.  On gfx950 non-packed FP32 instructions with VGPR operands issue at
+# up to 32 lanes per clock per SIMD (two cycles per 64-lane instruction), which
+# is the 157.3 TFLOP/s rate (256 CUs x 4 SIMDs x 32 lanes x 2 flop x 2.4 GHz);
+# the valu_rate executable built beside the library measures it.
+FP32_TFLOPS = 157.3
 FP64_TFLOPS = 78.6
 FLOP_PER_PAIR = 20         # potential + field: 3 sub, r^2 (mul + 2 FMA), rsqrt, 3 mul, add, 3 FMA
 
@@ -171,12 +171,10 @@ def main():
         stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
         t_pairs = stage_ms["pairs"] * 1e-3
         achieved = FLOP_PER_PAIR * n * nb / t_pairs / 1e12
-        peak = FP32_NONPACKED_TFLOPS if args.precision == "fp32" else FP64_TFLOPS
+        peak = FP32_TFLOPS if args.precision == "fp32" else FP64_TFLOPS
         roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                 "frac": achieved / peak, "traffic": measured_traffic(args.precision),
-                "peak_basis": ("non-packed FP32 VALU: 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz"
-                               if args.precision == "fp32" else "FP64 vector, published"),
-                "frac_of_published_fp32_157_3": achieved / FP32_PUBLISHED_TFLOPS,
+                "peak_basis": "published %s vector peak" % ("FP32" if args.precision == "fp32" else "FP64"),
                 "kernel": "k_p2p_%s<%d,field> (particle near sums)" % ("f32" if args.precision == "fp32" else "f64",
                                                                     info["tile_targets"]),
                 "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,

@@ -7,10 +7,13 @@ namespace ps {
 constexpr int kTile = 256;         // sources staged per LDS tile
 constexpr int kGroup = 32;         // sources per near/far decision (one bounding box each)
 // A group is "far" for a target block of radius rT (about its centre c) when
-// its bounding box is farther than kFarFactor * rT from c.  In FP32 the
-// coordinate rounding error of a far pair relative to its separation is then
-// at most u (1 + 2/(kFarFactor - 1)), u = 2^-24.
-constexpr double kFarFactor = 2.0;
+// its bounding box is farther than kFarFactor * rT from c (FP32 kernel).  A far
+// pair is then more than (kFarFactor - 1) rT apart, and the sum of the two
+// points' distances from c is at most (kFarFactor + 1)/(kFarFactor - 1) times
+// their separation.  That ratio (5 at 1.5) bounds the one-float coordinate
+// error relative to the separation, and its square the cancellation in the
+// expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the FP32 rounding.
+constexpr double kFarFactor = 1.5;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.

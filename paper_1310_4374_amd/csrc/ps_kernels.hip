@@ -438,15 +438,16 @@ __global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, c
 // ----------------------------------------------------------------------------
 // A workgroup owns BT consecutive targets (one per lane) and one split of the
 // source tiles.  Sources are staged kTile at a time in LDS and read as
-// broadcasts.  A tile whose bounding box is farther than 4 x (target-block
-// radius) from the block centre is "far": it cannot hold a source coinciding
-// with a target, so its loop has no K(0) = 0 test; other tiles are "near" and
-// apply K(0) = 0.  Accumulation (FP32 kernel): the potential of every 8 pairs
-// is summed as a balanced FP32 tree and added to an FP64 accumulator; the field
-// runs in FP32 chains flushed to FP64 every 32 pairs.  (A serial FP32 sum over a
-// whole tile would add an error growing like sqrt(tile) times the per-pair
-// rounding.)  The FP64 kernel accumulates every pair in FP64.  Splits are
-// combined later in a fixed order.
+// broadcasts.  Each group of kGroup sources of a tile carries a bounding box;
+// a group farther than kFarFactor x (target-block radius) from the block
+// centre is "far": it cannot hold a source coinciding with a target, so its
+// loop has no K(0) = 0 test; other groups are "near" and apply K(0) = 0.
+// Accumulation (FP32 kernel): the potential of every 8 pairs is summed as a
+// balanced FP32 tree, four such sums are added in FP32 and the result goes to
+// an FP64 accumulator; the field runs in FP32 chains flushed to FP64 every 32
+// pairs.  (A serial FP32 sum over a whole tile would add an error growing like
+// sqrt(tile) times the per-pair rounding.)  The FP64 kernel accumulates every
+// pair in FP64.  Splits are combined later in a fixed order.
 struct SourceSplit {
     int64_t ns, t0, t1;
 };
@@ -470,16 +471,23 @@ __device__ __forceinline__ bool tile_is_far(const double* bb, double cx, double 
 }
 
 // FP32 pair arithmetic on coordinates relative to the target-block centre.
-// Far groups: one-float relative coordinates (their rounding error is a fixed
-// fraction of the pair distance there).  Near groups: two-float (hi + lo)
-// relative coordinates, d = (t_hi - s_hi) + (t_lo - s_lo), so close pairs keep
-// their full FP64-derived separation, and K(0) = 0 is applied.
+// LDS holds, per source, A = (-2 s_hi, q) and B = (s_lo, |s_hi|^2), where
+// s_hi + s_lo is the FP64 relative position split into two floats.
+// Near groups: d = (t_hi - s_hi) + (t_lo - s_lo), so close pairs keep their
+// full FP64-derived separation, and K(0) = 0 is applied.
+// Far groups: one-float coordinates and the expanded form
+// r^2 = |t|^2 + |s|^2 - 2 t.s (an add and three FMAs instead of three
+// differences, a product and two FMAs); the field sum over the group,
+// sum_j w_j (t - s_j) with w_j = q_j / r_j^3, is formed as
+// t * sum_j w_j + (1/2) sum_j w_j (-2 s_j) in FP64 at the flush.  Far pairs
+// are at least (kFarFactor - 1) x (block radius) apart, so the cancellation
+// in the expanded r^2 stays a bounded multiple of the FP32 rounding.
 template <bool NEAR, bool FIELD>
 __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
-                                            float hy, float hz, float lx, float ly, float lz, double& aP, double& aX,
-                                            double& aY, double& aZ)
+                                            float hy, float hz, float lx, float ly, float lz, float tt, double& aP,
+                                            double& aX, double& aY, double& aZ)
 {
-    float fX = 0.f, fY = 0.f, fZ = 0.f;
+    float fX = 0.f, fY = 0.f, fZ = 0.f, fW = 0.f;
     float p32 = 0.f;
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
@@ -487,37 +495,52 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const float4 s = sA[g * 8 + u];
-            float dx, dy, dz;
+            float dx = 0.f, dy = 0.f, dz = 0.f, r2;
             if (NEAR) {
                 const float4 l = sB[g * 8 + u];
-                dx = (hx - s.x) + (lx - l.x);
-                dy = (hy - s.y) + (ly - l.y);
-                dz = (hz - s.z) + (lz - l.z);
+                dx = __builtin_fmaf(0.5f, s.x, hx) + (lx - l.x);
+                dy = __builtin_fmaf(0.5f, s.y, hy) + (ly - l.y);
+                dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
+                r2 = dx * dx;
+                r2 = __builtin_fmaf(dy, dy, r2);
+                r2 = __builtin_fmaf(dz, dz, r2);
             } else {
-                dx = hx - s.x;
-                dy = hy - s.y;
-                dz = hz - s.z;
+                r2 = tt + sB[g * 8 + u].w;
+                r2 = __builtin_fmaf(hx, s.x, r2);
+                r2 = __builtin_fmaf(hy, s.y, r2);
+                r2 = __builtin_fmaf(hz, s.z, r2);
             }
-            float r2 = dx * dx;
-            r2 = __builtin_fmaf(dy, dy, r2);
-            r2 = __builtin_fmaf(dz, dz, r2);
             float ri = __builtin_amdgcn_rsqf(r2);
             if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
             qv[u] = s.w * ri;
             if (FIELD) {
                 const float qr3 = qv[u] * (ri * ri);
-                fX = __builtin_fmaf(qr3, dx, fX);
-                fY = __builtin_fmaf(qr3, dy, fY);
-                fZ = __builtin_fmaf(qr3, dz, fZ);
+                if (NEAR) {
+                    fX = __builtin_fmaf(qr3, dx, fX);
+                    fY = __builtin_fmaf(qr3, dy, fY);
+                    fZ = __builtin_fmaf(qr3, dz, fZ);
+                } else {
+                    fW += qr3;
+                    fX = __builtin_fmaf(qr3, s.x, fX);
+                    fY = __builtin_fmaf(qr3, s.y, fY);
+                    fZ = __builtin_fmaf(qr3, s.z, fZ);
+                }
             }
         }
         p32 += ((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7]));
     }
     aP += (double)p32;
     if (FIELD) {
-        aX += (double)fX;
-        aY += (double)fY;
-        aZ += (double)fZ;
+        if (NEAR) {
+            aX += (double)fX;
+            aY += (double)fY;
+            aZ += (double)fZ;
+        } else {
+            const double w = (double)fW;
+            aX += __builtin_fma((double)hx, w, 0.5 * (double)fX);
+            aY += __builtin_fma((double)hy, w, 0.5 * (double)fY);
+            aZ += __builtin_fma((double)hz, w, 0.5 * (double)fZ);
+        }
     }
 }
 
@@ -552,17 +575,21 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     }
     const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
+    const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
     double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
     for (int64_t t = sp.t0; t < sp.t1; ++t) {
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
             const int64_t j = t * kTile + k;
-            float4 a = make_float4(4096.f, 4096.f, 4096.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0.f);
+            // padding: a source of charge 0 at (2^60, 0, 0) from the centre, which
+            // coincides with no target and keeps r^2 finite in FP32
+            float4 a = make_float4(-0x1p61f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0x1p120f);
             if (j < sp.ns) {
                 const double ux = J.sx[j] - cx, uy = J.sy[j] - cy, uz = J.sz[j] - cz;
                 const float ax = (float)ux, ay = (float)uy, az = (float)uz;
-                a = make_float4(ax, ay, az, (float)J.sq[j]);
-                b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az), 0.f);
+                a = make_float4(-2.f * ax, -2.f * ay, -2.f * az, (float)J.sq[j]);
+                b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az),
+                                __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
             }
             sA[k] = a;
             sB[k] = b;
@@ -572,9 +599,11 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
+                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aX, aY,
+                                          aZ);
             else
-                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, aP, aX, aY, aZ);
+                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aX, aY,
+                                         aZ);
         }
     }
     if (active) {
@@ -651,7 +680,7 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
             const int64_t j = t * kTile + k;
-            Src64 s = {1e6, 1e6, 1e6, 0.0};
+            Src64 s = {0x1p500, 0.0, 0.0, 0.0};  // padding: charge 0, coincides with no target
             if (j < sp.ns) s = Src64{J.sx[j], J.sy[j], J.sz[j], J.sq[j]};
             sS[k] = s;
         }

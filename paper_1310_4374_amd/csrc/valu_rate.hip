@@ -1,0 +1,95 @@
+// Issue-rate measurement of gfx950 vector ALU instructions, for the ALU
+// ceiling of the pair kernels.  Each workgroup runs independent dependency
+// chains of one instruction form (12 chains per lane, 32 waves per SIMD over
+// the launch) so that latency is hidden and only issue throughput counts.
+// Reported per form: lanes per clock per SIMD at the nominal 2.4 GHz, the
+// nominal cycles per 64-lane instruction, and for FMA the FLOP rate.
+#include <hip/hip_runtime.h>
+#include <cstdio>
+#include <cstdlib>
+
+#define VR_CHECK(x)                                                                     \
+    do {                                                                                \
+        hipError_t e_ = (x);                                                            \
+        if (e_ != hipSuccess) {                                                         \
+            std::fprintf(stderr, "HIP error %s at line %d\n", hipGetErrorString(e_), __LINE__); \
+            std::exit(1);                                                               \
+        }                                                                               \
+    } while (0)
+
+namespace {
+constexpr int kChains = 12;
+constexpr int kThreads = 256;
+
+enum Form { FMA_VVV, MUL_VV, ADD_VV, ADD_VS, RSQ_V, FMA64_VVV };
+
+template <typename T, int F>
+__global__ __launch_bounds__(kThreads) void chains(T* out, int iters, T a, T b)
+{
+    T v[kChains], w[kChains];
+    const T la = a + (T)1e-9 * (T)threadIdx.x;  // per-lane values live in VGPRs
+    const T lb = b + (T)1e-9 * (T)threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kChains; ++u) {
+        v[u] = (T)1 + (T)1e-3 * (T)(threadIdx.x + u);
+        w[u] = (T)0.5 + (T)1e-3 * (T)(threadIdx.x + u);
+    }
+    for (int i = 0; i < iters; ++i) {
+#pragma unroll
+        for (int u = 0; u < kChains; ++u) {
+            if (F == FMA_VVV || F == FMA64_VVV) v[u] = v[u] * la + lb;
+            else if (F == MUL_VV) v[u] = v[u] * la;
+            else if (F == ADD_VV) v[u] = v[u] + w[u];
+            else if (F == ADD_VS) v[u] = v[u] + b;  // b is uniform: an SGPR operand
+            else if (F == RSQ_V) v[u] = __builtin_amdgcn_rsqf(v[u]);
+        }
+    }
+    T s = 0;
+#pragma unroll
+    for (int u = 0; u < kChains; ++u) s += v[u] + w[u];
+    out[blockIdx.x * kThreads + threadIdx.x] = s;
+}
+}  // namespace
+
+int main()
+{
+    hipDeviceProp_t pr;
+    VR_CHECK(hipGetDeviceProperties(&pr, 0));
+    const int cus = pr.multiProcessorCount;
+    std::printf("device %s, %d CUs, nominal clock %.2f GHz\n", pr.gcnArchName, cus, pr.clockRate * 1e-6);
+    const int blocks = cus * 32, iters = 4096;
+    void* buf = nullptr;
+    VR_CHECK(hipMalloc(&buf, (size_t)blocks * kThreads * sizeof(double)));
+    hipEvent_t e0, e1;
+    VR_CHECK(hipEventCreate(&e0));
+    VR_CHECK(hipEventCreate(&e1));
+    const double clk = 2.4e9, simds = 4.0 * cus;
+    auto run = [&](const char* name, int flop_per_op, auto launch) {
+        launch();
+        VR_CHECK(hipDeviceSynchronize());
+        VR_CHECK(hipEventRecord(e0));
+        for (int r = 0; r < 5; ++r) launch();
+        VR_CHECK(hipEventRecord(e1));
+        VR_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VR_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 5.f;
+        const double lane_ops = (double)blocks * kThreads * iters * kChains;
+        const double rate = lane_ops / (ms * 1e-3);
+        const double lanes = rate / (simds * clk);
+        std::printf("%-28s %8.3f ms  %6.2f lanes/clk/SIMD  %5.2f cycles/instr", name, ms, lanes, 64.0 / lanes);
+        if (flop_per_op) std::printf("  %6.1f TFLOP/s", rate * flop_per_op * 1e-12);
+        std::printf("\n");
+        std::fflush(stdout);
+    };
+    float* f = static_cast<float*>(buf);
+    double* d = static_cast<double*>(buf);
+    run("v_fma_f32  (VGPR operands)", 2, [&] { chains<float, FMA_VVV><<<blocks, kThreads>>>(f, iters, 1.0000001f, 1e-7f); });
+    run("v_mul_f32  (VGPR operands)", 1, [&] { chains<float, MUL_VV><<<blocks, kThreads>>>(f, iters, 1.0000001f, 1e-7f); });
+    run("v_add_f32  (VGPR operands)", 1, [&] { chains<float, ADD_VV><<<blocks, kThreads>>>(f, iters, 1e-7f, 1e-7f); });
+    run("v_add_f32  (an SGPR operand)", 1, [&] { chains<float, ADD_VS><<<blocks, kThreads>>>(f, iters, 1e-7f, 1e-7f); });
+    run("v_rsq_f32", 0, [&] { chains<float, RSQ_V><<<blocks, kThreads>>>(f, iters, 1.f, 0.f); });
+    run("v_fma_f64  (VGPR operands)", 2, [&] { chains<double, FMA64_VVV><<<blocks, kThreads>>>(d, iters, 1.0000001, 1e-7); });
+    VR_CHECK(hipFree(buf));
+    return 0;
+}
