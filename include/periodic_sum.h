@@ -57,7 +57,8 @@ typedef enum {
     PS_E_RANK = 4,         /* fitting matrix numerically rank deficient beyond rcond */
     PS_E_NOMEM = 5,        /* device or host allocation failed */
     PS_E_HIP = 6,          /* a HIP runtime call failed */
-    PS_E_UNSUPPORTED = 7   /* request outside what this build supports */
+    PS_E_UNSUPPORTED = 7,  /* request outside what this build supports */
+    PS_E_IO = 8            /* a plan file could not be written or read, or is not a valid plan file */
 } ps_status;
 
 typedef enum {
@@ -172,6 +173,27 @@ ps_status periodic_sum_energy_vjp(ps_plan plan, int64_t n,
  * mean and rcond are taken from prm[0]).  Same host steps as periodic_sum_plan
  * per system; device tables are packed per system. */
 ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int device, ps_plan* out);
+
+/* Saves the result of the "set" phase (Sec. 2.3; its cost grows like P^3 with
+ * the SVD, Tables 2-4) so that a later process can skip it: for every system the
+ * parameters, check points and partners, A^+, the box integrals R_t^(0), the
+ * image list and the RBF centres, plus the plan's tuned launch shape.  Nothing
+ * of the last eval is saved.  Format: little-endian binary, "PSPLAN01" magic,
+ * version 1, a 64-bit FNV-1a checksum of all preceding bytes at the end.
+ *   path: host string, a file path; an existing file is replaced.
+ * Errors: PS_E_INVALID (NULL plan or path), PS_E_IO (the file could not be
+ * written completely). */
+ps_status periodic_sum_plan_save(ps_plan plan, const char* path);
+
+/* Rebuilds a plan on `device` from a file written by periodic_sum_plan_save,
+ * without repeating the set phase: the loaded tables are used as saved
+ * (bitwise), and device workspace is allocated as by periodic_sum_plan(_batched).
+ * *out receives the plan (NULL on failure).
+ * Errors: PS_E_INVALID (NULL arguments, device out of range), PS_E_IO (missing
+ * or unreadable file, wrong magic or version, checksum mismatch, sizes that are
+ * inconsistent or outside the limits periodic_sum_plan enforces), PS_E_NOMEM,
+ * PS_E_HIP. */
+ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out);
 
 /* Batched "get": all systems in one hipGraph launch on `stream`.  offsets: host
  * array [nsys+1], system k owns particles offsets[k] .. offsets[k+1]-1 of the

@@ -10,19 +10,20 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "_lib", "libperiodic_sum.so")
 
-PS_OK, PS_E_INVALID, PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX, PS_E_RANK, PS_E_NOMEM, PS_E_HIP, PS_E_UNSUPPORTED = range(8)
+(PS_OK, PS_E_INVALID, PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX, PS_E_RANK, PS_E_NOMEM, PS_E_HIP, PS_E_UNSUPPORTED,
+ PS_E_IO) = range(9)
 PS_FP64, PS_FP32_ACC64 = 0, 1
 PS_MEAN_ZERO, PS_MEAN_NONE = 0, 1
 PS_BASIS_SPHERICAL, PS_BASIS_RBF = 0, 1
 
 STATUS_NAMES = {0: "PS_OK", 1: "PS_E_INVALID", 2: "PS_E_NOT_NEUTRAL", 3: "PS_E_OUT_OF_BOX", 4: "PS_E_RANK",
-                5: "PS_E_NOMEM", 6: "PS_E_HIP", 7: "PS_E_UNSUPPORTED"}
+                5: "PS_E_NOMEM", 6: "PS_E_HIP", 7: "PS_E_UNSUPPORTED", 8: "PS_E_IO"}
 
 EXPORTS = ["periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "periodic_sum_energy_vjp",
            "periodic_sum_plan_batched", "periodic_sum_eval_batched", "periodic_sum_status", "periodic_sum_plan_info",
            "periodic_sum_plan_tables", "periodic_sum_last_coefficients", "periodic_sum_set_profiling",
            "periodic_sum_stage_times", "periodic_sum_autotune", "periodic_sum_near_counts", "periodic_sum_destroy",
-           "periodic_sum_last_error"]
+           "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load"]
 STAGES = ["sort", "near", "bounds", "check", "solve", "mean", "pairs", "far"]
 
 
@@ -93,6 +94,10 @@ def lib():
         L.periodic_sum_near_counts.restype = st
         L.periodic_sum_destroy.argtypes = [vp]
         L.periodic_sum_destroy.restype = None
+        L.periodic_sum_plan_save.argtypes = [vp, ctypes.c_char_p]
+        L.periodic_sum_plan_save.restype = st
+        L.periodic_sum_plan_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
+        L.periodic_sum_plan_load.restype = st
         L.periodic_sum_last_error.argtypes = []
         L.periodic_sum_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -101,6 +101,19 @@ class Plan:
     def handle(self):
         return self._h
 
+    def save(self, path):
+        """Write the plan's set data and launch shape to a file (see load)."""
+        _save(self, path)
+
+    @classmethod
+    def load(cls, path, device=0):
+        """A plan rebuilt from a file written by save, without repeating the set phase."""
+        obj = cls.__new__(cls)
+        obj.device = torch.device("cuda", device)
+        obj._h = _load(path, device)
+        obj.n_max = None
+        return obj
+
     def info(self):
         inf = ps_plan_info()
         check(lib().periodic_sum_plan_info(self._h, ctypes.byref(inf)))
@@ -206,6 +219,16 @@ def _autotune(obj, x, q, offsets):
     return best.value
 
 
+def _save(obj, path):
+    check(lib().periodic_sum_plan_save(obj._h, str(path).encode()))
+
+
+def _load(path, device):
+    h = ctypes.c_void_p()
+    check(lib().periodic_sum_plan_load(str(path).encode(), int(device), ctypes.byref(h)))
+    return h
+
+
 def _near_counts(obj, nsys):
     out = (ctypes.c_int64 * nsys)()
     check(lib().periodic_sum_near_counts(obj._h, out, nsys))
@@ -236,6 +259,19 @@ class BatchedPlan:
         if h is not None and h.value:
             lib().periodic_sum_destroy(h)
             self._h = None
+
+    def save(self, path):
+        """Write the plan's set data and launch shape to a file (see load)."""
+        _save(self, path)
+
+    @classmethod
+    def load(cls, path, device=0):
+        """A batched plan rebuilt from a file written by save, without repeating the set phase."""
+        obj = cls.__new__(cls)
+        obj.device = torch.device("cuda", device)
+        obj._h = _load(path, device)
+        obj.nsys = obj.info()["nsys"]
+        return obj
 
     def eval(self, x, q, offsets, out=None):
         """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints."""

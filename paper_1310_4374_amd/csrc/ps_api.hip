@@ -74,6 +74,7 @@ struct ps_plan_s {
     int maxP = 0, maxp = 0, maxL = 0;
     int64_t m_max = 0;
     std::vector<SystemSetup> setups;
+    std::vector<ps_params> prm;      // per system, pointer members cleared
     std::vector<int64_t> n_max;      // per system
     std::vector<SysDev> base;        // per system, static part
     // device tables
@@ -500,6 +501,42 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     if (prof) pl->ev_recorded = true;
 }
 
+// Fields of a new plan that follow from the parameters alone.
+ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
+{
+    pl->device = device;
+    pl->nsys = nsys;
+    pl->precision = prm[0].precision;
+    pl->mean = prm[0].mean;
+    pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
+    pl->n_split_req = prm[0].n_split;
+    pl->m_max = nsys == 1 ? prm[0].m_max : 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+        pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
+                       p2p_blocks_per_cu(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt);
+    pl->prm.assign(prm, prm + nsys);
+    for (ps_params& q : pl->prm) {
+        q.centres = nullptr;
+        q.check_points = nullptr;
+    }
+    pl->setups.resize(nsys);
+    pl->n_max.resize(nsys);
+    pl->base.resize(nsys);
+    return PS_OK;
+}
+
+ps_status select_device(int device)
+{
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PS_E_HIP, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(PS_E_INVALID, "device %d out of range [0, %d)", device, ndev);
+    HIPCHK(hipSetDevice(device));
+    return PS_OK;
+}
+
+ps_status finish_plan(ps_plan_s* pl, ps_plan* out);
+
 ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
 {
     if (!out) return fail(PS_E_INVALID, "output plan pointer is NULL");
@@ -510,29 +547,11 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
         ps_status st = check_params(&prm[s]);
         if (st != PS_OK) return st;
     }
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PS_E_HIP, "no HIP device available");
-    if (device < 0 || device >= ndev) return fail(PS_E_INVALID, "device %d out of range [0, %d)", device, ndev);
-    HIPCHK(hipSetDevice(device));
+    ps_status ds = select_device(device);
+    if (ds != PS_OK) return ds;
     ps_plan_s* pl = new (std::nothrow) ps_plan_s();
     if (!pl) return fail(PS_E_NOMEM, "host allocation failed");
-    pl->device = device;
-    pl->nsys = nsys;
-    pl->precision = prm[0].precision;
-    pl->mean = prm[0].mean;
-    pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
-
-    pl->n_split_req = prm[0].n_split;
-    pl->m_max = nsys == 1 ? prm[0].m_max : 0;
-    {
-        hipDeviceProp_t prop;
-        if (hipGetDeviceProperties(&prop, device) == hipSuccess)
-            pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
-                           p2p_blocks_per_cu(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt);
-    }
-    pl->setups.resize(nsys);
-    pl->n_max.resize(nsys);
-    pl->base.resize(nsys);
+    init_plan(pl, nsys, prm, device);
     // host "set" per system
     std::vector<std::string> errs(nsys);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -544,6 +563,15 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
             delete pl;
             return fail(PS_E_INVALID, "system %d: %s", s, errs[s].c_str());
         }
+    return finish_plan(pl, out);
+}
+
+// Device tables and workspace of a plan whose set data (pl->setups) and
+// parameters (pl->prm) are in place.  Deletes pl on failure.
+ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
+{
+    const int nsys = pl->nsys;
+    const ps_params* prm = pl->prm.data();
     // pack offsets
     int64_t img_tot = 0, pinv_tot = 0, coef_tot = 0, rec_tot = 0, f_tot = 0;
     int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0, cen_tot = 0, pfar = 0;
@@ -738,6 +766,26 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     return PS_OK;
 }
 
+// Plan files: magic, version, system count, tuned launch shape, then per system
+// the scalar parameters and the set data, then a checksum of all prior bytes.
+const char kPlanMagic[8] = {'P', 'S', 'P', 'L', 'A', 'N', '0', '1'};
+const uint32_t kPlanVersion = 1;
+
+template <typename T>
+void put_scalar(std::vector<unsigned char>& out, const T& v)
+{
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+    out.insert(out.end(), b, b + sizeof(T));
+}
+template <typename T>
+bool get_scalar(const std::vector<unsigned char>& in, size_t& pos, T& v)
+{
+    if (pos > in.size() || in.size() - pos < sizeof(T)) return false;
+    std::memcpy(&v, in.data() + pos, sizeof(T));
+    pos += sizeof(T);
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -749,6 +797,115 @@ ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out) { re
 ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int device, ps_plan* out)
 {
     return make_plan(nsys, prm, device, out);
+}
+
+ps_status periodic_sum_plan_save(ps_plan pl, const char* path)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (!path) return fail(PS_E_INVALID, "path is NULL");
+    std::vector<unsigned char> buf(kPlanMagic, kPlanMagic + 8);
+    put_scalar(buf, kPlanVersion);
+    put_scalar(buf, static_cast<int32_t>(pl->nsys));
+    put_scalar(buf, static_cast<int32_t>(pl->bt));
+    put_scalar(buf, pl->split_scale);
+    for (int s = 0; s < pl->nsys; ++s) {
+        const ps_params& q = pl->prm[s];
+        for (int k = 0; k < 3; ++k) put_scalar(buf, q.box[k]);
+        put_scalar(buf, q.p);
+        put_scalar(buf, q.R_b);
+        put_scalar(buf, q.lambda);
+        put_scalar(buf, q.precision);
+        put_scalar(buf, q.mean);
+        put_scalar(buf, q.rcond);
+        put_scalar(buf, q.n_max);
+        put_scalar(buf, q.m_max);
+        put_scalar(buf, q.tile_targets);
+        put_scalar(buf, q.n_split);
+        put_scalar(buf, q.basis);
+        pl->setups[s].serialize(buf);
+    }
+    put_scalar(buf, fnv1a64(buf.data(), buf.size()));
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(PS_E_IO, "cannot open %s for writing", path);
+    const size_t w = std::fwrite(buf.data(), 1, buf.size(), f);
+    const int c = std::fclose(f);
+    if (w != buf.size() || c != 0) return fail(PS_E_IO, "writing %s failed", path);
+    return PS_OK;
+}
+
+ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
+{
+    if (!out) return fail(PS_E_INVALID, "output plan pointer is NULL");
+    *out = nullptr;
+    if (!path) return fail(PS_E_INVALID, "path is NULL");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(PS_E_IO, "cannot open %s", path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t r;
+    while ((r = std::fread(chunk, 1, sizeof(chunk), f)) > 0) buf.insert(buf.end(), chunk, chunk + r);
+    const bool rerr = std::ferror(f) != 0;
+    std::fclose(f);
+    if (rerr) return fail(PS_E_IO, "reading %s failed", path);
+    const size_t head = 8 + sizeof(uint32_t) + 2 * sizeof(int32_t) + sizeof(double);
+    if (buf.size() < head + sizeof(uint64_t)) return fail(PS_E_IO, "%s is too short for a plan file", path);
+    if (std::memcmp(buf.data(), kPlanMagic, 8) != 0) return fail(PS_E_IO, "%s is not a plan file", path);
+    uint64_t sum = 0;
+    std::memcpy(&sum, buf.data() + buf.size() - sizeof(uint64_t), sizeof(uint64_t));
+    buf.resize(buf.size() - sizeof(uint64_t));
+    if (fnv1a64(buf.data(), buf.size()) != sum) return fail(PS_E_IO, "%s: checksum mismatch", path);
+    size_t pos = 8;
+    uint32_t version = 0;
+    int32_t nsys = 0, bt = 0;
+    double scale = 1.0;
+    get_scalar(buf, pos, version);
+    get_scalar(buf, pos, nsys);
+    get_scalar(buf, pos, bt);
+    get_scalar(buf, pos, scale);
+    if (version != kPlanVersion) return fail(PS_E_IO, "%s: unsupported plan file version %u", path, version);
+    if (nsys < 1 || nsys > (1 << 20)) return fail(PS_E_IO, "%s: bad system count", path);
+    if (bt != 64 && bt != 128 && bt != 256) return fail(PS_E_IO, "%s: bad targets per workgroup", path);
+    if (!(scale > 0.0) || !(scale <= 64.0)) return fail(PS_E_IO, "%s: bad split scale", path);
+    std::vector<ps_params> prm(nsys);
+    std::vector<SystemSetup> setups(nsys);
+    for (int s = 0; s < nsys; ++s) {
+        ps_params& q = prm[s];
+        q = ps_params{};
+        bool ok = true;
+        for (int k = 0; k < 3; ++k) ok = ok && get_scalar(buf, pos, q.box[k]);
+        ok = ok && get_scalar(buf, pos, q.p) && get_scalar(buf, pos, q.R_b) && get_scalar(buf, pos, q.lambda) &&
+             get_scalar(buf, pos, q.precision) && get_scalar(buf, pos, q.mean) && get_scalar(buf, pos, q.rcond) &&
+             get_scalar(buf, pos, q.n_max) && get_scalar(buf, pos, q.m_max) &&
+             get_scalar(buf, pos, q.tile_targets) && get_scalar(buf, pos, q.n_split) && get_scalar(buf, pos, q.basis);
+        if (!ok) return fail(PS_E_IO, "%s: truncated parameters of system %d", path, s);
+        const std::string why = setups[s].deserialize(buf.data(), buf.size(), pos);
+        if (!why.empty()) return fail(PS_E_IO, "%s: system %d: %s", path, s, why.c_str());
+        const SystemSetup& su = setups[s];
+        if (q.p != su.p || q.basis != su.basis) return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
+        for (int k = 0; k < 3; ++k)
+            if (q.box[k] != su.box[k]) return fail(PS_E_IO, "%s: system %d: box does not match its tables", path, s);
+        if (su.basis == PS_BASIS_RBF) {
+            q.n_centres = static_cast<int32_t>(su.centres.size() / 3);
+            q.centres = su.centres.data();
+        }
+        q.n_check = 0;
+        q.check_points = nullptr;
+        if (check_params(&q) != PS_OK) return fail(PS_E_IO, "%s: system %d: %s", path, s, g_err.c_str());
+    }
+    if (pos != buf.size()) return fail(PS_E_IO, "%s: trailing bytes after the last system", path);
+    ps_status ds = select_device(device);
+    if (ds != PS_OK) return ds;
+    ps_plan_s* pl = new (std::nothrow) ps_plan_s();
+    if (!pl) return fail(PS_E_NOMEM, "host allocation failed");
+    init_plan(pl, nsys, prm.data(), device);
+    pl->setups = std::move(setups);
+    pl->bt = bt;
+    pl->split_scale = scale;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess)
+        pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
+                       p2p_blocks_per_cu(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt);
+    return finish_plan(pl, out);
 }
 
 void periodic_sum_destroy(ps_plan plan) { delete plan; }

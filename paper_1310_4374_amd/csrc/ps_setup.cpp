@@ -378,4 +378,110 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     return std::string();
 }
 
+// ---------------------------------------------------------------------------
+// serialization of the set data
+// ---------------------------------------------------------------------------
+namespace {
+template <typename T>
+void put(std::vector<unsigned char>& out, const T& v)
+{
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&v);
+    out.insert(out.end(), b, b + sizeof(T));
+}
+template <typename T>
+void put_vec(std::vector<unsigned char>& out, const std::vector<T>& v)
+{
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(v.data());
+    out.insert(out.end(), b, b + sizeof(T) * v.size());
+}
+template <typename T>
+bool get(const unsigned char* data, size_t size, size_t& pos, T& v)
+{
+    if (size - pos < sizeof(T) || pos > size) return false;
+    std::memcpy(&v, data + pos, sizeof(T));
+    pos += sizeof(T);
+    return true;
+}
+template <typename T>
+bool get_vec(const unsigned char* data, size_t size, size_t& pos, std::vector<T>& v, size_t n)
+{
+    if (pos > size || (size - pos) / sizeof(T) < n) return false;
+    v.resize(n);
+    if (n) std::memcpy(v.data(), data + pos, sizeof(T) * n);
+    pos += sizeof(T) * n;
+    return true;
+}
+}  // namespace
+
+uint64_t fnv1a64(const unsigned char* data, size_t n)
+{
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= data[i];
+        h *= 0x100000001b3ull;
+    }
+    return h;
+}
+
+void SystemSetup::serialize(std::vector<unsigned char>& out) const
+{
+    for (int k = 0; k < 3; ++k) put(out, box[k]);
+    put(out, static_cast<int32_t>(basis));
+    put(out, R0);
+    put(out, R_b);
+    put(out, thr);
+    put(out, V0);
+    put(out, static_cast<int32_t>(p));
+    put(out, static_cast<int32_t>(P));
+    put(out, static_cast<int32_t>(L));
+    put(out, static_cast<int32_t>(rank));
+    put(out, cond);
+    put(out, static_cast<int32_t>(images.size() / 3));
+    put(out, static_cast<int32_t>(centres.size() / 3));
+    put_vec(out, yc);
+    put_vec(out, yt);
+    put_vec(out, pinv);
+    put_vec(out, box_means);
+    put_vec(out, images);
+    put_vec(out, centres);
+}
+
+std::string SystemSetup::deserialize(const unsigned char* data, size_t size, size_t& pos)
+{
+    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0;
+    bool ok = true;
+    for (int k = 0; k < 3; ++k) ok = ok && get(data, size, pos, box[k]);
+    ok = ok && get(data, size, pos, b) && get(data, size, pos, R0) && get(data, size, pos, R_b) &&
+         get(data, size, pos, thr) && get(data, size, pos, V0) && get(data, size, pos, p_) &&
+         get(data, size, pos, P_) && get(data, size, pos, L_) && get(data, size, pos, rank_) &&
+         get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M);
+    if (!ok) return "truncated system record";
+    for (int k = 0; k < 3; ++k)
+        if (!(box[k] > 0.0) || !std::isfinite(box[k])) return "bad box lengths";
+    if (b != 0 && b != 1) return "bad basis";
+    if (p_ < 2 || p_ > 40) return "p out of range";
+    if (b == 0 && (P_ != p_ * p_ || M != 0)) return "basis size does not match p";
+    if (b == 1 && (M < 1 || M > 4096 || P_ != M + 1)) return "bad RBF centre count";
+    if (L_ < 1 || L_ > (1 << 20) || L_ < P_ - 1) return "bad check-point count";
+    if (rank_ < 1 || rank_ > P_ - 1) return "bad rank";
+    if (nimg < 1 || nimg > (1 << 20)) return "bad image count";
+    if (!(R0 > 0.0) || !(R_b > R0) || !std::isfinite(R_b) || !(thr > 0.0) || !(V0 > 0.0)) return "bad geometry";
+    basis = b;
+    p = p_;
+    P = P_;
+    L = L_;
+    rank = rank_;
+    const size_t l3 = static_cast<size_t>(L) * 3;
+    ok = get_vec(data, size, pos, yc, l3) && get_vec(data, size, pos, yt, l3) &&
+         get_vec(data, size, pos, pinv, static_cast<size_t>(P - 1) * L) && get_vec(data, size, pos, box_means, P) &&
+         get_vec(data, size, pos, images, static_cast<size_t>(nimg) * 3) &&
+         get_vec(data, size, pos, centres, static_cast<size_t>(M) * 3);
+    if (!ok) return "truncated system arrays";
+    if (images[0] != 0 || images[1] != 0 || images[2] != 0) return "the first image must be the box itself";
+    for (double v : pinv)
+        if (!std::isfinite(v)) return "non-finite pseudo-inverse entry";
+    rec.build(p);
+    return std::string();
+}
+
 }  // namespace ps

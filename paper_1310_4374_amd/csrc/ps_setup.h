@@ -46,6 +46,15 @@ struct SystemSetup {
     std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
                       int n_centres = 0, const double* centres = nullptr, int n_check = 0,
                       const double* check_points = nullptr);
+    // Binary form of the set data (little-endian scalars and arrays; the
+    // recurrence coefficients are rebuilt from p on reading).
+    void serialize(std::vector<unsigned char>& out) const;
+    // Reads what serialize wrote, advancing pos; checks every size against the
+    // bounds build() enforces.  Returns an empty string on success.
+    std::string deserialize(const unsigned char* data, size_t size, size_t& pos);
 };
+
+// 64-bit FNV-1a hash of a byte range (file integrity check).
+uint64_t fnv1a64(const unsigned char* data, size_t n);
 
 }  // namespace ps

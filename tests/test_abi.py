@@ -77,3 +77,54 @@ def test_near_radius_must_exceed_circumradius(kw):
     L = _lib.lib()
     h = ctypes.c_void_p()
     assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == _lib.PS_E_INVALID
+
+
+def test_plan_file_errors_reported_before_any_device_work(tmp_path):
+    """Loading a missing, foreign, truncated or corrupted plan file fails with
+    PS_E_IO on the host; NULL arguments with PS_E_INVALID."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    assert L.periodic_sum_plan_load(None, 0, ctypes.byref(h)) == _lib.PS_E_INVALID
+    assert L.periodic_sum_plan_load(b"x", 0, None) == _lib.PS_E_INVALID
+    assert L.periodic_sum_plan_save(None, b"x") == _lib.PS_E_INVALID
+    assert L.periodic_sum_plan_load(str(tmp_path / "missing.plan").encode(), 0, ctypes.byref(h)) == _lib.PS_E_IO
+    assert h.value is None
+    cases = {
+        "empty": b"",
+        "foreign": b"NOTAPLAN" + bytes(64),
+        "short": b"PSPLAN01" + bytes(4),
+        # right magic, wrong checksum
+        "corrupt": b"PSPLAN01" + (1).to_bytes(4, "little") + (1).to_bytes(4, "little") + (256).to_bytes(4, "little")
+                   + bytes(8) + bytes(8),
+    }
+    for name, data in cases.items():
+        f = tmp_path / (name + ".plan")
+        f.write_bytes(data)
+        st = L.periodic_sum_plan_load(str(f).encode(), 0, ctypes.byref(h))
+        assert st == _lib.PS_E_IO, name
+        assert b"plan" in L.periodic_sum_last_error() or b"checksum" in L.periodic_sum_last_error(), name
+
+
+def _fnv1a64(data):
+    h = 0xcbf29ce484222325
+    for b in data:
+        h = ((h ^ b) * 0x100000001b3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_plan_file_with_valid_checksum_but_bad_contents_is_refused(tmp_path):
+    """The reader checks every size and range, not only the checksum: a file
+    whose system record claims p = 99 is refused with PS_E_IO."""
+    import struct
+    L = _lib.lib()
+    head = b"PSPLAN01" + struct.pack("<Iiid", 1, 1, 256, 1.0)
+    prm = struct.pack("<3didd", 1.0, 1.0, 1.0, 99, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
+        + struct.pack("<qqiii", 100, 0, 0, 0, 0)
+    setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) + struct.pack("<4id", 99, 99 * 99, 10, 5, 1.0) \
+        + struct.pack("<ii", 1, 0)
+    body = head + prm + setup
+    f = tmp_path / "bad_p.plan"
+    f.write_bytes(body + struct.pack("<Q", _fnv1a64(body)))
+    h = ctypes.c_void_p()
+    assert L.periodic_sum_plan_load(str(f).encode(), 0, ctypes.byref(h)) == _lib.PS_E_IO
+    assert b"p out of range" in L.periodic_sum_last_error()

@@ -509,3 +509,63 @@ def test_batched_mixed_bases(ps):
     r1 = OPlan(boxes[1], 12, lam=lam, basis="rbf", centres=cen).solve(xs[1], qs[1])
     assert _rel(phi[off[0]:off[1]], r0[0]) <= 1e-12 and _rel(field[off[0]:off[1]], r0[1]) <= 1e-12
     assert _rel(phi[off[1]:off[2]], r1[0]) <= 1e-9 and _rel(field[off[1]:off[2]], r1[1]) <= 1e-9
+
+
+# --------------------------------------------------------------------------
+# plan files: the set phase saved and reloaded
+# --------------------------------------------------------------------------
+def test_plan_save_load_round_trip(ps, tmp_path):
+    """A reloaded plan has the same tables, shape and info, and gives bitwise the
+    same sums as the plan it was saved from; a corrupted file is refused."""
+    box = (1.0, 1.2, 0.9)
+    x, q = W.uniform_box(3000, box, charges="gauss", seed=41)
+    pl = ps.Plan(box, 12, lam=float(np.sqrt(3)), precision="fp32", n_max=3000, tile_targets=128)
+    phi0, field0 = pl.eval(_dev(x.T), _dev(q))
+    pl.status()
+    path = tmp_path / "cube.plan"
+    pl.save(path)
+    pl2 = ps.Plan.load(path)
+    i1, i2 = pl.info(), pl2.info()
+    for k in ("p", "P", "L", "n_images", "rank", "R0", "R_b", "cond", "tile_targets", "nsys"):
+        assert i1[k] == i2[k], k
+    for a, b in zip(pl.tables(), pl2.tables()):
+        assert torch.equal(a, b)
+    phi1, field1 = pl2.eval(_dev(x.T), _dev(q))
+    pl2.status()
+    assert torch.equal(phi0, phi1) and torch.equal(field0, field1)
+    data = bytearray(path.read_bytes())
+    data[len(data) // 2] ^= 0x10
+    bad = tmp_path / "bad.plan"
+    bad.write_bytes(bytes(data))
+    with pytest.raises(ps.PeriodicSumError) as err:
+        ps.Plan.load(bad)
+    assert err.value.status == ps._lib.PS_E_IO
+
+
+def test_batched_plan_save_load_mixed_bases(ps, tmp_path):
+    """A batch of a spherical box, an RBF box and a box with caller-given check
+    points, saved after autotuning and reloaded, reproduces its sums bitwise."""
+    boxes = [np.array([1.0, 1.3, 1.1]), np.array([1.2, 1.0, 1.0]), np.array([1.1, 1.1, 0.9])]
+    ns = [700, 1000, 500]
+    data = [W.uniform_box(n, b, charges="gauss", seed=500 + k) for k, (n, b) in enumerate(zip(ns, boxes))]
+    lam = 1.7
+    R0 = [0.5 * np.linalg.norm(b) for b in boxes]
+    systems = [dict(box=boxes[0], n_max=ns[0]),
+               dict(box=boxes[1], n_max=ns[1], centres=W.fibonacci_sphere(200, lam * R0[1])),
+               dict(box=boxes[2], n_max=ns[2], check_points=W.random_sphere(400, R0[2], seed=9))]
+    bp = ps.BatchedPlan(systems, p=12, lam=lam, precision="fp32")
+    off = np.concatenate([[0], np.cumsum(ns)])
+    X = _dev(np.concatenate([d[0] for d in data]).T)
+    Q = _dev(np.concatenate([d[1] for d in data]))
+    bp.autotune(X, Q, off)
+    phi0, field0 = bp.eval(X, Q, off)
+    bp.status()
+    path = tmp_path / "batch.plan"
+    bp.save(path)
+    bp2 = ps.BatchedPlan.load(path)
+    assert bp2.nsys == 3 and bp2.info()["tile_targets"] == bp.info()["tile_targets"]
+    phi1, field1 = bp2.eval(X, Q, off)
+    bp2.status()
+    assert torch.equal(phi0, phi1) and torch.equal(field0, field1)
+    ref = OPlan(boxes[0], 12, lam=lam).solve(data[0][0], data[0][1])
+    assert _rel(phi1.cpu().numpy()[off[0]:off[1]], ref[0]) <= TOL["fp32"]
