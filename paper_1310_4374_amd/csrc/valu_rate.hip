@@ -49,6 +49,323 @@ __global__ __launch_bounds__(kThreads) void chains(T* out, int iters, T a, T b)
     for (int u = 0; u < kChains; ++u) s += v[u] + w[u];
     out[blockIdx.x * kThreads + threadIdx.x] = s;
 }
+// 24 v_fmac_f32 per iteration, sources of mixed register parity
+__global__ __launch_bounds__(kThreads) void asm_fmac_mixed_parity(float* out, int iters)
+{
+    float r;
+    asm volatile(
+        "v_mov_b32 v16, 1.0\n"
+        "v_mov_b32 v18, 1.0\n"
+        "v_mov_b32 v20, 1.0\n"
+        "v_mov_b32 v22, 1.0\n"
+        "v_mov_b32 v24, 1.0\n"
+        "v_mov_b32 v26, 1.0\n"
+        "v_mov_b32 v28, 1.0\n"
+        "v_mov_b32 v30, 1.0\n"
+        "v_mov_b32 v32, 1.0\n"
+        "v_mov_b32 v34, 1.0\n"
+        "v_mov_b32 v36, 1.0\n"
+        "v_mov_b32 v38, 1.0\n"
+        "v_mov_b32 v1, 0x3f800001\n"
+        "v_mov_b32 v3, 0x3f800001\n"
+        "s_mov_b32 s40, %1\n"
+        "1:\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "s_sub_u32 s40, s40, 1\n"
+        "s_cmp_lg_u32 s40, 0\n"
+        "s_cbranch_scc1 1b\n"
+        "v_mov_b32 %0, v16\n"
+        : "=v"(r) : "s"(iters) : "v1", "v3", "v16", "v18", "v20", "v22", "v24", "v26", "v28", "v30", "v32", "v34", "v36", "v38", "s40", "scc");
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// 24 v_fmac_f32 per iteration, all three sources even-numbered
+__global__ __launch_bounds__(kThreads) void asm_fmac_same_parity(float* out, int iters)
+{
+    float r;
+    asm volatile(
+        "v_mov_b32 v16, 1.0\n"
+        "v_mov_b32 v18, 1.0\n"
+        "v_mov_b32 v20, 1.0\n"
+        "v_mov_b32 v22, 1.0\n"
+        "v_mov_b32 v24, 1.0\n"
+        "v_mov_b32 v26, 1.0\n"
+        "v_mov_b32 v28, 1.0\n"
+        "v_mov_b32 v30, 1.0\n"
+        "v_mov_b32 v32, 1.0\n"
+        "v_mov_b32 v34, 1.0\n"
+        "v_mov_b32 v36, 1.0\n"
+        "v_mov_b32 v38, 1.0\n"
+        "v_mov_b32 v4, 0x3f800001\n"
+        "v_mov_b32 v6, 0x3f800001\n"
+        "s_mov_b32 s40, %1\n"
+        "1:\n"
+        "v_fmac_f32 v16, v4, v6\n"
+        "v_fmac_f32 v18, v4, v6\n"
+        "v_fmac_f32 v20, v4, v6\n"
+        "v_fmac_f32 v22, v4, v6\n"
+        "v_fmac_f32 v24, v4, v6\n"
+        "v_fmac_f32 v26, v4, v6\n"
+        "v_fmac_f32 v28, v4, v6\n"
+        "v_fmac_f32 v30, v4, v6\n"
+        "v_fmac_f32 v32, v4, v6\n"
+        "v_fmac_f32 v34, v4, v6\n"
+        "v_fmac_f32 v36, v4, v6\n"
+        "v_fmac_f32 v38, v4, v6\n"
+        "v_fmac_f32 v16, v4, v6\n"
+        "v_fmac_f32 v18, v4, v6\n"
+        "v_fmac_f32 v20, v4, v6\n"
+        "v_fmac_f32 v22, v4, v6\n"
+        "v_fmac_f32 v24, v4, v6\n"
+        "v_fmac_f32 v26, v4, v6\n"
+        "v_fmac_f32 v28, v4, v6\n"
+        "v_fmac_f32 v30, v4, v6\n"
+        "v_fmac_f32 v32, v4, v6\n"
+        "v_fmac_f32 v34, v4, v6\n"
+        "v_fmac_f32 v36, v4, v6\n"
+        "v_fmac_f32 v38, v4, v6\n"
+        "s_sub_u32 s40, s40, 1\n"
+        "s_cmp_lg_u32 s40, 0\n"
+        "s_cbranch_scc1 1b\n"
+        "v_mov_b32 %0, v16\n"
+        : "=v"(r) : "s"(iters) : "v4", "v6", "v16", "v18", "v20", "v22", "v24", "v26", "v28", "v30", "v32", "v34", "v36", "v38", "s40", "scc");
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// 24 v_rsq_f32 per iteration
+__global__ __launch_bounds__(kThreads) void asm_rsq_only(float* out, int iters)
+{
+    float r;
+    asm volatile(
+        "v_mov_b32 v60, 1.0\n"
+        "v_mov_b32 v62, 1.0\n"
+        "v_mov_b32 v64, 1.0\n"
+        "v_mov_b32 v66, 1.0\n"
+        "v_mov_b32 v68, 1.0\n"
+        "v_mov_b32 v70, 1.0\n"
+        "v_mov_b32 v61, 0x3f800001\n"
+        "v_mov_b32 v63, 0x3f800001\n"
+        "v_mov_b32 v65, 0x3f800001\n"
+        "v_mov_b32 v67, 0x3f800001\n"
+        "v_mov_b32 v69, 0x3f800001\n"
+        "v_mov_b32 v71, 0x3f800001\n"
+        "s_mov_b32 s40, %1\n"
+        "1:\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_rsq_f32 v70, v71\n"
+        "s_sub_u32 s40, s40, 1\n"
+        "s_cmp_lg_u32 s40, 0\n"
+        "s_cbranch_scc1 1b\n"
+        "v_mov_b32 %0, v60\n"
+        : "=v"(r) : "s"(iters) : "v60", "v61", "v62", "v63", "v64", "v65", "v66", "v67", "v68", "v69", "v70", "v71", "s40", "scc");
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
+
+// 96 v_fmac_f32 and 24 v_rsq_f32 per iteration, one rsq after every four FMAs
+__global__ __launch_bounds__(kThreads) void asm_fmac_rsq_mixed(float* out, int iters)
+{
+    float r;
+    asm volatile(
+        "v_mov_b32 v16, 1.0\n"
+        "v_mov_b32 v18, 1.0\n"
+        "v_mov_b32 v20, 1.0\n"
+        "v_mov_b32 v22, 1.0\n"
+        "v_mov_b32 v24, 1.0\n"
+        "v_mov_b32 v26, 1.0\n"
+        "v_mov_b32 v28, 1.0\n"
+        "v_mov_b32 v30, 1.0\n"
+        "v_mov_b32 v32, 1.0\n"
+        "v_mov_b32 v34, 1.0\n"
+        "v_mov_b32 v36, 1.0\n"
+        "v_mov_b32 v38, 1.0\n"
+        "v_mov_b32 v60, 1.0\n"
+        "v_mov_b32 v62, 1.0\n"
+        "v_mov_b32 v64, 1.0\n"
+        "v_mov_b32 v66, 1.0\n"
+        "v_mov_b32 v68, 1.0\n"
+        "v_mov_b32 v70, 1.0\n"
+        "v_mov_b32 v1, 0x3f800001\n"
+        "v_mov_b32 v3, 0x3f800001\n"
+        "v_mov_b32 v61, 0x3f800001\n"
+        "v_mov_b32 v63, 0x3f800001\n"
+        "v_mov_b32 v65, 0x3f800001\n"
+        "v_mov_b32 v67, 0x3f800001\n"
+        "v_mov_b32 v69, 0x3f800001\n"
+        "v_mov_b32 v71, 0x3f800001\n"
+        "s_mov_b32 s40, %1\n"
+        "1:\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v70, v71\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v60, v61\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v62, v63\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v64, v65\n"
+        "v_fmac_f32 v16, v1, v3\n"
+        "v_fmac_f32 v18, v1, v3\n"
+        "v_fmac_f32 v20, v1, v3\n"
+        "v_fmac_f32 v22, v1, v3\n"
+        "v_rsq_f32 v66, v67\n"
+        "v_fmac_f32 v24, v1, v3\n"
+        "v_fmac_f32 v26, v1, v3\n"
+        "v_fmac_f32 v28, v1, v3\n"
+        "v_fmac_f32 v30, v1, v3\n"
+        "v_rsq_f32 v68, v69\n"
+        "v_fmac_f32 v32, v1, v3\n"
+        "v_fmac_f32 v34, v1, v3\n"
+        "v_fmac_f32 v36, v1, v3\n"
+        "v_fmac_f32 v38, v1, v3\n"
+        "v_rsq_f32 v70, v71\n"
+        "s_sub_u32 s40, s40, 1\n"
+        "s_cmp_lg_u32 s40, 0\n"
+        "s_cbranch_scc1 1b\n"
+        "v_mov_b32 %0, v16\n"
+        : "=v"(r) : "s"(iters) : "v1", "v3", "v16", "v18", "v20", "v22", "v24", "v26", "v28", "v30", "v32", "v34", "v36", "v38", "v60", "v61", "v62", "v63", "v64", "v65", "v66", "v67", "v68", "v69", "v70", "v71", "s40", "scc");
+    out[blockIdx.x * kThreads + threadIdx.x] = r;
+}
 }  // namespace
 
 int main()
@@ -90,6 +407,34 @@ int main()
     run("v_add_f32  (an SGPR operand)", 1, [&] { chains<float, ADD_VS><<<blocks, kThreads>>>(f, iters, 1e-7f, 1e-7f); });
     run("v_rsq_f32", 0, [&] { chains<float, RSQ_V><<<blocks, kThreads>>>(f, iters, 1.f, 0.f); });
     run("v_fma_f64  (VGPR operands)", 2, [&] { chains<double, FMA64_VVV><<<blocks, kThreads>>>(d, iters, 1.0000001, 1e-7); });
+
+    // instruction streams with fixed registers: nominal cycles per loop iteration and SIMD
+    auto run_asm = [&](const char* name, int ninstr, int nblocks, auto launch) {
+        launch();
+        VR_CHECK(hipDeviceSynchronize());
+        VR_CHECK(hipEventRecord(e0));
+        for (int r = 0; r < 5; ++r) launch();
+        VR_CHECK(hipEventRecord(e1));
+        VR_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        VR_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        ms /= 5.f;
+        const double iters_per_simd = (double)nblocks * (kThreads / 64) * iters / simds;
+        const double cyc = ms * 1e-3 * clk / iters_per_simd;
+        std::printf("%-44s %8.3f ms  %7.1f cycles/iteration  %5.2f cycles/instr\n", name, ms, cyc, cyc / ninstr);
+        std::fflush(stdout);
+    };
+    run_asm("v_fmac_f32 x24, mixed-parity sources", 24, blocks,
+            [&] { asm_fmac_mixed_parity<<<blocks, kThreads>>>(f, iters); });
+    run_asm("v_fmac_f32 x24, same-parity sources", 24, blocks,
+            [&] { asm_fmac_same_parity<<<blocks, kThreads>>>(f, iters); });
+    run_asm("v_rsq_f32 x24", 24, blocks, [&] { asm_rsq_only<<<blocks, kThreads>>>(f, iters); });
+    run_asm("v_fmac_f32 x96 + v_rsq_f32 x24, interleaved", 120, blocks,
+            [&] { asm_fmac_rsq_mixed<<<blocks, kThreads>>>(f, iters); });
+    // one workgroup (one wave per SIMD) per CU at a time: the LDS request keeps others off the CU
+    VR_CHECK(hipFuncSetAttribute((const void*)asm_fmac_mixed_parity, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024));
+    run_asm("v_fmac_f32 x24, one wave per SIMD", 24, cus * 4,
+            [&] { asm_fmac_mixed_parity<<<cus * 4, kThreads, 96 * 1024>>>(f, iters); });
     VR_CHECK(hipFree(buf));
     return 0;
 }
