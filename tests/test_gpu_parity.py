@@ -569,3 +569,26 @@ def test_batched_plan_save_load_mixed_bases(ps, tmp_path):
     assert torch.equal(phi0, phi1) and torch.equal(field0, field1)
     ref = OPlan(boxes[0], 12, lam=lam).solve(data[0][0], data[0][1])
     assert _rel(phi1.cpu().numpy()[off[0]:off[1]], ref[0]) <= TOL["fp32"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_thomson_check_points_and_centres_match_oracle(ps, prec):
+    """400 Thomson check points (Table 1's T(400)) with the spherical basis, and
+    with 256 Thomson RBF centres on S_b (Sec. 4.1): the library matches the oracle
+    given the same point sets."""
+    box = (1.0, 1.1, 0.95)
+    lam = 1.7
+    R0 = 0.5 * np.linalg.norm(box)
+    yc = W.thomson_points(400, R0)
+    cen = W.thomson_points(256, lam * R0)
+    x, q = W.uniform_box(800, box, charges="gauss", seed=88)
+    for kw, tol in ((dict(check_points=yc), TOL[prec]), (dict(check_points=yc, centres=cen), TOL_RBF[prec])):
+        okw = dict(kw)
+        if "centres" in okw:
+            okw["basis"] = "rbf"
+        ref = OPlan(box, 14, lam=lam, **okw).solve(x, q)
+        pl = ps.Plan(box, 14, lam=lam, precision=prec, n_max=800, **kw)
+        phi, field = pl.eval(_dev(x.T), _dev(q))
+        pl.status()
+        assert _rel(phi.cpu().numpy(), ref[0]) <= tol
+        assert _rel(field.cpu().numpy().T, ref[1]) <= tol

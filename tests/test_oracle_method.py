@@ -158,13 +158,26 @@ def test_random_check_points_table1_order_of_magnitude():
         assert ref / 10 < max(errs) < ref * 10
 
 
+@pytest.mark.parametrize("p", [8, 12, 16])
+def test_table1_thomson_400_order_of_magnitude(p):
+    """Table 1, T(400) column (lambda = sqrt 3): 400 Thomson check points give eps_M
+    of the paper's order (the set's orientation and the partner rule are not
+    stated; the paper's points come from a database, ours from a minimizer)."""
+    ref = GOLD["table1_thomson"]["eps_M"]["400"][str(p)]
+    c = W.nacl_cell()
+    yc = W.thomson_points(400, np.sqrt(3) / 2)
+    phi, _ = Plan(c["box"], p, R_b=1.5, check_points=yc).solve(c["x"], c["q"])
+    e = np.max(np.abs(phi * 0.5 / (-c["q"] * MADELUNG_NACL) - 1))
+    assert ref / 10 < e < ref * 10
+
+
 def test_rbf_basis_madelung_and_ewald():
-    """Sec. 4.1, RBF basis (eq. (5)) with 256 sources on the sphere S_b: eps_M of
-    the order of the paper's 1.32e-7 (Fibonacci-lattice sources stand in for the
-    Thomson points); random charges match Ewald to the method's accuracy."""
+    """Sec. 4.1, RBF basis (eq. (5)) with 256 Thomson sources on the sphere S_b and
+    the Gauss check points of p = 16: eps_M of the order of the paper's 1.32e-7;
+    random charges match Ewald to the method's accuracy."""
     ref = GOLD["rbf_basis"]
     c = W.nacl_cell()
-    cen = W.fibonacci_sphere(ref["M"], 1.5)
+    cen = W.thomson_points(ref["M"], 1.5)
     pl = Plan(c["box"], ref["p"], R_b=1.5, basis="rbf", centres=cen)
     phi, E = pl.solve(c["x"], c["q"])
     e = np.max(np.abs(phi * 0.5 / (-c["q"] * MADELUNG_NACL) - 1))

@@ -23,6 +23,8 @@ boxes of several aspect ratios):
 5. rock-salt lattice of 32^3 sites (spacing 1/32 in a unit cube), q=(-1)^(i+j+k),
    positions jittered by N(0, 0.002^2) per coordinate
 """
+import functools
+
 import numpy as np
 
 BASE_SEED = 20131015
@@ -141,6 +143,48 @@ def fibonacci_sphere(m, radius):
     ph = t * np.pi * (3.0 - np.sqrt(5.0))
     r = np.sqrt(1.0 - z * z)
     return np.ascontiguousarray(radius * np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1))
+
+
+def thomson_energy(x):
+    """Coulomb energy sum_{i<j} 1/|x_i - x_j| of a point set."""
+    d = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
+    iu = np.triu_indices(len(x), 1)
+    return float(np.sum(1.0 / d[iu]))
+
+
+def _thomson_energy_grad(v):
+    """Energy of the points v/|v| (flattened) and its gradient with respect to v."""
+    y = v.reshape(-1, 3)
+    n = np.linalg.norm(y, axis=1)
+    x = y / n[:, None]
+    dv = x[:, None, :] - x[None, :, :]
+    r2 = (dv ** 2).sum(-1)
+    np.fill_diagonal(r2, np.inf)
+    inv = 1.0 / np.sqrt(r2)
+    e = 0.5 * float(inv.sum())
+    gx = -(dv * (inv ** 3)[..., None]).sum(1)           # dE/dx_i
+    g = (gx - (gx * x).sum(1)[:, None] * x) / n[:, None]  # through the normalization
+    return e, g.ravel()
+
+
+@functools.lru_cache(maxsize=16)
+def _thomson_unit(m, gtol):
+    from scipy.optimize import minimize
+    x0 = fibonacci_sphere(m, 1.0)
+    if m < 2:
+        return x0
+    res = minimize(_thomson_energy_grad, x0.ravel(), jac=True, method="L-BFGS-B",
+                   options={"maxiter": 20000, "gtol": gtol, "ftol": 0.0, "maxcor": 30})
+    x = res.x.reshape(-1, 3)
+    return np.ascontiguousarray(x / np.linalg.norm(x, axis=1)[:, None])
+
+
+def thomson_points(m, radius, gtol=1e-10):
+    """m points on a sphere at a local minimum of their mutual Coulomb energy (the
+    Thomson problem), for check points and RBF centres.  Deterministic: L-BFGS on
+    the energy of the normalized points, started from the Fibonacci lattice.
+    Stands in for a database of Thomson points."""
+    return np.ascontiguousarray(radius * _thomson_unit(int(m), float(gtol)))
 
 
 def random_sphere(m, radius, seed):
