@@ -57,7 +57,7 @@ typedef enum {
     PS_E_RANK = 4,         /* fitting matrix numerically rank deficient beyond rcond */
     PS_E_NOMEM = 5,        /* device or host allocation failed */
     PS_E_HIP = 6,          /* a HIP runtime call failed */
-    PS_E_UNSUPPORTED = 7,  /* request outside what this build supports */
+    PS_E_UNSUPPORTED = 7,  /* request outside what this library supports */
     PS_E_IO = 8            /* a plan file could not be written or read, or is not a valid plan file */
 } ps_status;
 

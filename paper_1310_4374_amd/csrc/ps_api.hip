@@ -554,7 +554,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     init_plan(pl, nsys, prm, device);
     // host "set" per system
     std::vector<std::string> errs(nsys);
-#pragma omp parallel for schedule(dynamic, 1)
+#pragma omp parallel for schedule(dynamic, 1) if (nsys > 1)
     for (int s = 0; s < nsys; ++s)
         errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
                                       prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points);
@@ -1164,7 +1164,8 @@ ps_status periodic_sum_last_coefficients(ps_plan pl, double* C)
 
 namespace {
 
-constexpr int kMomBlocks = 64;
+constexpr int kMomBlocks = 64;       // source splits of the RBF moment pair sum
+constexpr int kMomWaves = 256;       // one-wave workgroups of the spherical moment kernel
 
 ps_status ensure_forward_tables(ps_plan_s* pl, int64_t n, hipStream_t st)
 {
@@ -1200,7 +1201,7 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_adj_bb, (ns / kTile + 1) * (kTile / kGroup) * 6)
     AL(pl->d_adj_tblk, pl->adj_tb_cap * 4)
     AL(pl->d_adj_part, pl->adj_part_cap)
-    AL(pl->d_mom, (int64_t)kMomBlocks * S.P)
+    AL(pl->d_mom, (int64_t)std::max(kMomBlocks, kMomWaves) * S.P)
     AL(pl->d_dq, pl->n_max[0])
     AL(pl->d_dx, 3 * pl->n_max[0])
     AL(pl->d_adj_t, pl->adj_tb_cap)
@@ -1330,7 +1331,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
             launch_tblock(static_cast<int64_t>(pl->mom_t.size()), pl->d_mom_job, pl->d_mom_t, st);
             launch_p2p(0, 256, false, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p, st);
         } else {
-            launch_moments(S.P, S.p, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec, pl->d_mom, kMomBlocks,
+            mom_blocks = kMomWaves;
+            launch_moments(S.P, S.p, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec, pl->d_mom, mom_blocks,
                            st);
         }
         launch_adjoint_sources(S.P, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mom, mom_blocks,

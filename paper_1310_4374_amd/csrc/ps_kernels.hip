@@ -1066,12 +1066,13 @@ __global__ __launch_bounds__(256) void k_energy(const SysDev* __restrict__ sys, 
 }
 
 // Partial moments u_t = sum_k q_k R^_t(x_k / R0), t >= 1, over a slice of the
-// particles: each wave evaluates the basis recurrence for 64 particles and
-// reduces every term across its lanes; part[block][t].
-__global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, const double* __restrict__ sx,
-                                                const double* __restrict__ sy, const double* __restrict__ sz,
-                                                const double* __restrict__ sq, const double* __restrict__ rec,
-                                                double* __restrict__ part)
+// particles: one wave per workgroup evaluates the basis recurrence for 64
+// particles at a time and reduces every term across its lanes; part[block][t].
+// (One wave keeps the LDS at (3P + p) doubles, under 40 KB for p <= 40.)
+__global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, const double* __restrict__ sx,
+                                               const double* __restrict__ sy, const double* __restrict__ sz,
+                                               const double* __restrict__ sq, const double* __restrict__ rec,
+                                               double* __restrict__ part)
 {
     extern __shared__ double lds[];
     const SysDev& S = sys[0];
@@ -1079,17 +1080,16 @@ __global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, 
     double* A = lds;
     double* B = lds + P;
     double* Cd = lds + 2 * P;
-    double* acc = lds + 2 * P + p;  // [4][P]
-    for (int t = threadIdx.x; t < P; t += 256) {
+    double* acc = lds + 2 * P + p;  // [P]
+    for (int t = threadIdx.x; t < P; t += 64) {
         A[t] = rec[S.rec_off + t];
         B[t] = rec[S.rec_off + P + t];
-        for (int w = 0; w < 4; ++w) acc[w * P + t] = 0.0;
+        acc[t] = 0.0;
     }
-    for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
+    for (int t = threadIdx.x; t < p; t += 64) Cd[t] = rec[S.rec_off + 2 * P + t];
     __syncthreads();
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    double* aw = acc + w * P;
-    for (int64_t base = ((int64_t)blockIdx.x * 4 + w) * 64; base < S.n; base += (int64_t)gridDim.x * 256) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < S.n; base += (int64_t)gridDim.x * 64) {
         const int64_t i = base + lane;
         const bool v = i < S.n;
         const double x = v ? sx[S.n_off + i] * S.inv_R0 : 0.0, y = v ? sy[S.n_off + i] * S.inv_R0 : 0.0,
@@ -1110,13 +1110,13 @@ __global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, 
                 const int t0 = m * m + m + mm;
                 if (t0 > 0) {
                     const double r = wave_sum(q * v1);
-                    if (lane == 0) aw[t0] += r;
+                    if (lane == 0) acc[t0] += r;
                 }
                 for (int n = m + 1; n < p; ++n) {
                     const int t = n * n + n + mm;
                     const double vv = -A[t] * z * v1 - B[t] * r2 * v2;
                     const double r = wave_sum(q * vv);
-                    if (lane == 0) aw[t] += r;
+                    if (lane == 0) acc[t] += r;
                     v2 = v1;
                     v1 = vv;
                 }
@@ -1124,8 +1124,7 @@ __global__ __launch_bounds__(256) void k_moment(const SysDev* __restrict__ sys, 
         }
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < P; t += 256)
-        part[(int64_t)blockIdx.x * P + t] = ((acc[t] + acc[P + t]) + acc[2 * P + t]) + acc[3 * P + t];
+    for (int t = threadIdx.x; t < P; t += 64) part[(int64_t)blockIdx.x * P + t] = acc[t];
 }
 
 // u = sum of the moment partials; w = (A^+)^T u; adjoint sources: the sorted
@@ -1248,8 +1247,8 @@ void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* 
 void launch_moments(int P, int p, const SysDev* sys, const double* sx, const double* sy, const double* sz,
                     const double* sq, const double* rec, double* mom_part, int mom_blocks, hipStream_t st)
 {
-    PS_LAUNCH(k_moment, dim3(mom_blocks), dim3(256), (2 * P + p + 4 * P) * sizeof(double), st, sys, sx, sy, sz, sq,
-              rec, mom_part);
+    PS_LAUNCH(k_moment, dim3(mom_blocks), dim3(64), (3 * P + p) * sizeof(double), st, sys, sx, sy, sz, sq, rec,
+              mom_part);
 }
 void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
                             const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,

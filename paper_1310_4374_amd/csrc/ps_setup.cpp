@@ -128,7 +128,9 @@ namespace {
 // Pseudo-inverse of the L x n matrix A (column-major) by Householder QR
 // followed by a one-sided (Hestenes) Jacobi SVD of the n x n factor R:
 // A = Q R, R = U S V^T, A^+ = V S^+ U^T Q^T with singular values below
-// rcond * s_max dropped.  Returns A^+ row-major (n x L).
+// rcond * s_max dropped.  Returns A^+ row-major (n x L).  The Jacobi sweeps
+// visit the column pairs in round-robin order: each step rotates n/2 disjoint
+// pairs, which run in parallel; the result does not depend on the thread count.
 void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vector<double>& pinv,
                     int& rank, double& cond)
 {
@@ -146,12 +148,14 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
         double vv = 0.0;
         for (int i = k; i < L; ++i) vv += v[i] * v[i];
         beta[k] = vv > 0 ? 2.0 / vv : 0.0;
+        const double bk = beta[k];
+#pragma omp parallel for schedule(static) if (n - k > 64)
         for (int j = k; j < n; ++j) {
             double* cj = &A[static_cast<size_t>(j) * L];
-            double s = 0.0;
-            for (int i = k; i < L; ++i) s += v[i] * cj[i];
-            s *= beta[k];
-            for (int i = k; i < L; ++i) cj[i] -= s * v[i];
+            double sum = 0.0;
+            for (int i = k; i < L; ++i) sum += v[i] * cj[i];
+            sum *= bk;
+            for (int i = k; i < L; ++i) cj[i] -= sum * v[i];
         }
     }
     // R (n x n, column-major) and V = I
@@ -160,10 +164,18 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
         for (int i = 0; i <= j; ++i) R[static_cast<size_t>(j) * n + i] = A[static_cast<size_t>(j) * L + i];
         V[static_cast<size_t>(j) * n + j] = 1.0;
     }
+    // round-robin pairing over m = n rounded up to even; index n (if present) is a dummy
+    const int m = n + (n & 1);
+    std::vector<int> pos(m);
+    for (int i = 0; i < m; ++i) pos[i] = i;
     for (int sweep = 0; sweep < 80; ++sweep) {
         double off = 0.0;
-        for (int i = 0; i < n - 1; ++i)
-            for (int j = i + 1; j < n; ++j) {
+        for (int step = 0; step < m - 1; ++step) {
+#pragma omp parallel for schedule(static) reduction(max : off) if (n > 64)
+            for (int h = 0; h < m / 2; ++h) {
+                int i = pos[h], j = pos[m - 1 - h];
+                if (i >= n || j >= n) continue;
+                if (i > j) std::swap(i, j);
                 double* ci = &R[static_cast<size_t>(i) * n];
                 double* cj = &R[static_cast<size_t>(j) * n];
                 double al = 0, be = 0, ga = 0;
@@ -178,28 +190,33 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
                 if (o < 1e-15) continue;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
-                const double c = 1.0 / std::sqrt(1.0 + t * t), s = c * t;
+                const double c = 1.0 / std::sqrt(1.0 + t * t), sn = c * t;
                 for (int k = 0; k < n; ++k) {
                     const double xi = ci[k], xj = cj[k];
-                    ci[k] = c * xi - s * xj;
-                    cj[k] = s * xi + c * xj;
+                    ci[k] = c * xi - sn * xj;
+                    cj[k] = sn * xi + c * xj;
                 }
                 double* vi = &V[static_cast<size_t>(i) * n];
                 double* vj = &V[static_cast<size_t>(j) * n];
                 for (int k = 0; k < n; ++k) {
                     const double xi = vi[k], xj = vj[k];
-                    vi[k] = c * xi - s * xj;
-                    vj[k] = s * xi + c * xj;
+                    vi[k] = c * xi - sn * xj;
+                    vj[k] = sn * xi + c * xj;
                 }
             }
+            // rotate positions 1 .. m-1 (position 0 stays)
+            const int last = pos[m - 1];
+            for (int q = m - 1; q > 1; --q) pos[q] = pos[q - 1];
+            if (m > 1) pos[1] = last;
+        }
         if (off < 1e-15) break;
     }
     std::vector<double> sig(n);
     double smax = 0.0;
     for (int j = 0; j < n; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < n; ++k) s += R[static_cast<size_t>(j) * n + k] * R[static_cast<size_t>(j) * n + k];
-        sig[j] = std::sqrt(s);
+        double sum = 0.0;
+        for (int k = 0; k < n; ++k) sum += R[static_cast<size_t>(j) * n + k] * R[static_cast<size_t>(j) * n + k];
+        sig[j] = std::sqrt(sum);
         smax = std::max(smax, sig[j]);
     }
     rank = 0;
@@ -214,23 +231,26 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
     cond = smax / smin;
     // B = R^+ = V S^-2 (R V)^T  (columns of R now hold R V = U S); M = [B^T; 0] (L x n)
     std::vector<double> M(static_cast<size_t>(L) * n, 0.0);  // column-major
+#pragma omp parallel for schedule(static) if (n > 64)
     for (int a = 0; a < n; ++a)        // row a of B
         for (int r = 0; r < n; ++r) {  // column r of B
-            double s = 0.0;
+            double sum = 0.0;
             for (int j = 0; j < n; ++j)
-                if (inv2[j] != 0.0) s += V[static_cast<size_t>(j) * n + a] * inv2[j] * R[static_cast<size_t>(j) * n + r];
-            M[static_cast<size_t>(a) * L + r] = s;  // M[r][a] = B[a][r]
+                if (inv2[j] != 0.0) sum += V[static_cast<size_t>(j) * n + a] * inv2[j] * R[static_cast<size_t>(j) * n + r];
+            M[static_cast<size_t>(a) * L + r] = sum;  // M[r][a] = B[a][r]
         }
     // A^+T = H_0 H_1 ... H_{n-1} M
     for (int k = n - 1; k >= 0; --k) {
         if (beta[k] == 0.0) continue;
         const double* v = &vs[static_cast<size_t>(k) * L];
+        const double bk = beta[k];
+#pragma omp parallel for schedule(static) if (n > 64)
         for (int j = 0; j < n; ++j) {
             double* cj = &M[static_cast<size_t>(j) * L];
-            double s = 0.0;
-            for (int i = k; i < L; ++i) s += v[i] * cj[i];
-            s *= beta[k];
-            for (int i = k; i < L; ++i) cj[i] -= s * v[i];
+            double sum = 0.0;
+            for (int i = k; i < L; ++i) sum += v[i] * cj[i];
+            sum *= bk;
+            for (int i = k; i < L; ++i) cj[i] -= sum * v[i];
         }
     }
     pinv.assign(static_cast<size_t>(n) * L, 0.0);

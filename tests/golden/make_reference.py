@@ -1,9 +1,10 @@
-"""Write the oracle's reference values for the full-size workloads.
+"""Write the oracle's reference values for the full-size workloads, and the
+independent Ewald potential for the parameter-choice tests of Table 2.
 
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5 table2]
 """
 import os
 import sys
@@ -15,6 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
+from oracle.ewald import Ewald  # noqa: E402
 from oracle.method import Plan  # noqa: E402
 
 OUT = os.path.dirname(os.path.abspath(__file__))
@@ -70,6 +72,22 @@ def cfg5(nsample=200):
     r = W.rocksalt(32)
     lphi, lfield = pl.solve(r["x"], r["q"], targets=r["x"][:2])
     _save("ref_cfg5.npz", subset=sub, phi=phi, field=field, lattice_phi=lphi, lattice_q=r["q"][:2])
+
+
+def table2():
+    """Sec. 4.2, Table 2: 27,000 charges +-1 on a 30^3 grid in the unit cube.  The
+    classical Ewald sum (O2) at 2,000 seeded sample charges, the reference for the
+    relative L2 error eps_2 of eq. (st2)."""
+    x, q = W.grid_charges(30, 2)
+    sub = np.sort(W.rng(7).choice(len(q), 2000, replace=False))
+    phi, _ = Ewald((1.0, 1.0, 1.0)).solve(x, q, targets=x[sub])
+    out = dict(subset=sub, phi_ewald=phi)
+    for lam, p in TABLE2_CASES:   # the method (O1) at Table 2's p_min, for GPU parity
+        out["phi_method_%g_%d" % (lam, p)], _ = Plan((1.0, 1.0, 1.0), p, lam=lam).solve(x, q, targets=x[sub])
+    _save("ref_table2.npz", **out)
+
+
+TABLE2_CASES = ((1.3, 34), (1.5, 24), (1.7, 19))
 
 
 if __name__ == "__main__":

@@ -145,6 +145,18 @@ def fibonacci_sphere(m, radius):
     return np.ascontiguousarray(radius * np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1))
 
 
+def grid_charges(m, seed):
+    """m^3 charges at the cell centres of a regular m x m x m grid in the unit cube
+    [-1/2, 1/2)^3, with random signs, m^3/2 of each (m even): the accuracy and
+    parameter-choice tests of Sec. 4.2 (Tables 2 and 3, Figs. 4-6)."""
+    g = (np.arange(m, dtype=np.float64) + 0.5) / m - 0.5
+    x = np.stack(np.meshgrid(g, g, g, indexing="ij"), axis=-1).reshape(-1, 3)
+    n = m ** 3
+    q = np.concatenate([np.ones(n // 2), -np.ones(n - n // 2)])
+    rng(seed).shuffle(q)
+    return np.ascontiguousarray(x), q
+
+
 def thomson_energy(x):
     """Coulomb energy sum_{i<j} 1/|x_i - x_j| of a point set."""
     d = np.sqrt(((x[:, None, :] - x[None, :, :]) ** 2).sum(-1))
