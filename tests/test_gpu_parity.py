@@ -632,3 +632,40 @@ def test_largest_truncation_number_energy_and_adjoint(ps):
     assert abs(float(e.cpu()[0]) - E) <= 1e-12 * abs(E)
     assert _rel(gx.cpu().numpy().T, dx) <= 1e-11
     assert _rel(gq.cpu().numpy(), dq) <= 1e-11
+
+
+# --------------------------------------------------------------------------
+# elongated and flat boxes of Table 5 (hundreds of lattice images)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_elongated_box_matches_oracle(ps, prec):
+    """Table 5's 10 x 1 x 1 box at lambda = 1.3 (A_gf = 53.9; 3 x 15 x 15 lattice
+    images before pruning): the library matches the oracle."""
+    box = (10.0, 1.0, 1.0)
+    x, q = W.uniform_box(2000, box, charges="gauss", seed=51)
+    ref = OPlan(box, 16, lam=1.3).solve(x, q)
+    pl = ps.Plan(box, 16, lam=1.3, precision=prec, n_max=2000)
+    phi, field = pl.eval(_dev(x.T), _dev(q))
+    pl.status()
+    assert _rel(phi.cpu().numpy(), ref[0]) <= TOL[prec]
+    assert _rel(field.cpu().numpy().T, ref[1]) <= TOL[prec]
+
+
+def test_table5_near_set_sizes(ps):
+    """Table 5 (N = 1e5 uniform, lambda = 1.3): the device's near-set size for each
+    box is within 6 standard deviations of A_gf lambda^3 N (eq. (o2.1)), as the
+    paper's counts are."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")))["table5"]
+    for k, (box, nb_paper) in enumerate(zip(gold["boxes"], gold["N_b"])):
+        d = np.asarray(box, float)
+        agf = np.pi / 6 * np.sum(d * d) ** 1.5 / np.prod(d)
+        mean = agf * gold["lambda"] ** 3 * gold["N"]
+        x, q = W.uniform_box(gold["N"], d, charges="gauss", seed=60 + k)
+        pl = ps.Plan(d, 8, lam=gold["lambda"], precision="fp32", n_max=gold["N"])
+        pl.eval(_dev(x.T), _dev(q))
+        pl.status()
+        nb = pl.near_counts()[0]
+        assert abs(nb - mean) < 6 * np.sqrt(mean), (box, nb, mean)
+        assert abs(nb_paper - mean) < 6 * np.sqrt(mean)
