@@ -121,7 +121,10 @@ typedef struct {
  * spherical basis (App. B), the box-mean potential at each centre for the RBF
  * basis (App. C).  Host arrays in prm are read during the call only.
  * Uploads these and allocates all device workspace on `device`.
- * prm: host pointer, read during the call only.  *out receives the plan. */
+ * prm: host pointer, read during the call only.  *out receives the plan.
+ * Errors: PS_E_INVALID (parameters out of range, bad point sets),
+ * PS_E_UNSUPPORTED (n_max times the number of lattice images exceeds 2^31 - 1
+ * near-list entries), PS_E_NOMEM, PS_E_HIP. */
 ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out);
 
 /* Algorithm "get" (Sec. 2.3, steps 1-8) on the device, one system:

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -610,6 +611,12 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         cell_tot += S.ncell + 1;
         S.near_off = near_tot;
         S.near_cap = prm[s].n_max * S.nimg;
+        if (S.near_cap > INT32_MAX) {  // near entries are indexed with 32-bit integers
+            const int64_t cap = S.near_cap;
+            delete pl;
+            return fail(PS_E_UNSUPPORTED, "system %d: n_max x images = %lld exceeds 2^31 - 1 near-list entries", s,
+                        (long long)cap);
+        }
         near_tot += (S.near_cap + kTile - 1) / kTile * kTile;  // tiles never straddle systems
         S.img_off = img_tot;
         img_tot += S.nimg;

@@ -160,6 +160,9 @@ def test_status_reports_data_errors(ps):
     pl.status()
     with pytest.raises(PeriodicSumError, match="INVALID"):
         pl.eval(_dev(np.zeros((3, 2000))), _dev(np.zeros(2000)))
+    # a near list that 32-bit entry indices cannot address is refused before allocation
+    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
+        ps.Plan(c["box"], 4, R_b=1.5, n_max=2 ** 30)
 
 
 def test_bitwise_reproducible(ps):
