@@ -482,7 +482,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     launch_tile_bounds(nsys, nsys == 1 ? 1024 : 64, pjobs, st);
     launch_tblock(T.nt_items, pl->d_jobs, pl->d_t_items, st);
     mark(3);
-    launch_p2p(0, 256, false, T.nchk, cjobs, pl->d_chk_items, st);                      // step 3 at the check points
+    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, 256, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);

@@ -55,9 +55,12 @@ def test_small_cube_config(ps, prec):
     info = pl.info()
     assert info["n_near_last"] == ref["n_near"]
     assert info["L"] == 2 * c["p"] ** 2 - c["p"] and info["rank"] == c["p"] ** 2 - 1
+    # FP64: the coefficients to rounding; FP32: the check-point sums are FP32 pair
+    # sums (FP64 accumulation), which moves C by ~1e-6 relative
     C = pl.coefficients().numpy()
-    assert _rel(C[1:], ref["C"][1:]) < 1e-12
-    assert abs(C[0] - ref["C"][0]) < 1e-12 * max(1.0, abs(ref["C"][0]))
+    ctol = 1e-12 if prec == "fp64" else 2e-5
+    assert _rel(C[1:], ref["C"][1:]) < ctol
+    assert abs(C[0] - ref["C"][0]) < ctol * max(1.0, abs(ref["C"][0]))
 
 
 def test_plan_tables_match_oracle(ps):
@@ -672,3 +675,31 @@ def test_table5_near_set_sizes(ps):
         nb = pl.near_counts()[0]
         assert abs(nb - mean) < 6 * np.sqrt(mean), (box, nb, mean)
         assert abs(nb_paper - mean) < 6 * np.sqrt(mean)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_nearly_coincident_pairs(ps, prec):
+    """Pairs of charges 1e-4 .. 1e-7 apart, whose mutual field dominates the field
+    norm: the FP32 path's two-float relative coordinates keep the separation
+    exact enough that both potential and field meet the FP32 bar."""
+    g = np.random.default_rng(23)
+    box = (1.0, 1.0, 1.0)
+    x, q = W.uniform_box(1500, box, charges="gauss", seed=23)
+    pairs = []
+    for k, sep in enumerate(np.logspace(-4, -7, 40)):
+        c = g.uniform(-0.45, 0.45, size=3)
+        u = g.standard_normal(3)
+        u /= np.linalg.norm(u)
+        pairs += [c, c + sep * u]
+    xp = np.array(pairs)
+    m = g.uniform(0.5, 1.5, size=len(xp) // 2)
+    qp = np.stack([m, -m], axis=1).ravel()        # each close pair is a dipole
+    X = np.concatenate([x, xp])
+    Q = np.concatenate([q, qp])
+    Q -= Q.mean()
+    ref = OPlan(box, 12, R_b=1.5).solve(X, Q)
+    pl = ps.Plan(box, 12, R_b=1.5, precision=prec, n_max=len(Q))
+    phi, field = pl.eval(_dev(X.T), _dev(Q))
+    pl.status()
+    assert _rel(phi.cpu().numpy(), ref[0]) <= TOL[prec]
+    assert _rel(field.cpu().numpy().T, ref[1]) <= TOL[prec]
