@@ -63,9 +63,11 @@ typedef enum {
 
 typedef enum {
     PS_FP64 = 0,        /* every step in FP64 */
-    PS_FP32_ACC64 = 1   /* particle near sums with FP32 pair arithmetic on
-                           block-relative coordinates (two-float near tiles) and
-                           FP64 accumulation; every other step in FP64 */
+    PS_FP32_ACC64 = 1   /* particle and check-point near sums with FP32 pair
+                           arithmetic on block-relative coordinates (two-float
+                           coordinates for near source groups) and FP64
+                           accumulation; the fit, the zero-mean constant and the
+                           far field in FP64 */
 } ps_precision;
 
 typedef enum {
@@ -245,7 +247,7 @@ ps_status periodic_sum_set_profiling(ps_plan plan, int32_t enable);
 
 /* Durations in milliseconds of the last profiled eval's stages, in this order
  * (PS_N_STAGES values): 0 validation + spatial ordering, 1 near-set build
- * (steps 1-2), 2 tile bounds and target blocks, 3 FP64 check-point sums
+ * (steps 1-2), 2 tile bounds and target blocks, 3 check-point sums
  * (step 3 at Y_c1, Y_c2), 4 least-squares solve (steps 4-5), 5 zero-mean
  * constant (step 6), 6 particle pair sums (step 3 at Y0), 7 far field and
  * combination (steps 7-8).  Synchronizes on the last event.  ms: host [n],

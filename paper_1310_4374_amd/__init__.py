@@ -1,7 +1,7 @@
 """MI355X implementation of the periodized Coulomb sum of Gumerov & Duraiswami,
 "A method to compute periodic sums" (arXiv:1310.4374).
 
-The hot path -- near-set build, FP64 check-point sums, least-squares
+The hot path -- near-set build, check-point sums, least-squares
 coefficients, zero-mean constant, near pair sums and far-field expansion --
 runs in hand-written HIP kernels behind the C ABI of include/periodic_sum.h.
 This package only marshals torch tensors (device memory, streams) into it.

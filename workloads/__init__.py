@@ -136,8 +136,8 @@ def nacl_cell(d=1.0):
 
 def fibonacci_sphere(m, radius):
     """m nearly uniform points on a sphere (spherical Fibonacci lattice):
-    z_t = 1 - (2t + 1)/m, azimuth t * pi (3 - sqrt 5).  A deterministic stand-in
-    for the Thomson points, whose database is not available."""
+    z_t = 1 - (2t + 1)/m, azimuth t * pi (3 - sqrt 5).  Deterministic and cheap;
+    also the starting point of thomson_points."""
     t = np.arange(m, dtype=np.float64)
     z = 1.0 - (2.0 * t + 1.0) / m
     ph = t * np.pi * (3.0 - np.sqrt(5.0))
