@@ -40,6 +40,24 @@ ps_status fail(ps_status s, const char* fmt, ...)
         if (e_ != hipSuccess) return fail(PS_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Makes a device current for the guard's lifetime and then restores the
+// caller's current device: the library never leaves it changed.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int device)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != device) err = hipSetDevice(device);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
 constexpr int kCheckItemTarget = 4096;
 constexpr int kMaxSplit = 256;
@@ -146,7 +164,7 @@ struct ps_plan_s {
 
     ~ps_plan_s()
     {
-        if (device >= 0) (void)hipSetDevice(device);
+        DeviceGuard dev_guard(device);
         if (graph) (void)hipGraphExecDestroy(graph);
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
@@ -249,14 +267,13 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T = Tables();
     const int nsys = pl->nsys;
     T.sys = pl->base;
-    int64_t off = 0, coff = 0;
+    int64_t off = 0;
     for (int s = 0; s < nsys; ++s) {
         SysDev& S = T.sys[s];
         if (n[s] > pl->n_max[s]) { why = "particle count exceeds n_max"; return false; }
         S.n_off = off;
         S.n = n[s];
         off += n[s];
-        (void)coff;
     }
     // per-particle chunks (sort) and near-build items
     for (int s = 0; s < nsys; ++s) {
@@ -271,7 +288,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     }
     const bool separate = m > 0;
     const int bt = pl->bt;
-    // jobs: check sums (FP64, potential) then particle sums
+    // jobs: check-point sums (potential only), then particle sums, then RBF far fields
     T.jobs.resize(3 * nsys);
     int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
     struct Est { int64_t ntb, nbexp; };
@@ -527,12 +544,11 @@ ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
     return PS_OK;
 }
 
-ps_status select_device(int device)
+ps_status check_device(int device)
 {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PS_E_HIP, "no HIP device available");
     if (device < 0 || device >= ndev) return fail(PS_E_INVALID, "device %d out of range [0, %d)", device, ndev);
-    HIPCHK(hipSetDevice(device));
     return PS_OK;
 }
 
@@ -548,8 +564,10 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
         ps_status st = check_params(&prm[s]);
         if (st != PS_OK) return st;
     }
-    ps_status ds = select_device(device);
+    ps_status ds = check_device(device);
     if (ds != PS_OK) return ds;
+    DeviceGuard dev_guard(device);
+    HIPCHK(dev_guard.err);
     ps_plan_s* pl = new (std::nothrow) ps_plan_s();
     if (!pl) return fail(PS_E_NOMEM, "host allocation failed");
     init_plan(pl, nsys, prm, device);
@@ -900,8 +918,10 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
         if (check_params(&q) != PS_OK) return fail(PS_E_IO, "%s: system %d: %s", path, s, g_err.c_str());
     }
     if (pos != buf.size()) return fail(PS_E_IO, "%s: trailing bytes after the last system", path);
-    ps_status ds = select_device(device);
+    ps_status ds = check_device(device);
     if (ds != PS_OK) return ds;
+    DeviceGuard dev_guard(device);
+    HIPCHK(dev_guard.err);
     ps_plan_s* pl = new (std::nothrow) ps_plan_s();
     if (!pl) return fail(PS_E_NOMEM, "host allocation failed");
     init_plan(pl, nsys, prm.data(), device);
@@ -928,7 +948,8 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
     if (m < 0 || m > pl->m_max) return fail(PS_E_INVALID, "m=%lld outside [0, m_max=%lld]", (long long)m, (long long)pl->m_max);
     if (m > 0 && (!tx || !ty || !tz)) return fail(PS_E_INVALID, "target arrays must not be NULL when m > 0");
     if (!phi && !ex && !ey && !ez) return fail(PS_E_INVALID, "no output array given");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const std::vector<int64_t> key = {n, m, reinterpret_cast<int64_t>(tx), reinterpret_cast<int64_t>(ty),
                                       reinterpret_cast<int64_t>(tz)};
@@ -961,7 +982,8 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
         if (n[s] < 1 || n[s] > pl->n_max[s])
             return fail(PS_E_INVALID, "system %d: n=%lld outside [1, n_max=%lld]", s, (long long)n[s], (long long)pl->n_max[s]);
     }
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool same_shape = pl->tab_valid && pl->tab.key == n;
     if (!same_shape) {
@@ -999,7 +1021,8 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
 ps_status periodic_sum_status(ps_plan pl, void* stream)
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     int h = 0;
     HIPCHK(hipMemcpyAsync(&h, pl->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1026,7 +1049,8 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
     out->tile_targets = pl->bt;
     out->n_split = pl->tab.jobs.size() > static_cast<size_t>(pl->nsys) ? pl->tab.jobs[pl->nsys].nsplit : 0;
     out->nsys = pl->nsys;
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
     int64_t nb = 0;
     HIPCHK(hipMemcpy(&nb, pl->d_nnear, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -1050,7 +1074,8 @@ ps_status periodic_sum_near_counts(ps_plan pl, int64_t* out, int32_t nsys)
 {
     if (!pl || !out) return fail(PS_E_INVALID, "NULL argument");
     if (nsys != pl->nsys) return fail(PS_E_INVALID, "nsys %d does not match the plan's %d", nsys, pl->nsys);
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(out, pl->d_nnear, sizeof(int64_t) * nsys, hipMemcpyDeviceToHost));
     return PS_OK;
@@ -1061,7 +1086,8 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
                                 void* stream)
 {
     if (!pl || !offsets) return fail(PS_E_INVALID, "NULL argument");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool f32 = pl->precision == PS_FP32_ACC64;
     const int cand[3] = {64, 128, 256};
@@ -1135,7 +1161,8 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
 ps_status periodic_sum_set_profiling(ps_plan pl, int32_t enable)
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     if (enable && !pl->ev[0])
         for (hipEvent_t& e : pl->ev) HIPCHK(hipEventCreate(&e));
     pl->prof = enable != 0;
@@ -1148,7 +1175,8 @@ ps_status periodic_sum_stage_times(ps_plan pl, double* ms, int32_t n)
     if (!pl || !ms) return fail(PS_E_INVALID, "NULL argument");
     if (n < PS_N_STAGES) return fail(PS_E_INVALID, "need room for %d stages", PS_N_STAGES);
     if (!pl->ev_recorded) return fail(PS_E_INVALID, "no profiled eval has been enqueued");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     HIPCHK(hipEventSynchronize(pl->ev[PS_N_STAGES]));
     for (int k = 0; k < PS_N_STAGES; ++k) {
         float t = 0.f;
@@ -1161,7 +1189,8 @@ ps_status periodic_sum_stage_times(ps_plan pl, double* ms, int32_t n)
 ps_status periodic_sum_last_coefficients(ps_plan pl, double* C)
 {
     if (!pl || !C) return fail(PS_E_INVALID, "NULL argument");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(C, pl->d_coef, sizeof(double) * pl->setups[0].P, hipMemcpyDeviceToHost));
     return PS_OK;
@@ -1236,7 +1265,8 @@ ps_status periodic_sum_energy(ps_plan pl, int64_t n, const double* x, const doub
     if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy is available for single-system plans");
     if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max]", (long long)n);
     if (!x || !y || !z || !q || !energy) return fail(PS_E_INVALID, "NULL argument");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     ps_status s = ensure_forward_tables(pl, n, st);
     if (s != PS_OK) return s;
@@ -1257,7 +1287,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     const std::vector<int64_t> key = {n, 0, 0, 0, 0};
     if (!pl->tab_valid || pl->tab.key != key || pl->last_n != n)
         return fail(PS_E_INVALID, "energy_vjp must follow a forward pass at the same particles");
-    HIPCHK(hipSetDevice(pl->device));
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
     if (exact) {
