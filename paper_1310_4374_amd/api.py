@@ -70,6 +70,28 @@ def _soa(x, device):
     return x.contiguous()
 
 
+def _vec(t, n, device, name):
+    """t as a contiguous float64 device tensor of n elements, or ValueError (the
+    library reads n doubles through the pointer; a wrong dtype, device or size
+    must not reach it)."""
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.dtype != torch.float64 or t.device != device:
+        raise ValueError("%s must be float64 on %s (got %s on %s)" % (name, device, t.dtype, t.device))
+    if t.numel() != n:
+        raise ValueError("%s must have %d elements (got %d)" % (name, n, t.numel()))
+    return t.reshape(n).contiguous()
+
+
+def _field_out(t, n, device, name):
+    """A (3, n) float64 device output whose rows are contiguous."""
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != device:
+        raise ValueError("%s must be a float64 tensor on %s" % (name, device))
+    if tuple(t.shape) != (3, n) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous (3, %d) tensor" % (name, n))
+    return t
+
+
 def _stream(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
@@ -141,8 +163,8 @@ class Plan:
         """phi (N,) and field -grad phi (3, N) at the particles, or at separate
         targets (3, M).  Returns device tensors; enqueued on the current stream."""
         x = _soa(x, self.device)
-        q = q.contiguous()
         n = x.shape[1]
+        q = _vec(q, n, self.device, "q")
         if targets is not None:
             t = _soa(targets, self.device)
             m = t.shape[1]
@@ -156,6 +178,9 @@ class Plan:
             field = torch.empty(3, cnt, dtype=torch.float64, device=self.device)
         else:
             phi, field = out
+            if phi.data_ptr() != _vec(phi, cnt, self.device, "phi").data_ptr():
+                raise ValueError("phi must be contiguous")
+            _field_out(field, cnt, self.device, "field")
         check(lib().periodic_sum_eval(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), m, *tp,
                                       _ptr(phi), _ptr(field[0]), _ptr(field[1]), _ptr(field[2]),
                                       _stream(self.device)))
@@ -183,8 +208,12 @@ class Plan:
 
     def energy(self, x, q, phi=None, field=None):
         x = _soa(x, self.device)
-        q = q.contiguous()
         n = x.shape[1]
+        q = _vec(q, n, self.device, "q")
+        if phi is not None and phi.data_ptr() != _vec(phi, n, self.device, "phi").data_ptr():
+            raise ValueError("phi must be contiguous")
+        if field is not None:
+            _field_out(field, n, self.device, "field")
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         f = field if field is not None else None
         check(lib().periodic_sum_energy(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(e), _ptr(phi),
@@ -194,11 +223,11 @@ class Plan:
 
     def energy_vjp(self, x, q, gE, exact=True):
         x = _soa(x, self.device)
-        q = q.contiguous()
         n = x.shape[1]
+        q = _vec(q, n, self.device, "q")
         dx = torch.empty(3, n, dtype=torch.float64, device=self.device)
         dq = torch.empty(n, dtype=torch.float64, device=self.device)
-        gE = gE.reshape(1).to(torch.float64).contiguous()
+        gE = torch.as_tensor(gE).to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
         check(lib().periodic_sum_energy_vjp(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(gE),
                                             _ptr(dx[0]), _ptr(dx[1]), _ptr(dx[2]), _ptr(dq), int(bool(exact)),
                                             _stream(self.device)))
@@ -207,8 +236,9 @@ class Plan:
 
 def _autotune(obj, x, q, offsets):
     x = _soa(x, obj.device)
-    q = q.contiguous()
     n = x.shape[1]
+    q = _vec(q, n, obj.device, "q")
+    _check_offsets(offsets, n)
     off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
     phi = torch.empty(n, dtype=torch.float64, device=obj.device)
     field = torch.empty(3, n, dtype=torch.float64, device=obj.device)
@@ -217,6 +247,13 @@ def _autotune(obj, x, q, offsets):
                                       _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), ctypes.byref(best),
                                       _stream(obj.device)))
     return best.value
+
+
+def _check_offsets(offsets, n):
+    if len(offsets) < 2 or int(offsets[0]) != 0 or int(offsets[-1]) != n:
+        raise ValueError("offsets must start at 0 and end at the particle count %d" % n)
+    if any(int(b) <= int(a) for a, b in zip(offsets[:-1], offsets[1:])):
+        raise ValueError("offsets must be strictly increasing")
 
 
 def _save(obj, path):
@@ -276,14 +313,20 @@ class BatchedPlan:
     def eval(self, x, q, offsets, out=None):
         """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints."""
         x = _soa(x, self.device)
-        q = q.contiguous()
-        off = (ctypes.c_int64 * (self.nsys + 1))(*[int(v) for v in offsets])
         n = x.shape[1]
+        q = _vec(q, n, self.device, "q")
+        if len(offsets) != self.nsys + 1:
+            raise ValueError("offsets must have nsys + 1 = %d entries" % (self.nsys + 1))
+        _check_offsets(offsets, n)
+        off = (ctypes.c_int64 * (self.nsys + 1))(*[int(v) for v in offsets])
         if out is None:
             phi = torch.empty(n, dtype=torch.float64, device=self.device)
             field = torch.empty(3, n, dtype=torch.float64, device=self.device)
         else:
             phi, field = out
+            if phi.data_ptr() != _vec(phi, n, self.device, "phi").data_ptr():
+                raise ValueError("phi must be contiguous")
+            _field_out(field, n, self.device, "field")
         check(lib().periodic_sum_eval_batched(self._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
                                               _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), _stream(self.device)))
         return phi, field

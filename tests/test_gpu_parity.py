@@ -703,3 +703,24 @@ def test_nearly_coincident_pairs(ps, prec):
     pl.status()
     assert _rel(phi.cpu().numpy(), ref[0]) <= TOL[prec]
     assert _rel(field.cpu().numpy().T, ref[1]) <= TOL[prec]
+
+
+def test_binding_refuses_mismatched_tensors(ps):
+    """float32 or short charge arrays and offsets that do not cover the packed
+    arrays are refused before the library runs; the plan still works after."""
+    c = W.config1()
+    pl = ps.Plan(c["box"], 8, R_b=1.5, n_max=1000)
+    x = _dev(c["x"].T)
+    with pytest.raises(ValueError):
+        pl.eval(x, _dev(c["q"]).float())
+    with pytest.raises(ValueError):
+        pl.eval(x, _dev(c["q"][:999]))
+    with pytest.raises(ValueError):
+        pl.eval(x, _dev(c["q"]), out=(torch.empty(1000, device="cuda:0", dtype=torch.float64),
+                                      torch.empty(1000, 3, device="cuda:0", dtype=torch.float64)))
+    bp = ps.BatchedPlan([dict(box=c["box"], n_max=600), dict(box=c["box"], n_max=600)], p=8, lam=1.8)
+    with pytest.raises(ValueError):
+        bp.eval(x, _dev(c["q"]), [0, 500, 900])
+    phi, _ = pl.eval(x, _dev(c["q"]))
+    pl.status()
+    assert np.isfinite(phi.cpu().numpy()).all()
