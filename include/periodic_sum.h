@@ -141,7 +141,11 @@ ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out);
  *   phi           : device [n] (or [m]) potential.
  *   ex, ey, ez    : device [n] (or [m]) field -grad phi; all three NULL to skip
  *                   nothing (the field is always computed) but not store it.
- * Enqueued on `stream`; returns before the work completes. */
+ * Enqueued on `stream`; returns before the work completes.  The first call
+ * for a given (n, m, target pointers) builds and uploads the plan's work
+ * tables, which synchronizes `stream`; later calls with the same shape only
+ * enqueue kernels (no allocation, memset or synchronization), so they may be
+ * captured into a hipGraph by the caller. */
 ps_status periodic_sum_eval(ps_plan plan, int64_t n,
                             const double* x, const double* y, const double* z, const double* q,
                             int64_t m, const double* tx, const double* ty, const double* tz,
