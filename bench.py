@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt", "bases"],
                     help="cube (default): the headline solve; the others measure the batched, clustered and "
                          "differentiated workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -105,7 +105,8 @@ def main():
     import workloads as W
 
     if args.workload != "cube":
-        out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt}[args.workload](args)
+        out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt,
+               "bases": bench_bases}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -338,6 +339,37 @@ def bench_rocksalt(args):
                      "n_near": pl.info()["n_near_last"]}
     out["value"] = out["fp32"]["steps_per_s"]
     out["ms_per_step"] = out["fp32"]["ms_per_step"]
+    return out
+
+
+def bench_bases(args):
+    """Table 4's comparison (lambda = 1.5, p = 16): the spherical basis and 256
+    Thomson RBF centres on S_b, for 27,000 and 216,000 charges +-1 on grids in the
+    unit cube; solve time per basis and, for 27,000, eps_2 against the stored
+    Ewald sum at 2,000 sampled charges."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    ref = np.load(os.path.join(ROOT, "tests", "golden", "ref_table2.npz"))
+    cen = W.thomson_points(256, 1.5 * np.sqrt(3) / 2)
+    out = {"metric": "periodic solves/s by basis (Table 4 setting)", "unit": "solves/s", "n_gpus": 1,
+           "dtype": "f32" if args.precision == "fp32" else "f64",
+           "config": {"workload": "grid charges +-1 in the unit cube, lambda=1.5, p=16, 256 Thomson RBF centres"}}
+    for m in (30, 60):
+        x, q = W.grid_charges(m, 2)
+        xt, qt = torch.tensor(np.ascontiguousarray(x.T), device=dev), torch.tensor(q, device=dev)
+        for name, kw in (("spherical", {}), ("rbf", dict(centres=cen))):
+            pl = ps.Plan((1.0, 1.0, 1.0), 16, lam=1.5, precision=args.precision, n_max=len(q), **kw)
+            res = {}
+            ms = _time(lambda: res.update(phi=pl.eval(xt, qt)[0]), max(3, args.steps), max(1, args.warmup))
+            pl.status()
+            row = {"N": len(q), "ms_per_solve": ms, "n_near": pl.info()["n_near_last"]}
+            if m == 30:
+                row["eps_2_vs_ewald"] = _rel(res["phi"].cpu().numpy()[ref["subset"]], ref["phi_ewald"])
+            out["%s_N%d" % (name, len(q))] = row
+    out["value"] = 1e3 / out["spherical_N216000"]["ms_per_solve"]
+    out["ms_per_step"] = out["spherical_N216000"]["ms_per_solve"]
     return out
 
 
