@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5 table2]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5 table2 table3]
 """
 import os
 import sys
@@ -93,6 +93,23 @@ def table2():
 
 
 TABLE2_CASES = ((1.3, 34), (1.5, 24), (1.7, 19))
+
+
+def table3():
+    """Sec. 4.2, Table 3: 216,000 charges +-1 on a 60^3 grid in the unit cube; the
+    Ewald sum (O2) and the method (O1) at Table 3's p_min, at 2,000 sampled charges."""
+    x, q = W.grid_charges(60, 3)
+    sub = np.sort(W.rng(8).choice(len(q), 2000, replace=False))
+    phi, _ = Ewald((1.0, 1.0, 1.0)).solve(x, q, targets=x[sub])
+    out = dict(subset=sub, phi_ewald=phi)
+    for lam, p in TABLE3_CASES:
+        out["phi_method_%g_%d" % (lam, p)], _ = Plan((1.0, 1.0, 1.0), p, lam=lam).solve(x, q, targets=x[sub])
+        print("table3 lam %g p %d eps_2 %.3e" % (lam, p, np.linalg.norm(out["phi_method_%g_%d" % (lam, p)] - phi)
+                                                    / np.linalg.norm(phi)), flush=True)
+    _save("ref_table3.npz", **out)
+
+
+TABLE3_CASES = ((1.3, 34), (1.5, 25), (1.7, 19))
 
 
 if __name__ == "__main__":
