@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt", "bases"],
+    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect"],
                     help="cube (default): the headline solve; the others measure the batched, clustered and "
                          "differentiated workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -106,7 +106,7 @@ def main():
 
     if args.workload != "cube":
         out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt,
-               "bases": bench_bases}[args.workload](args)
+               "bases": bench_bases, "aspect": bench_aspect}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -370,6 +370,41 @@ def bench_bases(args):
             out["%s_N%d" % (name, len(q))] = row
     out["value"] = 1e3 / out["spherical_N216000"]["ms_per_solve"]
     out["ms_per_step"] = out["spherical_N216000"]["ms_per_solve"]
+    return out
+
+
+def bench_aspect(args):
+    """Table 5's setting: N = 1e5 uniform charges, lambda = 1.3, p = 34, box aspect
+    ratios 1:1:1 ... 10:2:1; solve time with and without the zero-mean constant,
+    near-set size, and the host set time."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    n = 100000
+    out = {"metric": "periodic solve time by box aspect ratio (Table 5 setting)", "unit": "ms", "n_gpus": 1,
+           "dtype": "f32" if args.precision == "fp32" else "f64", "higher_is_better": False,
+           "config": {"workload": "N=1e5 uniform, q~N(0,1)-mean, lambda=1.3, p=34"}, "boxes": []}
+    for k, box in enumerate([(1, 1, 1), (2, 1, 1), (5, 1, 1), (10, 1, 1), (2, 2, 1), (5, 5, 1), (10, 2, 1)]):
+        d = np.asarray(box, float)
+        x, q = W.uniform_box(n, d, charges="gauss", seed=60 + k)
+        xt, qt = torch.tensor(np.ascontiguousarray(x.T), device=dev), torch.tensor(q, device=dev)
+        row = {"box": list(box)}
+        for mean in ("zero", "none"):
+            t0 = time.perf_counter()
+            pl = ps.Plan(d, 34, lam=1.3, precision=args.precision, mean=mean, n_max=n)
+            if mean == "zero":
+                row["set_s"] = time.perf_counter() - t0
+            ms = _time(lambda: pl.eval(xt, qt), max(2, args.steps), max(1, args.warmup))
+            pl.status()
+            row["ms" if mean == "zero" else "ms_no_mean"] = ms
+            row["n_near"] = pl.info()["n_near_last"]
+            row["cond"] = pl.info()["cond"]
+            del pl
+        out["boxes"].append(row)
+        log("aspect %s: %.1f ms (no mean %.1f ms), N_b %d" % (box, row["ms"], row["ms_no_mean"], row["n_near"]))
+    out["value"] = out["boxes"][0]["ms"]
+    out["ms_per_step"] = out["boxes"][0]["ms"]
     return out
 
 

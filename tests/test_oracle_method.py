@@ -257,3 +257,19 @@ def test_table3_p_min_meets_the_tolerance():
     for lam in (1.3, 1.5, 1.7):
         phi = ref["phi_method_%g_%d" % (lam, rows[lam])]
         assert _rel(phi, ref["phi_ewald"]) < 5e-7
+
+
+def test_aspect_ratio_does_not_degrade_accuracy():
+    """Sec. 4.2 (Table 5 discussion): at fixed lambda = 1.3 and p = 34 the box
+    aspect ratio hardly changes the accuracy.  A 5:1:1 box meets the same
+    tolerance against the Ewald sum as the cube, and its fitting matrix stays well
+    conditioned with the basis evaluated at y/R0."""
+    errs = []
+    for k, box in enumerate([(1.0, 1.0, 1.0), (5.0, 1.0, 1.0)]):
+        x, q = W.uniform_box(600, box, charges="gauss", seed=90 + k)
+        pl = Plan(box, 34, lam=1.3)
+        phi, _ = pl.solve(x, q)
+        ref, _ = Ewald(box).solve(x, q)
+        errs.append(_rel(phi, ref))
+        assert pl.rank == 34 * 34 - 1 and pl.cond < 100
+    assert max(errs) < 5e-7 and errs[1] < 10 * errs[0]
