@@ -813,3 +813,29 @@ def test_table3_accuracy_at_the_papers_p_min(ps, lam, p):
     ph = phi.cpu().numpy()[sub]
     assert _rel(ph, ref["phi_ewald"]) < 5e-7
     assert _rel(ph, ref["phi_method_%g_%d" % (lam, p)]) <= TOL["fp64"]
+
+
+def test_stage_profiling(ps):
+    """set_profiling / stage_times: refused before a profiled eval; afterwards eight
+    non-negative stage durations whose sum matches the eval's own event timing,
+    with the particle pair sums the largest stage at this size."""
+    from paper_1310_4374_amd import PeriodicSumError
+    x, q = W.uniform_box(20000, (1.0, 1.0, 1.0), charges="gauss", seed=99)
+    pl = ps.Plan((1.0, 1.0, 1.0), 12, R_b=1.5, precision="fp32", n_max=20000)
+    xt, qt = _dev(x.T), _dev(q)
+    pl.eval(xt, qt)
+    with pytest.raises(PeriodicSumError, match="INVALID"):
+        pl.stage_times()
+    pl.set_profiling(True)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    pl.eval(xt, qt)
+    b.record()
+    st = pl.stage_times()
+    pl.status()
+    total = a.elapsed_time(b)
+    assert list(st) == list(ps._lib.STAGES)
+    assert all(v >= 0.0 for v in st.values())
+    assert max(st, key=st.get) == "pairs"
+    assert abs(sum(st.values()) - total) < 0.2 * total + 0.05
+    pl.set_profiling(False)
