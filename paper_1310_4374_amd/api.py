@@ -114,10 +114,7 @@ class Plan:
         self.n_max = int(n_max)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().periodic_sum_destroy(h)
-            self._h = None
+        _destroy(self)
 
     @property
     def handle(self):
@@ -256,6 +253,19 @@ def _check_offsets(offsets, n):
         raise ValueError("offsets must be strictly increasing")
 
 
+def _destroy(obj):
+    """Release the plan.  At interpreter exit the module globals may already be
+    gone; the process is ending then and the plan's memory goes with it."""
+    h = getattr(obj, "_h", None)
+    if h is None or not h.value:
+        return
+    try:
+        lib().periodic_sum_destroy(h)
+    except (AttributeError, TypeError):
+        pass
+    obj._h = None
+
+
 def _save(obj, path):
     check(lib().periodic_sum_plan_save(obj._h, str(path).encode()))
 
@@ -292,10 +302,7 @@ class BatchedPlan:
         self.nsys = len(systems)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib().periodic_sum_destroy(h)
-            self._h = None
+        _destroy(self)
 
     def save(self, path):
         """Write the plan's set data and launch shape to a file (see load)."""
