@@ -59,7 +59,7 @@ struct DeviceGuard {
 };
 
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
-constexpr int kCheckItemTarget = 4096;
+constexpr int kCheckWaveTarget = 16384;  // check-point sums of one system: aim for this many waves
 constexpr int kMaxSplit = 256;
 constexpr int kMaxCheckSplit = 2048;
 
@@ -72,12 +72,13 @@ struct DBuf {
 struct Tables {                     // per-shape item tables (depend on the particle counts)
     std::vector<int64_t> key;       // particle counts (and target count) they were built for
     std::vector<CItem> sort_items, far_items;
+    std::vector<CItem> w_items;     // near-size-weighted workgroups: (system, its workgroup count, index among them)
     std::vector<NItem> near_items;
     std::vector<TItem> t_items;
     std::vector<PItem> chk_items, p_items, f_items;
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
     std::vector<SysDev> sys;
-    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0;
+    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0;
 };
 
 }  // namespace
@@ -88,6 +89,7 @@ struct ps_plan_s {
     int precision = 0;
     int mean = 0;
     int bt = 256;
+    int bt_chk = 256;                  // targets per workgroup of the check-point sums
     int n_split_req = 0;
     double split_scale = 1.0;          // autotuned factor on the automatic split count
     int maxP = 0, maxp = 0, maxL = 0;
@@ -122,17 +124,18 @@ struct ps_plan_s {
     double* d_mean_part = nullptr;
     double* d_val_part = nullptr;
     int64_t* d_scan_tot = nullptr;
-    int mean_blocks = 32, val_blocks = 8, scan_blocks = 4;
+    int64_t w_total = 1024;             // workgroups of the near-size-weighted table (box mean, tile bounds)
+    int val_blocks = 8, scan_blocks = 4;
     int64_t capacity = 2048;            // resident pair-sum workgroups on the device
     double* d_osort = nullptr;
     int* d_status = nullptr;
     // item tables on the device
-    CItem *d_sort_items = nullptr, *d_far_items = nullptr;
+    CItem *d_sort_items = nullptr, *d_far_items = nullptr, *d_w_items = nullptr;
     NItem* d_near_items = nullptr;
     TItem* d_t_items = nullptr;
     PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
     PJob* d_jobs = nullptr;
-    int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0;
+    int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0, cap_w = 0;
     Tables tab;
     bool tab_valid = false;
     int64_t last_n = 0;
@@ -231,10 +234,14 @@ ps_status check_params(const ps_params* prm)
 
 // Source splits for one system's pair sum: the workgroup count ntb * S should
 // fill whole rounds of the device's resident capacity (at least four rounds
-// when the sources allow), so that the last round is not mostly idle.
+// when the sources allow), so that the last round is not mostly idle.  A split
+// normally covers at least eight source tiles; a system too small to fill one
+// round that way is split further, down to one tile per split, since there the
+// per-workgroup latency rather than the per-item overhead sets the time.
 int split_for_capacity(int64_t ntb, int64_t capacity, int64_t ntiles_exp, int64_t max_split)
 {
-    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(max_split, std::max<int64_t>(1, ntiles_exp / 8)));
+    const int64_t fill = std::min<int64_t>(ntiles_exp, (capacity + ntb - 1) / ntb);
+    const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(max_split, std::max<int64_t>(ntiles_exp / 8, fill)));
     int best = 1;
     double best_score = -1.0;
     for (int64_t sp = 1; sp <= smax; ++sp) {
@@ -256,6 +263,46 @@ int split_for(int64_t ntb, int64_t target)
     int64_t s = (target + ntb - 1) / ntb;
     if (s >= 8) s = (s + 7) / 8 * 8;
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMaxSplit, s)));
+}
+
+// Expected near-set size of a system with n particles: the ball of radius R_b
+// holds about its volume's share of the lattice's particles.
+double near_expected(const SystemSetup& su, int64_t n)
+{
+    return std::max<double>(1.0, 4.18879020478639 * su.R_b * su.R_b * su.R_b / su.V0 * static_cast<double>(n));
+}
+
+// Source splits of one system's check-point sums (ntb_c target blocks of bt_chk).
+// A single system is split towards kCheckWaveTarget waves, down to one tile per
+// split; in a batch the systems together fill the device, and a split keeps at
+// least four tiles.
+int check_splits(int64_t ntb_c, int bt_chk, int64_t ntiles_exp, int nsys)
+{
+    const int64_t items = (static_cast<int64_t>(kCheckWaveTarget) * 64 / bt_chk + ntb_c - 1) / ntb_c;
+    const int64_t by_tiles = std::max<int64_t>(1, ntiles_exp / (nsys == 1 ? 1 : 4));
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kMaxCheckSplit, items), by_tiles)));
+}
+
+// Targets per workgroup of the check-point sums: the width that wastes the
+// fewest lanes on the 2L check targets of each system, counting each halving
+// of the width as 2.5% dearer (its workgroups stage every source tile for
+// fewer targets).
+int pick_check_bt(const std::vector<SystemSetup>& setups)
+{
+    int best = 256;
+    double best_cost = 0.0;
+    const int widths[3] = {256, 128, 64};
+    for (int k = 0; k < 3; ++k) {
+        const int bt = widths[k];
+        double lanes = 0.0;
+        for (const SystemSetup& su : setups) lanes += static_cast<double>((2 * su.L + bt - 1) / bt * bt);
+        const double cost = lanes * (1.0 + 0.025 * k);
+        if (k == 0 || cost < best_cost) {
+            best_cost = cost;
+            best = bt;
+        }
+    }
+    return best;
 }
 
 // Build every per-shape table for particle counts n[k] (and m separate targets
@@ -309,14 +356,12 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         C.ns_dev = pl->d_nnear + s;
         C.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * (kTile / kGroup) * 6;
         C.tblk = pl->d_tblk_chk + tb_c_off * 4;
-        const int64_t ntb_c = (C.nt + 255) / 256;
-        // expected near-set size: the ball's volume fraction of the lattice (eq. (o2.1))
-        const double nb_exp = std::max<double>(1.0, 4.18879020478639 * su.R_b * su.R_b * su.R_b / su.V0 * S.n);
+        const int64_t ntb_c = (C.nt + pl->bt_chk - 1) / pl->bt_chk;
+        const double nb_exp = near_expected(su, S.n);
         const int64_t ntiles_exp = static_cast<int64_t>(nb_exp / kTile) + 1;
-        C.nsplit = static_cast<int>(std::min<int64_t>(std::min<int64_t>(kMaxCheckSplit, (kCheckItemTarget + ntb_c - 1) / ntb_c),
-                                                      std::max<int64_t>(1, ntiles_exp / 2)));
+        C.nsplit = check_splits(ntb_c, pl->bt_chk, ntiles_exp, nsys);
         C.ncomp = 1;
-        C.bt = 256;
+        C.bt = pl->bt_chk;
         C.part = pl->d_part_chk + pc_off;
         pc_off += static_cast<int64_t>(C.nsplit) * C.nt;
         for (int64_t tb = 0; tb < ntb_c; ++tb) {
@@ -350,6 +395,21 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         tb_p_off += ntb;
         Pj.ncomp = 4;
         Pj.bt = bt;
+    }
+    // near-size-weighted workgroups (box mean, tile bounds): w_total shared in
+    // proportion to the expected near-set sizes, at least one per system
+    {
+        double wsum = 0.0;
+        for (int s = 0; s < nsys; ++s) wsum += static_cast<double>(est[s].nbexp);
+        for (int s = 0; s < nsys; ++s) {
+            const int64_t nb = std::max<int64_t>(
+                1, std::llround(static_cast<double>(pl->w_total) * static_cast<double>(est[s].nbexp) / wsum));
+            T.sys[s].witem_off = static_cast<int64_t>(T.w_items.size());
+            T.sys[s].witem_n = nb;
+            for (int64_t j = 0; j < nb; ++j) T.w_items.push_back(CItem{s, static_cast<int>(nb), j});
+        }
+        T.nw = static_cast<int64_t>(T.w_items.size());
+        if (T.nw > pl->cap_w) { why = "weighted workgroup table too small"; return false; }
     }
     // splits of the particle sums: aim for kItemTarget workgroups over the batch
     int64_t ntb_all = 0;
@@ -429,11 +489,11 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         }
     }
     if (pf_off > pl->part_far_cap) { why = "far-field partial workspace too small"; return false; }
-    // far-field/combine chunks of 256 targets
+    // far-field/combine chunks of kFarChunk targets
     for (int s = 0; s < nsys; ++s) {
         const int64_t nt = T.jobs[nsys + s].nt;
-        for (int64_t b = 0; b < nt; b += 256)
-            T.far_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(256, nt - b)), b});
+        for (int64_t b = 0; b < nt; b += kFarChunk)
+            T.far_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(kFarChunk, nt - b)), b});
     }
     T.nsort = T.sort_items.size();
     T.nfar = T.far_items.size();
@@ -462,6 +522,7 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     UP(pl->d_sys, T.sys)
     UP(pl->d_sort_items, T.sort_items)
     UP(pl->d_far_items, T.far_items)
+    UP(pl->d_w_items, T.w_items)
     UP(pl->d_near_items, T.near_items)
     UP(pl->d_t_items, T.t_items)
     UP(pl->d_chk_items, T.chk_items)
@@ -496,14 +557,14 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     const PJob* cjobs = pl->d_jobs;
     const PJob* pjobs = pl->d_jobs + nsys;
     mark(2);
-    launch_tile_bounds(nsys, nsys == 1 ? 1024 : 64, pjobs, st);
+    launch_tile_bounds_w(T.nw, pjobs, pl->d_w_items, st);
     launch_tblock(T.nt_items, pl->d_jobs, pl->d_t_items, st);
     mark(3);
-    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, 256, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
+    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
-    launch_mean(nsys, pl->mean_blocks, pl->d_sys, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part, pl->d_bm,
+    launch_mean(nsys, T.nw, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part, pl->d_bm,
                 pl->d_coef, st);                                                          // step 6
     mark(6);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
@@ -689,16 +750,22 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         }
     }
     // capacities of the per-shape tables
-    int64_t sort_cap = 0, near_items_cap = 0, far_cap = 0, tb_p = 0, tb_c = 0;
+    int64_t sort_cap = 0, near_items_cap = 0, far_cap = 0, tb_p = 0, tb_c = 0, chk_items_cap = 16;
     int64_t nt_sum = 0;
+    pl->bt_chk = pick_check_bt(pl->setups);
     for (int s = 0; s < nsys; ++s) {
         const SysDev& S = pl->base[s];
         const int64_t nt = std::max<int64_t>(prm[s].n_max, nsys == 1 ? prm[0].m_max : 0);
         sort_cap += (prm[s].n_max + kChunk - 1) / kChunk;
         near_items_cap += S.nimg * ((prm[s].n_max + kChunk - 1) / kChunk);
-        far_cap += (nt + 255) / 256;
+        far_cap += (nt + kFarChunk - 1) / kFarChunk;
         tb_p += (nt + 63) / 64;
-        tb_c += (2 * S.L + 255) / 256;
+        const int64_t ntb_c = (2 * S.L + pl->bt_chk - 1) / pl->bt_chk;
+        tb_c += ntb_c;
+        // the split count grows with the particle count, so n_max bounds it
+        chk_items_cap += ntb_c * check_splits(ntb_c, pl->bt_chk,
+                                              static_cast<int64_t>(near_expected(pl->setups[s], prm[s].n_max) / kTile) + 1,
+                                              nsys);
         nt_sum += nt;
     }
     pl->cap_sort = sort_cap;
@@ -707,7 +774,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     pl->cap_t = tb_p + tb_c;
     pl->tblk_p_cap = tb_p;
     pl->tblk_chk_cap = tb_c;
-    pl->cap_chk = tb_c * kMaxCheckSplit + 16;
+    pl->cap_chk = chk_items_cap;
     pl->cap_p = std::max<int64_t>(tb_p * kMaxSplit, 1);
     pl->part_chk_cap = chk_tot * kMaxCheckSplit + 16;
     pl->part_p_cap = std::max<int64_t>(4 * nt_sum * 16, 4 * (int64_t)kItemTarget * 256 * 2) + 4 * nt_sum * 8;
@@ -747,10 +814,12 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_tblk_p, tb_p * 4)
     AL(pl->d_part_chk, pl->part_chk_cap)
     AL(pl->d_part_p, pl->part_p_cap)
-    pl->mean_blocks = nsys == 1 ? 1024 : 32;
+    pl->w_total = std::max<int64_t>(1024, 32 * (int64_t)nsys);
+    pl->cap_w = pl->w_total + nsys;
     pl->val_blocks = nsys == 1 ? 256 : 8;
     pl->scan_blocks = nsys == 1 ? 256 : 4;
-    AL(pl->d_mean_part, (int64_t)nsys * pl->mean_blocks)
+    AL(pl->d_mean_part, pl->cap_w)
+    AL(pl->d_w_items, pl->cap_w)
     AL(pl->d_val_part, (int64_t)2 * nsys * pl->val_blocks)
     AL(pl->d_scan_tot, (int64_t)nsys * pl->scan_blocks)
     AL(pl->d_status, 1)

@@ -15,6 +15,8 @@ constexpr int kGroup = 32;         // sources per near/far decision (one boundin
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the FP32 rounding.
 constexpr double kFarFactor = 1.5;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
+constexpr int kFarLanes = 4;       // lanes per target in the far-field/combine kernel
+constexpr int kFarChunk = 64;      // targets per far-field/combine workgroup (256 / kFarLanes)
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.
 struct SysDev {
@@ -37,6 +39,7 @@ struct SysDev {
     int64_t inv_off;             // inverse near map: nimg x n (entry index or -1)
     int64_t nitem_begin, nitem_end;  // near-build items of this system
     int64_t f_off;               // L right-hand-side values
+    int64_t witem_off, witem_n;  // this system's workgroups in the near-size-weighted item table
 };
 
 // A pair-sum job: every target of a set against every source of another.

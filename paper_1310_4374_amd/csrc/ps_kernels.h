@@ -17,12 +17,14 @@ void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nite
                  const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
                  int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st);
 void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st);
+void launch_tile_bounds_w(int64_t nwitems, const PJob* jobs, const CItem* witems, hipStream_t st);
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st);
 void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
                   double* coef, double* f, hipStream_t st);
-void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
-                 const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st);
+void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
+                 const double* nx, const double* ny, const double* nz, const double* nq, double* part,
+                 const double* bm, double* coef, hipStream_t st);
 void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
                 const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
                 double* ey, double* ez, double* osort, hipStream_t st);

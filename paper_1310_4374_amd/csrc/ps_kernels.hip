@@ -52,6 +52,19 @@ __device__ double block_reduce(double v, double* sh)
     return r;
 }
 
+// Block-wide int64 sum, valid in every thread (same contract as block_reduce).
+__device__ int64_t block_sum_i64(int64_t v, int64_t* sh)
+{
+    v = wave_sum_i64(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    int64_t r = 0;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+    return r;
+}
+
 // Exclusive block scan of one int64 per thread (blockDim <= 1024); returns the
 // exclusive prefix, and the block total in *total.
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total)
@@ -112,16 +125,18 @@ __global__ __launch_bounds__(256) void k_validate(const SysDev* __restrict__ sys
     }
 }
 
-__global__ void k_validate_final(const double* __restrict__ part, int nblk, int* status)
+// One wave per system: lane-strided partial sums, then a butterfly (fixed order).
+__global__ __launch_bounds__(64) void k_validate_final(const double* __restrict__ part, int nblk, int* status)
 {
-    if (threadIdx.x != 0) return;
     double sq = 0.0, sa = 0.0;
     const double* o = part + 2 * (int64_t)blockIdx.x * nblk;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = threadIdx.x; b < nblk; b += 64) {
         sq += o[2 * b];
         sa += o[2 * b + 1];
     }
-    if (!(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
+    sq = wave_sum(sq);
+    sa = wave_sum(sa);
+    if (threadIdx.x == 0 && !(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -188,7 +203,8 @@ __global__ __launch_bounds__(256) void k_scan_chunks(const SysDev* __restrict__ 
     __shared__ int64_t sh[4];
     const SysDev& S = sys[blockIdx.y];
     int64_t base = 0;
-    for (int b = 0; b < (int)blockIdx.x; ++b) base += btot[(int64_t)blockIdx.y * gridDim.x + b];
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += 256) base += btot[(int64_t)blockIdx.y * gridDim.x + b];
+    base = block_sum_i64(base, sh);
     int64_t lo, hi;
     scan_chunk(S.ncell + 1, gridDim.x, blockIdx.x, &lo, &hi);
     for (int64_t c0 = lo; c0 < hi; c0 += 256) {
@@ -385,13 +401,13 @@ __device__ __forceinline__ double half_max(double v)
     return v;
 }
 
-__global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jobs)
+// Bounding box of every group of kGroup sources of job J, tiles first, first + stride, ...
+__device__ void tile_bounds(const PJob& J, int64_t first, int64_t stride)
 {
-    const PJob& J = jobs[blockIdx.y];
     const int64_t ns = J.ns_dev ? *J.ns_dev : J.ns_host;
     const int64_t ntiles = (ns + kTile - 1) / kTile;
     double* bb = const_cast<double*>(J.tile_bb);
-    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    for (int64_t t = first; t < ntiles; t += stride) {
         const int64_t j = t * kTile + threadIdx.x;
         const bool v = j < ns;
         const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
@@ -407,6 +423,20 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jo
             o[5] = hz;
         }
     }
+}
+
+// grid: blocks x jobs, the same number of workgroups per job
+__global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jobs)
+{
+    tile_bounds(jobs[blockIdx.y], blockIdx.x, gridDim.x);
+}
+
+// one workgroup per item: item (sys, count, start) is workgroup `start` of the
+// `count` that system `sys` has in the near-size-weighted table
+__global__ __launch_bounds__(256) void k_tile_bounds_w(const PJob* __restrict__ jobs, const CItem* __restrict__ witems)
+{
+    const CItem it = witems[blockIdx.x];
+    tile_bounds(jobs[it.sys], it.start, it.count);
 }
 
 __global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, const TItem* __restrict__ items)
@@ -781,40 +811,41 @@ __device__ double prism_corner(double a, double b, double c)
     return F;
 }
 
-__device__ double box_mean_potential(const SysDev& S, double x, double y, double z)
+// Corner k (bit 0: +x side, bit 1: +y, bit 2: +z) of Phi0(x): its signed term over V0.
+__device__ double box_mean_corner(const SysDev& S, int k, double x, double y, double z)
 {
-    double tot = 0.0;
-    for (int k = 0; k < 8; ++k) {
-        const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
-        tot += sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z);
-    }
-    return tot / S.V0;
+    const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
+    return sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z) / S.V0;
 }
 
-__global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, const int64_t* __restrict__ nnear,
-                                              const double* __restrict__ nx, const double* __restrict__ ny,
-                                              const double* __restrict__ nz, const double* __restrict__ nq,
-                                              double* __restrict__ part)
+// One workgroup per item of the near-size-weighted table (see k_tile_bounds_w);
+// part[item] receives the workgroup's share of sum_e q_e Phi0(x_e).
+__global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, const CItem* __restrict__ witems,
+                                              const int64_t* __restrict__ nnear, const double* __restrict__ nx,
+                                              const double* __restrict__ ny, const double* __restrict__ nz,
+                                              const double* __restrict__ nq, double* __restrict__ part)
 {
     __shared__ double sh[4];
-    const SysDev& S = sys[blockIdx.y];
-    const int64_t nb = nnear[blockIdx.y];
+    const CItem it = witems[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    const int64_t nb = nnear[it.sys];
+    // one lane per (near source, corner): q_e times corner k of Phi0(x_e)
     double acc = 0.0;
-    for (int64_t e = blockIdx.x * 256ll + threadIdx.x; e < nb; e += (int64_t)gridDim.x * 256) {
-        const int64_t o = S.near_off + e;
-        acc += nq[o] * box_mean_potential(S, nx[o], ny[o], nz[o]);
+    for (int64_t u = it.start * 256 + threadIdx.x; u < 8 * nb; u += (int64_t)it.count * 256) {
+        const int64_t o = S.near_off + (u >> 3);
+        acc += nq[o] * box_mean_corner(S, static_cast<int>(u & 7), nx[o], ny[o], nz[o]);
     }
     acc = block_reduce<0>(acc, sh);
-    if (threadIdx.x == 0) part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
-__global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part, int nblk,
+__global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part,
                                             const double* __restrict__ bm, double* __restrict__ coef)
 {
     __shared__ double sh[4];
     const SysDev& S = sys[blockIdx.x];
     double sm = 0.0, d = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += 256) sm += part[(int64_t)blockIdx.x * nblk + b];
+    for (int64_t b = threadIdx.x; b < S.witem_n; b += 256) sm += part[S.witem_off + b];
     for (int t = 1 + threadIdx.x; t < S.P; t += 256) d += coef[S.coef_off + t] * bm[S.bm_off + t];
     sm = block_reduce<0>(sm, sh);
     d = block_reduce<0>(d, sh);
@@ -827,18 +858,25 @@ __global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, cons
 // phi_far = sum_{t>=2} C_t R^_t(u), u = y/R0, with the renormalized recurrence
 // (coefficients a, b, c in LDS) differentiated in forward mode: every value is
 // carried with its gradient, which gives grad phi_far without separate
-// gradient coefficients.
-__device__ void far_field(int p, const double* __restrict__ C, const double* __restrict__ A,
-                          const double* __restrict__ B, const double* __restrict__ Cd, double x, double y, double z,
-                          double& phi, double& gx, double& gy, double& gz)
+// gradient coefficients.  The orders m are shared among the kFarLanes lanes of
+// a target: in round r lane g takes m = r kFarLanes + g (r even) or
+// r kFarLanes + kFarLanes - 1 - g (r odd), which keeps the loop lengths of the
+// lanes of one round close and each lane's orders increasing, so that the
+// sectoral values (m, +-m) are carried forward from the lane's previous order.
+__device__ void far_field_lane(int p, int g, const double* __restrict__ C, const double* __restrict__ A,
+                               const double* __restrict__ B, const double* __restrict__ Cd, double x, double y,
+                               double z, double& phi, double& gx, double& gy, double& gz)
 {
     const double r2 = x * x + y * y + z * z;
     double dA = 1.0, dAx = 0.0, dAy = 0.0, dAz = 0.0;
     double dB = 0.0, dBx = 0.0, dBy = 0.0, dBz = 0.0;
     double P0 = 0.0, X0 = 0.0, Y0 = 0.0, Z0 = 0.0;
-    for (int m = 0; m < p; ++m) {
-        if (m > 0) {
-            const double c = Cd[m];
+    int mc = 0;
+    for (int r = 0; r * kFarLanes < p; ++r) {
+        const int m = r * kFarLanes + ((r & 1) ? kFarLanes - 1 - g : g);
+        if (m >= p) continue;
+        while (mc < m) {
+            const double c = Cd[++mc];
             const double nA = -c * (x * dA + y * dB);
             const double nAx = -c * (dA + x * dAx + y * dBx);
             const double nAy = -c * (x * dAy + dB + y * dBy);
@@ -885,11 +923,20 @@ __device__ void far_field(int p, const double* __restrict__ C, const double* __r
     gz = Z0;
 }
 
-// One workgroup per chunk of a system's targets: fixed-order sum of the pair
-// partials, far field and constant, store (to the original particle order when
-// perm is given; `osort` keeps a copy in sorted order: phi, ex, ey, ez).
-// Spherical basis: the far field is evaluated here from the coefficients.  RBF
-// basis: it was summed by the far pair job (fjobs), whose partials hold
+// Sum over the kFarLanes adjacent lanes of one target (butterfly: the same
+// value in each of them, in a fixed order).
+__device__ __forceinline__ double far_lanes_sum(double v)
+{
+    for (int o = 1; o < kFarLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// One workgroup per chunk of kFarChunk targets of a system, kFarLanes lanes per
+// target: fixed-order sum of the pair partials (lane g takes the splits
+// s = g mod kFarLanes), far field and constant, store (to the original particle
+// order when perm is given; `osort` keeps a copy in sorted order: phi, ex, ey,
+// ez).  Spherical basis: the far field is evaluated here from the coefficients.
+// RBF basis: it was summed by the far pair job (fjobs), whose partials hold
 // sum_t C_t K(y - x_t) and its field.
 __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
                                                      const PJob* __restrict__ pjobs, const PJob* __restrict__ fjobs,
@@ -898,6 +945,7 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
                                                      double* __restrict__ ex, double* __restrict__ ey,
                                                      double* __restrict__ ez, double* __restrict__ osort)
 {
+    static_assert(kFarLanes * kFarChunk == 256 && (kFarLanes & (kFarLanes - 1)) == 0, "far-combine lane layout");
     extern __shared__ double lds[];
     const CItem it = items[blockIdx.x];
     const SysDev& S = sys[it.sys];
@@ -917,42 +965,53 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
         for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
     }
     __syncthreads();
-    const int k = threadIdx.x;
-    if (k >= it.count) return;
-    const int64_t i = it.start + k;
+    const int k = threadIdx.x / kFarLanes, g = threadIdx.x % kFarLanes;
+    const bool act = k < it.count;  // every lane stays for the shuffles below
+    const int64_t i = it.start + (act ? k : 0);
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
-    for (int s = 0; s < J.nsplit; ++s) {
-        const double* P_ = J.part + (int64_t)s * 4 * J.nt;
-        ph += P_[i];
-        fx += P_[J.nt + i];
-        fy += P_[2 * J.nt + i];
-        fz += P_[3 * J.nt + i];
+    if (act) {
+#pragma unroll 8
+        for (int s = g; s < J.nsplit; s += kFarLanes) {
+            const double* P_ = J.part + (int64_t)s * 4 * J.nt;
+            ph += P_[i];
+            fx += P_[J.nt + i];
+            fy += P_[2 * J.nt + i];
+            fz += P_[3 * J.nt + i];
+        }
+        if (rbf) {
+            if (g == 0) {
+                const PJob& F = fjobs[it.sys];
+                ph += F.part[i] + coef[S.coef_off];
+                fx += F.part[F.nt + i];
+                fy += F.part[2 * F.nt + i];
+                fz += F.part[3 * F.nt + i];
+            }
+        } else {
+            double pf, gx, gy, gz;
+            far_field_lane(p, g, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy,
+                           gz);
+            ph += pf + (g == 0 ? C[0] : 0.0);
+            fx -= gx * S.inv_R0;
+            fy -= gy * S.inv_R0;
+            fz -= gz * S.inv_R0;
+        }
     }
-    if (rbf) {
-        const PJob& F = fjobs[it.sys];
-        ph += F.part[i] + coef[S.coef_off];
-        fx += F.part[F.nt + i];
-        fy += F.part[2 * F.nt + i];
-        fz += F.part[3 * F.nt + i];
-    } else {
-        double pf, gx, gy, gz;
-        far_field(p, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy, gz);
-        ph += pf + C[0];
-        fx -= gx * S.inv_R0;
-        fy -= gy * S.inv_R0;
-        fz -= gz * S.inv_R0;
-    }
+    ph = far_lanes_sum(ph);
+    fx = far_lanes_sum(fx);
+    fy = far_lanes_sum(fy);
+    fz = far_lanes_sum(fz);
+    if (!act || g != 0) return;
     const int64_t o = perm ? S.n_off + perm[S.n_off + i] : S.n_off + i;
     if (phi) phi[o] = ph;
     if (ex) ex[o] = fx;
     if (ey) ey[o] = fy;
     if (ez) ez[o] = fz;
     if (osort) {
-        const int64_t g = S.n_off + i;
-        osort[4 * g + 0] = ph;
-        osort[4 * g + 1] = fx;
-        osort[4 * g + 2] = fy;
-        osort[4 * g + 3] = fz;
+        const int64_t gi = S.n_off + i;
+        osort[4 * gi + 0] = ph;
+        osort[4 * gi + 1] = fx;
+        osort[4 * gi + 2] = fy;
+        osort[4 * gi + 3] = fz;
     }
 }
 
@@ -1000,6 +1059,11 @@ void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStre
 {
     PS_LAUNCH(k_tile_bounds, dim3(blocks_per_job, njobs), dim3(256), 0, st, jobs);
 }
+void launch_tile_bounds_w(int64_t nwitems, const PJob* jobs, const CItem* witems, hipStream_t st)
+{
+    if (nwitems <= 0) return;
+    PS_LAUNCH(k_tile_bounds_w, dim3((unsigned)nwitems), dim3(256), 0, st, jobs, witems);
+}
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st)
 {
     if (nitems <= 0) return;
@@ -1031,11 +1095,12 @@ void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* c
     PS_LAUNCH(k_rhs, dim3((maxL + 63) / 64, nsys), dim3(1024), 0, st, sys, cjobs, f);
     PS_LAUNCH(k_gemv, dim3((maxP - 1 + 3) / 4, nsys), dim3(256), 0, st, sys, pinv, f, coef);
 }
-void launch_mean(int nsys, int nblk, const SysDev* sys, const int64_t* nnear, const double* nx, const double* ny,
-                 const double* nz, const double* nq, double* part, const double* bm, double* coef, hipStream_t st)
+void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
+                 const double* nx, const double* ny, const double* nz, const double* nq, double* part,
+                 const double* bm, double* coef, hipStream_t st)
 {
-    PS_LAUNCH(k_mean, dim3(nblk, nsys), dim3(256), 0, st, sys, nnear, nx, ny, nz, nq, part);
-    PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, nblk, bm, coef);
+    if (nwitems > 0) PS_LAUNCH(k_mean, dim3((unsigned)nwitems), dim3(256), 0, st, sys, witems, nnear, nx, ny, nz, nq, part);
+    PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, bm, coef);
 }
 void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
                 const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
