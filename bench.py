@@ -89,7 +89,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="cube", choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect"],
+    ap.add_argument("--workload", default="cube",
+                    choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect", "small"],
                     help="cube (default): the headline solve; the others measure the batched, clustered and "
                          "differentiated workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -106,7 +107,7 @@ def main():
 
     if args.workload != "cube":
         out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt,
-               "bases": bench_bases, "aspect": bench_aspect}[args.workload](args)
+               "bases": bench_bases, "aspect": bench_aspect, "small": bench_small}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -370,6 +371,41 @@ def bench_bases(args):
             out["%s_N%d" % (name, len(q))] = row
     out["value"] = 1e3 / out["spherical_N216000"]["ms_per_solve"]
     out["ms_per_step"] = out["spherical_N216000"]["ms_per_solve"]
+    return out
+
+
+def bench_small(args):
+    """Latency of one small solve: unit cube, N = 1,000 and 10,000 uniform
+    charges, p = 12, R_b = 1.5, in FP32 and FP64; eager calls against replays of
+    the same solve captured in a graph."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    steps = max(100, args.steps)
+    out = {"metric": "solve latency of a small box", "unit": "ms", "n_gpus": 1, "higher_is_better": False,
+           "data": "synthetic", "config": {"workload": "unit cube, N uniform, q~N(0,1)-mean, p=12, R_b=1.5"},
+           "rows": []}
+    for n in (1000, 10000):
+        x, q = W.uniform_box(n, (1.0, 1.0, 1.0), charges="gauss", seed=3)
+        xt, qt = torch.tensor(np.ascontiguousarray(x.T), device=dev), torch.tensor(q, device=dev)
+        for prec in ("fp32", "fp64"):
+            pl = ps.Plan((1.0, 1.0, 1.0), 12, R_b=1.5, precision=prec, n_max=n)
+            phi = torch.empty(n, dtype=torch.float64, device=dev)
+            fld = torch.empty(3, n, dtype=torch.float64, device=dev)
+            ms = _time(lambda: pl.eval(xt, qt, out=(phi, fld)), steps, max(5, args.warmup))
+            pl.status()
+            g = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                with torch.cuda.graph(g, stream=side):
+                    pl.eval(xt, qt, out=(phi, fld))
+            torch.cuda.synchronize()
+            ms_graph = _time(g.replay, steps, 5)
+            out["rows"].append({"N": n, "precision": prec, "ms_per_solve": ms, "ms_per_graph_replay": ms_graph})
+    out["value"] = out["rows"][0]["ms_per_solve"]
+    out["ms_per_step"] = out["value"]
     return out
 
 
