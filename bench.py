@@ -90,7 +90,7 @@ def main():
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
     ap.add_argument("--workload", default="cube",
-                    choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect", "small"],
+                    choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect", "small", "select"],
                     help="cube (default): the headline solve; the others measure the batched, clustered and "
                          "differentiated workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -107,7 +107,8 @@ def main():
 
     if args.workload != "cube":
         out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt,
-               "bases": bench_bases, "aspect": bench_aspect, "small": bench_small}[args.workload](args)
+               "bases": bench_bases, "aspect": bench_aspect, "small": bench_small,
+               "select": bench_select}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
 
@@ -405,6 +406,34 @@ def bench_small(args):
             ms_graph = _time(g.replay, steps, 5)
             out["rows"].append({"N": n, "precision": prec, "ms_per_solve": ms, "ms_per_graph_replay": ms_graph})
     out["value"] = out["rows"][0]["ms_per_solve"]
+    out["ms_per_step"] = out["value"]
+    return out
+
+
+def bench_select(args):
+    """Parameter selection (eqs. (o1)-(o2)) on two workloads: Table 2's 27,000
+    grid charges in FP64 at the paper's tolerance 5e-7, and the uniform cube
+    (N = 100,000) in FP32 at 2e-6; lambda in 1.3 ... 1.7."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    dev = torch.device("cuda", 0)
+    lams = (1.3, 1.4, 1.5, 1.6, 1.7)
+    out = {"metric": "fastest (lambda, p) meeting a tolerance on phi", "unit": "ms", "n_gpus": 1,
+           "higher_is_better": False, "data": "synthetic", "settings": []}
+    c = W.config2()
+    cases = [("Table 2: 27,000 grid charges +-1, unit cube", W.grid_charges(30, 2), (1.0, 1.0, 1.0), 5e-7, "fp64", 36),
+             ("uniform cube N=100000, q~N(0,1)-mean", (c["x"], c["q"]), tuple(c["box"]), 2e-6, "fp32", 30)]
+    for name, (x, q), box, tol, prec, p_ref in cases:
+        xt = torch.tensor(np.ascontiguousarray(x.T), device=dev)
+        qt = torch.tensor(q, device=dev)
+        log("selecting for %s (tol %g, %s) ..." % (name, tol, prec))
+        t0 = time.perf_counter()
+        best, rows = ps.select_parameters(box, xt, qt, tol, lambdas=lams, precision=prec, p_ref=p_ref)
+        out["settings"].append({"workload": name, "N": len(q), "tol": tol, "precision": prec, "p_ref": p_ref,
+                                "select_s": time.perf_counter() - t0, "best": best, "rows": rows})
+    b = out["settings"][-1]["best"]
+    out["value"] = b["ms"] if b else None
     out["ms_per_step"] = out["value"]
     return out
 

@@ -224,6 +224,46 @@ ps_status periodic_sum_autotune(ps_plan plan, const int64_t* offsets,
                                 const double* x, const double* y, const double* z, const double* q,
                                 double* phi, double* ex, double* ey, double* ez, double* best_ms, void* stream);
 
+/* One candidate of periodic_sum_select. */
+typedef struct {
+    double  lambda;    /* R_b / R0 */
+    int32_t p;         /* smallest truncation number found whose FP64 solve meets tol; 0: none up to 40 */
+    int32_t n_solves;  /* FP64 solves spent on this candidate (calibration and search) */
+    double  B_P;       /* constant of eps_P = B_P lambda^-p (eq. (o2)) from the solve at p = 8 */
+    double  err;       /* relative L2 error of phi at p, FP64 solve, against the reference */
+    double  err_prec;  /* the same for a solve in the requested precision */
+    double  ms;        /* time per eval at (lambda, p) in the requested precision (HIP events) */
+    double  set_s;     /* host set time of that plan, seconds */
+} ps_select_row;
+
+/* Parameter selection for the caller's charges (Sec. 3.3, eq. (o1)): for each
+ * candidate lambda, the smallest p whose solve meets a relative L2 tolerance
+ * on phi, then the candidate whose solve is fastest.  The errors are measured,
+ * as the paper advises, not predicted: every solve is compared with one FP64
+ * reference solve at the largest lambda and p_ref (0: 36), on all n particles.
+ * Eq. (o2), eps_P = B_P lambda^-p, fitted to a solve at p = 8 and then to the
+ * measured errors, proposes each next p of a bracketing search that ends when p
+ * meets tol and p - 1 does not.  All solves use the zero-mean constant (step 6)
+ * so that they approximate the same potential; the chosen p does not depend on
+ * that choice.
+ *   base       : box, precision, rcond and tile_targets of the plans (host);
+ *                spherical basis and Gauss check points only.
+ *   n, x..q    : particles as for periodic_sum_eval (device, n >= 1).
+ *   tol        : relative L2 tolerance on phi, in (1e-13, 1).
+ *   lambdas    : host [n_lambda] candidates in (1, 4], 1 <= n_lambda <= 64.
+ *   rows       : host [n_lambda], one result per candidate (see ps_select_row).
+ *   best       : index of the fastest candidate whose solve in the requested
+ *                precision meets tol, or -1 if none does.
+ * Builds and frees a plan per solve (host set time grows like p^6: p = 40
+ * takes ~20 s on 8 cores) and allocates n doubles of device memory; synchronizes
+ * the stream.  Errors: PS_E_INVALID, PS_E_UNSUPPORTED (other basis or check
+ * set; a reference not accurate to a tenth of tol), and those of
+ * periodic_sum_plan / periodic_sum_eval / periodic_sum_status. */
+ps_status periodic_sum_select(const ps_params* base, int device, int64_t n,
+                              const double* x, const double* y, const double* z, const double* q,
+                              double tol, const double* lambdas, int32_t n_lambda, int32_t p_ref,
+                              ps_select_row* rows, int32_t* best, void* stream);
+
 /* Near-set sizes N_b of every system after the last completed eval
  * (host [nsys]; synchronizes the device). */
 ps_status periodic_sum_near_counts(ps_plan plan, int64_t* out, int32_t nsys);

@@ -8,4 +8,4 @@ This package only marshals torch tensors (device memory, streams) into it.
 """
 from ._lib import (PS_FP32_ACC64, PS_FP64, PS_MEAN_NONE, PS_MEAN_ZERO, PeriodicSumError,  # noqa: F401
                    lib)
-from .api import BatchedPlan, PeriodicEnergy, Plan  # noqa: F401
+from .api import BatchedPlan, PeriodicEnergy, Plan, select_parameters  # noqa: F401

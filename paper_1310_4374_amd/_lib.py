@@ -23,7 +23,7 @@ EXPORTS = ["periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "per
            "periodic_sum_plan_batched", "periodic_sum_eval_batched", "periodic_sum_status", "periodic_sum_plan_info",
            "periodic_sum_plan_tables", "periodic_sum_last_coefficients", "periodic_sum_set_profiling",
            "periodic_sum_stage_times", "periodic_sum_autotune", "periodic_sum_near_counts", "periodic_sum_destroy",
-           "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load"]
+           "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load", "periodic_sum_select"]
 STAGES = ["sort", "near", "bounds", "check", "solve", "mean", "pairs", "far"]
 
 
@@ -41,6 +41,12 @@ class ps_plan_info(ctypes.Structure):
                 ("rank", ctypes.c_int32), ("R0", ctypes.c_double), ("R_b", ctypes.c_double), ("cond", ctypes.c_double),
                 ("n_near_last", ctypes.c_int64), ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32),
                 ("nsys", ctypes.c_int32)]
+
+
+class ps_select_row(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("p", ctypes.c_int32), ("n_solves", ctypes.c_int32),
+                ("B_P", ctypes.c_double), ("err", ctypes.c_double), ("err_prec", ctypes.c_double),
+                ("ms", ctypes.c_double), ("set_s", ctypes.c_double)]
 
 
 class PeriodicSumError(RuntimeError):
@@ -98,6 +104,10 @@ def lib():
         L.periodic_sum_plan_save.restype = st
         L.periodic_sum_plan_load.argtypes = [ctypes.c_char_p, ctypes.c_int, ctypes.POINTER(vp)]
         L.periodic_sum_plan_load.restype = st
+        L.periodic_sum_select.argtypes = [ctypes.POINTER(ps_params), ctypes.c_int, i64, vp, vp, vp, vp, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.POINTER(ps_select_row), ctypes.POINTER(ctypes.c_int32), vp]
+        L.periodic_sum_select.restype = st
         L.periodic_sum_last_error.argtypes = []
         L.periodic_sum_last_error.restype = ctypes.c_char_p
         _lib = L

@@ -9,7 +9,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import check, lib, ps_params, ps_plan_info
+from ._lib import check, lib, ps_params, ps_plan_info, ps_select_row
 
 _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
@@ -352,6 +352,28 @@ class BatchedPlan:
 
     def status(self):
         check(lib().periodic_sum_status(self._h, _stream(self.device)))
+
+
+def select_parameters(box, x, q, tol, lambdas=(1.3, 1.4, 1.5, 1.6, 1.7), precision="fp32", p_ref=0, rcond=1e-13,
+                      tile_targets=0, device=0):
+    """Smallest p meeting a relative L2 tolerance on phi for each candidate
+    lambda, and the fastest candidate, measured on these charges (eq. (o1)).
+    Returns (best, rows): best is the chosen row (a dict) or None, rows one dict
+    per lambda with keys lambda, p, n_solves, B_P, err, err_prec, ms, set_s."""
+    dev = torch.device("cuda", device)
+    x = _soa(x, dev)
+    n = x.shape[1]
+    q = _vec(q, n, dev, "q")
+    lam = [float(v) for v in lambdas]
+    prm = _params(box, 8, lam=lam[0], precision=precision, rcond=rcond, n_max=n, tile_targets=tile_targets)
+    arr = (ctypes.c_double * len(lam))(*lam)
+    rows = (ps_select_row * len(lam))()
+    best = ctypes.c_int32(-1)
+    check(lib().periodic_sum_select(ctypes.byref(prm), device, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q),
+                                    float(tol), arr, len(lam), int(p_ref), rows, ctypes.byref(best), _stream(dev)))
+    out = [{"lambda": r.lambda_, "p": r.p, "n_solves": r.n_solves, "B_P": r.B_P, "err": r.err,
+            "err_prec": r.err_prec, "ms": r.ms, "set_s": r.set_s} for r in rows]
+    return (out[best.value] if best.value >= 0 else None), out
 
 
 class PeriodicEnergy(torch.autograd.Function):

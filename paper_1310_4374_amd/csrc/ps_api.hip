@@ -4,11 +4,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -1456,6 +1458,229 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     launch_adjoint_finish(n, pl->d_sys, pl->d_adj_job, pl->d_inv, pl->d_sq, pl->d_osort, exact ? 1 : 0, pl->d_dq,
                           pl->d_dx, pl->d_perm, gE, dEdq, dEdx, dEdy, dEdz, st);
     HIPCHK(hipGetLastError());
+    return PS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------
+// parameter selection (Sec. 3.3, eqs. (o1)-(o2))
+// ----------------------------------------------------------------------------
+namespace {
+
+constexpr int kSelectCal = 8;     // truncation number of the calibration solve per lambda
+constexpr int kSelectPMax = 40;   // largest truncation number a plan takes
+
+double rel_l2(const std::vector<double>& a, const std::vector<double>& r)
+{
+    double num = 0.0, den = 0.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        const double d = a[i] - r[i];
+        num += d * d;
+        den += r[i] * r[i];
+    }
+    return den > 0.0 ? std::sqrt(num / den) : std::sqrt(num);
+}
+
+struct DevDoubles {
+    double* p = nullptr;
+    ~DevDoubles()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Solves of the caller's particles with spherical-basis, Gauss-grid plans built
+// from `base` at a given (lambda, p), always with the zero-mean constant so that
+// every solve approximates the same periodic potential.
+struct SelectSolver {
+    const ps_params* base;
+    int device;
+    int64_t n;
+    const double *x, *y, *z, *q;
+    double* d_phi;
+    void* stream;
+
+    // phi of the particles to the host; set_s (may be NULL): host set time;
+    // ms (may be NULL): time per eval over three evals after the first.
+    ps_status run(double lambda, int p, int precision, std::vector<double>& phi, double* set_s, double* ms) const
+    {
+        ps_params prm = *base;
+        prm.p = p;
+        prm.R_b = 0.0;
+        prm.lambda = lambda;
+        prm.precision = precision;
+        prm.mean = PS_MEAN_ZERO;
+        prm.n_max = n;
+        prm.m_max = 0;
+        prm.n_split = 0;
+        prm.basis = PS_BASIS_SPHERICAL;
+        prm.n_centres = 0;
+        prm.centres = nullptr;
+        prm.n_check = 0;
+        prm.check_points = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
+        ps_plan pl = nullptr;
+        ps_status s = periodic_sum_plan(&prm, device, &pl);
+        if (s != PS_OK) return s;
+        struct Destroy {
+            ps_plan p;
+            ~Destroy() { periodic_sum_destroy(p); }
+        } destroy{pl};
+        if (set_s) *set_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        auto eval = [&]() {
+            return periodic_sum_eval(pl, n, x, y, z, q, 0, nullptr, nullptr, nullptr, d_phi, nullptr, nullptr, nullptr,
+                                     stream);
+        };
+        if ((s = eval()) != PS_OK) return s;
+        if (ms) {
+            hipStream_t st = static_cast<hipStream_t>(stream);
+            EventPair ev;
+            HIPCHK(hipEventCreate(&ev.a));
+            HIPCHK(hipEventCreate(&ev.b));
+            HIPCHK(hipEventRecord(ev.a, st));
+            for (int r = 0; r < 3; ++r)
+                if ((s = eval()) != PS_OK) return s;
+            HIPCHK(hipEventRecord(ev.b, st));
+            HIPCHK(hipEventSynchronize(ev.b));
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, ev.a, ev.b));
+            *ms = t / 3.0;
+        }
+        if ((s = periodic_sum_status(pl, stream)) != PS_OK) return s;  // synchronizes
+        phi.resize(static_cast<size_t>(n));
+        HIPCHK(hipMemcpy(phi.data(), d_phi, sizeof(double) * n, hipMemcpyDeviceToHost));
+        return PS_OK;
+    }
+};
+
+// Next truncation number to try for tolerance tol, given the errors measured
+// so far: the model eps = B rho^-p of eq. (o2), with the rate rho taken from
+// the two measured points that bracket (or are nearest to) the target, and lambda
+// itself when there is only one point or the fit is not decreasing.
+int select_next_p(const std::map<int, double>& err, double tol, double lambda, int lo, int hi)
+{
+    auto log_rate = [&](int a, int b) {
+        const double r = std::log(err.at(a) / err.at(b)) / (b - a);
+        return r > 1e-3 ? r : std::log(lambda);
+    };
+    if (lo && hi) {
+        const double lr = log_rate(lo, hi);
+        const int p = lo + static_cast<int>(std::ceil(std::log(err.at(lo) / tol) / lr - 1e-9));
+        return std::min(hi - 1, std::max(lo + 1, p));
+    }
+    if (lo) {  // every measured p fails
+        auto it = err.find(lo);
+        const double lr = it != err.begin() ? log_rate(std::prev(it)->first, lo) : std::log(lambda);
+        const int p = lo + static_cast<int>(std::ceil(std::log(err.at(lo) / tol) / lr - 1e-9));
+        return std::min(kSelectPMax, std::max(lo + 1, p));
+    }
+    // every measured p passes
+    auto it = err.find(hi);
+    auto nx = std::next(it);
+    const double lr = nx != err.end() ? log_rate(hi, nx->first) : std::log(lambda);
+    const int down = static_cast<int>(std::floor(std::log(tol / err.at(hi)) / lr + 1e-9));
+    return std::max(2, hi - std::max(1, down));
+}
+
+}  // namespace
+
+extern "C" {
+
+ps_status periodic_sum_select(const ps_params* base, int device, int64_t n, const double* x, const double* y,
+                              const double* z, const double* q, double tol, const double* lambdas, int32_t n_lambda,
+                              int32_t p_ref, ps_select_row* rows, int32_t* best, void* stream)
+{
+    if (!base || !x || !y || !z || !q || !lambdas || !rows || !best) return fail(PS_E_INVALID, "NULL argument");
+    *best = -1;
+    if (n < 1) return fail(PS_E_INVALID, "n must be at least 1");
+    if (!(tol > 1e-13 && tol < 1.0)) return fail(PS_E_INVALID, "tol must lie in (1e-13, 1)");
+    if (n_lambda < 1 || n_lambda > 64) return fail(PS_E_INVALID, "n_lambda must be in [1, 64]");
+    if (p_ref == 0) p_ref = 36;
+    if (p_ref < kSelectCal + 2 || p_ref > kSelectPMax)
+        return fail(PS_E_INVALID, "p_ref must be in [%d, %d]", kSelectCal + 2, kSelectPMax);
+    if (base->basis != PS_BASIS_SPHERICAL || base->n_check != 0)
+        return fail(PS_E_UNSUPPORTED, "selection covers the spherical basis with the Gauss check points");
+    if (base->precision != PS_FP64 && base->precision != PS_FP32_ACC64)
+        return fail(PS_E_INVALID, "unknown precision %d", base->precision);
+    double lam_ref = 0.0;
+    for (int k = 0; k < n_lambda; ++k) {
+        if (!(lambdas[k] > 1.0 && lambdas[k] <= 4.0)) return fail(PS_E_INVALID, "each lambda must lie in (1, 4]");
+        lam_ref = std::max(lam_ref, lambdas[k]);
+    }
+    DeviceGuard dev_guard(device);
+    HIPCHK(dev_guard.err);
+    DevDoubles d_phi;
+    HIPCHK(hipMalloc(&d_phi.p, sizeof(double) * n));
+    const SelectSolver S{base, device, n, x, y, z, q, d_phi.p, stream};
+    std::vector<double> ref, phi;
+    ps_status s = S.run(lam_ref, p_ref, PS_FP64, ref, nullptr, nullptr);
+    if (s != PS_OK) return s;
+    // the reference must be far more accurate than tol; eq. (o2) through a
+    // calibration solve at the reference's lambda estimates its error
+    if ((s = S.run(lam_ref, kSelectCal, PS_FP64, phi, nullptr, nullptr)) != PS_OK) return s;
+    const double ref_err = rel_l2(phi, ref) * std::pow(lam_ref, kSelectCal - p_ref);
+    if (!(ref_err <= 0.1 * tol))
+        return fail(PS_E_UNSUPPORTED,
+                    "the reference solve (lambda %.3g, p %d) is expected to be accurate to about %.2g, not well below "
+                    "tol %.2g: raise p_ref or lambda",
+                    lam_ref, p_ref, ref_err, tol);
+    float best_ms = 0.f;
+    for (int k = 0; k < n_lambda; ++k) {
+        ps_select_row& R = rows[k];
+        R = ps_select_row{};
+        R.lambda = lambdas[k];
+        std::map<int, double> err;  // FP64 error against the reference, by p
+        auto measure = [&](int p) -> ps_status {
+            if (err.count(p)) return PS_OK;
+            ps_status s2 = S.run(R.lambda, p, PS_FP64, phi, nullptr, nullptr);
+            if (s2 == PS_OK) err[p] = rel_l2(phi, ref);
+            return s2;
+        };
+        if ((s = measure(kSelectCal)) != PS_OK) return s;
+        R.B_P = err[kSelectCal] * std::pow(R.lambda, kSelectCal);  // eq. (o2)
+        int p = static_cast<int>(std::ceil(std::log(R.B_P / tol) / std::log(R.lambda) - 1e-9));
+        p = std::min(kSelectPMax, std::max(2, p));
+        int lo = 0, hi = 0;
+        for (int it = 0; it < 16; ++it) {
+            if ((s = measure(p)) != PS_OK) return s;
+            // hi: smallest p that meets tol; lo: largest failing p below it
+            hi = 0;
+            for (const auto& kv : err)
+                if (kv.second <= tol) {
+                    hi = kv.first;
+                    break;
+                }
+            lo = 0;
+            for (const auto& kv : err)
+                if (kv.second > tol && (!hi || kv.first < hi)) lo = kv.first;
+            if (hi && (hi == 2 || lo == hi - 1)) break;
+            if (!hi && lo >= kSelectPMax) break;
+            p = select_next_p(err, tol, R.lambda, lo, hi);
+        }
+        R.n_solves = static_cast<int32_t>(err.size());
+        if (!(hi && (hi == 2 || lo == hi - 1))) continue;  // tolerance not reached within p <= 40
+        R.p = hi;
+        R.err = err[hi];
+        double ms = 0.0, set_s = 0.0;
+        if ((s = S.run(R.lambda, hi, base->precision, phi, &set_s, &ms)) != PS_OK) return s;
+        R.err_prec = rel_l2(phi, ref);
+        R.ms = ms;
+        R.set_s = set_s;
+        if (R.err_prec <= tol && (*best < 0 || ms < best_ms)) {
+            *best = k;
+            best_ms = static_cast<float>(ms);
+        }
+    }
     return PS_OK;
 }
 

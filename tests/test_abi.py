@@ -128,3 +128,45 @@ def test_plan_file_with_valid_checksum_but_bad_contents_is_refused(tmp_path):
     h = ctypes.c_void_p()
     assert L.periodic_sum_plan_load(str(f).encode(), 0, ctypes.byref(h)) == _lib.PS_E_IO
     assert b"p out of range" in L.periodic_sum_last_error()
+
+
+def _select(prm, tol=1e-6, lambdas=(1.3, 1.5), p_ref=0, n=10, null=None):
+    """periodic_sum_select with stand-in particle pointers: every case here is
+    rejected by the argument checks, before any device call."""
+    L = _lib.lib()
+    fake = ctypes.c_void_p(0x1000)
+    lam = (ctypes.c_double * max(1, len(lambdas)))(*lambdas)
+    rows = (_lib.ps_select_row * max(1, len(lambdas)))()
+    best = ctypes.c_int32(7)
+    args = [ctypes.byref(prm), 0, n, fake, fake, fake, fake, tol, lam, len(lambdas), p_ref, rows, ctypes.byref(best),
+            None]
+    if null is not None:
+        args[null] = None
+    return L.periodic_sum_select(*args), best.value
+
+
+def test_select_row_layout():
+    assert ctypes.sizeof(_lib.ps_select_row) == 8 + 4 + 4 + 5 * 8
+    assert _lib.ps_select_row.B_P.offset == 16
+
+
+@pytest.mark.parametrize("null", [0, 3, 6, 8, 11, 12])
+def test_select_null_arguments_rejected(null):
+    st, _ = _select(_params(), null=null)
+    assert st == _lib.PS_E_INVALID
+
+
+@pytest.mark.parametrize("kw", [dict(tol=0.0), dict(tol=1e-14), dict(tol=1.0), dict(tol=float("nan")),
+                                dict(lambdas=()), dict(lambdas=(1.0,)), dict(lambdas=(1.5, 4.5)),
+                                dict(p_ref=9), dict(p_ref=41), dict(n=0)])
+def test_select_invalid_arguments_rejected(kw):
+    st, best = _select(_params(), **kw)
+    assert st == _lib.PS_E_INVALID
+    assert best == -1
+    assert _lib.lib().periodic_sum_last_error()
+
+
+@pytest.mark.parametrize("kw", [dict(basis=1, n_centres=4), dict(n_check=10)])
+def test_select_other_bases_unsupported(kw):
+    st, _ = _select(_params(**kw))
+    assert st == _lib.PS_E_UNSUPPORTED
