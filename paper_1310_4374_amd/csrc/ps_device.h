@@ -7,12 +7,12 @@ namespace ps {
 constexpr int kTile = 256;         // sources staged per LDS tile
 constexpr int kGroup = 32;         // sources per near/far decision (one bounding box each)
 // A group is "far" for a target block of radius rT (about its centre c) when
-// its bounding box is farther than kFarFactor * rT from c (FP32 kernel).  A far
+// its bounding box is farther than kFarFactor * rT from c (both pair kernels).  A far
 // pair is then more than (kFarFactor - 1) rT apart, and the sum of the two
 // points' distances from c is at most (kFarFactor + 1)/(kFarFactor - 1) times
 // their separation.  That ratio (5 at 1.5) bounds the one-float coordinate
 // error relative to the separation, and its square the cancellation in the
-// expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the FP32 rounding.
+// expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
 constexpr int kFarLanes = 4;       // lanes per target in the far-field/combine kernel

@@ -647,40 +647,48 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     }
 }
 
-// FP64 reciprocal square root: the hardware estimate (relative error ~5e-8)
-// refined by one Newton step y <- y + y/2 (1 - r2 y^2).
-__device__ __forceinline__ double rsqrt64(double r2)
-{
-    double y = __builtin_amdgcn_rsq(r2);
-    const double h = r2 * y;
-    const double e = __builtin_fma(-h, y, 1.0);
-    return __builtin_fma(0.5 * y, e, y);
-}
-
-struct Src64 {
-    double x, y, z, q;
-};
-
+// FP64 pair kernel.  The reciprocal square root is the hardware estimate y0
+// (relative error ~5e-8) refined by one Newton step and kept doubled,
+// u = y0 (3 - r2 y0^2) = 2/r to rounding: with the halved charge (q/2) u = q/r,
+// and (q/r) u^2 = 4 q/r^3, whose factor 4 is removed once at the end.  Far
+// groups (beyond kFarFactor times the block radius) work relative to the block
+// centre c: r^2 = |h|^2 + |s|^2 - 2 h.s and the field h sum w - sum w s
+// (w = 4 q/r^3), with the cancellation bounded as for the FP32 kernel.  Near
+// groups take differences of the absolute coordinates, exact for close pairs,
+// and apply K(0) = 0.  LDS per source: F = (-(x - c), |x - c|^2) for far groups
+// and N = (x, q/2) for near groups (which read the halved charge for both).
 template <bool NEAR, bool FIELD>
-__device__ __forceinline__ void group32_f64(const Src64* __restrict__ sS, double tx, double ty, double tz, double& aP,
-                                            double& aX, double& aY, double& aZ)
+__device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, const double4* __restrict__ sN, double tx,
+                                            double ty, double tz, double h2x, double h2y, double h2z, double tt,
+                                            double& aP, double& aW, double& aX, double& aY, double& aZ)
 {
 #pragma unroll 8
     for (int k = 0; k < kGroup; ++k) {
-        const Src64 s = sS[k];
-        const double dx = tx - s.x, dy = ty - s.y, dz = tz - s.z;
-        double r2 = dx * dx;
-        r2 = __builtin_fma(dy, dy, r2);
-        r2 = __builtin_fma(dz, dz, r2);
-        double ri = rsqrt64(r2);
-        if (NEAR) ri = r2 > 0.0 ? ri : 0.0;  // K(0) = 0
-        const double qr = s.q * ri;
+        const double4 n = sN[k];
+        double r2, dx, dy, dz;
+        if (NEAR) {
+            dx = tx - n.x;
+            dy = ty - n.y;
+            dz = tz - n.z;
+            r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+        } else {
+            const double4 f = sF[k];
+            dx = f.x;  // -(x - c): the far field accumulates w times these
+            dy = f.y;
+            dz = f.z;
+            r2 = __builtin_fma(h2x, f.x, __builtin_fma(h2y, f.y, __builtin_fma(h2z, f.z, tt + f.w)));
+        }
+        const double y0 = __builtin_amdgcn_rsq(r2);
+        double u = y0 * __builtin_fma(-(r2 * y0), y0, 3.0);  // 2/r
+        if (NEAR) u = r2 > 0.0 ? u : 0.0;                     // K(0) = 0
+        const double qr = n.w * u;                            // q/r
         aP += qr;
         if (FIELD) {
-            const double qr3 = qr * (ri * ri);
-            aX = __builtin_fma(qr3, dx, aX);
-            aY = __builtin_fma(qr3, dy, aY);
-            aZ = __builtin_fma(qr3, dz, aZ);
+            const double w = qr * (u * u);  // 4 q/r^3
+            if (!NEAR) aW += w;
+            aX = __builtin_fma(w, dx, aX);
+            aY = __builtin_fma(w, dy, aY);
+            aZ = __builtin_fma(w, dz, aZ);
         }
     }
 }
@@ -688,7 +696,8 @@ __device__ __forceinline__ void group32_f64(const Src64* __restrict__ sS, double
 template <int BT, bool FIELD>
 __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
-    __shared__ Src64 sS[kTile];
+    __shared__ double4 sF[kTile];
+    __shared__ double4 sN[kTile];
     const PItem it = items[blockIdx.x];
     const PJob& J = jobs[it.job];
     const SourceSplit sp = split_range(J, it.split);
@@ -696,41 +705,52 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
     const bool active = i < J.nt;
     const double* tb = J.tblk + (int64_t)it.tb * 4;
     const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
-    // FP64 coordinates need no precision margin: a group is far as soon as it
-    // cannot hold a source coinciding with a target
-    const double far2 = rT * rT;
-    double tx = 0.0, ty = 0.0, tz = 0.0;
+    const double far2 = kFarFactor * kFarFactor * rT * rT;
+    double tx = cx, ty = cy, tz = cz;
     if (active) {
         tx = J.tx[i];
         ty = J.ty[i];
         tz = J.tz[i];
     }
-    double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
+    const double hx = tx - cx, hy = ty - cy, hz = tz - cz;
+    const double tt = __builtin_fma(hz, hz, __builtin_fma(hy, hy, hx * hx));
+    const double h2x = 2.0 * hx, h2y = 2.0 * hy, h2z = 2.0 * hz;
+    double aP = 0.0, aW = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
     for (int64_t t = sp.t0; t < sp.t1; ++t) {
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
             const int64_t j = t * kTile + k;
-            Src64 s = {0x1p500, 0.0, 0.0, 0.0};  // padding: charge 0, coincides with no target
-            if (j < sp.ns) s = Src64{J.sx[j], J.sy[j], J.sz[j], J.sq[j]};
-            sS[k] = s;
+            // padding: charge 0 at 2^500 from the centre, coincides with no target
+            double4 f = make_double4(-0x1p500, 0.0, 0.0, 0x1p1000);
+            double4 n = make_double4(cx + 0x1p500, cy, cz, 0.0);
+            if (j < sp.ns) {
+                const double x = J.sx[j], y = J.sy[j], z = J.sz[j];
+                const double ux = x - cx, uy = y - cy, uz = z - cz;
+                f = make_double4(-ux, -uy, -uz, __builtin_fma(uz, uz, __builtin_fma(uy, uy, ux * ux)));
+                n = make_double4(x, y, z, 0.5 * J.sq[j]);
+            }
+            sF[k] = f;
+            sN[k] = n;
         }
         __syncthreads();
         const uint64_t farm = far_group_mask(J.tile_bb + t * (kTile / kGroup) * 6, cx, cy, cz, far2);
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f64<false, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);
+                group32_f64<false, FIELD>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt, aP, aW,
+                                          aX, aY, aZ);
             else
-                group32_f64<true, FIELD>(sS + gq * kGroup, tx, ty, tz, aP, aX, aY, aZ);
+                group32_f64<true, FIELD>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt, aP, aW,
+                                         aX, aY, aZ);
         }
     }
     if (active) {
         double* P_ = J.part + (int64_t)it.split * J.ncomp * J.nt;
         P_[i] = aP;
         if (FIELD) {
-            P_[J.nt + i] = aX;
-            P_[2 * J.nt + i] = aY;
-            P_[3 * J.nt + i] = aZ;
+            P_[J.nt + i] = 0.25 * __builtin_fma(hx, aW, aX);
+            P_[2 * J.nt + i] = 0.25 * __builtin_fma(hy, aW, aY);
+            P_[3 * J.nt + i] = 0.25 * __builtin_fma(hz, aW, aZ);
         }
     }
 }

@@ -21,7 +21,7 @@ namespace {
 constexpr int kChains = 12;
 constexpr int kThreads = 256;
 
-enum Form { FMA_VVV, MUL_VV, ADD_VV, ADD_VS, RSQ_V, FMA64_VVV };
+enum Form { FMA_VVV, MUL_VV, ADD_VV, ADD_VS, RSQ_V, FMA64_VVV, MUL64_VV, ADD64_VV, RSQ64_V, FMA64_RSQ64 };
 
 template <typename T, int F>
 __global__ __launch_bounds__(kThreads) void chains(T* out, int iters, T a, T b)
@@ -38,8 +38,10 @@ __global__ __launch_bounds__(kThreads) void chains(T* out, int iters, T a, T b)
 #pragma unroll
         for (int u = 0; u < kChains; ++u) {
             if (F == FMA_VVV || F == FMA64_VVV) v[u] = v[u] * la + lb;
-            else if (F == MUL_VV) v[u] = v[u] * la;
-            else if (F == ADD_VV) v[u] = v[u] + w[u];
+            else if (F == MUL_VV || F == MUL64_VV) v[u] = v[u] * la;
+            else if (F == ADD_VV || F == ADD64_VV) v[u] = v[u] + w[u];
+            else if (F == RSQ64_V) v[u] = __builtin_amdgcn_rsq(v[u]);
+            else if (F == FMA64_RSQ64) v[u] = (u % 4 == 0) ? __builtin_amdgcn_rsq(v[u]) : v[u] * la + lb;
             else if (F == ADD_VS) v[u] = v[u] + b;  // b is uniform: an SGPR operand
             else if (F == RSQ_V) v[u] = __builtin_amdgcn_rsqf(v[u]);
         }
@@ -407,6 +409,11 @@ int main()
     run("v_add_f32  (an SGPR operand)", 1, [&] { chains<float, ADD_VS><<<blocks, kThreads>>>(f, iters, 1e-7f, 1e-7f); });
     run("v_rsq_f32", 0, [&] { chains<float, RSQ_V><<<blocks, kThreads>>>(f, iters, 1.f, 0.f); });
     run("v_fma_f64  (VGPR operands)", 2, [&] { chains<double, FMA64_VVV><<<blocks, kThreads>>>(d, iters, 1.0000001, 1e-7); });
+    run("v_mul_f64  (VGPR operands)", 1, [&] { chains<double, MUL64_VV><<<blocks, kThreads>>>(d, iters, 1.0000001, 1e-7); });
+    run("v_add_f64  (VGPR operands)", 1, [&] { chains<double, ADD64_VV><<<blocks, kThreads>>>(d, iters, 1e-7, 1e-7); });
+    run("v_rsq_f64", 0, [&] { chains<double, RSQ64_V><<<blocks, kThreads>>>(d, iters, 1.0, 0.0); });
+    run("v_fma_f64 x3 + v_rsq_f64 (mean)", 0,
+        [&] { chains<double, FMA64_RSQ64><<<blocks, kThreads>>>(d, iters, 1.0000001, 1e-7); });
 
     // instruction streams with fixed registers: nominal cycles per loop iteration and SIMD
     auto run_asm = [&](const char* name, int ninstr, int nblocks, auto launch) {
