@@ -504,18 +504,19 @@ __device__ __forceinline__ bool tile_is_far(const double* bb, double cx, double 
 // LDS holds, per source, A = (-2 s_hi, q) and B = (s_lo, |s_hi|^2), where
 // s_hi + s_lo is the FP64 relative position split into two floats.
 // Near groups: d = (t_hi - s_hi) + (t_lo - s_lo), so close pairs keep their
-// full FP64-derived separation, and K(0) = 0 is applied.
+// full FP64-derived separation, and K(0) = 0 is applied; the field adds
+// 2 w_j d_j (w_j = q_j / r_j^3) to the accumulators.
 // Far groups: one-float coordinates and the expanded form
 // r^2 = |t|^2 + |s|^2 - 2 t.s (an add and three FMAs instead of three
-// differences, a product and two FMAs); the field sum over the group,
-// sum_j w_j (t - s_j) with w_j = q_j / r_j^3, is formed as
-// t * sum_j w_j + (1/2) sum_j w_j (-2 s_j) in FP64 at the flush.  Far pairs
-// are at least (kFarFactor - 1) x (block radius) apart, so the cancellation
-// in the expanded r^2 stays a bounded multiple of the FP32 rounding.
+// differences, a product and two FMAs); the field adds w_j (-2 s_j) and,
+// apart, w_j, whose FP64 sum over the split is multiplied by t once at the end:
+// the field is t sum_j w_j + (1/2) (accumulators).  Far pairs are at least
+// (kFarFactor - 1) x (block radius) apart, so the cancellation in the expanded
+// r^2 stays a bounded multiple of the FP32 rounding.
 template <bool NEAR, bool FIELD>
 __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
                                             float hy, float hz, float lx, float ly, float lz, float tt, double& aP,
-                                            double& aX, double& aY, double& aZ)
+                                            double& aW, double& aX, double& aY, double& aZ)
 {
     float fX = 0.f, fY = 0.f, fZ = 0.f, fW = 0.f;
     float p32 = 0.f;
@@ -562,14 +563,14 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
     aP += (double)p32;
     if (FIELD) {
         if (NEAR) {
+            aX += 2.0 * (double)fX;
+            aY += 2.0 * (double)fY;
+            aZ += 2.0 * (double)fZ;
+        } else {
+            aW += (double)fW;
             aX += (double)fX;
             aY += (double)fY;
             aZ += (double)fZ;
-        } else {
-            const double w = (double)fW;
-            aX += __builtin_fma((double)hx, w, 0.5 * (double)fX);
-            aY += __builtin_fma((double)hy, w, 0.5 * (double)fY);
-            aZ += __builtin_fma((double)hz, w, 0.5 * (double)fZ);
         }
     }
 }
@@ -606,7 +607,7 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
     const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
-    double aP = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
+    double aP = 0.0, aW = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
     for (int64_t t = sp.t0; t < sp.t1; ++t) {
         __syncthreads();
         for (int k = threadIdx.x; k < kTile; k += BT) {
@@ -629,20 +630,20 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aX, aY,
-                                          aZ);
+                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
+                                          aY, aZ);
             else
-                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aX, aY,
-                                         aZ);
+                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
+                                         aY, aZ);
         }
     }
     if (active) {
         double* P_ = J.part + (int64_t)it.split * J.ncomp * J.nt;
         P_[i] = aP;
         if (FIELD) {
-            P_[J.nt + i] = aX;
-            P_[2 * J.nt + i] = aY;
-            P_[3 * J.nt + i] = aZ;
+            P_[J.nt + i] = __builtin_fma((double)hx, aW, 0.5 * aX);
+            P_[2 * J.nt + i] = __builtin_fma((double)hy, aW, 0.5 * aY);
+            P_[3 * J.nt + i] = __builtin_fma((double)hz, aW, 0.5 * aZ);
         }
     }
 }
