@@ -38,11 +38,11 @@ def log(*a):
 
 def pair_kernel_hash():
     """sha256 (16 hex digits) of the FP32 pair kernel's source text, between the
-    comment that opens it and the FP64 reciprocal square root that follows."""
+    comment that opens it and the one that opens the FP64 pair kernel."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_1310_4374_amd", "csrc", "ps_kernels.hip")).read()
     a = src.find("// FP32 pair arithmetic on coordinates relative to the target-block centre.")
-    b = src.find("// FP64 reciprocal square root", a)
+    b = src.find("// FP64 pair kernel.", a)
     if a < 0 or b < 0:
         return None
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
