@@ -130,8 +130,9 @@ typedef struct {
 ps_status periodic_sum_plan(const ps_params* prm, int device, ps_plan* out);
 
 /* Algorithm "get" (Sec. 2.3, steps 1-8) on the device, one system:
- * near-set build (steps 1-2), FP64 near sums at the 2L check points (step 3),
- * f and C = A^+ f (steps 4-5), the zero-mean constant C1 (step 6, eq. (pfx3)-(pfx4)),
+ * near-set build (steps 1-2), near sums at the 2L check points (step 3; pair
+ * arithmetic in the plan's precision, FP64 accumulation), f and C = A^+ f in
+ * FP64 (steps 4-5), the zero-mean constant C1 (step 6, eq. (pfx3)-(pfx4)),
  * near sums and the far-field expansion with its gradient at the targets
  * (steps 3 and 7), and the combination (step 8).
  *   n, x, y, z, q : particle count (1 <= n <= n_max) and device arrays [n].
