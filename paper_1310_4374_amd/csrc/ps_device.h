@@ -15,8 +15,8 @@ constexpr int kGroup = 32;         // sources per near/far decision (one boundin
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
-constexpr int kFarLanes = 4;       // lanes per target in the far-field/combine kernel
-constexpr int kFarChunk = 64;      // targets per far-field/combine workgroup (256 / kFarLanes)
+constexpr int kFarLanes = 8;       // lanes per target in the far-field/combine kernel
+constexpr int kFarChunk = 32;      // targets per far-field/combine workgroup (256 / kFarLanes)
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.
 struct SysDev {
