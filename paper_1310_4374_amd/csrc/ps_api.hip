@@ -559,8 +559,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     const PJob* cjobs = pl->d_jobs;
     const PJob* pjobs = pl->d_jobs + nsys;
     mark(2);
-    launch_tile_bounds_w(T.nw, pjobs, pl->d_w_items, st);
-    launch_tblock(T.nt_items, pl->d_jobs, pl->d_t_items, st);
+    launch_bounds(T.nw, pjobs, pl->d_w_items, T.nt_items, pl->d_jobs, pl->d_t_items, st);
     mark(3);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
     mark(4);

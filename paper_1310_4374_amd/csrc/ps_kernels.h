@@ -17,8 +17,9 @@ void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nite
                  const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
                  int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st);
 void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st);
-void launch_tile_bounds_w(int64_t nwitems, const PJob* jobs, const CItem* witems, hipStream_t st);
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st);
+void launch_bounds(int64_t nwitems, const PJob* pjobs, const CItem* witems, int64_t ntitems, const PJob* jobs,
+                   const TItem* titems, hipStream_t st);
 void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
                   double* coef, double* f, hipStream_t st);

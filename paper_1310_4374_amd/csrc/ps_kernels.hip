@@ -431,18 +431,11 @@ __global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jo
     tile_bounds(jobs[blockIdx.y], blockIdx.x, gridDim.x);
 }
 
-// one workgroup per item: item (sys, count, start) is workgroup `start` of the
-// `count` that system `sys` has in the near-size-weighted table
-__global__ __launch_bounds__(256) void k_tile_bounds_w(const PJob* __restrict__ jobs, const CItem* __restrict__ witems)
-{
-    const CItem it = witems[blockIdx.x];
-    tile_bounds(jobs[it.sys], it.start, it.count);
-}
 
-__global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, const TItem* __restrict__ items)
+// Centre and radius of one target block (all threads of the workgroup call it).
+__device__ void target_block(const PJob* __restrict__ jobs, const TItem it)
 {
     __shared__ double sh[4];
-    const TItem it = items[blockIdx.x];
     const PJob& J = jobs[it.job];
     const int64_t i = (int64_t)it.tb * J.bt + threadIdx.x;
     const bool v = (int)threadIdx.x < J.bt && i < J.nt;
@@ -460,6 +453,27 @@ __global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, c
         o[1] = cy;
         o[2] = cz;
         o[3] = r * (1.0 + 1e-12);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, const TItem* __restrict__ items)
+{
+    target_block(jobs, items[blockIdx.x]);
+}
+
+// Both bounding passes of a solve in one launch: workgroups [0, nw) take the
+// tile bounds of the particle jobs' near lists from the near-size-weighted
+// table (item (sys, count, start) is workgroup `start` of the `count` that
+// system `sys` has), the others one target block each (as k_tblock).
+__global__ __launch_bounds__(256) void k_bounds(const PJob* __restrict__ pjobs, const CItem* __restrict__ witems,
+                                                int64_t nw, const PJob* __restrict__ jobs,
+                                                const TItem* __restrict__ titems)
+{
+    if ((int64_t)blockIdx.x < nw) {
+        const CItem it = witems[blockIdx.x];
+        tile_bounds(pjobs[it.sys], it.start, it.count);
+    } else {
+        target_block(jobs, titems[blockIdx.x - nw]);
     }
 }
 
@@ -839,7 +853,7 @@ __device__ double box_mean_corner(const SysDev& S, int k, double x, double y, do
     return sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z) / S.V0;
 }
 
-// One workgroup per item of the near-size-weighted table (see k_tile_bounds_w);
+// One workgroup per item of the near-size-weighted table (see k_bounds);
 // part[item] receives the workgroup's share of sum_e q_e Phi0(x_e).
 __global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, const CItem* __restrict__ witems,
                                               const int64_t* __restrict__ nnear, const double* __restrict__ nx,
@@ -1080,10 +1094,11 @@ void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStre
 {
     PS_LAUNCH(k_tile_bounds, dim3(blocks_per_job, njobs), dim3(256), 0, st, jobs);
 }
-void launch_tile_bounds_w(int64_t nwitems, const PJob* jobs, const CItem* witems, hipStream_t st)
+void launch_bounds(int64_t nwitems, const PJob* pjobs, const CItem* witems, int64_t ntitems, const PJob* jobs,
+                   const TItem* titems, hipStream_t st)
 {
-    if (nwitems <= 0) return;
-    PS_LAUNCH(k_tile_bounds_w, dim3((unsigned)nwitems), dim3(256), 0, st, jobs, witems);
+    if (nwitems + ntitems <= 0) return;
+    PS_LAUNCH(k_bounds, dim3((unsigned)(nwitems + ntitems)), dim3(256), 0, st, pjobs, witems, nwitems, jobs, titems);
 }
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st)
 {
