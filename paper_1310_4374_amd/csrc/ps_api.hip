@@ -81,6 +81,7 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
     std::vector<SysDev> sys;
     int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0;
+    int far_lanes = 4;              // lanes per target of the far-field/combine kernel
 };
 
 }  // namespace
@@ -491,11 +492,15 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         }
     }
     if (pf_off > pl->part_far_cap) { why = "far-field partial workspace too small"; return false; }
-    // far-field/combine chunks of kFarChunk targets
+    // far-field/combine chunks of 256 / far_lanes targets
+    int64_t nt_all = 0;
+    for (int s = 0; s < nsys; ++s) nt_all += T.jobs[nsys + s].nt;
+    T.far_lanes = nt_all <= kFarWideMax ? 8 : 4;
+    const int far_chunk = 256 / T.far_lanes;
     for (int s = 0; s < nsys; ++s) {
         const int64_t nt = T.jobs[nsys + s].nt;
-        for (int64_t b = 0; b < nt; b += kFarChunk)
-            T.far_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(kFarChunk, nt - b)), b});
+        for (int64_t b = 0; b < nt; b += far_chunk)
+            T.far_items.push_back(CItem{s, static_cast<int>(std::min<int64_t>(far_chunk, nt - b)), b});
     }
     T.nsort = T.sort_items.size();
     T.nfar = T.far_items.size();
@@ -575,7 +580,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
         launch_tile_bounds(nsys, 16, fjobs, st);
         launch_p2p(0, pl->bt, true, T.nf, fjobs, pl->d_f_items, st);
     }
-    launch_far(T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
+    launch_far(T.far_lanes, T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
                separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
     mark(8);
     if (prof) pl->ev_recorded = true;
@@ -759,7 +764,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         const int64_t nt = std::max<int64_t>(prm[s].n_max, nsys == 1 ? prm[0].m_max : 0);
         sort_cap += (prm[s].n_max + kChunk - 1) / kChunk;
         near_items_cap += S.nimg * ((prm[s].n_max + kChunk - 1) / kChunk);
-        far_cap += (nt + kFarChunk - 1) / kFarChunk;
+        far_cap += (nt + 31) / 32;  // chunks of the narrowest far-combine form
         tb_p += (nt + 63) / 64;
         const int64_t ntb_c = (2 * S.L + pl->bt_chk - 1) / pl->bt_chk;
         tb_c += ntb_c;

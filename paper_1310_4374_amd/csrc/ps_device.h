@@ -15,8 +15,10 @@ constexpr int kGroup = 32;         // sources per near/far decision (one boundin
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
-constexpr int kFarLanes = 8;       // lanes per target in the far-field/combine kernel
-constexpr int kFarChunk = 32;      // targets per far-field/combine workgroup (256 / kFarLanes)
+// Lanes per target in the far-field/combine kernel: 8 when a shape has at most
+// kFarWideMax targets in all (spreading each target's work wider shortens a
+// small solve), else 4 (fewer lanes read the split partials of large ones).
+constexpr int64_t kFarWideMax = 65536;
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.
 struct SysDev {

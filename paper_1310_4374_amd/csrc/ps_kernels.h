@@ -26,9 +26,9 @@ void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* c
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
                  const double* nx, const double* ny, const double* nz, const double* nq, double* part,
                  const double* bm, double* coef, hipStream_t st);
-void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
-                const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
-                double* ey, double* ez, double* osort, hipStream_t st);
+void launch_far(int lanes, int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items,
+                const PJob* pjobs, const PJob* fjobs, const double* coef, const double* rec, const int* perm,
+                double* phi, double* ex, double* ey, double* ez, double* osort, hipStream_t st);
 
 }  // namespace ps
 

@@ -893,11 +893,12 @@ __global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, cons
 // phi_far = sum_{t>=2} C_t R^_t(u), u = y/R0, with the renormalized recurrence
 // (coefficients a, b, c in LDS) differentiated in forward mode: every value is
 // carried with its gradient, which gives grad phi_far without separate
-// gradient coefficients.  The orders m are shared among the kFarLanes lanes of
-// a target: in round r lane g takes m = r kFarLanes + g (r even) or
-// r kFarLanes + kFarLanes - 1 - g (r odd), which keeps the loop lengths of the
+// gradient coefficients.  The orders m are shared among the FL lanes of a
+// target: in round r lane g takes m = r FL + g (r even) or r FL + FL - 1 - g
+// (r odd), which keeps the loop lengths of the
 // lanes of one round close and each lane's orders increasing, so that the
 // sectoral values (m, +-m) are carried forward from the lane's previous order.
+template <int FL>
 __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const double* __restrict__ A,
                                const double* __restrict__ B, const double* __restrict__ Cd, double x, double y,
                                double z, double& phi, double& gx, double& gy, double& gz)
@@ -907,8 +908,8 @@ __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const
     double dB = 0.0, dBx = 0.0, dBy = 0.0, dBz = 0.0;
     double P0 = 0.0, X0 = 0.0, Y0 = 0.0, Z0 = 0.0;
     int mc = 0;
-    for (int r = 0; r * kFarLanes < p; ++r) {
-        const int m = r * kFarLanes + ((r & 1) ? kFarLanes - 1 - g : g);
+    for (int r = 0; r * FL < p; ++r) {
+        const int m = r * FL + ((r & 1) ? FL - 1 - g : g);
         if (m >= p) continue;
         while (mc < m) {
             const double c = Cd[++mc];
@@ -958,21 +959,24 @@ __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const
     gz = Z0;
 }
 
-// Sum over the kFarLanes adjacent lanes of one target (butterfly: the same
+// Sum over the FL adjacent lanes of one target (butterfly: the same
 // value in each of them, in a fixed order).
+template <int FL>
 __device__ __forceinline__ double far_lanes_sum(double v)
 {
-    for (int o = 1; o < kFarLanes; o <<= 1) v += __shfl_xor(v, o, 64);
+    for (int o = 1; o < FL; o <<= 1) v += __shfl_xor(v, o, 64);
     return v;
 }
 
-// One workgroup per chunk of kFarChunk targets of a system, kFarLanes lanes per
-// target: fixed-order sum of the pair partials (lane g takes the splits
-// s = g mod kFarLanes), far field and constant, store (to the original particle
+// One workgroup per chunk of 256 / FL targets of a system, FL lanes per
+// target (8 where the shape has few targets, so that each target's work is
+// spread wider; 4 otherwise): fixed-order sum of the pair partials (lane g takes the splits
+// s = g mod FL), far field and constant, store (to the original particle
 // order when perm is given; `osort` keeps a copy in sorted order: phi, ex, ey,
 // ez).  Spherical basis: the far field is evaluated here from the coefficients.
 // RBF basis: it was summed by the far pair job (fjobs), whose partials hold
 // sum_t C_t K(y - x_t) and its field.
+template <int FL>
 __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
                                                      const PJob* __restrict__ pjobs, const PJob* __restrict__ fjobs,
                                                      const double* __restrict__ coef, const double* __restrict__ rec,
@@ -980,7 +984,7 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
                                                      double* __restrict__ ex, double* __restrict__ ey,
                                                      double* __restrict__ ez, double* __restrict__ osort)
 {
-    static_assert(kFarLanes * kFarChunk == 256 && (kFarLanes & (kFarLanes - 1)) == 0, "far-combine lane layout");
+    static_assert(FL >= 1 && FL <= 64 && (FL & (FL - 1)) == 0, "far-combine lane layout");
     extern __shared__ double lds[];
     const CItem it = items[blockIdx.x];
     const SysDev& S = sys[it.sys];
@@ -1000,13 +1004,13 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
         for (int t = threadIdx.x; t < p; t += 256) Cd[t] = rec[S.rec_off + 2 * P + t];
     }
     __syncthreads();
-    const int k = threadIdx.x / kFarLanes, g = threadIdx.x % kFarLanes;
+    const int k = threadIdx.x / FL, g = threadIdx.x % FL;
     const bool act = k < it.count;  // every lane stays for the shuffles below
     const int64_t i = it.start + (act ? k : 0);
     double ph = 0.0, fx = 0.0, fy = 0.0, fz = 0.0;
     if (act) {
 #pragma unroll 8
-        for (int s = g; s < J.nsplit; s += kFarLanes) {
+        for (int s = g; s < J.nsplit; s += FL) {
             const double* P_ = J.part + (int64_t)s * 4 * J.nt;
             ph += P_[i];
             fx += P_[J.nt + i];
@@ -1023,7 +1027,7 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
             }
         } else {
             double pf, gx, gy, gz;
-            far_field_lane(p, g, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy,
+            far_field_lane<FL>(p, g, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy,
                            gz);
             ph += pf + (g == 0 ? C[0] : 0.0);
             fx -= gx * S.inv_R0;
@@ -1031,10 +1035,10 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
             fz -= gz * S.inv_R0;
         }
     }
-    ph = far_lanes_sum(ph);
-    fx = far_lanes_sum(fx);
-    fy = far_lanes_sum(fy);
-    fz = far_lanes_sum(fz);
+    ph = far_lanes_sum<FL>(ph);
+    fx = far_lanes_sum<FL>(fx);
+    fy = far_lanes_sum<FL>(fy);
+    fz = far_lanes_sum<FL>(fz);
     if (!act || g != 0) return;
     const int64_t o = perm ? S.n_off + perm[S.n_off + i] : S.n_off + i;
     if (phi) phi[o] = ph;
@@ -1138,13 +1142,18 @@ void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* wite
     if (nwitems > 0) PS_LAUNCH(k_mean, dim3((unsigned)nwitems), dim3(256), 0, st, sys, witems, nnear, nx, ny, nz, nq, part);
     PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, bm, coef);
 }
-void launch_far(int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items, const PJob* pjobs,
-                const PJob* fjobs, const double* coef, const double* rec, const int* perm, double* phi, double* ex,
-                double* ey, double* ez, double* osort, hipStream_t st)
+void launch_far(int lanes, int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items,
+                const PJob* pjobs, const PJob* fjobs, const double* coef, const double* rec, const int* perm,
+                double* phi, double* ex, double* ey, double* ez, double* osort, hipStream_t st)
 {
     if (nitems <= 0) return;
-    PS_LAUNCH(k_far_combine, dim3((unsigned)nitems), dim3(256), (3 * maxP + maxp) * sizeof(double), st, sys, items,
-              pjobs, fjobs, coef, rec, perm, phi, ex, ey, ez, osort);
+    const size_t lds = (3 * maxP + maxp) * sizeof(double);
+    if (lanes == 8)
+        PS_LAUNCH(k_far_combine<8>, dim3((unsigned)nitems), dim3(256), lds, st, sys, items, pjobs, fjobs, coef, rec,
+                  perm, phi, ex, ey, ez, osort);
+    else
+        PS_LAUNCH(k_far_combine<4>, dim3((unsigned)nitems), dim3(256), lds, st, sys, items, pjobs, fjobs, coef, rec,
+                  perm, phi, ex, ey, ez, osort);
 }
 
 }  // namespace ps
