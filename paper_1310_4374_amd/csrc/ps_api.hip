@@ -60,6 +60,19 @@ struct DeviceGuard {
     DeviceGuard& operator=(const DeviceGuard&) = delete;
 };
 
+// Two timing events, destroyed with the holder (also on early error returns).
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() = default;
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    ~EventPair()
+    {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
 constexpr int kCheckWaveTarget = 16384;  // check-point sums of one system: aim for this many waves
 constexpr int kMaxSplit = 256;
@@ -1167,9 +1180,10 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
     const bool f32 = pl->precision == PS_FP32_ACC64;
     const int cand[3] = {64, 128, 256};
     const double scales[3] = {0.5, 1.0, 2.0};
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    EventPair ev;
+    HIPCHK(hipEventCreate(&ev.a));
+    HIPCHK(hipEventCreate(&ev.b));
+    hipEvent_t e0 = ev.a, e1 = ev.b;
     const int keep_bt = pl->bt;
     const double keep_scale = pl->split_scale;
     const int keep_req = pl->n_split_req;
@@ -1178,8 +1192,10 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
     int best_bt = keep_bt;
     double best_scale = keep_scale;
     ps_status rs = PS_OK;
-    for (const int bt : cand)
-        for (double sc : scales) {
+    for (int ib = 0; ib < 3 && rs == PS_OK; ++ib)
+        for (int is = 0; is < 3 && rs == PS_OK; ++is) {
+            const int bt = cand[ib];
+            const double sc = scales[is];
             pl->bt = bt;
             pl->split_scale = sc;
             pl->tab_valid = false;
@@ -1201,13 +1217,14 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
                 continue;
             }
             if (rs != PS_OK) break;
-            HIPCHK(hipEventRecord(e0, st));
-            for (int r = 0; r < 2 && rs == PS_OK; ++r) rs = run();
-            HIPCHK(hipEventRecord(e1, st));
-            HIPCHK(hipEventSynchronize(e1));
-            if (rs != PS_OK) break;
+            hipError_t he = hipEventRecord(e0, st);
+            for (int r = 0; r < 2 && rs == PS_OK && he == hipSuccess; ++r) rs = run();
+            if (he == hipSuccess) he = hipEventRecord(e1, st);
+            if (he == hipSuccess) he = hipEventSynchronize(e1);
             float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            if (he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+            if (he != hipSuccess && rs == PS_OK) rs = fail(PS_E_HIP, "autotune timing failed: %s", hipGetErrorString(he));
+            if (rs != PS_OK) break;
             ms *= 0.5f;
             if (ms < best) {
                 best = ms;
@@ -1215,10 +1232,9 @@ ps_status periodic_sum_autotune(ps_plan pl, const int64_t* offsets, const double
                 best_scale = sc;
             }
         }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    pl->bt = best_bt;
-    pl->split_scale = best_scale;
+    // the best candidate (or, after an error, the plan's settings before the call)
+    pl->bt = rs == PS_OK ? best_bt : keep_bt;
+    pl->split_scale = rs == PS_OK ? best_scale : keep_scale;
     pl->n_split_req = keep_req;
     pl->tab_valid = false;
     {
@@ -1494,14 +1510,6 @@ struct DevDoubles {
     }
 };
 
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    ~EventPair()
-    {
-        if (a) (void)hipEventDestroy(a);
-        if (b) (void)hipEventDestroy(b);
-    }
-};
 
 // Solves of the caller's particles with spherical-basis, Gauss-grid plans built
 // from `base` at a given (lambda, p), always with the zero-mean constant so that
