@@ -140,6 +140,7 @@ def main():
     prof = not args.no_profile
     plan.set_profiling(prof)
     stage_sum = None
+    per_step = []
     torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
@@ -149,6 +150,7 @@ def main():
         if prof:
             st = plan.stage_times()
             stage_sum = st if stage_sum is None else {k: stage_sum[k] + st[k] for k in st}
+            per_step.append(sum(st.values()))
     end.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -202,6 +204,7 @@ def main():
                    "pairs_per_solve": pairs_per_step, "parallelism": "single GPU"},
         "roofline": roof,
         "stage_ms": stage_ms,
+        "get_ms_median": float(np.median(per_step)) if per_step else None,
     }
     out.update(acc)
     if not args.no_cpu_baseline:
