@@ -124,8 +124,10 @@ def main():
         del a, b
     x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
     q = torch.tensor(c["q"], device=dev)
+    t_set = time.perf_counter()
     plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n,
                    tile_targets=args.tile_targets)
+    t_set = time.perf_counter() - t_set
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty(3, n, dtype=torch.float64, device=dev)
     if args.autotune:
@@ -205,6 +207,7 @@ def main():
         "roofline": roof,
         "stage_ms": stage_ms,
         "get_ms_median": float(np.median(per_step)) if per_step else None,
+        "set_s": t_set,
     }
     out.update(acc)
     if not args.no_cpu_baseline:
