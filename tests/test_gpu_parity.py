@@ -280,6 +280,31 @@ def test_batched_matches_oracle_and_single(ps, prec):
         assert _rel(field[sl], ref[1]) <= TOL[prec]
 
 
+def test_batched_plan_across_particle_counts(ps):
+    """One batched plan evaluated with changing per-system particle counts
+    (each within its n_max), then with the first counts again: the work tables
+    and the captured graph are rebuilt for each shape, and every system matches
+    the oracle (FP32 pairs, bar 1e-6)."""
+    boxes = [(1.0, 1.0, 1.0), (1.5, 1.2, 1.0), (1.1, 1.9, 1.4)]
+    n_max = [1200, 900, 1500]
+    bp = ps.BatchedPlan([dict(box=b, n_max=m) for b, m in zip(boxes, n_max)], p=10, lam=1.7, precision="fp32")
+    for counts in ((1200, 900, 1500), (300, 900, 40), (1200, 900, 1500)):
+        xs, qs = [], []
+        for k, n in enumerate(counts):
+            x, q = W.uniform_box(n, boxes[k], charges="gauss", seed=200 + 10 * k + n % 7)
+            xs.append(x)
+            qs.append(q)
+        off = np.concatenate([[0], np.cumsum(counts)])
+        phi, field = bp.eval(_dev(np.concatenate(xs).T), _dev(np.concatenate(qs)), off)
+        bp.status()
+        phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+        for k in range(3):
+            sl = slice(off[k], off[k + 1])
+            ref = OPlan(boxes[k], 10, lam=1.7).solve(xs[k], qs[k])
+            assert _rel(phi[sl], ref[0]) <= TOL["fp32"], (counts, k)
+            assert _rel(field[sl], ref[1]) <= TOL["fp32"], (counts, k)
+
+
 def test_batched_graph_replays_with_eager_work_between(ps):
     """The batched path replays one captured graph while the caller's buffers
     stay put; new particle data written into those buffers between replays,
