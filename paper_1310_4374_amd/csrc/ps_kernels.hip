@@ -407,22 +407,23 @@ __device__ void tile_bounds(const PJob& J, int64_t first, int64_t stride)
     const int64_t ns = J.ns_dev ? *J.ns_dev : J.ns_host;
     const int64_t ntiles = (ns + kTile - 1) / kTile;
     double* bb = const_cast<double*>(J.tile_bb);
-    for (int64_t t = first; t < ntiles; t += stride) {
-        const int64_t j = t * kTile + threadIdx.x;
-        const bool v = j < ns;
-        const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
-        const double lx = half_min(v ? x : 1e300), ly = half_min(v ? y : 1e300), lz = half_min(v ? z : 1e300);
-        const double hx = half_max(v ? x : -1e300), hy = half_max(v ? y : -1e300), hz = half_max(v ? z : -1e300);
-        if ((threadIdx.x & (kGroup - 1)) == 0) {
-            double* o = bb + (t * (kTile / kGroup) + threadIdx.x / kGroup) * 6;
-            o[0] = lx;
-            o[1] = ly;
-            o[2] = lz;
-            o[3] = hx;
-            o[4] = hy;
-            o[5] = hz;
+    for (int64_t t = first; t < ntiles; t += stride)
+        for (int k = threadIdx.x; k < kTile; k += blockDim.x) {  // blockDim is a multiple of kGroup
+            const int64_t j = t * kTile + k;
+            const bool v = j < ns;
+            const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
+            const double lx = half_min(v ? x : 1e300), ly = half_min(v ? y : 1e300), lz = half_min(v ? z : 1e300);
+            const double hx = half_max(v ? x : -1e300), hy = half_max(v ? y : -1e300), hz = half_max(v ? z : -1e300);
+            if ((k & (kGroup - 1)) == 0) {
+                double* o = bb + (t * (kTile / kGroup) + k / kGroup) * 6;
+                o[0] = lx;
+                o[1] = ly;
+                o[2] = lz;
+                o[3] = hx;
+                o[4] = hy;
+                o[5] = hz;
+            }
         }
-    }
 }
 
 // grid: blocks x jobs, the same number of workgroups per job
