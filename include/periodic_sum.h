@@ -208,7 +208,12 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out);
 /* Batched "get": all systems in one hipGraph launch on `stream`.  offsets: host
  * array [nsys+1], system k owns particles offsets[k] .. offsets[k+1]-1 of the
  * packed device arrays x, y, z, q and of the outputs (targets = particles).
- * Work over (system, target block, source chunk) is ordered largest first. */
+ * Work over (system, target block, source chunk) is ordered largest first.
+ * The graph is captured on the first call for a set of particle counts and of
+ * buffer addresses, and replayed while both stay the same; other counts
+ * rebuild the work tables and capture again, other buffers only capture again
+ * (host work of about 0.4 ms at 512 systems).  Stage profiling records no
+ * events inside the graph. */
 ps_status periodic_sum_eval_batched(ps_plan plan, const int64_t* offsets,
                                     const double* x, const double* y, const double* z, const double* q,
                                     double* phi, double* ex, double* ey, double* ez, void* stream);

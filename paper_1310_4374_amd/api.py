@@ -318,7 +318,9 @@ class BatchedPlan:
         return obj
 
     def eval(self, x, q, offsets, out=None):
-        """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints."""
+        """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints.
+        The captured graph is replayed while the particle counts and the buffers
+        stay the same: in a loop, pass the same out=(phi, field) each time."""
         x = _soa(x, self.device)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")

@@ -559,7 +559,8 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
 {
     const Tables& T = pl->tab;
     const int nsys = pl->nsys;
-    const bool prof = pl->prof && nsys == 1;
+    const bool capturing = pl->cap_stream && st == pl->cap_stream;  // the batched path's private capture stream
+    const bool prof = pl->prof && nsys == 1 && !capturing;           // no event nodes in a captured graph
     auto mark = [&](int k) {
         if (prof) (void)hipEventRecord(pl->ev[k], st);
     };
@@ -1045,8 +1046,8 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
         std::string why;
         pl->tab_valid = false;
         if (!build_tables(pl, std::vector<int64_t>{n}, m, tx, ty, tz, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
-        pl->tab.key = key;
         HIPCHK(upload_tables(pl, st));
+        pl->tab.key = key;
         pl->tab_valid = true;
     }
     pl->last_n = n;
@@ -1075,15 +1076,18 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
     hipStream_t st = static_cast<hipStream_t>(stream);
     const bool same_shape = pl->tab_valid && pl->tab.key == n;
     if (!same_shape) {
+        // the host tables are rebuilt in place: until the upload has succeeded
+        // neither they nor the graph captured from the old ones may be reused
         std::string why;
-        if (!build_tables(pl, n, 0, nullptr, nullptr, nullptr, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
-        pl->tab.key = n;
-        HIPCHK(upload_tables(pl, st));
-        pl->tab_valid = true;
+        pl->tab_valid = false;
         if (pl->graph) {
             (void)hipGraphExecDestroy(pl->graph);
             pl->graph = nullptr;
         }
+        if (!build_tables(pl, n, 0, nullptr, nullptr, nullptr, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
+        HIPCHK(upload_tables(pl, st));
+        pl->tab.key = n;
+        pl->tab_valid = true;
     }
     // one graph per (shape, buffers): captured on a private stream, launched on the caller's
     std::vector<const void*> key = {x, y, z, q, phi, ex, ey, ez};
@@ -1302,8 +1306,8 @@ ps_status ensure_forward_tables(ps_plan_s* pl, int64_t n, hipStream_t st)
         pl->tab_valid = false;
         if (!build_tables(pl, std::vector<int64_t>{n}, 0, nullptr, nullptr, nullptr, why))
             return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
-        pl->tab.key = key;
         HIPCHK(upload_tables(pl, st));
+        pl->tab.key = key;
         pl->tab_valid = true;
     }
     return PS_OK;

@@ -352,6 +352,33 @@ def test_batched_graph_replays_with_eager_work_between(ps):
     assert np.array_equal(phi.cpu().numpy(), ph0)
 
 
+def test_batched_entry_on_a_single_plan_with_profiling_and_new_buffers(ps):
+    """A one-box plan driven through the batched entry point while stage
+    profiling is on: the graph holds no event records (stage times stay those
+    of the last eager eval), and a replay into other output buffers (the graph
+    is captured again for them) gives the eager eval's results bit for bit."""
+    import ctypes
+    n = 1500
+    x, q = W.uniform_box(n, (1.0, 1.2, 0.9), charges="gauss", seed=41)
+    pl = ps.Plan((1.0, 1.2, 0.9), 10, lam=1.7, precision="fp32", n_max=n)
+    pl.set_profiling(True)
+    xt, qt = _dev(x.T), _dev(q)
+    phi_e, field_e = pl.eval(xt, qt)
+    st = pl.stage_times()
+    off = (ctypes.c_int64 * 2)(0, n)
+    L = ps._lib.lib()
+    for rep in range(3):
+        phi = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda:0")
+        field = torch.full((3, n), float("nan"), dtype=torch.float64, device="cuda:0")
+        ps._lib.check(L.periodic_sum_eval_batched(
+            pl.handle, off, *(ctypes.c_void_p(t.data_ptr()) for t in (xt[0], xt[1], xt[2], qt, phi, field[0], field[1], field[2])),
+            ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+        pl.status()
+        assert torch.equal(phi, phi_e) and torch.equal(field, field_e), rep
+    assert pl.stage_times() == st
+    pl.set_profiling(False)
+
+
 # --------------------------------------------------------------------------
 # full-size workloads: sampled particles against stored oracle values
 # (tests/golden/make_reference.py, oracle only)
