@@ -33,7 +33,11 @@
  *     are asynchronous: they only enqueue work on that stream.  Argument errors
  *     are reported synchronously; data errors (non-neutral charges, particles
  *     outside the box) are detected on the device and returned by
- *     periodic_sum_status(), which synchronizes the stream.
+ *     periodic_sum_status(), which synchronizes the stream.  With the
+ *     environment variable PS_VALIDATE set (to anything but "0") when a plan is
+ *     made, that plan's periodic_sum_eval, _eval_batched and _energy calls
+ *     synchronize the stream and return those data errors themselves, except
+ *     while the stream is being captured into a graph.
  *   - Concurrency: one plan serves one eval at a time (its workspace is shared);
  *     different plans are independent.  Results are bitwise reproducible for
  *     identical inputs and plan.

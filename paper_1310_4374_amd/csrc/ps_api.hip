@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -176,6 +177,8 @@ struct ps_plan_s {
     bool prof = false;
     hipEvent_t ev[PS_N_STAGES + 1] = {};
     bool ev_recorded = false;
+    // PS_VALIDATE set (not "0") when the plan was made: evals return data errors themselves
+    bool sync_validate = false;
     // batched graph
     hipGraphExec_t graph = nullptr;
     std::vector<const void*> graph_key;
@@ -610,6 +613,8 @@ ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
     pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
     pl->n_split_req = prm[0].n_split;
     pl->m_max = nsys == 1 ? prm[0].m_max : 0;
+    const char* v = std::getenv("PS_VALIDATE");
+    pl->sync_validate = v && *v && std::strcmp(v, "0") != 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess)
         pl->capacity = static_cast<int64_t>(prop.multiProcessorCount) *
@@ -634,6 +639,19 @@ ps_status check_device(int device)
 }
 
 ps_status finish_plan(ps_plan_s* pl, ps_plan* out);
+
+// End of an eval: with synchronous validation, wait for the stream and return
+// the data errors that periodic_sum_status would report (not while the stream
+// is being captured into a graph, where waiting is not allowed).
+ps_status eval_done(ps_plan_s* pl, hipStream_t st)
+{
+    HIPCHK(hipGetLastError());
+    if (!pl->sync_validate) return PS_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return PS_OK;
+    return periodic_sum_status(pl, st);
+}
 
 ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
 {
@@ -1052,8 +1070,7 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
     }
     pl->last_n = n;
     enqueue_get(pl, x, y, z, q, m > 0, phi, ex, ey, ez, st);
-    HIPCHK(hipGetLastError());
-    return PS_OK;
+    return eval_done(pl, st);
 }
 
 ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const double* x, const double* y,
@@ -1107,7 +1124,7 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
         pl->graph_key = key;
     }
     HIPCHK(hipGraphLaunch(pl->graph, st));
-    return PS_OK;
+    return eval_done(pl, st);
 }
 
 ps_status periodic_sum_status(ps_plan pl, void* stream)
@@ -1368,8 +1385,7 @@ ps_status periodic_sum_energy(ps_plan pl, int64_t n, const double* x, const doub
     pl->last_n = n;
     enqueue_get(pl, x, y, z, q, false, phi, ex, ey, ez, st);
     launch_energy(1, pl->d_sys, pl->d_sq, pl->d_osort, energy, st);
-    HIPCHK(hipGetLastError());
-    return PS_OK;
+    return eval_done(pl, st);
 }
 
 ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const double* y, const double* z,

@@ -187,6 +187,41 @@ def test_status_reports_data_errors(ps):
         ps.Plan(c["box"], 4, R_b=1.5, n_max=2 ** 30)
 
 
+def test_synchronous_validation(ps, monkeypatch):
+    """With PS_VALIDATE set when a plan is made, eval itself reports the data
+    errors (single and batched plans); without it, eval only enqueues and the
+    error waits for status()."""
+    from paper_1310_4374_amd import PeriodicSumError
+    c = W.config1()
+    x, q = _dev(c["x"].T), _dev(c["q"])
+    q_bad = q.clone()
+    q_bad[0] += 0.5
+    monkeypatch.setenv("PS_VALIDATE", "1")
+    pl = ps.Plan(c["box"], 8, R_b=1.5, n_max=1000)
+    bp = ps.BatchedPlan([dict(box=c["box"], n_max=600), dict(box=c["box"], n_max=400)], p=8, R_b=1.5, precision="fp64")
+    pl.eval(x, q)
+    with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
+        pl.eval(x, q_bad)
+    pl.eval(x, q)
+    x_out = x.clone()
+    x_out[0, 7] = 0.5
+    with pytest.raises(PeriodicSumError, match="OUT_OF_BOX"):
+        pl.energy(x_out, q)
+    # two neutral halves of the +-1 charges; then one of them made non-neutral
+    order = np.argsort(c["q"], kind="stable")
+    idx = np.concatenate([order[:300], order[-300:], order[300:500], order[-500:-300]])
+    xb, qb = x[:, torch.tensor(idx, device="cuda:0")].contiguous(), q[torch.tensor(idx, device="cuda:0")].contiguous()
+    bp.eval(xb, qb, [0, 600, 1000])
+    qb[600] = 0.0
+    with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
+        bp.eval(xb, qb, [0, 600, 1000])
+    monkeypatch.setenv("PS_VALIDATE", "0")
+    pl2 = ps.Plan(c["box"], 8, R_b=1.5, n_max=1000)
+    pl2.eval(x, q_bad)
+    with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
+        pl2.status()
+
+
 def test_bitwise_reproducible(ps):
     c = W.config1()
     for prec in ("fp64", "fp32"):
