@@ -89,12 +89,13 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<int64_t> key;       // particle counts (and target count) they were built for
     std::vector<CItem> sort_items, far_items;
     std::vector<CItem> w_items;     // near-size-weighted workgroups: (system, its workgroup count, index among them)
+    std::vector<MItem> m_items;     // corner box mean: chunks of kMeanWave particles x corner-column slices
     std::vector<NItem> near_items;
     std::vector<TItem> t_items;
     std::vector<PItem> chk_items, p_items, f_items;
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
     std::vector<SysDev> sys;
-    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0;
+    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0, nm = 0;
     int far_lanes = 4;              // lanes per target of the far-field/combine kernel
 };
 
@@ -148,6 +149,11 @@ struct ps_plan_s {
     int* d_status = nullptr;
     // item tables on the device
     CItem *d_sort_items = nullptr, *d_far_items = nullptr, *d_w_items = nullptr;
+    MItem* d_m_items = nullptr;  // workgroups of the corner box mean
+    int* d_imap = nullptr;       // dense image maps of the corner box mean
+    double* d_mpart = nullptr;   // its per-workgroup partial sums
+    int64_t cap_m = 0;           // its workgroup capacity
+    int mcols = 0;               // its largest image-column count (LDS per workgroup)
     NItem* d_near_items = nullptr;
     TItem* d_t_items = nullptr;
     PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
@@ -430,6 +436,38 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         T.nw = static_cast<int64_t>(T.w_items.size());
         if (T.nw > pl->cap_w) { why = "weighted workgroup table too small"; return false; }
     }
+    // box mean by corners: chunks of kMeanWave particles, their corner columns
+    // split so that the launch has about kMeanTargetWaves workgroups; below
+    // kMeanMinWaves the per-entry kernel serves every system
+    {
+        int64_t chunks = 0, waves = 0;
+        for (const SysDev& S : T.sys)
+            if (S.mcorner) chunks += (S.n + kMeanWave - 1) / kMeanWave;
+        const int64_t want = chunks > 0 ? (kMeanTargetWaves + chunks - 1) / chunks : 1;
+        std::vector<int> slices(nsys, 0);
+        for (int s = 0; s < nsys; ++s) {
+            const SysDev& S = T.sys[s];
+            if (!S.mcorner) continue;
+            slices[s] = static_cast<int>(std::min<int64_t>(2 * S.mr[0] + 2, want));
+            waves += (S.n + kMeanWave - 1) / kMeanWave * slices[s];
+        }
+        const bool corners = waves >= kMeanMinWaves;
+        for (int s = 0; s < nsys; ++s) {
+            SysDev& S = T.sys[s];
+            S.mcorner = S.mcorner && corners;
+            S.mitem_off = static_cast<int64_t>(T.m_items.size());
+            if (S.mcorner) {
+                const int ncx = 2 * S.mr[0] + 2;  // corner columns along x
+                for (int64_t b = 0; b < S.n; b += kMeanWave)
+                    for (int k = 0; k < slices[s]; ++k)
+                        T.m_items.push_back(MItem{s, static_cast<int>(std::min<int64_t>(kMeanWave, S.n - b)), b,
+                                                  k * ncx / slices[s], (k + 1) * ncx / slices[s] - 1});
+            }
+            S.mitem_n = static_cast<int64_t>(T.m_items.size()) - S.mitem_off;
+        }
+    }
+    T.nm = static_cast<int64_t>(T.m_items.size());
+    if (T.nm > pl->cap_m) { why = "box-mean workgroup table too small"; return false; }
     // splits of the particle sums: aim for kItemTarget workgroups over the batch
     int64_t ntb_all = 0;
     for (int s = 0; s < nsys; ++s) ntb_all += est[s].ntb;
@@ -546,6 +584,7 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     UP(pl->d_sort_items, T.sort_items)
     UP(pl->d_far_items, T.far_items)
     UP(pl->d_w_items, T.w_items)
+    UP(pl->d_m_items, T.m_items)
     UP(pl->d_near_items, T.near_items)
     UP(pl->d_t_items, T.t_items)
     UP(pl->d_chk_items, T.chk_items)
@@ -587,8 +626,9 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
-    launch_mean(nsys, T.nw, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part, pl->d_bm,
-                pl->d_coef, st);                                                          // step 6
+    launch_mean(nsys, T.nw, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part,
+                T.nm, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
+                pl->d_bm, pl->d_coef, st);  // step 6
     mark(6);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
     mark(7);
@@ -693,6 +733,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     // pack offsets
     int64_t img_tot = 0, pinv_tot = 0, coef_tot = 0, rec_tot = 0, f_tot = 0;
     int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0, cen_tot = 0, pfar = 0;
+    int64_t imap_tot = 0, mitems_cap = 0;
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         SysDev& S = pl->base[s];
@@ -737,6 +778,17 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         near_tot += (S.near_cap + kTile - 1) / kTile * kTile;  // tiles never straddle systems
         S.img_off = img_tot;
         img_tot += S.nimg;
+        // the corner box mean takes systems whose image range fits its LDS masks
+        for (int k = 0; k < 3; ++k) S.mr[k] = 0;
+        for (size_t mi = 0; mi < su.images.size(); ++mi)
+            S.mr[mi % 3] = std::max(S.mr[mi % 3], std::abs(su.images[mi]));
+        S.mcorner = 2 * S.mr[2] + 1 <= kMeanZ && (2 * int64_t(S.mr[0]) + 1) * (2 * int64_t(S.mr[1]) + 1) <= kMeanCols;
+        S.imap_off = imap_tot;
+        if (S.mcorner) {
+            imap_tot += static_cast<int64_t>(2 * S.mr[0] + 1) * (2 * S.mr[1] + 1) * (2 * S.mr[2] + 1);
+            mitems_cap += (prm[s].n_max + kMeanWave - 1) / kMeanWave * (2 * S.mr[0] + 2);
+            pl->mcols = std::max(pl->mcols, (2 * S.mr[0] + 1) * (2 * S.mr[1] + 1));
+        }
         S.chk_off = chk_tot;
         chk_tot += 2 * S.L;
         S.pinv_off = pinv_tot;
@@ -766,11 +818,19 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     // host tables
     std::vector<double> h_img(img_tot * 3), h_chk(chk_tot * 3), h_pinv(pinv_tot), h_bm(coef_tot), h_rec(rec_tot);
     std::vector<double> h_cen(std::max<int64_t>(1, 3 * cen_tot), 1e3);  // padding: far from every box
+    std::vector<int> h_imap(std::max<int64_t>(1, imap_tot), -1);
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         const SysDev& S = pl->base[s];
         for (int mi = 0; mi < S.nimg; ++mi)
             for (int k = 0; k < 3; ++k) h_img[(S.img_off + mi) * 3 + k] = su.images[mi * 3 + k] * su.box[k];
+        if (S.mcorner) {
+            const int ny = 2 * S.mr[1] + 1, nz = 2 * S.mr[2] + 1;
+            for (int mi = 0; mi < S.nimg; ++mi) {
+                const int* b = &su.images[mi * 3];
+                h_imap[S.imap_off + (static_cast<int64_t>(b[0] + S.mr[0]) * ny + (b[1] + S.mr[1])) * nz + (b[2] + S.mr[2])] = mi;
+            }
+        }
         for (int l = 0; l < S.L; ++l)
             for (int k = 0; k < 3; ++k) {
                 h_chk[k * chk_tot + S.chk_off + l] = su.yc[l * 3 + k];
@@ -858,6 +918,10 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     pl->scan_blocks = nsys == 1 ? 256 : 4;
     AL(pl->d_mean_part, pl->cap_w)
     AL(pl->d_w_items, pl->cap_w)
+    pl->cap_m = mitems_cap;
+    AL(pl->d_imap, std::max<int64_t>(1, imap_tot))
+    AL(pl->d_mpart, std::max<int64_t>(1, mitems_cap))
+    AL(pl->d_m_items, std::max<int64_t>(1, mitems_cap))
     AL(pl->d_val_part, (int64_t)2 * nsys * pl->val_blocks)
     AL(pl->d_scan_tot, (int64_t)nsys * pl->scan_blocks)
     AL(pl->d_status, 1)
@@ -885,6 +949,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     UPS(pl->d_bm, h_bm)
     UPS(pl->d_rec, h_rec)
     UPS(pl->d_cen, h_cen)
+    UPS(pl->d_imap, h_imap)
 #undef UPS
     if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(pl->d_coef, 0, sizeof(double) * coef_tot);

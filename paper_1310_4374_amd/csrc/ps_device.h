@@ -19,6 +19,19 @@ constexpr int kChunk = 1024;       // particles per chunk in the per-particle ke
 // kFarWideMax targets in all (spreading each target's work wider shortens a
 // small solve), else 4 (fewer lanes read the split partials of large ones).
 constexpr int64_t kFarWideMax = 65536;
+// Box mean by corners (k_mean_corners): one wave per kMeanWave particles keeps,
+// per (x, y) image column, a bit mask of the particle's near images along z in
+// LDS; a system qualifies when it has at most kMeanCols columns and kMeanZ
+// images per column (else the per-entry kernel k_mean serves it).
+constexpr int kMeanWave = 64;
+constexpr int kMeanCols = 64;
+constexpr int kMeanZ = 31;
+// The corner columns of a chunk are split over up to (x range + 1) waves so
+// that a launch reaches about kMeanTargetWaves waves; a launch that would
+// still have fewer than kMeanMinWaves takes the per-entry kernel (a handful of
+// long waves is slower than many short lanes).
+constexpr int64_t kMeanTargetWaves = 4096;
+constexpr int64_t kMeanMinWaves = 2048;
 
 // One periodic system (a box with its particles).  Offsets index packed arrays.
 struct SysDev {
@@ -42,6 +55,9 @@ struct SysDev {
     int64_t nitem_begin, nitem_end;  // near-build items of this system
     int64_t f_off;               // L right-hand-side values
     int64_t witem_off, witem_n;  // this system's workgroups in the near-size-weighted item table
+    int mr[3], mcorner;          // box mean by corners: image ranges |i_k| <= mr[k]; 1 if used
+    int64_t imap_off;            // dense image map over the ranges (image index or -1)
+    int64_t mitem_off, mitem_n;  // this system's workgroups of the corner box mean
 };
 
 // A pair-sum job: every target of a set against every source of another.
@@ -65,6 +81,7 @@ struct PJob {
 struct PItem { int job, tb, split, pad; };           // one workgroup of a pair sum
 struct TItem { int job, tb; };                       // one target block
 struct CItem { int sys, count; int64_t start; };     // a chunk of a system's particles
+struct MItem { int sys, count; int64_t start; int ax0, ax1; };  // corner box mean: a chunk, corner columns ax0..ax1
 struct NItem { int sys, img; int64_t start; int count, pad; };  // near-build item
 
 }  // namespace ps

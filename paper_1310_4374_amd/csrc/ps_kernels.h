@@ -25,6 +25,8 @@ void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* c
                   double* coef, double* f, hipStream_t st);
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
                  const double* nx, const double* ny, const double* nz, const double* nq, double* part,
+                 int64_t nmitems, int mcols, const MItem* mitems, const int* imap, const double* img,
+                 const double* sx, const double* sy, const double* sz, const double* sq, double* mpart,
                  const double* bm, double* coef, hipStream_t st);
 void launch_far(int lanes, int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items,
                 const PJob* pjobs, const PJob* fjobs, const double* coef, const double* rec, const int* perm,

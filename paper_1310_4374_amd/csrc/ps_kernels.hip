@@ -864,7 +864,7 @@ __global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, co
     __shared__ double sh[4];
     const CItem it = witems[blockIdx.x];
     const SysDev& S = sys[it.sys];
-    const int64_t nb = nnear[it.sys];
+    const int64_t nb = S.mcorner ? 0 : nnear[it.sys];  // k_mean_corners serves the system
     // one lane per (near source, corner): q_e times corner k of Phi0(x_e)
     double acc = 0.0;
     for (int64_t u = it.start * 256 + threadIdx.x; u < 8 * nb; u += (int64_t)it.count * 256) {
@@ -875,13 +875,122 @@ __global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, co
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// The same sum regrouped by corner points.  Corner a (per axis) of the image
+// boxes sits at G_a = (1/2 - a) d: it is the upper corner (sign +) of box a and
+// the lower corner (sign -) of box a - 1.  So sum_{p in P_j} Phi0(x_j + p) V0 =
+// sum_a W_a F(G_a - x_j), where W_a adds the signs of corner a over the boxes
+// of P_j (particle j's near images) that share it.  W_a is zero wherever P_j's
+// indicator has no mixed difference across the corner, which removes about four
+// in five of the 8 |P_j| corner terms.  One wave per kMeanWave particles of a
+// system.  P_j is kept as one bit mask over the z images per (x, y) image
+// column (bit w: box (u, v, w - mr[2]) holds x_j + p within the ball, by the
+// same test as the near list).  The nonzero (particle, corner, W) go to a
+// queue in LDS, and the log/atan corner term is evaluated kMeanWave queue
+// entries at a time, so that every lane does one.  A workgroup takes the
+// corner columns ax0..ax1 (along x) of its chunk.
+__device__ __forceinline__ double mean_corner_term(const SysDev& S, unsigned e, const double4* sp)
+{
+    const int lane = e & 63, ax = (e >> 6) & 127, ay = (e >> 13) & 127, t = (e >> 20) & 31;
+    const int W = static_cast<int>((e >> 25) & 31) - 8;
+    const double4 P = sp[lane];
+    const double gx = (0.5 - (ax - S.mr[0])) * S.box[0];
+    const double gy = (0.5 - (ay - S.mr[1])) * S.box[1];
+    const double gz = (0.5 - (t - S.mr[2])) * S.box[2];
+    return P.w * W * prism_corner(gx - P.x, gy - P.y, gz - P.z);
+}
+
+__device__ __forceinline__ int mask_step(unsigned m, int t)  // bit t minus bit t - 1
+{
+    return static_cast<int>((m >> t) & 1u) - static_cast<int>(((m << 1) >> t) & 1u);
+}
+
+__global__ __launch_bounds__(kMeanWave) void k_mean_corners(const SysDev* __restrict__ sys,
+                                                            const MItem* __restrict__ mitems,
+                                                            const int* __restrict__ imap,
+                                                            const double* __restrict__ img,
+                                                            const double* __restrict__ sx,
+                                                            const double* __restrict__ sy,
+                                                            const double* __restrict__ sz,
+                                                            const double* __restrict__ sq, double* __restrict__ mpart)
+{
+    extern __shared__ unsigned smask[];  // [columns][kMeanWave]
+    __shared__ double4 sp[kMeanWave];
+    __shared__ unsigned sque[2 * kMeanWave];
+    const MItem it = mitems[blockIdx.x];
+    const SysDev& S = sys[it.sys];
+    const int lane = threadIdx.x;
+    const bool act = lane < it.count;
+    double x = 0.0, y = 0.0, z = 0.0, q = 0.0;
+    if (act) {
+        const int64_t g = S.n_off + it.start + lane;
+        x = sx[g];
+        y = sy[g];
+        z = sz[g];
+        q = sq[g];
+    }
+    sp[lane] = make_double4(x, y, z, q);
+    const int nx = 2 * S.mr[0] + 1, ny = 2 * S.mr[1] + 1, nz = 2 * S.mr[2] + 1;
+    const int* map = imap + S.imap_off;
+    // the columns next to corner columns ax0..ax1
+    const int c0 = (it.ax0 > 0 ? it.ax0 - 1 : 0) * ny, c1 = (it.ax1 < nx ? it.ax1 + 1 : nx) * ny;
+    for (int c = c0; c < c1; ++c) {
+        unsigned m = 0u;
+        for (int w = 0; w < nz; ++w) {
+            const int idx = map[c * nz + w];
+            if (idx >= 0 && act) {
+                const double* pv = img + (S.img_off + idx) * 3;
+                if (in_ball(x, y, z, pv[0], pv[1], pv[2], S.thr).in) m |= 1u << w;
+            }
+        }
+        smask[c * kMeanWave + lane] = m;
+    }
+    __syncthreads();
+    const uint64_t below = (uint64_t(1) << lane) - 1;
+    int cnt = 0;  // queued entries (wave-uniform)
+    double acc = 0.0;
+    for (int ax = it.ax0; ax <= it.ax1; ++ax)
+        for (int ay = 0; ay <= ny; ++ay) {
+            // the four columns sharing corner column (ax, ay), with their x-y signs
+            const unsigned m00 = (ax < nx && ay < ny) ? smask[(ax * ny + ay) * kMeanWave + lane] : 0u;
+            const unsigned m10 = (ax > 0 && ay < ny) ? smask[((ax - 1) * ny + ay) * kMeanWave + lane] : 0u;
+            const unsigned m01 = (ax < nx && ay > 0) ? smask[(ax * ny + ay - 1) * kMeanWave + lane] : 0u;
+            const unsigned m11 = (ax > 0 && ay > 0) ? smask[((ax - 1) * ny + ay - 1) * kMeanWave + lane] : 0u;
+            const unsigned edge = (m00 ^ (m00 << 1)) | (m10 ^ (m10 << 1)) | (m01 ^ (m01 << 1)) | (m11 ^ (m11 << 1));
+            for (int t = 0; t <= nz; ++t) {
+                if (!__ballot((edge >> t) & 1u)) continue;
+                const int W = mask_step(m00, t) - mask_step(m10, t) - mask_step(m01, t) + mask_step(m11, t);
+                const uint64_t b = __ballot(W != 0);
+                if (W != 0)
+                    sque[cnt + __popcll(b & below)] = static_cast<unsigned>(lane) | (static_cast<unsigned>(ax) << 6) |
+                                                      (static_cast<unsigned>(ay) << 13) |
+                                                      (static_cast<unsigned>(t) << 20) |
+                                                      (static_cast<unsigned>(W + 8) << 25);
+                cnt += __popcll(b);
+                if (cnt >= kMeanWave) {
+                    __syncthreads();
+                    acc += mean_corner_term(S, sque[cnt - kMeanWave + lane], sp);
+                    cnt -= kMeanWave;
+                    __syncthreads();
+                }
+            }
+        }
+    __syncthreads();
+    if (lane < cnt) acc += mean_corner_term(S, sque[lane], sp);
+    acc = wave_sum(acc);
+    if (lane == 0) mpart[blockIdx.x] = acc / S.V0;
+}
+
 __global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, const double* __restrict__ part,
-                                            const double* __restrict__ bm, double* __restrict__ coef)
+                                            const double* __restrict__ mpart, const double* __restrict__ bm,
+                                            double* __restrict__ coef)
 {
     __shared__ double sh[4];
     const SysDev& S = sys[blockIdx.x];
     double sm = 0.0, d = 0.0;
-    for (int64_t b = threadIdx.x; b < S.witem_n; b += 256) sm += part[S.witem_off + b];
+    if (S.mcorner)
+        for (int64_t b = threadIdx.x; b < S.mitem_n; b += 256) sm += mpart[S.mitem_off + b];
+    else
+        for (int64_t b = threadIdx.x; b < S.witem_n; b += 256) sm += part[S.witem_off + b];
     for (int t = 1 + threadIdx.x; t < S.P; t += 256) d += coef[S.coef_off + t] * bm[S.bm_off + t];
     sm = block_reduce<0>(sm, sh);
     d = block_reduce<0>(d, sh);
@@ -1138,10 +1247,15 @@ void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* c
 }
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
                  const double* nx, const double* ny, const double* nz, const double* nq, double* part,
+                 int64_t nmitems, int mcols, const MItem* mitems, const int* imap, const double* img,
+                 const double* sx, const double* sy, const double* sz, const double* sq, double* mpart,
                  const double* bm, double* coef, hipStream_t st)
 {
     if (nwitems > 0) PS_LAUNCH(k_mean, dim3((unsigned)nwitems), dim3(256), 0, st, sys, witems, nnear, nx, ny, nz, nq, part);
-    PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, bm, coef);
+    if (nmitems > 0)
+        PS_LAUNCH(k_mean_corners, dim3((unsigned)nmitems), dim3(kMeanWave), sizeof(unsigned) * kMeanWave * mcols, st,
+                  sys, mitems, imap, img, sx, sy, sz, sq, mpart);
+    PS_LAUNCH(k_c1, dim3(nsys), dim3(256), 0, st, sys, part, mpart, bm, coef);
 }
 void launch_far(int lanes, int64_t nitems, int maxP, int maxp, const SysDev* sys, const CItem* items,
                 const PJob* pjobs, const PJob* fjobs, const double* coef, const double* rec, const int* perm,

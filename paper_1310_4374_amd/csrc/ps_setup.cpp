@@ -2,6 +2,7 @@
 #include "ps_setup.h"
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 
@@ -498,6 +499,14 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
          get_vec(data, size, pos, centres, static_cast<size_t>(M) * 3);
     if (!ok) return "truncated system arrays";
     if (images[0] != 0 || images[1] != 0 || images[2] != 0) return "the first image must be the box itself";
+    for (int v : images)
+        if (v < -(1 << 16) || v > (1 << 16)) return "image index out of range";
+    {
+        std::vector<std::array<int, 3>> sorted(nimg);
+        for (int i = 0; i < nimg; ++i) sorted[i] = {images[3 * i], images[3 * i + 1], images[3 * i + 2]};
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end()) return "repeated image";
+    }
     for (double v : pinv)
         if (!std::isfinite(v)) return "non-finite pseudo-inverse entry";
     rec.build(p);

@@ -623,6 +623,26 @@ def test_batched_mixed_bases(ps):
     assert _rel(phi[off[1]:off[2]], r1[0]) <= 1e-9 and _rel(field[off[1]:off[2]], r1[1]) <= 1e-9
 
 
+def test_batched_box_mean_by_corners_and_by_entries(ps):
+    """The box mean C1 takes two routes: by corner points for boxes whose image
+    range fits the per-wave column masks (at most 64 (x, y) image columns and
+    31 z images), else by near entries.  A batch holding one box of each (the
+    1 x 1 x 10 box at lambda = 1.3 has 15 x 15 image columns) matches the
+    oracle in both (FP64, bar 1e-12)."""
+    boxes = [np.array([1.0, 1.0, 1.0]), np.array([1.0, 1.0, 10.0])]
+    ns = [500, 400]
+    data = [W.uniform_box(n, b, charges="gauss", seed=900 + k) for k, (b, n) in enumerate(zip(boxes, ns))]
+    bp = ps.BatchedPlan([dict(box=b, n_max=n) for b, n in zip(boxes, ns)], p=10, lam=1.3, precision="fp64")
+    off = np.concatenate([[0], np.cumsum(ns)])
+    phi, field = bp.eval(_dev(np.concatenate([d[0] for d in data]).T), _dev(np.concatenate([d[1] for d in data])), off)
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    for k in range(2):
+        ref = OPlan(boxes[k], 10, lam=1.3).solve(data[k][0], data[k][1])
+        sl = slice(off[k], off[k + 1])
+        assert _rel(phi[sl], ref[0]) <= 1e-12 and _rel(field[sl], ref[1]) <= 1e-12, k
+
+
 # --------------------------------------------------------------------------
 # plan files: the set phase saved and reloaded
 # --------------------------------------------------------------------------
