@@ -96,6 +96,7 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
     std::vector<SysDev> sys;
     int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0, nm = 0;
+    bool mean_entries = true;       // some system takes the per-entry box mean
     int far_lanes = 4;              // lanes per target of the far-field/combine kernel
 };
 
@@ -465,6 +466,8 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
             }
             S.mitem_n = static_cast<int64_t>(T.m_items.size()) - S.mitem_off;
         }
+        T.mean_entries = false;
+        for (const SysDev& S : T.sys) T.mean_entries = T.mean_entries || !S.mcorner;
     }
     T.nm = static_cast<int64_t>(T.m_items.size());
     if (T.nm > pl->cap_m) { why = "box-mean workgroup table too small"; return false; }
@@ -626,7 +629,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
-    launch_mean(nsys, T.nw, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part,
+    launch_mean(nsys, T.mean_entries ? T.nw : 0, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part,
                 T.nm, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
                 pl->d_bm, pl->d_coef, st);  // step 6
     mark(6);
