@@ -888,6 +888,8 @@ __global__ __launch_bounds__(256) void k_mean(const SysDev* __restrict__ sys, co
 // queue in LDS, and the log/atan corner term is evaluated kMeanWave queue
 // entries at a time, so that every lane does one.  A workgroup takes the
 // corner columns ax0..ax1 (along x) of its chunk.
+// Queue entry: lane (6 bits) | corner column ax << 6 | ay << 13 | corner t along z << 20 | (W + 8) << 25;
+// ax, ay and t count from the lowest corner (a = -mr).
 __device__ __forceinline__ double mean_corner_term(const SysDev& S, unsigned e, const double4* sp)
 {
     const int lane = e & 63, ax = (e >> 6) & 127, ay = (e >> 13) & 127, t = (e >> 20) & 31;
