@@ -130,6 +130,34 @@ def test_plan_file_with_valid_checksum_but_bad_contents_is_refused(tmp_path):
     assert b"p out of range" in L.periodic_sum_last_error()
 
 
+def test_plan_file_with_bad_image_list_is_refused(tmp_path):
+    """A checksummed file whose image list repeats an image, or holds an image
+    index beyond 2^16, is refused with PS_E_IO (the box-mean tables index a
+    dense map over the image range)."""
+    import struct
+    L = _lib.lib()
+    p, P, Lc = 2, 4, 6
+
+    def plan_file(images):
+        head = b"PSPLAN01" + struct.pack("<Iiid", 1, 1, 256, 1.0)
+        prm = struct.pack("<3didd", 1.0, 1.0, 1.0, p, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
+            + struct.pack("<qqiii", 100, 0, 0, 0, 0)
+        setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) \
+            + struct.pack("<4id", p, P, Lc, P - 1, 1.0) + struct.pack("<ii", len(images), 0)
+        arrays = struct.pack("<%dd" % (2 * 3 * Lc + (P - 1) * Lc + P), *([0.1] * (2 * 3 * Lc + (P - 1) * Lc + P)))
+        arrays += struct.pack("<%di" % (3 * len(images)), *[v for im in images for v in im])
+        body = head + prm + setup + arrays
+        return body + struct.pack("<Q", _fnv1a64(body))
+
+    h = ctypes.c_void_p()
+    for name, images, msg in (("repeated", [(0, 0, 0), (1, 0, 0), (1, 0, 0)], b"repeated image"),
+                              ("far", [(0, 0, 0), (0, 70000, 0)], b"image index out of range")):
+        f = tmp_path / (name + ".plan")
+        f.write_bytes(plan_file(images))
+        assert L.periodic_sum_plan_load(str(f).encode(), 0, ctypes.byref(h)) == _lib.PS_E_IO, name
+        assert msg in L.periodic_sum_last_error(), (name, L.periodic_sum_last_error())
+
+
 def _select(prm, tol=1e-6, lambdas=(1.3, 1.5), p_ref=0, n=10, null=None):
     """periodic_sum_select with stand-in particle pointers: every case here is
     rejected by the argument checks, before any device call."""
