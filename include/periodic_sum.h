@@ -114,6 +114,8 @@ typedef struct {
     int64_t n_near_last;      /* N_b of the last completed eval (synchronizes) */
     int32_t tile_targets, n_split;
     int32_t nsys;             /* 1, or the number of systems of a batched plan */
+    int32_t mean_corners;     /* systems whose box mean (eq. (pfx4)) the last particle-count shape sums by
+                                 corner points rather than per near entry (a launch-size choice, same result) */
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and

@@ -40,7 +40,7 @@ class ps_plan_info(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("P", ctypes.c_int32), ("L", ctypes.c_int32), ("n_images", ctypes.c_int32),
                 ("rank", ctypes.c_int32), ("R0", ctypes.c_double), ("R_b", ctypes.c_double), ("cond", ctypes.c_double),
                 ("n_near_last", ctypes.c_int64), ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32),
-                ("nsys", ctypes.c_int32)]
+                ("nsys", ctypes.c_int32), ("mean_corners", ctypes.c_int32)]
 
 
 class ps_select_row(ctypes.Structure):

@@ -1226,6 +1226,9 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
     out->tile_targets = pl->bt;
     out->n_split = pl->tab.jobs.size() > static_cast<size_t>(pl->nsys) ? pl->tab.jobs[pl->nsys].nsplit : 0;
     out->nsys = pl->nsys;
+    out->mean_corners = 0;
+    if (pl->tab_valid)
+        for (const SysDev& S : pl->tab.sys) out->mean_corners += S.mcorner;
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());

@@ -55,6 +55,7 @@ def test_small_cube_config(ps, prec):
     info = pl.info()
     assert info["n_near_last"] == ref["n_near"]
     assert info["L"] == 2 * c["p"] ** 2 - c["p"] and info["rank"] == c["p"] ** 2 - 1
+    assert info["mean_corners"] == 0  # 16 waves of 64 particles: the per-entry box mean
     # FP64: the coefficients to rounding; FP32: the check-point sums are FP32 pair
     # sums (FP64 accumulation), which moves C by ~1e-6 relative
     C = pl.coefficients().numpy()
@@ -435,6 +436,7 @@ def test_full_size_uniform_cube(ps, prec):
     pl, phi, field = _run(ps, c["box"], c["p"], c["x"], c["q"], prec, R_b=c["R_b"])
     sub = ref["subset"]
     assert pl.info()["n_near_last"] == int(ref["n_near"])
+    assert pl.info()["mean_corners"] == 1  # the box mean by corner points
     e1, e2 = _rel(phi[sub], ref["phi"]), _rel(field[sub], ref["field"])
     print(prec, "cfg2 rel-L2 phi %.3e field %.3e" % (e1, e2))
     assert e1 <= TOL[prec] and e2 <= TOL[prec]
@@ -626,19 +628,22 @@ def test_batched_mixed_bases(ps):
 def test_batched_box_mean_by_corners_and_by_entries(ps):
     """The box mean C1 takes two routes: by corner points for boxes whose image
     range fits the per-wave column masks (at most 64 (x, y) image columns and
-    31 z images), else by near entries.  A batch holding one box of each (the
-    1 x 1 x 10 box at lambda = 1.3 has 15 x 15 image columns) matches the
-    oracle in both (FP64, bar 1e-12)."""
-    boxes = [np.array([1.0, 1.0, 1.0]), np.array([1.0, 1.0, 10.0])]
-    ns = [500, 400]
+    31 z images) when the launch has at least 2,048 workgroups of 64
+    particles x corner-column slices, else by near entries.  Here 40 cubes of
+    4,000 particles (2,520 chunks, 2 slices each) take the corner route and the
+    1 x 1 x 10 box at lambda = 1.3 (15 x 15 image columns) the per-entry one;
+    sampled systems of both match the oracle (FP64, bar 1e-12)."""
+    boxes = [np.array([1.0, 1.0, 1.0])] * 40 + [np.array([1.0, 1.0, 10.0])]
+    ns = [4000] * 40 + [400]
     data = [W.uniform_box(n, b, charges="gauss", seed=900 + k) for k, (b, n) in enumerate(zip(boxes, ns))]
-    bp = ps.BatchedPlan([dict(box=b, n_max=n) for b, n in zip(boxes, ns)], p=10, lam=1.3, precision="fp64")
+    bp = ps.BatchedPlan([dict(box=b, n_max=n) for b, n in zip(boxes, ns)], p=8, lam=1.3, precision="fp64")
     off = np.concatenate([[0], np.cumsum(ns)])
     phi, field = bp.eval(_dev(np.concatenate([d[0] for d in data]).T), _dev(np.concatenate([d[1] for d in data])), off)
     bp.status()
+    assert bp.info()["mean_corners"] == 40
     phi, field = phi.cpu().numpy(), field.cpu().numpy().T
-    for k in range(2):
-        ref = OPlan(boxes[k], 10, lam=1.3).solve(data[k][0], data[k][1])
+    for k in (0, 17, 39, 40):
+        ref = OPlan(boxes[k], 8, lam=1.3).solve(data[k][0], data[k][1])
         sl = slice(off[k], off[k + 1])
         assert _rel(phi[sl], ref[0]) <= 1e-12 and _rel(field[sl], ref[1]) <= 1e-12, k
 
