@@ -57,7 +57,7 @@ typedef enum {
     PS_OK = 0,
     PS_E_INVALID = 1,      /* bad argument (null pointer, size, parameter range) */
     PS_E_NOT_NEUTRAL = 2,  /* |sum q| > 1e-12 sum |q| (eq. (1) requires neutrality) */
-    PS_E_OUT_OF_BOX = 3,   /* a particle or target outside [-d/2, d/2) */
+    PS_E_OUT_OF_BOX = 3,   /* a particle outside [-d/2, d/2), or a NaN coordinate or charge */
     PS_E_RANK = 4,         /* fitting matrix numerically rank deficient beyond rcond */
     PS_E_NOMEM = 5,        /* device or host allocation failed */
     PS_E_HIP = 6,          /* a HIP runtime call failed */
@@ -281,7 +281,8 @@ ps_status periodic_sum_select(const ps_params* base, int device, int64_t n,
 ps_status periodic_sum_near_counts(ps_plan plan, int64_t* out, int32_t nsys);
 
 /* Synchronizes `stream` and returns the data-dependent status of the last eval
- * (PS_E_NOT_NEUTRAL, PS_E_OUT_OF_BOX) or PS_OK, then clears it. */
+ * or PS_OK, then clears it: PS_E_OUT_OF_BOX for a particle outside the box or
+ * a NaN coordinate or charge (reported first), else PS_E_NOT_NEUTRAL. */
 ps_status periodic_sum_status(ps_plan plan, void* stream);
 
 /* Plan facts; n_near_last synchronizes the device. */

@@ -1206,8 +1206,9 @@ ps_status periodic_sum_status(ps_plan pl, void* stream)
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipMemsetAsync(pl->d_status, 0, sizeof(int), st));
     HIPCHK(hipStreamSynchronize(st));
-    if (h & 1) return fail(PS_E_NOT_NEUTRAL, "charges are not neutral (|sum q| > 1e-12 sum |q|)");
+    // a NaN charge also fails the neutrality test: the box/NaN error goes first
     if (h & 2) return fail(PS_E_OUT_OF_BOX, "a particle lies outside [-d/2, d/2) or has a NaN coordinate/charge");
+    if (h & 1) return fail(PS_E_NOT_NEUTRAL, "charges are not neutral (|sum q| > 1e-12 sum |q|)");
     return PS_OK;
 }
 

@@ -179,6 +179,18 @@ def test_status_reports_data_errors(ps):
     pl.eval(_dev(x.T), _dev(c["q"]))
     with pytest.raises(PeriodicSumError, match="OUT_OF_BOX"):
         pl.status()
+    # a NaN coordinate or charge is reported the same way (every index the
+    # kernels form comes from counts, and the cell key clamps NaN to cell 0)
+    x = c["x"].copy()
+    x[11, 2] = np.nan
+    pl.eval(_dev(x.T), _dev(c["q"]))
+    with pytest.raises(PeriodicSumError, match="OUT_OF_BOX"):
+        pl.status()
+    q = c["q"].copy()
+    q[3] = np.nan
+    pl.eval(_dev(c["x"].T), _dev(q))
+    with pytest.raises(PeriodicSumError, match="OUT_OF_BOX"):
+        pl.status()
     pl.eval(_dev(c["x"].T), _dev(c["q"]))
     pl.status()
     with pytest.raises(PeriodicSumError, match="INVALID"):
@@ -221,6 +233,28 @@ def test_synchronous_validation(ps, monkeypatch):
     pl2.eval(x, q_bad)
     with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
         pl2.status()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_charges_give_zero(ps, prec):
+    """Degenerate input: all charges zero (neutral).  Every stage sums zeros, so
+    the potential and the field are exactly zero, in a single plan and in a
+    batch next to an ordinary box (which still matches the oracle)."""
+    x, _ = W.uniform_box(777, (1.0, 1.2, 0.9), charges="gauss", seed=71)
+    z = np.zeros(777)
+    pl = ps.Plan((1.0, 1.2, 0.9), 10, lam=1.6, precision=prec, n_max=777)
+    phi, field = pl.eval(_dev(x.T), _dev(z))
+    pl.status()
+    assert not torch.any(phi != 0) and not torch.any(field != 0)
+    x2, q2 = W.uniform_box(500, (1.1, 1.0, 1.3), charges="gauss", seed=72)
+    bp = ps.BatchedPlan([dict(box=(1.0, 1.2, 0.9), n_max=777), dict(box=(1.1, 1.0, 1.3), n_max=500)], p=10, lam=1.6,
+                        precision=prec)
+    phi, field = bp.eval(_dev(np.concatenate([x, x2]).T), _dev(np.concatenate([z, q2])), [0, 777, 1277])
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    assert not np.any(phi[:777]) and not np.any(field[:777])
+    ref = OPlan((1.1, 1.0, 1.3), 10, lam=1.6).solve(x2, q2)
+    assert _rel(phi[777:], ref[0]) <= TOL[prec] and _rel(field[777:], ref[1]) <= TOL[prec]
 
 
 def test_bitwise_reproducible(ps):
