@@ -663,11 +663,13 @@ def test_batched_box_mean_by_corners_and_by_entries(ps):
     """The box mean C1 takes two routes: by corner points for boxes whose image
     range fits the per-wave column masks (at most 64 (x, y) image columns and
     31 z images) when the launch has at least 2,048 workgroups of 64
-    particles x corner-column slices, else by near entries.  Here 40 cubes of
-    4,000 particles (2,520 chunks, 2 slices each) take the corner route and the
+    particles x corner-column slices, else by near entries.  Here 40 boxes
+    with sides U[1, 2] (unequal image ranges per axis) of 4,000 particles
+    (2,520 chunks, at least 2 slices each) take the corner route and the
     1 x 1 x 10 box at lambda = 1.3 (15 x 15 image columns) the per-entry one;
     sampled systems of both match the oracle (FP64, bar 1e-12)."""
-    boxes = [np.array([1.0, 1.0, 1.0])] * 40 + [np.array([1.0, 1.0, 10.0])]
+    g = np.random.default_rng(901)
+    boxes = [g.uniform(1.0, 2.0, size=3) for _ in range(40)] + [np.array([1.0, 1.0, 10.0])]
     ns = [4000] * 40 + [400]
     data = [W.uniform_box(n, b, charges="gauss", seed=900 + k) for k, (b, n) in enumerate(zip(boxes, ns))]
     bp = ps.BatchedPlan([dict(box=b, n_max=n) for b, n in zip(boxes, ns)], p=8, lam=1.3, precision="fp64")
