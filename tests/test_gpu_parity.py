@@ -266,6 +266,41 @@ def test_bitwise_reproducible(ps):
         assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
 
 
+def test_independent_plans_on_two_streams(ps):
+    """Two plans (one single box, one batch) evaluated concurrently on two
+    default-priority streams, several rounds without synchronizing in between:
+    plans share no device state, so every result equals the plan's own
+    sequential eval bit for bit."""
+    xa, qa = W.uniform_box(3000, (1.0, 1.1, 1.2), charges="gauss", seed=81)
+    xb = [W.uniform_box(n, b, charges="gauss", seed=82 + k)
+          for k, (n, b) in enumerate(zip((900, 1400), ((1.3, 1.0, 1.0), (1.0, 1.5, 1.2))))]
+    pa = ps.Plan((1.0, 1.1, 1.2), 10, lam=1.6, precision="fp32", n_max=3000)
+    pb = ps.BatchedPlan([dict(box=(1.3, 1.0, 1.0), n_max=900), dict(box=(1.0, 1.5, 1.2), n_max=1400)], p=10, lam=1.6,
+                        precision="fp64")
+    XA, QA = _dev(xa.T), _dev(qa)
+    XB, QB = _dev(np.concatenate([d[0] for d in xb]).T), _dev(np.concatenate([d[1] for d in xb]))
+    off = [0, 900, 2300]
+    ref_a = [t.clone() for t in pa.eval(XA, QA)]
+    ref_b = [t.clone() for t in pb.eval(XB, QB, off)]
+    torch.cuda.synchronize()
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    sa.wait_stream(torch.cuda.current_stream())
+    sb.wait_stream(torch.cuda.current_stream())
+    outs = []
+    for _ in range(3):
+        with torch.cuda.stream(sa):
+            oa = pa.eval(XA, QA)
+        with torch.cuda.stream(sb):
+            ob = pb.eval(XB, QB, off)
+        outs.append((oa, ob))
+    torch.cuda.synchronize()
+    pa.status()
+    pb.status()
+    for oa, ob in outs:
+        assert torch.equal(oa[0], ref_a[0]) and torch.equal(oa[1], ref_a[1])
+        assert torch.equal(ob[0], ref_b[0]) and torch.equal(ob[1], ref_b[1])
+
+
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6)])
 def test_energy_and_exact_adjoint(ps, prec, tol):
     box = (1.0, 1.1, 0.9)
