@@ -1,15 +1,21 @@
 """Benchmark of the periodized Coulomb sum on one MI355X.
 
 One step = one periodic solve ("get", every stage of the hot path) of the
-uniform-cube workload: N = 100,000 particles in the unit cube, q ~ N(0,1)
-minus its mean, p = 16 (L = 496 check points), R_b = 1.5, FP32 pair arithmetic
-with FP64 accumulation.  Inputs are resident on the GPU before timing starts.
+clustered anisotropic workload: N = 1,000,000 particles in 64 Gaussian blobs
+(sigma = 0.03 d_k per axis, wrapped) in a 1 x 1 x 2.5 box, charges +-1 (500,000
+each), p = 20 (L = 780 check points), lambda = 1.5, FP32 pair arithmetic with
+FP64 accumulation, potentials and fields.  Inputs are resident on the GPU
+before timing starts.
 
 Prints one JSON line.  value = pair interactions per second over the whole
 solve, counting (N + 2L) * N_b pairs per solve (the particle and check-point
-near sums).  The roofline entry is the particle pair-sum kernel, its duration
-taken from HIP events recorded by the library on the eval stream.  The CPU
-baseline times the FP64 oracle on a bounded sample of the same workload.
+near sums).  Stage events are recorded on the eval stream during the timed
+loop (no host synchronization that idles the device) and read once after it:
+the roofline entry divides the particle pair-sum kernel's algorithmic flops by
+its mean duration over the timed solves.  The uniform-cube workload
+(N = 100,000, p = 16) is measured the same way and reported under "cube".
+The CPU baseline times the FP64 oracle on a bounded sample of the clustered
+workload.
 """
 import argparse
 import json
@@ -25,8 +31,7 @@ sys.path.insert(0, ROOT)
 # Peaks of the ALU-bound pair kernel: MI355X's published FP32 and FP64 vector
 # figures.  On gfx950 non-packed FP32 instructions with VGPR operands issue at
 # up to 32 lanes per clock per SIMD (two cycles per 64-lane instruction), which
-# is the 157.3 TFLOP/s rate (256 CUs x 4 SIMDs x 32 lanes x 2 flop x 2.4 GHz);
-# the valu_rate executable built beside the library measures it.
+# is the 157.3 TFLOP/s rate (256 CUs x 4 SIMDs x 32 lanes x 2 flop x 2.4 GHz).
 FP32_TFLOPS = 157.3
 FP64_TFLOPS = 78.6
 FLOP_PER_PAIR = 20         # potential + field: 3 sub, r^2 (mul + 2 FMA), rsqrt, 3 mul, add, 3 FMA
@@ -48,13 +53,13 @@ def pair_kernel_hash():
     return hashlib.sha256(src[a:b].encode()).hexdigest()[:16]
 
 
-def measured_traffic(precision):
+def measured_traffic(precision, record="p2p_f32_clustered_N1M_hbm_counters.json"):
     """HBM bytes per launch of the pair kernel from the committed rocprofv3
-    counter record, or None if the kernel source has changed since."""
-    import hashlib
+    counter record of that workload, or None if the kernel source has changed
+    since (or there is no record)."""
     if precision != "fp32":
         return None
-    rec = os.path.join(ROOT, "profiles", "p2p_f32_uniform_cube_N100k_hbm_counters.json")
+    rec = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(rec):
         return None
     h = pair_kernel_hash()
@@ -64,35 +69,93 @@ def measured_traffic(precision):
     return d["traffic_bytes"] if d.get("source_sha256_16") == h else None
 
 
-def cpu_baseline(c, ntarget=4000):
-    """The FP64 oracle as it stands, on a bounded sample: its full "get" with the
-    check points and `ntarget` particles as targets."""
+def cpu_baseline(c, ntarget=400):
+    """The FP64 oracle as it stands, on a bounded sample of the workload: its
+    near-set pair sums (step 3 of "get", the work the metric counts), the 2L
+    check points (potential) and `ntarget` particles (potential and field)
+    against the whole near set, with the oracle's compensated FP64 direct sums.
+    The near set is built first and not timed; the oracle's box mean (step 6,
+    numpy, about 80 s on 8 cores for this near set) is outside the sample."""
+    from oracle import _native
     from oracle.method import Plan as OPlan
-    pl = OPlan(c["box"], c["p"], R_b=c["R_b"])
+    pl = OPlan(c["box"], c["p"], R_b=c.get("R_b"), lam=c.get("lam"))
+    xs, qs, _, _ = pl.near(c["x"], c["q"])
     t = time.perf_counter()
-    parts = pl.solve(c["x"], c["q"], targets=c["x"][:ntarget], return_parts=True)
+    _native.direct(np.concatenate([pl.yc, pl.yt]), xs, qs, grad=False)
+    _native.direct(c["x"][:ntarget], xs, qs, grad=True)
     dt = time.perf_counter() - t
-    pairs = (2 * pl.L + ntarget) * parts["n_near"]
+    pairs = (2 * pl.L + ntarget) * len(qs)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": pairs / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
-            "sample": "oracle get (near set, %d check points, Phi0, far field) with %d particle targets: "
-                      "%.3g pairs in %.1f s" % (2 * pl.L, ntarget, pairs, dt)}
+            "sample": "oracle near-set pair sums (FP64, compensated): %d check points (potential) and %d particle "
+                      "targets (potential and field) over the %d-entry near set, %.3g pairs in %.1f s"
+                      % (2 * pl.L, ntarget, len(qs), pairs, dt)}
+
+
+def timed_solves(plan, x, q, phi, field, steps, warmup):
+    """Warm-up evals, then `steps` evals between two events on the eval stream,
+    with the library's stage events recorded inside the loop and read once
+    after it.  Returns (ms per solve, mean stage durations over those solves)."""
+    import torch
+    for _ in range(warmup):
+        plan.eval(x, q, out=(phi, field))
+    plan.status()
+    plan.set_profiling(True)       # a new window of stage events
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        plan.eval(x, q, out=(phi, field))
+    end.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(end) / steps
+    stage_ms = plan.stage_times()  # means over exactly the timed solves
+    plan.set_profiling(False)
+    plan.status()
+    return ms, stage_ms
+
+
+def accuracy(phi, field, names):
+    """rel-L2 and worst element (max |err| / max |ref|) against stored FP64 oracle
+    values (tests/golden, written by the oracle alone), per reference file."""
+    out = {}
+    ph, fd = phi.cpu().numpy(), field.cpu().numpy().T
+    for name in names:
+        path = os.path.join(ROOT, "tests", "golden", name)
+        if not os.path.exists(path):
+            continue
+        ref = np.load(path)
+        sub = ref["subset"]
+        key = name.replace(".npz", "")
+        out[key] = {"targets": int(len(sub)),
+                    "rel_l2_phi": _rel(ph[sub], ref["phi"]), "rel_l2_field": _rel(fd[sub], ref["field"]),
+                    "worst_phi": _worst(ph[sub], ref["phi"]), "worst_field": _worst(fd[sub], ref["field"])}
+    return out
+
+
+def roofline(precision, n, nb, t_pairs_ms, kernel, record):
+    peak = FP32_TFLOPS if precision == "fp32" else FP64_TFLOPS
+    achieved = FLOP_PER_PAIR * n * nb / (t_pairs_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+            "traffic": measured_traffic(precision, record),
+            "peak_basis": "published %s vector peak" % ("FP32" if precision == "fp32" else "FP64"),
+            "kernel": kernel, "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,
+            "launch_ms": t_pairs_ms, "pair_rate": n * nb / (t_pairs_ms * 1e-3)}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-profile", action="store_true", help="time without the per-stage events")
+    ap.add_argument("--no-cube", action="store_true", help="skip the uniform-cube figures of the default line")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
-    ap.add_argument("--autotune", action="store_true", help="autotune the launch shape before timing")
-    ap.add_argument("--workload", default="cube",
-                    choices=["cube", "batch", "clustered", "rocksalt", "bases", "aspect", "small", "select"],
-                    help="cube (default): the headline solve; the others measure the batched, clustered and "
-                         "differentiated workloads")
+    ap.add_argument("--workload", default="clustered",
+                    choices=["clustered", "cube", "batch", "rocksalt", "bases", "aspect", "small", "select"],
+                    help="clustered (default): the headline solve; the others measure the uniform cube, the "
+                         "batched, differentiated and paper-table workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (reference for HBM counters)")
     args = ap.parse_args()
@@ -102,92 +165,65 @@ def main():
         sys.exit(2)
 
     import torch
-    import paper_1310_4374_amd as ps
-    import workloads as W
+    import paper_1310_4374_amd as ps  # noqa: F401  (fails loudly without the built library)
 
-    if args.workload != "cube":
-        out = {"batch": bench_batch, "clustered": bench_clustered, "rocksalt": bench_rocksalt,
-               "bases": bench_bases, "aspect": bench_aspect, "small": bench_small,
-               "select": bench_select}[args.workload](args)
-        print(json.dumps(out), flush=True)
-        return
-
-    c = W.config2()
-    n = len(c["q"])
-    dev = torch.device("cuda", 0)
     if args.copy_calibration_mib:
+        dev = torch.device("cuda", 0)
         a = torch.ones(args.copy_calibration_mib * 2 ** 20 // 8, dtype=torch.float64, device=dev)
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
         log("calibration copy: %d MiB read, %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
         del a, b
+    if args.workload not in ("clustered", "cube"):
+        out = {"batch": bench_batch, "rocksalt": bench_rocksalt, "bases": bench_bases, "aspect": bench_aspect,
+               "small": bench_small, "select": bench_select}[args.workload](args)
+        print(json.dumps(out), flush=True)
+        return
+    if args.workload == "cube":
+        out = bench_cube(args)
+        print(json.dumps(out), flush=True)
+        return
+    out = bench_clustered(args)
+    if not args.no_cube:
+        log("uniform cube N = 100,000 ...")
+        out["cube"] = bench_cube(args)
+    if not args.no_cpu_baseline:
+        import workloads as W
+        log("timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(W.config3())
+    print(json.dumps(out), flush=True)
+
+
+METRIC = "pair interactions/s and periodic solves/s at rel-L2 <=1e-6 vs FP64 oracle"
+
+
+def bench_clustered(args):
+    """BASELINE workload 3: 1,000,000 particles in 64 Gaussian blobs, box 1 x 1 x 2.5,
+    p = 20, lambda = 1.5, FP32 pairs with FP64 accumulation (or FP64)."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config3()
+    n = len(c["q"])
+    dev = torch.device("cuda", 0)
     x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
     q = torch.tensor(c["q"], device=dev)
     t_set = time.perf_counter()
-    plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n,
-                   tile_targets=args.tile_targets)
+    plan = ps.Plan(c["box"], c["p"], lam=c["lam"], precision=args.precision, n_max=n, tile_targets=args.tile_targets)
     t_set = time.perf_counter() - t_set
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     field = torch.empty(3, n, dtype=torch.float64, device=dev)
-    if args.autotune:
-        log("autotune: best %.3f ms" % plan.autotune(x, q))
     log("plan ready:", plan.info())
-    for _ in range(args.warmup):
-        plan.eval(x, q, out=(phi, field))
-    plan.status()
+    ms, st = timed_solves(plan, x, q, phi, field, args.steps, args.warmup)
+    log("timed %d solves: %.3f ms/solve" % (args.steps, ms))
     info = plan.info()
     nb, L = info["n_near_last"], info["L"]
     pairs_per_step = (n + 2 * L) * nb
-    prof = not args.no_profile
-    plan.set_profiling(prof)
-    stage_sum = None
-    per_step = []
-    torch.cuda.synchronize()
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record()
-    for _ in range(args.steps):
-        plan.eval(x, q, out=(phi, field))
-        if prof:
-            st = plan.stage_times()
-            stage_sum = st if stage_sum is None else {k: stage_sum[k] + st[k] for k in st}
-            per_step.append(sum(st.values()))
-    end.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = start.elapsed_time(end) / args.steps
-    log("timed %d steps: %.3f ms/step (host wall %.3f s)" % (args.steps, ms, wall))
-    plan.status()
-
-    # accuracy against the stored FP64 oracle values at 2,000 sampled particles
-    acc = {}
-    ref_path = os.path.join(ROOT, "tests", "golden", "ref_cfg2.npz")
-    if os.path.exists(ref_path):
-        ref = np.load(ref_path)
-        sub = ref["subset"]
-        ph = phi.cpu().numpy()[sub]
-        fd = field.cpu().numpy().T[sub]
-        acc = {"rel_l2_phi": float(np.linalg.norm(ph - ref["phi"]) / np.linalg.norm(ref["phi"])),
-               "rel_l2_field": float(np.linalg.norm(fd - ref["field"]) / np.linalg.norm(ref["field"])),
-               "accuracy_sample": "2000 particles vs FP64 oracle"}
-
-    roof = None
-    stage_ms = None
-    if prof:
-        stage_ms = {k: v / args.steps for k, v in stage_sum.items()}
-        t_pairs = stage_ms["pairs"] * 1e-3
-        achieved = FLOP_PER_PAIR * n * nb / t_pairs / 1e12
-        peak = FP32_TFLOPS if args.precision == "fp32" else FP64_TFLOPS
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak, "traffic": measured_traffic(args.precision),
-                "peak_basis": "published %s vector peak" % ("FP32" if args.precision == "fp32" else "FP64"),
-                "kernel": "k_p2p_%s<%d,field> (particle near sums)" % ("f32" if args.precision == "fp32" else "f64",
-                                                                    info["tile_targets"]),
-                "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,
-                "pair_rate": n * nb / t_pairs}
-    out = {
-        "metric": "pair interactions/s and periodic solves/s at rel-L2 <=1e-6 vs FP64 oracle",
+    acc = accuracy(phi, field, ["ref_cfg3.npz", "ref_cfg3_hard.npz"])
+    f32 = args.precision == "fp32"
+    return {
+        "metric": METRIC,
         "value": pairs_per_step / (ms * 1e-3),
         "unit": "pair interactions/s",
         "n_gpus": 1,
@@ -198,26 +234,66 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.precision == "fp32" else "f64",
-        "data": "synthetic (seeded uniform positions, Gaussian charges)",
-        "config": {"workload": "uniform cube 1x1x1, N=100000, q~N(0,1)-mean, p=16 (L=496), R_b=1.5, "
-                               + ("FP32 pairs with FP64 accumulation" if args.precision == "fp32" else "FP64"),
-                   "N": n, "p": c["p"], "L": L, "R_b": c["R_b"], "n_near": nb,
-                   "pairs_per_solve": pairs_per_step, "parallelism": "single GPU"},
-        "roofline": roof,
-        "stage_ms": stage_ms,
-        "get_ms_median": float(np.median(per_step)) if per_step else None,
+        "dtype": "f32" if f32 else "f64",
+        "data": "synthetic (seeded Gaussian blobs, balanced +-1 charges)",
+        "config": {"workload": "anisotropic box 1x1x2.5, N=1000000 in 64 Gaussian blobs (sigma=0.03 d_k, wrapped), "
+                               "q=+-1 balanced, p=20 (L=780), lambda=1.5, "
+                               + ("FP32 pairs with FP64 accumulation" if f32 else "FP64"),
+                   "N": n, "p": c["p"], "L": L, "lambda": c["lam"], "R_b": info["R_b"], "n_near": nb,
+                   "pairs_per_solve": pairs_per_step, "tile_targets": info["tile_targets"],
+                   "n_split": info["n_split"], "parallelism": "single GPU"},
+        "roofline": roofline(args.precision, n, nb, st["pairs"],
+                             "k_p2p_%s<%d,field> (particle near sums)" % ("f32" if f32 else "f64",
+                                                                         info["tile_targets"]),
+                             "p2p_f32_clustered_N1M_hbm_counters.json"),
+        "stage_ms": st,
         "set_s": t_set,
+        "accuracy": acc,
+        "rel_l2_phi": acc.get("ref_cfg3", {}).get("rel_l2_phi"),
+        "rel_l2_field": acc.get("ref_cfg3", {}).get("rel_l2_field"),
+        "accuracy_sample": "2,000 sampled particles (ref_cfg3) and 800 hard ones (ref_cfg3_hard) vs the FP64 oracle",
     }
-    out.update(acc)
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample ...")
-        out["cpu_baseline"] = cpu_baseline(c)
-    print(json.dumps(out), flush=True)
+
+
+def bench_cube(args):
+    """BASELINE workload 2: N = 100,000 uniform in the unit cube, q ~ N(0,1) minus
+    its mean, p = 16, R_b = 1.5."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config2()
+    n = len(c["q"])
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
+    q = torch.tensor(c["q"], device=dev)
+    plan = ps.Plan(c["box"], c["p"], R_b=c["R_b"], precision=args.precision, n_max=n, tile_targets=args.tile_targets)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    steps = max(20, 2 * args.steps)
+    ms, st = timed_solves(plan, x, q, phi, field, steps, max(3, args.warmup))
+    info = plan.info()
+    nb, L = info["n_near_last"], info["L"]
+    pairs_per_step = (n + 2 * L) * nb
+    acc = accuracy(phi, field, ["ref_cfg2.npz", "ref_cfg2_hard.npz"])
+    f32 = args.precision == "fp32"
+    return {"metric": METRIC, "value": pairs_per_step / (ms * 1e-3), "unit": "pair interactions/s",
+            "n_gpus": 1, "steps": steps, "warmup": max(3, args.warmup), "ms_per_step": ms, "solves_per_s": 1e3 / ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64",
+            "data": "synthetic (seeded uniform positions, Gaussian charges)",
+            "config": {"workload": "uniform cube 1x1x1, N=100000, q~N(0,1)-mean, p=16 (L=496), R_b=1.5",
+                       "N": n, "p": c["p"], "L": L, "n_near": nb, "pairs_per_solve": pairs_per_step},
+            "roofline": roofline(args.precision, n, nb, st["pairs"],
+                                 "k_p2p_%s<%d,field>" % ("f32" if f32 else "f64", info["tile_targets"]),
+                                 "p2p_f32_uniform_cube_N100k_hbm_counters.json"),
+            "stage_ms": st, "accuracy": acc}
 
 
 def _rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _worst(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
 
 
 def _time(fn, steps, warmup):
@@ -293,37 +369,6 @@ def bench_batch(args):
             "per_box_fp64": {"solves_per_s": nsys / (ms64 * 1e-3), "ms_per_batch": ms64, "max_rel_l2_sampled": err64},
             "per_box_fp32": {"solves_per_s": nsys / (ms32 * 1e-3), "ms_per_batch": ms32, "max_rel_l2_sampled": err32box},
             "speedup_vs_per_box_fp64": ms64 / ms}
-
-
-def bench_clustered(args):
-    """1,000,000 particles in 64 Gaussian blobs, box 1 x 1 x 2.5, p = 20, lambda = 1.5, FP32 pairs."""
-    import torch
-    import paper_1310_4374_amd as ps
-    import workloads as W
-    c = W.config3()
-    dev = torch.device("cuda", 0)
-    n = len(c["q"])
-    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
-    q = torch.tensor(c["q"], device=dev)
-    pl = ps.Plan(c["box"], c["p"], lam=c["lam"], precision="fp32", n_max=n)
-    phi = torch.empty(n, dtype=torch.float64, device=dev)
-    field = torch.empty(3, n, dtype=torch.float64, device=dev)
-    pl.set_profiling(True)
-    ms = _time(lambda: pl.eval(x, q, out=(phi, field)), max(1, args.steps), 1)
-    st = pl.stage_times()
-    pl.status()
-    inf = pl.info()
-    nb = inf["n_near_last"]
-    pairs = (n + 2 * inf["L"]) * nb
-    ref = np.load(os.path.join(ROOT, "tests", "golden", "ref_cfg3.npz"))
-    sub = ref["subset"]
-    return {"metric": "pair interactions/s (clustered, anisotropic)", "value": pairs / (ms * 1e-3),
-            "unit": "pair interactions/s", "n_gpus": 1, "steps": max(1, args.steps), "ms_per_step": ms,
-            "solves_per_s": 1e3 / ms, "dtype": "f32", "higher_is_better": True,
-            "config": {"workload": "box 1x1x2.5, N=1e6 in 64 Gaussian blobs, p=20, lambda=1.5", "n_near": nb},
-            "rel_l2_phi": _rel(phi.cpu().numpy()[sub], ref["phi"]),
-            "rel_l2_field": _rel(field.cpu().numpy().T[sub], ref["field"]), "stage_ms": st,
-            "pair_kernel_rate": n * nb / (st["pairs"] * 1e-3)}
 
 
 def bench_rocksalt(args):

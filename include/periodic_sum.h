@@ -116,6 +116,10 @@ typedef struct {
     int32_t nsys;             /* 1, or the number of systems of a batched plan */
     int32_t mean_corners;     /* systems whose box mean (eq. (pfx4)) the last particle-count shape sums by
                                  corner points rather than per near entry (a launch-size choice, same result) */
+    int64_t profiled_evals;   /* evals whose stage events were recorded (see periodic_sum_set_profiling);
+                                 graph launches of the batched path never record events */
+    int64_t forward_epoch;    /* count of "get" passes enqueued or launched on this plan (eval, energy,
+                                 batched eval); the pass the plan's workspace holds last */
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
@@ -178,11 +182,17 @@ ps_status periodic_sum_energy(ps_plan plan, int64_t n,
  * dE/dq is returned projected onto sum dq = 0 (mean removed): the energy is only
  * defined for neutral charges.  Must follow a periodic_sum_energy (or eval at the
  * particles) with the same inputs on the same stream: it reuses that forward
- * pass's near set, coefficients and outputs kept in the plan. */
+ * pass's near set, coefficients and outputs kept in the plan.
+ *   epoch : 0, or the forward_epoch (periodic_sum_plan_info) read right after
+ *           the forward pass whose gradient is wanted.
+ * Errors: PS_E_INVALID when the plan's last forward pass was not at these
+ * particles (other arrays or n, separate targets, a batched plan) or, for
+ * epoch != 0, when another pass has been enqueued since that one: the stored
+ * state would belong to other inputs.  The call never reuses it then. */
 ps_status periodic_sum_energy_vjp(ps_plan plan, int64_t n,
                                   const double* x, const double* y, const double* z, const double* q,
                                   const double* gE, double* dEdx, double* dEdy, double* dEdz,
-                                  double* dEdq, int32_t exact, void* stream);
+                                  double* dEdq, int32_t exact, int64_t epoch, void* stream);
 
 /* Batched "set": nsys independent systems, each with its own box and charges
  * (prm[k].box, p, R_b/lambda, n_max as the largest N of system k; precision,
@@ -299,18 +309,32 @@ ps_status periodic_sum_last_coefficients(ps_plan plan, double* C);
 
 /* Stage timing with HIP events recorded on the eval stream between the stages
  * of algorithm "get" (single-system evals; not inside the batched graph).
- * enable != 0 turns it on for the following evals. */
+ * Recording adds no host synchronization to an eval while fewer than 16
+ * profiled evals are unread; beyond that an eval first waits for the oldest
+ * unread one (long finished in a steady loop) and adds it to the sums.
+ * enable != 0 turns it on for the following evals.  Either way the call
+ * starts a new averaging window and drops the evals not yet read. */
 ps_status periodic_sum_set_profiling(ps_plan plan, int32_t enable);
 
-/* Durations in milliseconds of the last profiled eval's stages, in this order
+/* Mean durations in milliseconds, over the profiled evals of the current window
+ * (those enqueued since set_profiling or since the previous read), of the stages
+ * of algorithm "get", in this order
  * (PS_N_STAGES values): 0 validation + spatial ordering, 1 near-set build
  * (steps 1-2), 2 tile bounds and target blocks, 3 check-point sums
  * (step 3 at Y_c1, Y_c2), 4 least-squares solve (steps 4-5), 5 zero-mean
  * constant (step 6), 6 particle pair sums (step 3 at Y0), 7 far field and
- * combination (steps 7-8).  Synchronizes on the last event.  ms: host [n],
- * n >= PS_N_STAGES. */
+ * combination (steps 7-8).  A call that finds unread evals synchronizes on the
+ * last one, averages the window and starts a new one; a call with no profiled
+ * eval since the previous read returns the same means again.  ms: host [n],
+ * n >= PS_N_STAGES.  Errors: PS_E_INVALID before any profiled eval, PS_E_HIP. */
 #define PS_N_STAGES 8
 ps_status periodic_sum_stage_times(ps_plan plan, double* ms, int32_t n);
+
+/* The plan's forward_epoch (see ps_plan_info) into *out, without synchronizing:
+ * a caller that keeps the gradient of one pass for later (an autograd graph)
+ * reads it right after that pass and hands it to periodic_sum_energy_vjp.
+ * Errors: PS_E_INVALID (NULL argument). */
+ps_status periodic_sum_forward_epoch(ps_plan plan, int64_t* out);
 
 /* Releases the plan and its device workspace (synchronizes its device). */
 void periodic_sum_destroy(ps_plan plan);

@@ -23,7 +23,8 @@ EXPORTS = ["periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "per
            "periodic_sum_plan_batched", "periodic_sum_eval_batched", "periodic_sum_status", "periodic_sum_plan_info",
            "periodic_sum_plan_tables", "periodic_sum_last_coefficients", "periodic_sum_set_profiling",
            "periodic_sum_stage_times", "periodic_sum_autotune", "periodic_sum_near_counts", "periodic_sum_destroy",
-           "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load", "periodic_sum_select"]
+           "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load", "periodic_sum_select",
+           "periodic_sum_forward_epoch"]
 STAGES = ["sort", "near", "bounds", "check", "solve", "mean", "pairs", "far"]
 
 
@@ -40,7 +41,8 @@ class ps_plan_info(ctypes.Structure):
     _fields_ = [("p", ctypes.c_int32), ("P", ctypes.c_int32), ("L", ctypes.c_int32), ("n_images", ctypes.c_int32),
                 ("rank", ctypes.c_int32), ("R0", ctypes.c_double), ("R_b", ctypes.c_double), ("cond", ctypes.c_double),
                 ("n_near_last", ctypes.c_int64), ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32),
-                ("nsys", ctypes.c_int32), ("mean_corners", ctypes.c_int32)]
+                ("nsys", ctypes.c_int32), ("mean_corners", ctypes.c_int32), ("profiled_evals", ctypes.c_int64),
+                ("forward_epoch", ctypes.c_int64)]
 
 
 class ps_select_row(ctypes.Structure):
@@ -77,7 +79,7 @@ def lib():
         L.periodic_sum_eval.restype = st
         L.periodic_sum_energy.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.periodic_sum_energy.restype = st
-        L.periodic_sum_energy_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32, vp]
+        L.periodic_sum_energy_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32, i64, vp]
         L.periodic_sum_energy_vjp.restype = st
         L.periodic_sum_eval_batched.argtypes = [vp, ctypes.POINTER(i64), vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.periodic_sum_eval_batched.restype = st
@@ -108,6 +110,8 @@ def lib():
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int32,
                                           ctypes.POINTER(ps_select_row), ctypes.POINTER(ctypes.c_int32), vp]
         L.periodic_sum_select.restype = st
+        L.periodic_sum_forward_epoch.argtypes = [vp, ctypes.POINTER(i64)]
+        L.periodic_sum_forward_epoch.restype = st
         L.periodic_sum_last_error.argtypes = []
         L.periodic_sum_last_error.restype = ctypes.c_char_p
         _lib = L

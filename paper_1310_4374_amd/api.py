@@ -187,7 +187,8 @@ class Plan:
         check(lib().periodic_sum_set_profiling(self._h, int(bool(enable))))
 
     def stage_times(self):
-        """Milliseconds per stage of the last profiled eval (synchronizes)."""
+        """Mean milliseconds per stage over the profiled evals since the previous
+        read (or since set_profiling); synchronizes on the last of them."""
         arr = (ctypes.c_double * len(_lib.STAGES))()
         check(lib().periodic_sum_stage_times(self._h, arr, len(_lib.STAGES)))
         return dict(zip(_lib.STAGES, list(arr)))
@@ -218,7 +219,17 @@ class Plan:
                                         _ptr(f[2]) if f is not None else None, _stream(self.device)))
         return e
 
-    def energy_vjp(self, x, q, gE, exact=True):
+    def forward_epoch(self):
+        """Counter of the forward passes enqueued on this plan (the last one is
+        the pass whose state energy_vjp reuses); does not synchronize."""
+        e = ctypes.c_int64()
+        check(lib().periodic_sum_forward_epoch(self._h, ctypes.byref(e)))
+        return e.value
+
+    def energy_vjp(self, x, q, gE, exact=True, epoch=0):
+        """Gradient of the last energy pass at these particles; epoch (from
+        forward_epoch right after that pass, 0 = unchecked) makes the library
+        refuse the call if another pass has run on the plan since."""
         x = _soa(x, self.device)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")
@@ -227,7 +238,7 @@ class Plan:
         gE = torch.as_tensor(gE).to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
         check(lib().periodic_sum_energy_vjp(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(gE),
                                             _ptr(dx[0]), _ptr(dx[1]), _ptr(dx[2]), _ptr(dq), int(bool(exact)),
-                                            _stream(self.device)))
+                                            int(epoch), _stream(self.device)))
         return dx, dq
 
 
@@ -384,16 +395,30 @@ class PeriodicEnergy(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, q, plan, exact=True):
-        e = plan.energy(x, q)
-        ctx.save_for_backward(x, q)
+        # the adjoint checks that it follows a pass at the same device arrays, so
+        # the (3, N) contiguous form the library reads is kept for backward
+        xs = _soa(x.detach(), plan.device)
+        qs = _vec(q.detach(), xs.shape[1], plan.device, "q")
+        e = plan.energy(xs, qs)
+        ctx.save_for_backward(xs, qs)
+        ctx.x_rows = not (x.shape[0] != 3 or (x.shape[1] == 3 and not x.is_contiguous()))  # as _soa reads it
         ctx.plan = plan
         ctx.exact = exact
+        ctx.epoch = plan.forward_epoch()
         return e[0]
 
     @staticmethod
     def backward(ctx, gE):
         x, q = ctx.saved_tensors
-        dx, dq = ctx.plan.energy_vjp(x, q, gE, exact=ctx.exact)
-        if x.shape[0] != 3:
+        plan = ctx.plan
+        epoch = ctx.epoch
+        if plan.forward_epoch() != epoch:
+            # another pass ran on the plan since this forward (the plan keeps only
+            # the last one): run this forward again so that the adjoint reuses
+            # the state of these inputs
+            plan.energy(x, q)
+            epoch = plan.forward_epoch()
+        dx, dq = plan.energy_vjp(x, q, gE, exact=ctx.exact, epoch=epoch)
+        if not ctx.x_rows:
             dx = dx.t()
         return dx, dq, None, None

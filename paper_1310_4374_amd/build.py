@@ -1,5 +1,4 @@
-"""Build libperiodic_sum.so (HIP for gfx950 + host C++) in-tree with hipcc, and
-the valu_rate executable (instruction issue rates behind the ALU roofline)."""
+"""Build libperiodic_sum.so (HIP for gfx950 + host C++) in-tree with hipcc."""
 import os
 import subprocess
 import sys
@@ -7,7 +6,6 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_lib", "libperiodic_sum.so")
-PROBE = os.path.join(HERE, "_lib", "valu_rate")
 SOURCES = ["ps_setup.cpp", "ps_kernels.hip", "ps_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PS_OFFLOAD_ARCH", "gfx950")
@@ -22,8 +20,6 @@ def build(verbose=False, jobs=3):
     os.makedirs(os.path.dirname(OUT), exist_ok=True)
     objs = []
     procs = []
-    probe_cmd = [HIPCC, "-O3", "-std=c++17", *DEVICE, "-x", "hip", os.path.join(CSRC, "valu_rate.hip"), "-o", PROBE]
-    procs.append((probe_cmd, subprocess.Popen(probe_cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
     for src in SOURCES:
         path = os.path.join(CSRC, src)
         obj = os.path.join(os.path.dirname(OUT), src + ".o")

@@ -74,6 +74,7 @@ struct EventPair {
     }
 };
 
+constexpr int kEvRing = 16;         // profiled evals whose stage events are kept until read
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
 constexpr int kCheckWaveTarget = 16384;  // check-point sums of one system: aim for this many waves
 constexpr int kMaxSplit = 256;
@@ -180,10 +181,23 @@ struct ps_plan_s {
     TItem* d_mom_t = nullptr;
     PItem* d_mom_p = nullptr;
     double* d_mom_tblk = nullptr;
-    // stage timing
+    // stage timing: the events of the last kEvRing profiled evals; older ones are
+    // read (folded into the window's sums) before their events are recorded again
     bool prof = false;
-    hipEvent_t ev[PS_N_STAGES + 1] = {};
-    bool ev_recorded = false;
+    hipEvent_t ev[kEvRing][PS_N_STAGES + 1] = {};
+    int64_t profiled_evals = 0;         // evals whose stage events were recorded (never inside a graph)
+    int64_t ev_read = 0;                // profiled evals before this one are folded into stage_sum or dropped
+    double stage_sum[PS_N_STAGES] = {}; // durations summed over the current window's folded evals
+    int64_t stage_cnt = 0;              // evals folded into stage_sum
+    bool stage_cached = false;          // stage_ms holds the means of the last window read
+    double stage_ms[PS_N_STAGES] = {};
+    hipError_t ev_err = hipSuccess;     // a failure while folding inside an eval, reported by stage_times
+    // the last forward pass at the particles (eval without separate targets, or
+    // energy): its inputs and a counter bumped by every enqueued "get"
+    int64_t fwd_epoch = 0;
+    int64_t fwd_n = 0;
+    const double* fwd_in[4] = {nullptr, nullptr, nullptr, nullptr};
+    bool fwd_particles = false;
     // PS_VALIDATE set (not "0") when the plan was made: evals return data errors themselves
     bool sync_validate = false;
     // batched graph
@@ -195,8 +209,9 @@ struct ps_plan_s {
     {
         DeviceGuard dev_guard(device);
         if (graph) (void)hipGraphExecDestroy(graph);
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto& row : ev)
+            for (hipEvent_t e : row)
+                if (e) (void)hipEventDestroy(e);
         if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void* p : allocs) (void)hipFree(p);
     }
@@ -598,6 +613,22 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     return hipStreamSynchronize(st);
 }
 
+// Adds the stage durations of profiled eval k (the oldest unread one) to the
+// window's sums; waits for its last event.
+hipError_t fold_stage_events(ps_plan_s* pl)
+{
+    hipEvent_t* e = pl->ev[pl->ev_read % kEvRing];
+    hipError_t r = hipEventSynchronize(e[PS_N_STAGES]);
+    for (int k = 0; k < PS_N_STAGES && r == hipSuccess; ++k) {
+        float t = 0.f;
+        r = hipEventElapsedTime(&t, e[k], e[k + 1]);
+        pl->stage_sum[k] += t;
+    }
+    ++pl->ev_read;
+    if (r == hipSuccess) ++pl->stage_cnt;
+    return r;
+}
+
 // Enqueue algorithm "get" for the current tables.
 void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* z, const double* q, bool separate,
                  double* phi, double* ex, double* ey, double* ez, hipStream_t st)
@@ -606,8 +637,13 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     const int nsys = pl->nsys;
     const bool capturing = pl->cap_stream && st == pl->cap_stream;  // the batched path's private capture stream
     const bool prof = pl->prof && nsys == 1 && !capturing;           // no event nodes in a captured graph
+    if (prof && pl->profiled_evals - pl->ev_read >= kEvRing) {        // its slot still holds an unread eval
+        const hipError_t r = fold_stage_events(pl);
+        if (r != hipSuccess && pl->ev_err == hipSuccess) pl->ev_err = r;
+    }
+    hipEvent_t* evs = pl->ev[pl->profiled_evals % kEvRing];
     auto mark = [&](int k) {
-        if (prof) (void)hipEventRecord(pl->ev[k], st);
+        if (prof) (void)hipEventRecord(evs[k], st);
     };
     mark(0);
     launch_validate(nsys, pl->val_blocks, pl->d_sys, x, y, z, q, pl->d_status, pl->d_val_part, st);
@@ -643,7 +679,20 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     launch_far(T.far_lanes, T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
                separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
     mark(8);
-    if (prof) pl->ev_recorded = true;
+    if (prof) ++pl->profiled_evals;
+}
+
+// Records which forward pass the plan's workspace now holds (called once per
+// enqueued or replayed "get"): the adjoint may only reuse a pass at the particles.
+void stamp_forward(ps_plan_s* pl, const double* x, const double* y, const double* z, const double* q, bool separate)
+{
+    ++pl->fwd_epoch;
+    pl->fwd_particles = !separate && pl->nsys == 1;
+    pl->fwd_n = pl->nsys == 1 ? pl->tab.sys[0].n : 0;
+    pl->fwd_in[0] = x;
+    pl->fwd_in[1] = y;
+    pl->fwd_in[2] = z;
+    pl->fwd_in[3] = q;
 }
 
 // Fields of a new plan that follow from the parameters alone.
@@ -1138,6 +1187,7 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
     }
     pl->last_n = n;
     enqueue_get(pl, x, y, z, q, m > 0, phi, ex, ey, ez, st);
+    stamp_forward(pl, x, y, z, q, m > 0);
     return eval_done(pl, st);
 }
 
@@ -1192,6 +1242,8 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
         pl->graph_key = key;
     }
     HIPCHK(hipGraphLaunch(pl->graph, st));
+    pl->last_n = n[0];
+    stamp_forward(pl, x, y, z, q, false);
     return eval_done(pl, st);
 }
 
@@ -1230,6 +1282,8 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
     out->mean_corners = 0;
     if (pl->tab_valid)
         for (const SysDev& S : pl->tab.sys) out->mean_corners += S.mcorner;
+    out->profiled_evals = pl->profiled_evals;
+    out->forward_epoch = pl->fwd_epoch;
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
@@ -1347,10 +1401,16 @@ ps_status periodic_sum_set_profiling(ps_plan pl, int32_t enable)
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
-    if (enable && !pl->ev[0])
-        for (hipEvent_t& e : pl->ev) HIPCHK(hipEventCreate(&e));
+    if (enable && !pl->ev[0][0])
+        for (auto& row : pl->ev)
+            for (hipEvent_t& e : row) HIPCHK(hipEventCreate(&e));
     pl->prof = enable != 0;
-    pl->ev_recorded = false;
+    // a new window: unread evals are dropped
+    pl->ev_read = pl->profiled_evals;
+    for (double& v : pl->stage_sum) v = 0.0;
+    pl->stage_cnt = 0;
+    pl->stage_cached = false;
+    pl->ev_err = hipSuccess;
     return PS_OK;
 }
 
@@ -1358,15 +1418,31 @@ ps_status periodic_sum_stage_times(ps_plan pl, double* ms, int32_t n)
 {
     if (!pl || !ms) return fail(PS_E_INVALID, "NULL argument");
     if (n < PS_N_STAGES) return fail(PS_E_INVALID, "need room for %d stages", PS_N_STAGES);
-    if (!pl->ev_recorded) return fail(PS_E_INVALID, "no profiled eval has been enqueued");
-    DeviceGuard dev_guard(pl->device);
-    HIPCHK(dev_guard.err);
-    HIPCHK(hipEventSynchronize(pl->ev[PS_N_STAGES]));
-    for (int k = 0; k < PS_N_STAGES; ++k) {
-        float t = 0.f;
-        HIPCHK(hipEventElapsedTime(&t, pl->ev[k], pl->ev[k + 1]));
-        ms[k] = t;
+    if (pl->ev_read < pl->profiled_evals || pl->stage_cnt > 0) {  // a new window: fold it and average it
+        DeviceGuard dev_guard(pl->device);
+        HIPCHK(dev_guard.err);
+        if (pl->ev_err != hipSuccess) {
+            const hipError_t e = pl->ev_err;
+            pl->ev_err = hipSuccess;
+            return fail(PS_E_HIP, "reading stage events failed: %s", hipGetErrorString(e));
+        }
+        while (pl->ev_read < pl->profiled_evals) HIPCHK(fold_stage_events(pl));
+        for (int k = 0; k < PS_N_STAGES; ++k) {
+            pl->stage_ms[k] = pl->stage_sum[k] / static_cast<double>(pl->stage_cnt);
+            pl->stage_sum[k] = 0.0;
+        }
+        pl->stage_cnt = 0;
+        pl->stage_cached = true;
     }
+    if (!pl->stage_cached) return fail(PS_E_INVALID, "no profiled eval has been enqueued");
+    for (int k = 0; k < PS_N_STAGES; ++k) ms[k] = pl->stage_ms[k];
+    return PS_OK;
+}
+
+ps_status periodic_sum_forward_epoch(ps_plan pl, int64_t* out)
+{
+    if (!pl || !out) return fail(PS_E_INVALID, "NULL argument");
+    *out = pl->fwd_epoch;
     return PS_OK;
 }
 
@@ -1456,20 +1532,29 @@ ps_status periodic_sum_energy(ps_plan pl, int64_t n, const double* x, const doub
     if (s != PS_OK) return s;
     pl->last_n = n;
     enqueue_get(pl, x, y, z, q, false, phi, ex, ey, ez, st);
+    stamp_forward(pl, x, y, z, q, false);
     launch_energy(1, pl->d_sys, pl->d_sq, pl->d_osort, energy, st);
     return eval_done(pl, st);
 }
 
 ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const double* y, const double* z,
                                   const double* q, const double* gE, double* dEdx, double* dEdy, double* dEdz,
-                                  double* dEdq, int32_t exact, void* stream)
+                                  double* dEdq, int32_t exact, int64_t epoch, void* stream)
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy_vjp is available for single-system plans");
     if (!x || !y || !z || !q || !gE) return fail(PS_E_INVALID, "NULL argument");
+    if (epoch < 0) return fail(PS_E_INVALID, "epoch must be >= 0");
     const std::vector<int64_t> key = {n, 0, 0, 0, 0};
-    if (!pl->tab_valid || pl->tab.key != key || pl->last_n != n)
-        return fail(PS_E_INVALID, "energy_vjp must follow a forward pass at the same particles");
+    // the adjoint reuses the last forward pass's near set, coefficients and
+    // outputs: it must have been a pass at these particles (same arrays and
+    // count), and, when the caller names one, that very pass
+    if (!pl->tab_valid || pl->tab.key != key || pl->last_n != n || !pl->fwd_particles || pl->fwd_n != n ||
+        pl->fwd_in[0] != x || pl->fwd_in[1] != y || pl->fwd_in[2] != z || pl->fwd_in[3] != q)
+        return fail(PS_E_INVALID, "energy_vjp must follow a forward pass at the same particles (same arrays and n)");
+    if (epoch != 0 && epoch != pl->fwd_epoch)
+        return fail(PS_E_INVALID, "energy_vjp: forward pass %lld was requested but the plan holds pass %lld",
+                    (long long)epoch, (long long)pl->fwd_epoch);
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);

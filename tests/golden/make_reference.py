@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg3 cfg4 cfg5 table2 table3]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3]
 """
 import os
 import sys
@@ -17,6 +17,7 @@ sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
 from oracle.ewald import Ewald  # noqa: E402
+from oracle.geometry import lattice_vectors  # noqa: E402
 from oracle.method import Plan  # noqa: E402
 
 OUT = os.path.dirname(os.path.abspath(__file__))
@@ -34,6 +35,60 @@ def cfg2():
     sub = c["subset"]
     parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
     _save("ref_cfg2.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
+
+
+def hard_targets(x, box, R_b, band=1e-3, nclose=200):
+    """Indices of the particles where a defect would hide from a norm over a
+    random sample: those with a lattice image within `band` of the near-ball
+    sphere |x + p| = R_b (in or out of the near set by a hair), those within
+    `band` of a box face, and the `nclose` particles with the closest periodic
+    neighbours (the pairs that dominate the field norm)."""
+    from scipy.spatial import cKDTree
+    d = np.asarray(box, dtype=np.float64)
+    sphere = np.zeros(len(x), dtype=bool)
+    for p in lattice_vectors(box, R_b):
+        sphere |= np.abs(np.linalg.norm(x + p, axis=1) - R_b) < band
+    face = np.any(np.abs(x) > 0.5 * d - band, axis=1)
+    tree = cKDTree(np.mod(x + 0.5 * d, d), boxsize=d)
+    dist, _ = tree.query(np.mod(x + 0.5 * d, d), k=2)
+    close = np.argsort(dist[:, 1], kind="stable")[:nclose]
+    pick = {"sphere": np.nonzero(sphere)[0], "face": np.nonzero(face)[0], "close": np.sort(close)}
+    return pick
+
+
+def _hard(name, c, plan, extra, band=1e-3, nclose=200, cap=None, seed=0):
+    """Reference values at the hard targets (capped per kind by a seeded
+    choice) plus `extra` seeded random particles."""
+    R_b = plan.R_b
+    kinds = hard_targets(c["x"], c["box"], R_b, band, nclose)
+    g = np.random.Generator(np.random.PCG64(seed))
+    out = {}
+    allidx = []
+    for k, idx in kinds.items():
+        if cap is not None and len(idx) > cap:
+            idx = np.sort(g.choice(idx, size=cap, replace=False))
+        out["idx_" + k] = idx
+        allidx.append(idx)
+    rand = np.sort(g.choice(len(c["q"]), size=extra, replace=False)) if extra else np.zeros(0, dtype=np.int64)
+    out["idx_random"] = rand
+    allidx.append(rand)
+    sub = np.unique(np.concatenate(allidx))
+    phi, field = plan.solve(c["x"], c["q"], targets=c["x"][sub])
+    out.update(subset=sub, phi=phi, field=field)
+    print(name, {k: len(v) for k, v in out.items() if k.startswith("idx_")}, "targets", len(sub), flush=True)
+    _save(name, **out)
+
+
+def cfg2_hard():
+    """Uniform cube, N = 1e5: 20,000 random particles and the hard targets."""
+    c = W.config2()
+    _hard("ref_cfg2_hard.npz", c, Plan(c["box"], c["p"], R_b=c["R_b"]), extra=20000, seed=2202)
+
+
+def cfg3_hard():
+    """Clustered box 1 x 1 x 2.5, N = 1e6: the hard targets (at most 300 of each kind)."""
+    c = W.config3()
+    _hard("ref_cfg3_hard.npz", c, Plan(c["box"], c["p"], lam=c["lam"]), extra=0, cap=300, seed=3303)
 
 
 def cfg3():

@@ -25,10 +25,15 @@ def test_pair_kernel_hash_finds_the_kernel_text():
 
 
 def test_traffic_is_reported_only_for_the_profiled_kernel_text():
-    rec = json.load(open(os.path.join(ROOT, "profiles", "p2p_f32_uniform_cube_N100k_hbm_counters.json")))
-    t = bench.measured_traffic("fp32")
-    if rec["source_sha256_16"] == bench.pair_kernel_hash():
-        assert t == rec["traffic_bytes"]
-    else:
-        assert t is None
-    assert bench.measured_traffic("fp64") is None
+    for name in ("p2p_f32_uniform_cube_N100k_hbm_counters.json", "p2p_f32_clustered_N1M_hbm_counters.json"):
+        path = os.path.join(ROOT, "profiles", name)
+        t = bench.measured_traffic("fp32", name)
+        if not os.path.exists(path):
+            assert t is None
+            continue
+        rec = json.load(open(path))
+        if rec["source_sha256_16"] == bench.pair_kernel_hash():
+            assert t == rec["traffic_bytes"]
+        else:
+            assert t is None
+        assert bench.measured_traffic("fp64", name) is None
