@@ -14,6 +14,11 @@ Parts:
   * ``ewald``   -- an independent classical Ewald sum (App. D);
   * ``adjoint`` -- the exact gradient of the method's energy with respect to
     positions and charges (derived from eqs. (3), (8), (10), (pfx3)-(pfx4));
+  * ``slab``    -- the method with the periodic extension along x and y only
+    (Sec. 1, closing paragraph), with the reading that completes it: decay
+    rows on planes above and below the box fix the far field's x/y-periodic
+    harmonic modes that periodicity alone leaves free;
+  * ``ewald2d`` -- an independent Ewald sum for charges periodic in x and y;
   * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
 
 Pins (tests/test_oracle_*.py): the basis against an independent assembly from
@@ -24,5 +29,9 @@ integrals against closed forms; Phi0 against the textbook prism potential,
 quadrature and its Laplacian; Ewald against its splitting-parameter
 independence and the NaCl Madelung constant (eq. (st1)); the method against
 the Madelung constant, Table 1's Gauss-grid errors, Ewald, periodicity and
-translation invariance; the adjoint against central finite differences.
+translation invariance; the adjoint against central finite differences; the
+slab Ewald sum against brute-force square-shell lattice sums (extrapolated), its
+splitting parameter and Gauss's law; the slab method against that Ewald sum
+(thin, thick and elongated cells, a dipolar cell), x/y periodicity and in-plane
+translation invariance.
 """
