@@ -103,7 +103,17 @@ typedef struct {
     int32_t n_check;      /* 0: Gauss spherical grid of L = 2p^2 - p points (Sec. 2.2);
                              > 0: that many caller-given check points */
     const double* check_points; /* host [3*n_check], xyz interleaved, |y| <= R0 and outside the box
-                                   along at least one axis (so a partner exists, Sec. 2.3 step 3) */
+                                   along at least one periodic axis (so a partner exists, Sec. 2.3 step 3) */
+    int32_t periodic;     /* periodic axes as a bit mask: 0 or 7 = x, y and z; 3 = x and y only (a slab,
+                             z free with vacuum on both sides; Sec. 1 says the extension may be along one
+                             or two coordinates).  For a slab: in-plane images only; the Gauss check points
+                             that an in-plane shift moves into S0 (partners along x or y); and, because
+                             x/y periodicity leaves the far field's x/y-periodic harmonic modes free, decay
+                             rows in the fit: on the planes z = +-(d3/2 + R0/10) every in-plane Fourier
+                             mode k = 2 pi (n1/d1, n2/d2), |n1|, |n2| <= ceil(p/4) + 1, satisfies
+                             <(d/dz + s|k|) phi, trig(k.rho)> = 0 (s = +1 above, -1 below; k = 0 is
+                             Gauss's law), by m x m Gauss-Legendre points per plane,
+                             m = max(2p + 8, ceil(40 max(d1, d2) / R0)).  Spherical basis only. */
 } ps_params;
 
 typedef struct {
@@ -120,6 +130,8 @@ typedef struct {
                                  graph launches of the batched path never record events */
     int64_t forward_epoch;    /* count of "get" passes enqueued or launched on this plan (eval, energy,
                                  batched eval); the pass the plan's workspace holds last */
+    int32_t periodic;         /* periodic axes of system 0 (7 or 3) */
+    int32_t n_rows;           /* rows of system 0's fit: L periodicity rows, then (slab) the decay rows */
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
@@ -299,8 +311,8 @@ ps_status periodic_sum_status(ps_plan plan, void* stream);
 ps_status periodic_sum_plan_info(ps_plan plan, ps_plan_info* out);
 
 /* Copies the plan's check points (host buffers [3*L] each, xyz interleaved),
- * the pseudo-inverse [(P-1)*L] row-major and the box integrals [P]; any pointer
- * may be NULL.  Sizes from periodic_sum_plan_info.  Single-system plans only. */
+ * the pseudo-inverse [(P-1)*n_rows] row-major and the box integrals [P]; any
+ * pointer may be NULL.  Sizes from periodic_sum_plan_info.  Single-system plans only. */
 ps_status periodic_sum_plan_tables(ps_plan plan, double* check_points, double* partners,
                                    double* pinv, double* box_means);
 

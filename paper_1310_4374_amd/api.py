@@ -13,6 +13,7 @@ from ._lib import check, lib, ps_params, ps_plan_info, ps_select_row
 
 _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
+_PERIODIC = {"xyz": 7, "xy": 3}
 
 
 def _host_points(a):
@@ -25,8 +26,9 @@ def _host_points(a):
 
 
 def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-            tile_targets=0, n_split=0, centres=None, check_points=None, keep=None):
-    """keep: a list that receives the host arrays the struct points to."""
+            tile_targets=0, n_split=0, centres=None, check_points=None, keep=None, periodic="xyz"):
+    """keep: a list that receives the host arrays the struct points to.
+    periodic: "xyz" (three periodic axes) or "xy" (a slab, z free)."""
     prm = ps_params()
     for k in range(3):
         prm.box[k] = float(box[k])
@@ -40,6 +42,7 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
     prm.m_max = int(m_max)
     prm.tile_targets = int(tile_targets)
     prm.n_split = int(n_split)
+    prm.periodic = _PERIODIC[periodic] if isinstance(periodic, str) else int(periodic)
     dp = ctypes.POINTER(ctypes.c_double)
     if centres is not None:
         c = _host_points(centres)
@@ -100,14 +103,15 @@ class Plan:
     """One periodic box: algorithm "set" at construction, "get" on each eval."""
 
     def __init__(self, box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-                 tile_targets=0, n_split=0, centres=None, check_points=None, device=0):
+                 tile_targets=0, n_split=0, centres=None, check_points=None, periodic="xyz", device=0):
         """centres: (M, 3) RBF centres outside the box (eq. (5)); None for the
         spherical-harmonic basis.  check_points: (L, 3) points on the
-        circumsphere; None for the Gauss spherical grid."""
+        circumsphere; None for the Gauss spherical grid.  periodic: "xyz", or
+        "xy" for a slab (periodic in x and y, vacuum above and below)."""
         self.device = torch.device("cuda", device)
         keep = []
         self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split,
-                            centres, check_points, keep)
+                            centres, check_points, keep, periodic)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan(ctypes.byref(self._prm), int(device), ctypes.byref(h)))
         self._h = h
@@ -139,12 +143,13 @@ class Plan:
         return {k: getattr(inf, k) for k, _ in inf._fields_}
 
     def tables(self):
-        """Check points (L,3), partners (L,3), pseudo-inverse (P-1,L), box means (P,) as CPU float64 tensors."""
+        """Check points (L,3), partners (L,3), pseudo-inverse (P-1, n_rows), box means (P,) as CPU
+        float64 tensors (n_rows = L, plus the decay rows of a slab)."""
         inf = self.info()
         L, P = inf["L"], inf["P"]
         yc = torch.empty(L, 3, dtype=torch.float64)
         yt = torch.empty(L, 3, dtype=torch.float64)
-        pinv = torch.empty(P - 1, L, dtype=torch.float64)
+        pinv = torch.empty(P - 1, inf["n_rows"], dtype=torch.float64)
         bm = torch.empty(P, dtype=torch.float64)
         dp = ctypes.POINTER(ctypes.c_double)
         check(lib().periodic_sum_plan_tables(self._h, *(ctypes.cast(t.data_ptr(), dp) for t in (yc, yt, pinv, bm))))
@@ -299,13 +304,14 @@ class BatchedPlan:
     def __init__(self, systems, p, lam=None, R_b=None, precision="fp32", mean="zero", rcond=1e-13, tile_targets=0,
                  n_split=0, device=0):
         """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam',
-        'centres', 'check_points')."""
+        'centres', 'check_points', 'periodic')."""
         self.device = torch.device("cuda", device)
         arr = (ps_params * len(systems))()
         keep = []
         for k, s in enumerate(systems):
             arr[k] = _params(s["box"], s.get("p", p), s.get("R_b", R_b), s.get("lam", lam), precision, mean, rcond,
-                             s["n_max"], 0, tile_targets, n_split, s.get("centres"), s.get("check_points"), keep)
+                             s["n_max"], 0, tile_targets, n_split, s.get("centres"), s.get("check_points"), keep,
+                             s.get("periodic", "xyz"))
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan_batched(len(systems), arr, int(device), ctypes.byref(h)))
         self._h = h

@@ -75,6 +75,7 @@ struct EventPair {
 };
 
 constexpr int kEvRing = 16;         // profiled evals whose stage events are kept until read
+constexpr int kDecayBt = 256;       // targets per workgroup of the slab decay-plane sums
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
 constexpr int kCheckWaveTarget = 16384;  // check-point sums of one system: aim for this many waves
 constexpr int kMaxSplit = 256;
@@ -93,10 +94,11 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<MItem> m_items;     // corner box mean: chunks of kMeanWave particles x corner-column slices
     std::vector<NItem> near_items;
     std::vector<TItem> t_items;
-    std::vector<PItem> chk_items, p_items, f_items;
-    std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs
+    std::vector<PItem> chk_items, p_items, f_items, d_items;
+    std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs;
+                                    // [3 nsys, 4 nsys): slab decay-plane jobs
     std::vector<SysDev> sys;
-    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0, nm = 0;
+    int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0, nm = 0, nd = 0;
     bool mean_entries = true;       // some system takes the per-entry box mean
     int far_lanes = 4;              // lanes per target of the far-field/combine kernel
 };
@@ -160,6 +162,14 @@ struct ps_plan_s {
     TItem* d_t_items = nullptr;
     PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
     PJob* d_jobs = nullptr;
+    // slab (two periodic axes): decay planes and rows
+    bool any_slab = false;
+    int max_dec = 0;                    // most decay rows of any system
+    int64_t dec_tot = 0;                // decay-plane points over all systems
+    double *d_dpts = nullptr, *d_dw = nullptr, *d_drows = nullptr;
+    double *d_part_dec = nullptr, *d_tblk_dec = nullptr;
+    int64_t part_dec_cap = 0, tblk_dec_cap = 0, cap_d = 0;
+    PItem* d_d_items = nullptr;
     int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0, cap_w = 0;
     Tables tab;
     bool tab_valid = false;
@@ -265,6 +275,10 @@ ps_status check_params(const ps_params* prm)
     if (prm->basis == PS_BASIS_RBF && (prm->n_centres < 1 || prm->n_centres > 4096 || !prm->centres))
         return fail(PS_E_INVALID, "the RBF basis needs 1..4096 centres");
     if (prm->n_check < 0 || (prm->n_check > 0 && !prm->check_points)) return fail(PS_E_INVALID, "bad check-point arguments");
+    if (prm->periodic != 0 && prm->periodic != 7 && prm->periodic != 3)
+        return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z) or 3 (x, y)");
+    if (prm->periodic == 3 && prm->basis == PS_BASIS_RBF)
+        return fail(PS_E_UNSUPPORTED, "the RBF basis is not supported with two periodic axes");
     for (int k = 0; k < 3; ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
     const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + prm->box[2] * prm->box[2]);
@@ -276,9 +290,10 @@ ps_status check_params(const ps_params* prm)
 // Source splits for one system's pair sum: the workgroup count ntb * S should
 // fill whole rounds of the device's resident capacity (at least four rounds
 // when the sources allow), so that the last round is not mostly idle.  A split
-// normally covers at least eight source tiles; a system too small to fill one
-// round that way is split further, down to one tile per split, since there the
-// per-workgroup latency rather than the per-item overhead sets the time.
+// normally covers at least eight
+// source tiles; a system too small to fill one round that way is split
+// further, down to one tile per split, since there the per-workgroup latency
+// rather than the per-item overhead sets the time.
 int split_for_capacity(int64_t ntb, int64_t capacity, int64_t ntiles_exp, int64_t max_split)
 {
     const int64_t fill = std::min<int64_t>(ntiles_exp, (capacity + ntb - 1) / ntb);
@@ -376,8 +391,9 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     }
     const bool separate = m > 0;
     const int bt = pl->bt;
-    // jobs: check-point sums (potential only), then particle sums, then RBF far fields
-    T.jobs.resize(3 * nsys);
+    // jobs: check-point sums (potential only), then particle sums, then RBF far
+    // fields, then the slab decay-plane sums (potential and field)
+    T.jobs.resize(4 * nsys);
     int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
     struct Est { int64_t ntb, nbexp; };
     std::vector<Est> est(nsys);
@@ -564,6 +580,39 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         }
     }
     if (pf_off > pl->part_far_cap) { why = "far-field partial workspace too small"; return false; }
+    // slab decay planes: near sums with the field at the 2 m^2 plane points
+    int64_t pd_off = 0, tb_d_off = 0;
+    for (int s = 0; s < nsys; ++s) {
+        const SysDev& S = T.sys[s];
+        const PJob& C = T.jobs[s];
+        PJob& D = T.jobs[3 * nsys + s];
+        D = PJob{};
+        D.ncomp = 4;
+        D.nsplit = 1;
+        D.bt = kDecayBt;
+        if (S.ndec == 0) continue;
+        D.tx = pl->d_dpts + S.dec_off;
+        D.ty = pl->d_dpts + pl->dec_tot + S.dec_off;
+        D.tz = pl->d_dpts + 2 * pl->dec_tot + S.dec_off;
+        D.nt = 2 * static_cast<int64_t>(S.m2);
+        D.sx = C.sx;
+        D.sy = C.sy;
+        D.sz = C.sz;
+        D.sq = C.sq;
+        D.ns_dev = C.ns_dev;
+        D.tblk = pl->d_tblk_dec + tb_d_off * 4;
+        const int64_t ntb_d = (D.nt + kDecayBt - 1) / kDecayBt;
+        const int64_t ntiles_exp = static_cast<int64_t>(near_expected(pl->setups[s], S.n) / kTile) + 1;
+        D.nsplit = check_splits(ntb_d, kDecayBt, ntiles_exp, nsys);
+        D.part = pl->d_part_dec + pd_off;
+        pd_off += static_cast<int64_t>(D.nsplit) * 4 * D.nt;
+        for (int64_t tb = 0; tb < ntb_d; ++tb) {
+            T.t_items.push_back(TItem{3 * nsys + s, static_cast<int>(tb)});
+            for (int sp = 0; sp < D.nsplit; ++sp) T.d_items.push_back(PItem{s, static_cast<int>(tb), sp, 0});
+        }
+        tb_d_off += ntb_d;
+    }
+    if (pd_off > pl->part_dec_cap || tb_d_off > pl->tblk_dec_cap) { why = "decay-plane workspace too small"; return false; }
     // far-field/combine chunks of 256 / far_lanes targets
     int64_t nt_all = 0;
     for (int s = 0; s < nsys; ++s) nt_all += T.jobs[nsys + s].nt;
@@ -581,8 +630,9 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T.nchk = T.chk_items.size();
     T.np = T.p_items.size();
     T.nf = T.f_items.size();
+    T.nd = T.d_items.size();
     if (T.nsort > pl->cap_sort || T.nfar > pl->cap_far || T.nnear_items > pl->cap_near_items || T.nt_items > pl->cap_t ||
-        T.nchk > pl->cap_chk || T.np > pl->cap_p || T.nf > pl->cap_t) {
+        T.nchk > pl->cap_chk || T.np > pl->cap_p || T.nf > pl->cap_t || T.nd > pl->cap_d) {
         why = "item table capacity exceeded";
         return false;
     }
@@ -608,6 +658,7 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     UP(pl->d_chk_items, T.chk_items)
     UP(pl->d_p_items, T.p_items)
     UP(pl->d_f_items, T.f_items)
+    UP(pl->d_d_items, T.d_items)
     UP(pl->d_jobs, T.jobs)
 #undef UP
     return hipStreamSynchronize(st);
@@ -633,6 +684,7 @@ hipError_t fold_stage_events(ps_plan_s* pl)
 void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* z, const double* q, bool separate,
                  double* phi, double* ex, double* ey, double* ez, hipStream_t st)
 {
+    const PJob* jobs = pl->d_jobs;
     const Tables& T = pl->tab;
     const int nsys = pl->nsys;
     const bool capturing = pl->cap_stream && st == pl->cap_stream;  // the batched path's private capture stream
@@ -656,12 +708,17 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     launch_near(nsys, T.nnear_items, pl->d_sys, pl->d_near_items, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq,
                 pl->d_ncount, pl->d_ioff, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_nbase, pl->d_inv,
                 st);
-    const PJob* cjobs = pl->d_jobs;
-    const PJob* pjobs = pl->d_jobs + nsys;
+    const PJob* cjobs = jobs;
+    const PJob* pjobs = jobs + nsys;
     mark(2);
-    launch_bounds(T.nw, pjobs, pl->d_w_items, T.nt_items, pl->d_jobs, pl->d_t_items, st);
+    launch_bounds(T.nw, pjobs, pl->d_w_items, T.nt_items, jobs, pl->d_t_items, st);
     mark(3);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
+    if (T.nd > 0) {  // slab: near sums at the decay planes, then the decay rows of f
+        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
+        launch_decay_rhs(nsys, pl->max_dec, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot, pl->d_dw, pl->d_drows,
+                         pl->d_f, st);
+    }
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
@@ -671,7 +728,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(6);
     launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
     mark(7);
-    const PJob* fjobs = pl->d_jobs + 2 * nsys;
+    const PJob* fjobs = jobs + 2 * nsys;
     if (pl->any_rbf) {  // step 7 for the RBF basis: sum over the M centres
         launch_tile_bounds(nsys, 16, fjobs, st);
         launch_p2p(0, pl->bt, true, T.nf, fjobs, pl->d_f_items, st);
@@ -767,7 +824,8 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
 #pragma omp parallel for schedule(dynamic, 1) if (nsys > 1)
     for (int s = 0; s < nsys; ++s)
         errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
-                                      prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points);
+                                      prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points,
+                                      prm[s].periodic == 3 ? 3 : 7);
     for (int s = 0; s < nsys; ++s)
         if (!errs[s].empty()) {
             delete pl;
@@ -785,11 +843,23 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     // pack offsets
     int64_t img_tot = 0, pinv_tot = 0, coef_tot = 0, rec_tot = 0, f_tot = 0;
     int64_t near_tot = 0, cell_tot = 0, inv_tot = 0, chk_tot = 0, n_tot = 0, cen_tot = 0, pfar = 0;
-    int64_t imap_tot = 0, mitems_cap = 0;
+    int64_t imap_tot = 0, mitems_cap = 0, dec_tot = 0, dw_tot = 0, drow_tot = 0;
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         SysDev& S = pl->base[s];
         S = SysDev{};
+        S.periodic = su.periodic;
+        S.Lf = su.rows();
+        S.ndec = su.n_dec;
+        S.m2 = su.m * su.m;
+        S.dec_off = dec_tot;
+        S.dw_off = dw_tot;
+        S.drow_off = drow_tot;
+        dec_tot += 2 * static_cast<int64_t>(S.m2);
+        dw_tot += S.m2;
+        drow_tot += 5 * static_cast<int64_t>(S.ndec);
+        pl->any_slab = pl->any_slab || su.n_dec > 0;
+        pl->max_dec = std::max(pl->max_dec, su.n_dec);
         pl->n_max[s] = prm[s].n_max;
         for (int k = 0; k < 3; ++k) {
             S.box[k] = su.box[k];
@@ -844,14 +914,14 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.chk_off = chk_tot;
         chk_tot += 2 * S.L;
         S.pinv_off = pinv_tot;
-        pinv_tot += static_cast<int64_t>(S.P - 1) * S.L;
+        pinv_tot += static_cast<int64_t>(S.P - 1) * S.Lf;
         S.coef_off = coef_tot;
         S.bm_off = coef_tot;
         coef_tot += S.P;
         S.rec_off = rec_tot;
         rec_tot += su.basis == 1 ? 0 : 2 * S.P + S.p;
         S.f_off = f_tot;
-        f_tot += S.L;
+        f_tot += S.Lf;
         S.inv_off = inv_tot;
         inv_tot += prm[s].n_max * S.nimg;
         n_tot += prm[s].n_max;
@@ -867,10 +937,13 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     pl->tiles_tot = near_tot / kTile + 1;
     pl->cen_tot = cen_tot;
     pl->part_far_cap = pfar;
+    pl->dec_tot = dec_tot;
     // host tables
     std::vector<double> h_img(img_tot * 3), h_chk(chk_tot * 3), h_pinv(pinv_tot), h_bm(coef_tot), h_rec(rec_tot);
     std::vector<double> h_cen(std::max<int64_t>(1, 3 * cen_tot), 1e3);  // padding: far from every box
     std::vector<int> h_imap(std::max<int64_t>(1, imap_tot), -1);
+    std::vector<double> h_dpts(std::max<int64_t>(1, 3 * dec_tot)), h_dw(std::max<int64_t>(1, dw_tot)),
+        h_drows(std::max<int64_t>(1, drow_tot));
     for (int s = 0; s < nsys; ++s) {
         const SystemSetup& su = pl->setups[s];
         const SysDev& S = pl->base[s];
@@ -889,6 +962,10 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
                 h_chk[k * chk_tot + S.chk_off + S.L + l] = su.yt[l * 3 + k];
             }
         std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
+        for (int64_t k = 0; k < 2 * static_cast<int64_t>(S.m2); ++k)
+            for (int c = 0; c < 3; ++c) h_dpts[c * dec_tot + S.dec_off + k] = su.dec_pts[k * 3 + c];
+        std::copy(su.dec_w.begin(), su.dec_w.end(), h_dw.begin() + S.dw_off);
+        std::copy(su.dec_rows.begin(), su.dec_rows.end(), h_drows.begin() + S.drow_off);
         std::copy(su.box_means.begin(), su.box_means.end(), h_bm.begin() + S.bm_off);
         if (su.basis == 1) {
             for (int t = 0; t < S.M; ++t)
@@ -918,10 +995,28 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
                                               nsys);
         nt_sum += nt;
     }
+    {   // slab decay planes: target blocks, items, partials (the split count grows with n, so n_max bounds it)
+        int64_t tb_d = 0, items_d = 0, part_d = 0;
+        for (int s = 0; s < nsys; ++s) {
+            const SysDev& S = pl->base[s];
+            if (S.ndec == 0) continue;
+            const int64_t nt = 2 * static_cast<int64_t>(S.m2);
+            const int64_t ntb = (nt + kDecayBt - 1) / kDecayBt;
+            const int sp = check_splits(ntb, kDecayBt,
+                                        static_cast<int64_t>(near_expected(pl->setups[s], prm[s].n_max) / kTile) + 1,
+                                        nsys);
+            tb_d += ntb;
+            items_d += ntb * sp;
+            part_d += static_cast<int64_t>(sp) * 4 * nt;
+        }
+        pl->tblk_dec_cap = tb_d;
+        pl->cap_d = items_d;
+        pl->part_dec_cap = part_d;
+    }
     pl->cap_sort = sort_cap;
     pl->cap_near_items = near_items_cap;
     pl->cap_far = far_cap;
-    pl->cap_t = tb_p + tb_c;
+    pl->cap_t = tb_p + tb_c + pl->tblk_dec_cap;   // the decay planes' target blocks share the item table
     pl->tblk_p_cap = tb_p;
     pl->tblk_chk_cap = tb_c;
     pl->cap_chk = chk_items_cap;
@@ -983,7 +1078,13 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_t_items, pl->cap_t)
     AL(pl->d_chk_items, pl->cap_chk)
     AL(pl->d_p_items, pl->cap_p)
-    AL(pl->d_jobs, 3 * nsys)
+    AL(pl->d_jobs, 4 * nsys)
+    AL(pl->d_dpts, 3 * std::max<int64_t>(1, dec_tot))
+    AL(pl->d_dw, std::max<int64_t>(1, dw_tot))
+    AL(pl->d_drows, std::max<int64_t>(1, drow_tot))
+    AL(pl->d_part_dec, std::max<int64_t>(1, pl->part_dec_cap))
+    AL(pl->d_tblk_dec, 4 * std::max<int64_t>(1, pl->tblk_dec_cap))
+    AL(pl->d_d_items, std::max<int64_t>(1, pl->cap_d))
     AL(pl->d_f_items, pl->cap_t)
     AL(pl->d_cen, 3 * std::max<int64_t>(1, cen_tot))
     AL(pl->d_cen_bb, (cen_tot / kTile + 1) * (kTile / kGroup) * 6)
@@ -1002,6 +1103,9 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     UPS(pl->d_rec, h_rec)
     UPS(pl->d_cen, h_cen)
     UPS(pl->d_imap, h_imap)
+    UPS(pl->d_dpts, h_dpts)
+    UPS(pl->d_dw, h_dw)
+    UPS(pl->d_drows, h_drows)
 #undef UPS
     if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int));
     if (e == hipSuccess) e = hipMemset(pl->d_coef, 0, sizeof(double) * coef_tot);
@@ -1018,7 +1122,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
 // Plan files: magic, version, system count, tuned launch shape, then per system
 // the scalar parameters and the set data, then a checksum of all prior bytes.
 const char kPlanMagic[8] = {'P', 'S', 'P', 'L', 'A', 'N', '0', '1'};
-const uint32_t kPlanVersion = 1;
+const uint32_t kPlanVersion = 2;
 
 template <typename T>
 void put_scalar(std::vector<unsigned char>& out, const T& v)
@@ -1071,6 +1175,7 @@ ps_status periodic_sum_plan_save(ps_plan pl, const char* path)
         put_scalar(buf, q.tile_targets);
         put_scalar(buf, q.n_split);
         put_scalar(buf, q.basis);
+        put_scalar(buf, q.periodic);
         pl->setups[s].serialize(buf);
     }
     put_scalar(buf, fnv1a64(buf.data(), buf.size()));
@@ -1125,12 +1230,14 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
         ok = ok && get_scalar(buf, pos, q.p) && get_scalar(buf, pos, q.R_b) && get_scalar(buf, pos, q.lambda) &&
              get_scalar(buf, pos, q.precision) && get_scalar(buf, pos, q.mean) && get_scalar(buf, pos, q.rcond) &&
              get_scalar(buf, pos, q.n_max) && get_scalar(buf, pos, q.m_max) &&
-             get_scalar(buf, pos, q.tile_targets) && get_scalar(buf, pos, q.n_split) && get_scalar(buf, pos, q.basis);
+             get_scalar(buf, pos, q.tile_targets) && get_scalar(buf, pos, q.n_split) && get_scalar(buf, pos, q.basis) &&
+             get_scalar(buf, pos, q.periodic);
         if (!ok) return fail(PS_E_IO, "%s: truncated parameters of system %d", path, s);
         const std::string why = setups[s].deserialize(buf.data(), buf.size(), pos);
         if (!why.empty()) return fail(PS_E_IO, "%s: system %d: %s", path, s, why.c_str());
         const SystemSetup& su = setups[s];
-        if (q.p != su.p || q.basis != su.basis) return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
+        if (q.p != su.p || q.basis != su.basis || (q.periodic == 3 ? 3 : 7) != su.periodic)
+            return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
         for (int k = 0; k < 3; ++k)
             if (q.box[k] != su.box[k]) return fail(PS_E_IO, "%s: system %d: box does not match its tables", path, s);
         if (su.basis == PS_BASIS_RBF) {
@@ -1284,6 +1391,8 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
         for (const SysDev& S : pl->tab.sys) out->mean_corners += S.mcorner;
     out->profiled_evals = pl->profiled_evals;
     out->forward_epoch = pl->fwd_epoch;
+    out->periodic = su.periodic;
+    out->n_rows = su.rows();
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
@@ -1559,6 +1668,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
+    if (exact && S.ndec > 0)
+        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with two periodic axes (exact = 0 is)");
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;

@@ -21,6 +21,8 @@ void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStre
 void launch_bounds(int64_t nwitems, const PJob* pjobs, const CItem* witems, int64_t ntitems, const PJob* jobs,
                    const TItem* titems, hipStream_t st);
 void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
+void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
+                      const double* dw, const double* drows, double* f, hipStream_t st);
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
                   double* coef, double* f, hipStream_t st);
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,

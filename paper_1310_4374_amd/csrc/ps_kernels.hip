@@ -507,14 +507,6 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
     return s;
 }
 
-__device__ __forceinline__ bool tile_is_far(const double* bb, double cx, double cy, double cz, double far2)
-{
-    const double gx = fmax(0.0, fmax(bb[0] - cx, cx - bb[3]));
-    const double gy = fmax(0.0, fmax(bb[1] - cy, cy - bb[4]));
-    const double gz = fmax(0.0, fmax(bb[2] - cz, cz - bb[5]));
-    return gx * gx + gy * gy + gz * gz > far2;
-}
-
 // FP32 pair arithmetic on coordinates relative to the target-block centre.
 // LDS holds, per source, A = (-2 s_hi, q) and B = (s_lo, |s_hi|^2), where
 // s_hi + s_lo is the FP64 relative position split into two floats.
@@ -590,21 +582,46 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
     }
 }
 
-// Near/far decisions of the kTile/kGroup groups of a staged tile, made once per
-// tile by one lane per group and shared through a ballot, so that the group
-// branch is wave-uniform.
-__device__ __forceinline__ uint64_t far_group_mask(const double* bb, double cx, double cy, double cz, double far2)
+// Near/far decisions of a staged tile's kTile/kGroup groups.  While staging,
+// each thread tests its own source: far when its FP64 distance from the target
+// block's centre exceeds kFarFactor x (block radius).  A group is far when all
+// of its sources are (then every pair of the group is at least
+// (kFarFactor - 1) x radius apart, the bound both pair forms rely on); a
+// coincident source is never far.  The 64 sources a wave stages in one step
+// are two whole groups: one ballot gives both groups' bits, which lane 0
+// writes to LDS.  After the barrier every wave reads the tile's mask back, so
+// the group branch is wave-uniform.
+__device__ __forceinline__ void store_far_bits(uint32_t* far_bits, int first, bool far)
 {
-    const int lane = threadIdx.x & 63;
-    const bool far = lane < kTile / kGroup && tile_is_far(bb + (lane & (kTile / kGroup - 1)) * 6, cx, cy, cz, far2);
-    return __ballot(far);
+    const uint64_t m = __ballot(far);
+    if ((threadIdx.x & 63) == 0) {
+        far_bits[(first >> 5)] = (uint32_t)m == 0xffffffffu;
+        far_bits[(first >> 5) + 1] = (uint32_t)(m >> 32) == 0xffffffffu;
+    }
+}
+__device__ __forceinline__ uint32_t load_far_mask(const uint32_t* far_bits)
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int g = 0; g < kTile / kGroup; ++g) m |= far_bits[g] << g;
+    return __builtin_amdgcn_readfirstlane(m);
 }
 
+// Occupancy hint for the register allocator: six waves per SIMD (at most 80
+// VGPRs) for 256- and 128-wide workgroups (79 VGPRs; 80 and one spilled
+// register outside the loops); 64-wide workgroups stage four sources per thread
+// and are held to four (92 VGPRs; their LDS allows five).
+template <int BT>
+constexpr int p2p_waves_hint() { return BT >= 128 ? 6 : 4; }
+
 template <int BT, bool FIELD>
-__global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hint<BT>()))) void k_p2p_f32(
+    const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
+    constexpr int PF = kTile / BT;  // sources each thread stages per tile
     __shared__ float4 sA[kTile];
     __shared__ float4 sB[kTile];
+    __shared__ uint32_t sFar[kTile / kGroup];
     const PItem it = items[blockIdx.x];
     const PJob& J = jobs[it.job];
     const SourceSplit sp = split_range(J, it.split);
@@ -622,33 +639,60 @@ __global__ __launch_bounds__(BT) void k_p2p_f32(const PJob* __restrict__ jobs, c
     const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
     const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
-    double aP = 0.0, aW = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
-    for (int64_t t = sp.t0; t < sp.t1; ++t) {
-        __syncthreads();
-        for (int k = threadIdx.x; k < kTile; k += BT) {
-            const int64_t j = t * kTile + k;
+    const double* __restrict__ SX = J.sx;
+    const double* __restrict__ SY = J.sy;
+    const double* __restrict__ SZ = J.sz;
+    const double* __restrict__ SQ = J.sq;
+    // staging: all of a thread's loads of a tile are issued before any is used
+    double px[PF], py[PF], pz[PF], pq[PF];
+    auto fetch = [&](int64_t t) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int64_t j = t * kTile + u * BT + threadIdx.x;
+            const bool v = j < sp.ns;
+            px[u] = v ? SX[j] : 0.0;
+            py[u] = v ? SY[j] : 0.0;
+            pz[u] = v ? SZ[j] : 0.0;
+            pq[u] = v ? SQ[j] : 0.0;
+        }
+    };
+    auto stage = [&](int64_t t) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int k = u * BT + threadIdx.x;
             // padding: a source of charge 0 at (2^60, 0, 0) from the centre, which
             // coincides with no target and keeps r^2 finite in FP32
             float4 a = make_float4(-0x1p61f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0x1p120f);
-            if (j < sp.ns) {
-                const double ux = J.sx[j] - cx, uy = J.sy[j] - cy, uz = J.sz[j] - cz;
+            bool far = true;
+            if (t * kTile + k < sp.ns) {
+                const double ux = px[u] - cx, uy = py[u] - cy, uz = pz[u] - cz;
+                far = ux * ux + uy * uy + uz * uz > far2;
                 const float ax = (float)ux, ay = (float)uy, az = (float)uz;
-                a = make_float4(-2.f * ax, -2.f * ay, -2.f * az, (float)J.sq[j]);
+                a = make_float4(-2.f * ax, -2.f * ay, -2.f * az, (float)pq[u]);
                 b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az),
                                 __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
             }
             sA[k] = a;
             sB[k] = b;
+            store_far_bits(sFar, k & ~63, far);
         }
+    };
+    double aP = 0.0, aW = 0.0, aX = 0.0, aY = 0.0, aZ = 0.0;
+    for (int64_t t = sp.t0; t < sp.t1; ++t) {
         __syncthreads();
-        const uint64_t farm = far_group_mask(J.tile_bb + t * (kTile / kGroup) * 6, cx, cy, cz, far2);
+        fetch(t);
+        stage(t);
+        __syncthreads();
+        const uint32_t farm = load_far_mask(sFar);
+        const float4* A = sA;
+        const float4* B = sB;
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f32<false, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
+                group32_f32<false, FIELD>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
                                           aY, aZ);
             else
-                group32_f32<true, FIELD>(sA + gq * kGroup, sB + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
+                group32_f32<true, FIELD>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
                                          aY, aZ);
         }
     }
@@ -714,6 +758,7 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
 {
     __shared__ double4 sF[kTile];
     __shared__ double4 sN[kTile];
+    __shared__ uint32_t sFar[kTile / kGroup];
     const PItem it = items[blockIdx.x];
     const PJob& J = jobs[it.job];
     const SourceSplit sp = split_range(J, it.split);
@@ -739,17 +784,20 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
             // padding: charge 0 at 2^500 from the centre, coincides with no target
             double4 f = make_double4(-0x1p500, 0.0, 0.0, 0x1p1000);
             double4 n = make_double4(cx + 0x1p500, cy, cz, 0.0);
+            bool far = true;
             if (j < sp.ns) {
                 const double x = J.sx[j], y = J.sy[j], z = J.sz[j];
                 const double ux = x - cx, uy = y - cy, uz = z - cz;
+                far = ux * ux + uy * uy + uz * uz > far2;
                 f = make_double4(-ux, -uy, -uz, __builtin_fma(uz, uz, __builtin_fma(uy, uy, ux * ux)));
                 n = make_double4(x, y, z, 0.5 * J.sq[j]);
             }
             sF[k] = f;
             sN[k] = n;
+            store_far_bits(sFar, k & ~63, far);
         }
         __syncthreads();
-        const uint64_t farm = far_group_mask(J.tile_bb + t * (kTile / kGroup) * 6, cx, cy, cz, far2);
+        const uint32_t farm = load_far_mask(sFar);
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
@@ -803,6 +851,43 @@ __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, co
     }
 }
 
+// Slab decay rows (two periodic axes): f[L + r] = <(E_z - s|k| phi_near) trig(k.rho)>
+// over decay plane s, i.e. -<(d phi_near/dz + s|k| phi_near) trig(k.rho)>, from the
+// split partials of the near sums at the plane points (potential and field).
+// One workgroup per (row, system); fixed-order reduction.
+__global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ djobs,
+                                                   const double* __restrict__ dpts, int64_t dec_tot,
+                                                   const double* __restrict__ dw, const double* __restrict__ drows,
+                                                   double* __restrict__ fout)
+{
+    __shared__ double sh[4];
+    const SysDev& S = sys[blockIdx.y];
+    const int r = blockIdx.x;
+    if (r >= S.ndec) return;  // uniform over the workgroup
+    const PJob& J = djobs[blockIdx.y];
+    const double* row = drows + S.drow_off + (int64_t)r * 5;
+    const double kx = row[0], ky = row[1], kk = row[2], sg = row[3];
+    const bool use_sin = row[4] != 0.0;
+    const int plane = sg > 0.0 ? 0 : 1;
+    const double* px = dpts + S.dec_off;
+    const double* py = dpts + dec_tot + S.dec_off;
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < S.m2; k += 256) {
+        const int64_t i = (int64_t)plane * S.m2 + k;
+        double phi = 0.0, ez = 0.0;
+        for (int sp = 0; sp < J.nsplit; ++sp) {
+            const double* P_ = J.part + (int64_t)sp * 4 * J.nt;
+            phi += P_[i];
+            ez += P_[3 * J.nt + i];
+        }
+        const double ph = kx * px[i] + ky * py[i];
+        const double tr = use_sin ? sin(ph) : cos(ph);
+        acc = __builtin_fma(dw[S.dw_off + k] * tr, ez - sg * kk * phi, acc);
+    }
+    acc = block_reduce<0>(acc, sh);
+    if (threadIdx.x == 0) fout[S.f_off + S.L + r] = acc;
+}
+
 __global__ __launch_bounds__(256) void k_gemv(const SysDev* __restrict__ sys, const double* __restrict__ pinv,
                                               const double* __restrict__ f, double* __restrict__ coef)
 {
@@ -810,10 +895,10 @@ __global__ __launch_bounds__(256) void k_gemv(const SysDev* __restrict__ sys, co
     const int lane = threadIdx.x & 63;
     const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (r >= S.P - 1) return;
-    const double* row = pinv + S.pinv_off + (int64_t)r * S.L;
+    const double* row = pinv + S.pinv_off + (int64_t)r * S.Lf;
     const double* fs = f + S.f_off;
     double acc = 0.0;
-    for (int l = lane; l < S.L; l += 64) acc = __builtin_fma(row[l], fs[l], acc);
+    for (int l = lane; l < S.Lf; l += 64) acc = __builtin_fma(row[l], fs[l], acc);
     acc = wave_sum(acc);
     if (lane == 0) coef[S.coef_off + 1 + r] = acc;
 }
@@ -1241,6 +1326,12 @@ void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, 
     P2P_CASE(256)
 #undef P2P_CASE
 }
+void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
+                      const double* dw, const double* drows, double* f, hipStream_t st)
+{
+    if (maxdec <= 0) return;
+    PS_LAUNCH(k_decay_rhs, dim3(maxdec, nsys), dim3(256), 0, st, sys, djobs, dpts, dec_tot, dw, drows, f);
+}
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
                   double* coef, double* f, hipStream_t st)
 {
@@ -1375,7 +1466,7 @@ __global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ 
     __syncthreads();
     for (int l = threadIdx.x; l < L; l += 256) {
         double w = 0.0;
-        for (int t = 1; t < P; ++t) w = __builtin_fma(pinv[S.pinv_off + (int64_t)(t - 1) * L + l], u[t], w);
+        for (int t = 1; t < P; ++t) w = __builtin_fma(pinv[S.pinv_off + (int64_t)(t - 1) * S.Lf + l], u[t], w);
         const int64_t o1 = S.n + l, o2 = S.n + L + l;
         const double* cx = chk + S.chk_off;
         const double* cy = chk + chk_tot + S.chk_off;

@@ -51,6 +51,37 @@ void Recurrence::eval(double x, double y, double z, double* out) const
     }
 }
 
+void Recurrence::eval_dz(double x, double y, double z, double* out, double* dout) const
+{
+    const double r2 = x * x + y * y + z * z;
+    double dA = 1.0, dB = 0.0;
+    for (int m = 0; m < p; ++m) {
+        if (m > 0) {
+            const double nA = -c[m] * (x * dA + y * dB);
+            const double nB = c[m] * (y * dA - x * dB);
+            dA = nA;
+            dB = nB;
+        }
+        for (int s = 0; s < (m ? 2 : 1); ++s) {
+            const int mm = s ? -m : m;
+            double prev2 = 0.0, prev1 = s ? dB : dA, dprev2 = 0.0, dprev1 = 0.0;
+            out[m * m + m + mm] = prev1;
+            dout[m * m + m + mm] = 0.0;
+            for (int n = m + 1; n < p; ++n) {
+                const int t = n * n + n + mm;
+                const double v = -a[t] * z * prev1 - b[t] * r2 * prev2;
+                const double dv = -a[t] * (prev1 + z * dprev1) - b[t] * (2.0 * z * prev2 + r2 * dprev2);
+                out[t] = v;
+                dout[t] = dv;
+                prev2 = prev1;
+                prev1 = v;
+                dprev2 = dprev1;
+                dprev1 = dv;
+            }
+        }
+    }
+}
+
 // Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1], ascending:
 // Newton's method on P_n evaluated by the three-term recurrence.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
@@ -261,10 +292,52 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
 
 }  // namespace
 
+void SystemSetup::build_decay()
+{
+    dec_pts.clear();
+    dec_w.clear();
+    dec_rows.clear();
+    n_dec = nk = m = 0;
+    zd = 0.0;
+    if (periodic == 7) return;
+    const double h = R0 / 10.0;
+    zd = 0.5 * box[2] + h;
+    nk = (p + 3) / 4 + 1;
+    m = std::max(2 * p + 8, static_cast<int>(std::ceil(4.0 * std::max(box[0], box[1]) / h)));
+    std::vector<double> g, w;
+    gauss_legendre(m, g, w);
+    dec_w.resize(static_cast<size_t>(m) * m);
+    dec_pts.resize(static_cast<size_t>(2) * m * m * 3);
+    for (int pl = 0; pl < 2; ++pl)
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                const size_t k = static_cast<size_t>(i) * m + j;
+                dec_w[k] = 0.25 * w[i] * w[j];
+                double* q = &dec_pts[(static_cast<size_t>(pl) * m * m + k) * 3];
+                q[0] = 0.5 * box[0] * g[i];
+                q[1] = 0.5 * box[1] * g[j];
+                q[2] = pl == 0 ? zd : -zd;
+            }
+    for (int pl = 0; pl < 2; ++pl)
+        for (int n1 = 0; n1 <= nk; ++n1)
+            for (int n2 = -nk; n2 <= nk; ++n2) {
+                if (n1 == 0 && n2 < 0) continue;   // one of each +-k pair
+                const double kx = 2.0 * M_PI * n1 / box[0], ky = 2.0 * M_PI * n2 / box[1];
+                const double kk = std::sqrt(kx * kx + ky * ky);
+                for (int trig = 0; trig < (n1 == 0 && n2 == 0 ? 1 : 2); ++trig)
+                    dec_rows.insert(dec_rows.end(), {kx, ky, kk, pl == 0 ? 1.0 : -1.0, static_cast<double>(trig)});
+            }
+    n_dec = static_cast<int>(dec_rows.size() / 5);
+}
+
 std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond, int basis_,
-                               int n_centres, const double* cen, int n_check, const double* chk)
+                               int n_centres, const double* cen, int n_check, const double* chk, int periodic_)
 {
     basis = basis_;
+    if (periodic_ != 7 && periodic_ != 3) return "periodic axes must be 7 (x, y, z) or 3 (x, y)";
+    if (periodic_ == 3 && basis_ != 0) return "the RBF basis is not supported with two periodic axes";
+    periodic = periodic_;
+    const int nper = periodic == 7 ? 3 : 2;   // axes a partner may be shifted along
     for (int k = 0; k < 3; ++k) {
         if (!(bx[k] > 0.0) || !std::isfinite(bx[k])) return "box lengths must be positive and finite";
         box[k] = bx[k];
@@ -283,7 +356,7 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     images.clear();
     images.insert(images.end(), {0, 0, 0});
     int K[3];
-    for (int k = 0; k < 3; ++k) K[k] = static_cast<int>(std::floor(R_b / box[k] + 0.5));
+    for (int k = 0; k < 3; ++k) K[k] = k < nper ? static_cast<int>(std::floor(R_b / box[k] + 0.5)) : 0;
     for (int i = -K[0]; i <= K[0]; ++i)
         for (int j = -K[1]; j <= K[1]; ++j)
             for (int l = -K[2]; l <= K[2]; ++l) {
@@ -306,8 +379,9 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
             const double* y = &yc[static_cast<size_t>(l) * 3];
             const double r2 = y[0] * y[0] + y[1] * y[1] + y[2] * y[2];
             bool outside = false;
-            for (int k = 0; k < 3; ++k) outside = outside || std::fabs(y[k]) > 0.5 * box[k];
-            if (!(r2 <= R0 * R0 * (1.0 + 1e-9)) || !outside) return "a check point is outside S0 or inside the box";
+            for (int k = 0; k < nper; ++k) outside = outside || std::fabs(y[k]) > 0.5 * box[k];
+            if (!(r2 <= R0 * R0 * (1.0 + 1e-9)) || !outside)
+                return "a check point is outside S0 or inside the box along every periodic axis";
         }
     } else {
         std::vector<double> mu, wq;
@@ -325,6 +399,15 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 y[2] = R0 * mu[a];
             }
         }
+        if (periodic == 3) {   // a slab keeps the points that an in-plane shift moves into S0
+            std::vector<double> kept;
+            for (int l = 0; l < L; ++l) {
+                const double* y = &yc[static_cast<size_t>(l) * 3];
+                if (std::fabs(y[0]) > 0.5 * box[0] || std::fabs(y[1]) > 0.5 * box[1]) kept.insert(kept.end(), y, y + 3);
+            }
+            yc.swap(kept);
+            L = static_cast<int>(yc.size() / 3);
+        }
     }
     yt.assign(static_cast<size_t>(L) * 3, 0.0);
     // step 3: partner = one coordinate shifted by its period, the coordinate that
@@ -333,7 +416,7 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
         const double* y = &yc[static_cast<size_t>(l) * 3];
         int kb = 0;
         double best = -1e300;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < nper; ++k) {
             const double g = box[k] * (2.0 * std::fabs(y[k]) - box[k]);
             if (g > best) { best = g; kb = k; }
         }
@@ -353,7 +436,10 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
         P = n_centres + 1;
     }
     const int n = P - 1;
-    std::vector<double> A(static_cast<size_t>(L) * n), r1(std::max(P, p * p)), r2(std::max(P, p * p));
+    build_decay();
+    const int Lf = rows();
+    if (Lf < n) return "fewer fit rows than basis functions: raise the number of check points";
+    std::vector<double> A(static_cast<size_t>(Lf) * n), r1(std::max(P, p * p)), r2(std::max(P, p * p));
     for (int l = 0; l < L; ++l) {
         const double* y = &yc[static_cast<size_t>(l) * 3];
         const double* t = &yt[static_cast<size_t>(l) * 3];
@@ -362,17 +448,43 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 const double* c = &centres[static_cast<size_t>(j) * 3];
                 const double a0 = y[0] - c[0], a1 = y[1] - c[1], a2 = y[2] - c[2];
                 const double b0 = t[0] - c[0], b1 = t[1] - c[1], b2 = t[2] - c[2];
-                A[static_cast<size_t>(j) * L + l] =
+                A[static_cast<size_t>(j) * Lf + l] =
                     1.0 / std::sqrt(a0 * a0 + a1 * a1 + a2 * a2) - 1.0 / std::sqrt(b0 * b0 + b1 * b1 + b2 * b2);
             }
         } else {
             rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
             rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
-            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * L + l] = r1[j + 1] - r2[j + 1];
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + l] = r1[j + 1] - r2[j + 1];
+        }
+    }
+    if (n_dec > 0) {
+        // decay rows: <(dR_t/dz + s|k| R_t) trig(k.rho)> over a plane, R_t at y/R0
+        const int m2 = m * m;
+        std::vector<double> V(static_cast<size_t>(2) * m2 * P), D(static_cast<size_t>(2) * m2 * P);
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < 2 * m2; ++k) {
+            const double* q = &dec_pts[static_cast<size_t>(k) * 3];
+            rec.eval_dz(q[0] / R0, q[1] / R0, q[2] / R0, &V[static_cast<size_t>(k) * P], &D[static_cast<size_t>(k) * P]);
+        }
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int r = 0; r < n_dec; ++r) {
+            const double* row = &dec_rows[static_cast<size_t>(r) * 5];
+            const int pl = row[3] > 0 ? 0 : 1;
+            std::vector<double> acc(n, 0.0);
+            for (int k = 0; k < m2; ++k) {
+                const double* q = &dec_pts[(static_cast<size_t>(pl) * m2 + k) * 3];
+                const double ph = row[0] * q[0] + row[1] * q[1];
+                const double wt = dec_w[k] * (row[4] == 0.0 ? std::cos(ph) : std::sin(ph));
+                const double* v = &V[(static_cast<size_t>(pl) * m2 + k) * P];
+                const double* d = &D[(static_cast<size_t>(pl) * m2 + k) * P];
+                const double sk = row[3] * row[2];
+                for (int j = 0; j < n; ++j) acc[j] += wt * (d[j + 1] / R0 + sk * v[j + 1]);
+            }
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + L + r] = acc[j];
         }
     }
     // step 5: decomposition -> pseudo-inverse
-    pseudo_inverse(L, n, std::move(A), rcond, pinv, rank, cond);
+    pseudo_inverse(Lf, n, std::move(A), rcond, pinv, rank, cond);
     if (rank < 1) return "fitting matrix has numerical rank zero";
     // step 6: box integrals of the basis: the box-mean potential at each RBF centre
     // (App. C), or tensor Gauss-Legendre with N_q = floor((p-1)/2) + 1 nodes (App. B)
@@ -459,6 +571,7 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
     put(out, cond);
     put(out, static_cast<int32_t>(images.size() / 3));
     put(out, static_cast<int32_t>(centres.size() / 3));
+    put(out, static_cast<int32_t>(periodic));
     put_vec(out, yc);
     put_vec(out, yt);
     put_vec(out, pinv);
@@ -469,21 +582,24 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
 
 std::string SystemSetup::deserialize(const unsigned char* data, size_t size, size_t& pos)
 {
-    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0;
+    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0, per = 0;
     bool ok = true;
     for (int k = 0; k < 3; ++k) ok = ok && get(data, size, pos, box[k]);
     ok = ok && get(data, size, pos, b) && get(data, size, pos, R0) && get(data, size, pos, R_b) &&
          get(data, size, pos, thr) && get(data, size, pos, V0) && get(data, size, pos, p_) &&
          get(data, size, pos, P_) && get(data, size, pos, L_) && get(data, size, pos, rank_) &&
-         get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M);
+         get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M) &&
+         get(data, size, pos, per);
     if (!ok) return "truncated system record";
+    if (per != 7 && per != 3) return "bad periodic axes";
+    if (per == 3 && b != 0) return "the RBF basis is not supported with two periodic axes";
     for (int k = 0; k < 3; ++k)
         if (!(box[k] > 0.0) || !std::isfinite(box[k])) return "bad box lengths";
     if (b != 0 && b != 1) return "bad basis";
     if (p_ < 2 || p_ > 40) return "p out of range";
     if (b == 0 && (P_ != p_ * p_ || M != 0)) return "basis size does not match p";
     if (b == 1 && (M < 1 || M > 4096 || P_ != M + 1)) return "bad RBF centre count";
-    if (L_ < 1 || L_ > (1 << 20) || L_ < P_ - 1) return "bad check-point count";
+    if (L_ < 1 || L_ > (1 << 20)) return "bad check-point count";
     if (rank_ < 1 || rank_ > P_ - 1) return "bad rank";
     if (nimg < 1 || nimg > (1 << 20)) return "bad image count";
     if (!(R0 > 0.0) || !(R_b > R0) || !std::isfinite(R_b) || !(thr > 0.0) || !(V0 > 0.0)) return "bad geometry";
@@ -492,9 +608,12 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
     P = P_;
     L = L_;
     rank = rank_;
+    periodic = per;
+    build_decay();
+    if (rows() < P - 1) return "bad check-point count";
     const size_t l3 = static_cast<size_t>(L) * 3;
     ok = get_vec(data, size, pos, yc, l3) && get_vec(data, size, pos, yt, l3) &&
-         get_vec(data, size, pos, pinv, static_cast<size_t>(P - 1) * L) && get_vec(data, size, pos, box_means, P) &&
+         get_vec(data, size, pos, pinv, static_cast<size_t>(P - 1) * rows()) && get_vec(data, size, pos, box_means, P) &&
          get_vec(data, size, pos, images, static_cast<size_t>(nimg) * 3) &&
          get_vec(data, size, pos, centres, static_cast<size_t>(M) * 3);
     if (!ok) return "truncated system arrays";

@@ -21,6 +21,9 @@ struct Recurrence {
     void build(int p_);
     // R^_t at (x, y, z) for t < p*p.
     void eval(double x, double y, double z, double* out) const;
+    // R^_t and dR^_t/dz (forward-mode differentiation of the same recurrence;
+    // the diagonal terms do not depend on z).
+    void eval_dz(double x, double y, double z, double* out, double* dout) const;
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -38,16 +41,29 @@ struct SystemSetup {
     int rank = 0;
     double cond = 0;
     std::vector<double> yc, yt;        // [L*3] check points and partners
-    std::vector<double> pinv;          // (P-1) x L, row-major: C_{t+1} = sum_l pinv[t*L+l] f_l
+    std::vector<double> pinv;          // (P-1) x rows(), row-major: C_{t+1} = sum_l pinv[t*rows()+l] f_l
     std::vector<double> box_means;     // [P]: R_t^(0), App. B
     std::vector<int> images;           // [nimg*3] lattice integers, (0,0,0) first
     Recurrence rec;
+    // Periodic axes: 7 (x, y and z) or 3 (x and y: a slab, z free).  For a slab
+    // the fit has n_dec decay rows after the L periodicity rows: on the planes
+    // z = +-zd (zd = d3/2 + R0/10) the in-plane Fourier modes of the potential
+    // decay away from the charges, <(d/dz + s|k|) phi, trig(k.rho)> = 0.
+    int periodic = 7;
+    int n_dec = 0, nk = 0, m = 0;      // decay rows, mode range |n1|,|n2| <= nk, m x m points per plane
+    double zd = 0;
+    std::vector<double> dec_pts;       // [2 m^2 * 3]: the top plane's points, then the bottom plane's
+    std::vector<double> dec_w;         // [m^2] quadrature weights (sum 1), shared by both planes
+    std::vector<double> dec_rows;      // [n_dec * 5]: kx, ky, |k|, s (+1 top, -1 bottom), trig (0 cos, 1 sin)
+    int rows() const { return L + n_dec; }   // rows of the fit (columns of pinv)
     // Returns an empty string on success, or the reason for failure.
     std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
                       int n_centres = 0, const double* centres = nullptr, int n_check = 0,
-                      const double* check_points = nullptr);
+                      const double* check_points = nullptr, int periodic = 7);
+    // The slab's decay planes and rows (a function of box, p and R0 alone).
+    void build_decay();
     // Binary form of the set data (little-endian scalars and arrays; the
-    // recurrence coefficients are rebuilt from p on reading).
+    // recurrence coefficients and the decay tables are rebuilt on reading).
     void serialize(std::vector<unsigned char>& out) const;
     // Reads what serialize wrote, advancing pos; checks every size against the
     // bounds build() enforces.  Returns an empty string on success.
