@@ -174,6 +174,30 @@ ps_status periodic_sum_eval(ps_plan plan, int64_t n,
                             int64_t m, const double* tx, const double* ty, const double* tz,
                             double* phi, double* ex, double* ey, double* ez, void* stream);
 
+/* For callers that cannot allocate device memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): periodic_sum_eval at
+ * the particles (targets = particles, as with m = 0) whose pair kernels write
+ * their partial sums, the eval's largest scratch, into a static device array of
+ * the library instead of the plan's buffers.  The array holds 8 Mi doubles
+ * (64 MiB) per device for the life of the process; its address is looked up
+ * once per device when a plan is made there.  Same kernels and work split as
+ * periodic_sum_eval, so the results are bitwise those of periodic_sum_eval.
+ * The call allocates nothing; like periodic_sum_eval, its first call for a
+ * particle count builds and uploads the plan's work tables (host work and a
+ * stream synchronization, no allocation), later calls only enqueue kernels.
+ * Every call on a device shares that device's array, which keeps the last
+ * call's contents: calls that overlap in time on one device (other streams,
+ * other plans) race and must be ordered by the caller.  Every element a call
+ * reads was written earlier in the same call, so nothing needs clearing.
+ * Arguments as periodic_sum_eval with m = 0.
+ * Errors: PS_E_INVALID (as periodic_sum_eval, or a batched plan),
+ * PS_E_UNSUPPORTED (an RBF-basis plan, or partial sums of this n beyond the
+ * array's 8 Mi doubles: 4 n x (source splits) + 2L x (check splits)),
+ * PS_E_HIP. */
+ps_status periodic_sum_eval_noalloc(ps_plan plan, int64_t n,
+                                    const double* x, const double* y, const double* z, const double* q,
+                                    double* phi, double* ex, double* ey, double* ez, void* stream);
+
 /* Energy E = (1/2) sum_i q_i phi(x_i) at the particles, with phi and the field
  * as in periodic_sum_eval (outputs may be NULL).  energy: device pointer to one
  * double, written by a deterministic reduction. */

@@ -24,7 +24,7 @@ EXPORTS = ["periodic_sum_plan", "periodic_sum_eval", "periodic_sum_energy", "per
            "periodic_sum_plan_tables", "periodic_sum_last_coefficients", "periodic_sum_set_profiling",
            "periodic_sum_stage_times", "periodic_sum_autotune", "periodic_sum_near_counts", "periodic_sum_destroy",
            "periodic_sum_last_error", "periodic_sum_plan_save", "periodic_sum_plan_load", "periodic_sum_select",
-           "periodic_sum_forward_epoch"]
+           "periodic_sum_forward_epoch", "periodic_sum_eval_noalloc"]
 STAGES = ["sort", "near", "bounds", "check", "solve", "mean", "pairs", "far"]
 
 
@@ -78,6 +78,8 @@ def lib():
         L.periodic_sum_plan_batched.restype = st
         L.periodic_sum_eval.argtypes = [vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp, vp, vp, vp, vp]
         L.periodic_sum_eval.restype = st
+        L.periodic_sum_eval_noalloc.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.periodic_sum_eval_noalloc.restype = st
         L.periodic_sum_energy.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.periodic_sum_energy.restype = st
         L.periodic_sum_energy_vjp.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_int32, i64, vp]

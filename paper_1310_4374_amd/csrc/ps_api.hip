@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -25,6 +26,31 @@ using namespace ps;
 namespace {
 
 thread_local std::string g_err;
+
+// Static device scratch of periodic_sum_eval_noalloc: the pair kernels' partial
+// sums (check points, then particles) of one eval.  Every device the library
+// runs on holds its own copy for the life of the process; host code reaches it
+// only through the address hipGetSymbolAddress returns for that device.
+constexpr int64_t kScratchDoubles = int64_t(8) << 20;  // 64 MiB
+__device__ __align__(256) double scratch[kScratchDoubles];
+std::mutex g_scratch_mu;
+std::map<int, double*> g_scratch_ptr;  // device -> address of its scratch
+
+// Address of `device`'s scratch (that device must be current); looked up once
+// per device.
+hipError_t scratch_address(int device, double** out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        it = g_scratch_ptr.emplace(device, static_cast<double*>(p)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
 
 ps_status fail(ps_status s, const char* fmt, ...)
 {
@@ -97,6 +123,9 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<PItem> chk_items, p_items, f_items, d_items;
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs;
                                     // [3 nsys, 4 nsys): slab decay-plane jobs
+    std::vector<PJob> jobs_s;       // the same jobs with their partial sums in the static scratch
+    bool scratch_fits = false;      // jobs_s is valid: the partial sums fit in kScratchDoubles
+    int64_t scratch_need = 0;       // doubles of partial sums one eval writes
     std::vector<SysDev> sys;
     int64_t nsort = 0, nfar = 0, nnear_items = 0, nt_items = 0, nchk = 0, np = 0, nf = 0, nw = 0, nm = 0, nd = 0;
     bool mean_entries = true;       // some system takes the per-entry box mean
@@ -162,6 +191,7 @@ struct ps_plan_s {
     TItem* d_t_items = nullptr;
     PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
     PJob* d_jobs = nullptr;
+    PJob* d_jobs_s = nullptr;           // jobs whose partial sums live in the static scratch
     // slab (two periodic axes): decay planes and rows
     bool any_slab = false;
     int max_dec = 0;                    // most decay rows of any system
@@ -170,6 +200,7 @@ struct ps_plan_s {
     double *d_part_dec = nullptr, *d_tblk_dec = nullptr;
     int64_t part_dec_cap = 0, tblk_dec_cap = 0, cap_d = 0;
     PItem* d_d_items = nullptr;
+    double* d_scratch = nullptr;        // this device's static scratch (periodic_sum_eval_noalloc)
     int64_t cap_sort = 0, cap_far = 0, cap_near_items = 0, cap_t = 0, cap_chk = 0, cap_p = 0, cap_w = 0;
     Tables tab;
     bool tab_valid = false;
@@ -530,6 +561,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     }
     if (pc_off > pl->part_chk_cap) { why = "check partial workspace too small"; return false; }
     if (pp_off > pl->part_p_cap) { why = "pair partial workspace too small"; return false; }
+    T.scratch_need = pc_off + pp_off;
     if (tb_p_off > pl->tblk_p_cap || tb_c_off > pl->tblk_chk_cap) { why = "target block workspace too small"; return false; }
     // particle pair items, largest systems first; splits of one target block are
     // consecutive so that workgroups sharing a source split land on the same XCD
@@ -629,6 +661,17 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T.nt_items = T.t_items.size();
     T.nchk = T.chk_items.size();
     T.np = T.p_items.size();
+    // the same jobs with the partial-sum layout in the static scratch
+    // (periodic_sum_eval_noalloc): check partials first, then the particle partials
+    T.scratch_fits = pl->d_scratch && !pl->any_rbf && !pl->any_slab && T.scratch_need <= kScratchDoubles;
+    T.jobs_s = T.jobs;
+    if (T.scratch_fits) {
+        const int64_t pc_tot = T.scratch_need - pp_off;
+        for (int s = 0; s < nsys; ++s) {
+            T.jobs_s[s].part = pl->d_scratch + (T.jobs[s].part - pl->d_part_chk);
+            T.jobs_s[nsys + s].part = pl->d_scratch + pc_tot + (T.jobs[nsys + s].part - pl->d_part_p);
+        }
+    }
     T.nf = T.f_items.size();
     T.nd = T.d_items.size();
     if (T.nsort > pl->cap_sort || T.nfar > pl->cap_far || T.nnear_items > pl->cap_near_items || T.nt_items > pl->cap_t ||
@@ -660,6 +703,7 @@ hipError_t upload_tables(ps_plan_s* pl, hipStream_t st)
     UP(pl->d_f_items, T.f_items)
     UP(pl->d_d_items, T.d_items)
     UP(pl->d_jobs, T.jobs)
+    UP(pl->d_jobs_s, T.jobs_s)
 #undef UP
     return hipStreamSynchronize(st);
 }
@@ -682,9 +726,9 @@ hipError_t fold_stage_events(ps_plan_s* pl)
 
 // Enqueue algorithm "get" for the current tables.
 void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* z, const double* q, bool separate,
-                 double* phi, double* ex, double* ey, double* ez, hipStream_t st)
+                 double* phi, double* ex, double* ey, double* ez, hipStream_t st, bool use_scratch = false)
 {
-    const PJob* jobs = pl->d_jobs;
+    const PJob* jobs = use_scratch ? pl->d_jobs_s : pl->d_jobs;
     const Tables& T = pl->tab;
     const int nsys = pl->nsys;
     const bool capturing = pl->cap_stream && st == pl->cap_stream;  // the batched path's private capture stream
@@ -1079,6 +1123,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_chk_items, pl->cap_chk)
     AL(pl->d_p_items, pl->cap_p)
     AL(pl->d_jobs, 4 * nsys)
+    AL(pl->d_jobs_s, 4 * nsys)
     AL(pl->d_dpts, 3 * std::max<int64_t>(1, dec_tot))
     AL(pl->d_dw, std::max<int64_t>(1, dw_tot))
     AL(pl->d_drows, std::max<int64_t>(1, drow_tot))
@@ -1093,6 +1138,11 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     if (e != hipSuccess) {
         delete pl;
         return fail(PS_E_NOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    e = scratch_address(pl->device, &pl->d_scratch);
+    if (e != hipSuccess) {
+        delete pl;
+        return fail(PS_E_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
     }
 #define UPS(dst, vec) \
     if (e == hipSuccess && !(vec).empty()) e = hipMemcpy(dst, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice);
@@ -1295,6 +1345,38 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
     pl->last_n = n;
     enqueue_get(pl, x, y, z, q, m > 0, phi, ex, ey, ez, st);
     stamp_forward(pl, x, y, z, q, m > 0);
+    return eval_done(pl, st);
+}
+
+ps_status periodic_sum_eval_noalloc(ps_plan pl, int64_t n, const double* x, const double* y, const double* z,
+                                    const double* q, double* phi, double* ex, double* ey, double* ez, void* stream)
+{
+    if (!pl) return fail(PS_E_INVALID, "plan is NULL");
+    if (pl->nsys != 1) return fail(PS_E_INVALID, "batched plan: the allocation-free eval takes single-system plans");
+    if (pl->any_rbf || pl->any_slab)
+        return fail(PS_E_UNSUPPORTED, "the allocation-free eval covers the spherical basis with three periodic axes");
+    if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max=%lld]", (long long)n, (long long)pl->n_max[0]);
+    if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
+    if (!phi && !ex && !ey && !ez) return fail(PS_E_INVALID, "no output array given");
+    if (!pl->d_scratch) return fail(PS_E_HIP, "the static scratch of this device has no address");
+    DeviceGuard dev_guard(pl->device);
+    HIPCHK(dev_guard.err);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const std::vector<int64_t> key = {n, 0, 0, 0, 0};
+    if (!pl->tab_valid || pl->tab.key != key) {
+        std::string why;
+        pl->tab_valid = false;
+        if (!build_tables(pl, std::vector<int64_t>{n}, 0, nullptr, nullptr, nullptr, why)) return fail(PS_E_UNSUPPORTED, "%s", why.c_str());
+        HIPCHK(upload_tables(pl, st));
+        pl->tab.key = key;
+        pl->tab_valid = true;
+    }
+    if (!pl->tab.scratch_fits)
+        return fail(PS_E_UNSUPPORTED, "n=%lld: the pair sums' partials need %lld doubles, more than the %lld of the static scratch",
+                    (long long)n, (long long)pl->tab.scratch_need, (long long)kScratchDoubles);
+    pl->last_n = n;
+    enqueue_get(pl, x, y, z, q, false, phi, ex, ey, ez, st, true);
+    stamp_forward(pl, x, y, z, q, false);
     return eval_done(pl, st);
 }
 

@@ -70,6 +70,7 @@ def test_null_arguments_rejected():
     assert L.periodic_sum_plan(ctypes.byref(_params()), 0, None) == _lib.PS_E_INVALID
     assert L.periodic_sum_eval(None, 10, *([None] * 4), 0, *([None] * 3), *([None] * 4), None) == _lib.PS_E_INVALID
     assert L.periodic_sum_status(None, None) == _lib.PS_E_INVALID
+    assert L.periodic_sum_eval_noalloc(None, 10, *([None] * 4), *([None] * 4), None) == _lib.PS_E_INVALID
     e = ctypes.c_int64(5)
     assert L.periodic_sum_forward_epoch(None, ctypes.byref(e)) == _lib.PS_E_INVALID
     assert L.periodic_sum_energy_vjp(None, 10, *([None] * 4), None, *([None] * 4), 1, 0, None) == _lib.PS_E_INVALID
