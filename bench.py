@@ -69,7 +69,7 @@ def measured_traffic(precision, record="p2p_f32_clustered_N1M_hbm_counters.json"
     return d["traffic_bytes"] if d.get("source_sha256_16") == h else None
 
 
-def cpu_baseline(c, ntarget=400):
+def cpu_baseline(c, ntarget=1200):
     """The FP64 oracle as it stands, on a bounded sample of the workload: its
     near-set pair sums (step 3 of "get", the work the metric counts), the 2L
     check points (potential) and `ntarget` particles (potential and field)

@@ -151,16 +151,17 @@ struct ps_plan_s {
     std::vector<SysDev> base;        // per system, static part
     // device tables
     SysDev* d_sys = nullptr;
+    double* d_chk_t = nullptr;          // the check targets in the order of the check-point sums
+    int* d_chk_slot = nullptr;          // position of check target k of a system in that order
     double *d_img = nullptr, *d_chk = nullptr, *d_pinv = nullptr, *d_bm = nullptr, *d_rec = nullptr;
     double *d_coef = nullptr, *d_f = nullptr;
     double* d_cen = nullptr;            // RBF centres, SoA over all systems
-    double* d_cen_bb = nullptr;         // their group bounding boxes
     double* d_part_far = nullptr;       // RBF far-field partials [4][nt] per system
     int64_t cen_tot = 0, part_far_cap = 0;
     bool any_rbf = false;
     int maxP_sph = 1;                   // largest spherical basis (LDS of the combine kernel)
     // workspace
-    int64_t ntot_max = 0, near_tot = 0, cell_tot = 0, tiles_tot = 0, chk_tot = 0, inv_tot = 0;
+    int64_t ntot_max = 0, near_tot = 0, cell_tot = 0, chk_tot = 0, inv_tot = 0;
     double *d_sx = nullptr, *d_sy = nullptr, *d_sz = nullptr, *d_sq = nullptr;
     int *d_perm = nullptr, *d_keys = nullptr, *d_slots = nullptr, *d_cnt = nullptr, *d_start = nullptr;
     double *d_nx = nullptr, *d_ny = nullptr, *d_nz = nullptr, *d_nq = nullptr;
@@ -168,7 +169,6 @@ struct ps_plan_s {
     int64_t* d_nnear = nullptr;
     int* d_ncount = nullptr;
     int64_t* d_ioff = nullptr;
-    double* d_tile_bb = nullptr;
     double *d_tblk_chk = nullptr, *d_tblk_p = nullptr;
     double *d_part_chk = nullptr, *d_part_p = nullptr;
     int64_t part_chk_cap = 0, part_p_cap = 0, tblk_p_cap = 0, tblk_chk_cap = 0;
@@ -209,7 +209,7 @@ struct ps_plan_s {
     // adjoint workspace (allocated by the first exact energy_vjp call)
     bool adj_ready = false;
     double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr, *d_aq = nullptr;
-    double *d_adj_bb = nullptr, *d_adj_tblk = nullptr, *d_adj_part = nullptr, *d_mom = nullptr;
+    double *d_adj_tblk = nullptr, *d_adj_part = nullptr, *d_mom = nullptr;
     double *d_dq = nullptr, *d_dx = nullptr, *d_energy = nullptr;
     TItem* d_adj_t = nullptr;
     PItem* d_adj_p = nullptr;
@@ -359,15 +359,57 @@ double near_expected(const SystemSetup& su, int64_t n)
     return std::max<double>(1.0, 4.18879020478639 * su.R_b * su.R_b * su.R_b / su.V0 * static_cast<double>(n));
 }
 
-// Source splits of one system's check-point sums (ntb_c target blocks of bt_chk).
-// A single system is split towards kCheckWaveTarget waves, down to one tile per
-// split; in a batch the systems together fill the device, and a split keeps at
-// least four tiles.
-int check_splits(int64_t ntb_c, int bt_chk, int64_t ntiles_exp, int nsys)
+// Source splits of one system's check-point sums (ntb_c target blocks, each
+// taken by workgroups of `waves` waves).  A single system is split towards
+// kCheckWaveTarget waves, down to one tile per split; in a batch the systems
+// together fill the device, and a split keeps at least four tiles.
+int check_splits(int64_t ntb_c, int waves, int64_t ntiles_exp, int nsys)
 {
-    const int64_t items = (static_cast<int64_t>(kCheckWaveTarget) * 64 / bt_chk + ntb_c - 1) / ntb_c;
+    const int64_t items = (static_cast<int64_t>(kCheckWaveTarget) / waves + ntb_c - 1) / ntb_c;
     const int64_t by_tiles = std::max<int64_t>(1, ntiles_exp / (nsys == 1 ? 1 : 4));
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kMaxCheckSplit, items), by_tiles)));
+}
+
+// Waves per workgroup of the check-point sums: kChkWaves sharing a 64-target
+// block (FP32), else one per 64 targets of the bt_chk-wide blocks (FP64).
+int check_waves(const ps_plan_s* pl)
+{
+    return pl->precision == PS_FP32_ACC64 ? kChkWaves : pl->bt_chk / 64;
+}
+
+// Order of one system's 2L check targets (points [n][3]) for the check-point
+// sums: recursive halving along the widest extent of each part's bounding box,
+// the first half a whole number of `blk`-target blocks, so that consecutive
+// blocks of blk targets (the pair kernels' target blocks) are compact and the
+// share of near source groups small.  Ties keep the input order.
+std::vector<int> check_order(const std::vector<double>& pts, int blk)
+{
+    const int n = static_cast<int>(pts.size() / 3);
+    std::vector<int> ord(n);
+    for (int i = 0; i < n; ++i) ord[i] = i;
+    struct Part { int lo, hi; };
+    std::vector<Part> stack{{0, n}};
+    while (!stack.empty()) {
+        const Part q = stack.back();
+        stack.pop_back();
+        if (q.hi - q.lo <= blk) continue;
+        double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+        for (int i = q.lo; i < q.hi; ++i)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = std::min(lo[k], pts[ord[i] * 3 + k]);
+                hi[k] = std::max(hi[k], pts[ord[i] * 3 + k]);
+            }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+        std::stable_sort(ord.begin() + q.lo, ord.begin() + q.hi,
+                         [&](int a, int b) { return pts[a * 3 + ax] < pts[b * 3 + ax]; });
+        const int m = q.hi - q.lo;
+        const int left = std::min(m - 1, (m / 2 + blk - 1) / blk * blk);
+        stack.push_back({q.lo + left, q.hi});
+        stack.push_back({q.lo, q.lo + left});
+    }
+    return ord;
 }
 
 // Targets per workgroup of the check-point sums: the width that wastes the
@@ -433,21 +475,20 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         const SystemSetup& su = pl->setups[s];
         PJob& C = T.jobs[s];
         C = PJob{};
-        C.tx = pl->d_chk + S.chk_off;
-        C.ty = pl->d_chk + pl->chk_tot + S.chk_off;
-        C.tz = pl->d_chk + 2 * pl->chk_tot + S.chk_off;
+        C.tx = pl->d_chk_t + S.chk_off;
+        C.ty = pl->d_chk_t + pl->chk_tot + S.chk_off;
+        C.tz = pl->d_chk_t + 2 * pl->chk_tot + S.chk_off;
         C.nt = 2 * S.L;
         C.sx = pl->d_nx + S.near_off;
         C.sy = pl->d_ny + S.near_off;
         C.sz = pl->d_nz + S.near_off;
         C.sq = pl->d_nq + S.near_off;
         C.ns_dev = pl->d_nnear + s;
-        C.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * (kTile / kGroup) * 6;
         C.tblk = pl->d_tblk_chk + tb_c_off * 4;
         const int64_t ntb_c = (C.nt + pl->bt_chk - 1) / pl->bt_chk;
         const double nb_exp = near_expected(su, S.n);
         const int64_t ntiles_exp = static_cast<int64_t>(nb_exp / kTile) + 1;
-        C.nsplit = check_splits(ntb_c, pl->bt_chk, ntiles_exp, nsys);
+        C.nsplit = check_splits(ntb_c, check_waves(pl), ntiles_exp, nsys);
         C.ncomp = 1;
         C.bt = pl->bt_chk;
         C.part = pl->d_part_chk + pc_off;
@@ -476,7 +517,6 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         Pj.sz = C.sz;
         Pj.sq = C.sq;
         Pj.ns_dev = C.ns_dev;
-        Pj.tile_bb = C.tile_bb;
         Pj.tblk = pl->d_tblk_p + tb_p_off * 4;
         const int64_t ntb = (Pj.nt + bt - 1) / bt;
         est[s] = Est{ntb, static_cast<int64_t>(nb_exp)};
@@ -600,14 +640,12 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
             F.sz = pl->d_cen + 2 * pl->cen_tot + S.cen_off;
             F.sq = pl->d_coef + S.coef_off + 1;
             F.ns_host = S.M;
-            F.tile_bb = pl->d_cen_bb + (S.cen_off / kTile) * (kTile / kGroup) * 6;
             F.part = pl->d_part_far + pf_off;
             pf_off += 4 * F.nt;
             for (int64_t tb = 0; tb < est[s].ntb; ++tb) T.f_items.push_back(PItem{s, static_cast<int>(tb), 0, 0});
         } else {
             F.sx = F.sy = F.sz = F.sq = Pj.sx;
             F.ns_host = 0;
-            F.tile_bb = Pj.tile_bb;
             F.part = nullptr;
         }
     }
@@ -635,7 +673,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         D.tblk = pl->d_tblk_dec + tb_d_off * 4;
         const int64_t ntb_d = (D.nt + kDecayBt - 1) / kDecayBt;
         const int64_t ntiles_exp = static_cast<int64_t>(near_expected(pl->setups[s], S.n) / kTile) + 1;
-        D.nsplit = check_splits(ntb_d, kDecayBt, ntiles_exp, nsys);
+        D.nsplit = check_splits(ntb_d, kDecayBt / 64, ntiles_exp, nsys);
         D.part = pl->d_part_dec + pd_off;
         pd_off += static_cast<int64_t>(D.nsplit) * 4 * D.nt;
         for (int64_t tb = 0; tb < ntb_d; ++tb) {
@@ -755,16 +793,19 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     const PJob* cjobs = jobs;
     const PJob* pjobs = jobs + nsys;
     mark(2);
-    launch_bounds(T.nw, pjobs, pl->d_w_items, T.nt_items, jobs, pl->d_t_items, st);
+    launch_tblock(T.nt_items, jobs, pl->d_t_items, st);
     mark(3);
-    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);  // step 3 at the check points
+    if (pl->precision == PS_FP32_ACC64)  // step 3 at the check points
+        launch_chk_f32(T.nchk, cjobs, pl->d_chk_items, st);
+    else
+        launch_p2p(0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);
     if (T.nd > 0) {  // slab: near sums at the decay planes, then the decay rows of f
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
         launch_decay_rhs(nsys, pl->max_dec, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot, pl->d_dw, pl->d_drows,
                          pl->d_f, st);
     }
     mark(4);
-    launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
+    launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_chk_slot, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
     launch_mean(nsys, T.mean_entries ? T.nw : 0, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part,
                 T.nm, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
@@ -774,7 +815,6 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(7);
     const PJob* fjobs = jobs + 2 * nsys;
     if (pl->any_rbf) {  // step 7 for the RBF basis: sum over the M centres
-        launch_tile_bounds(nsys, 16, fjobs, st);
         launch_p2p(0, pl->bt, true, T.nf, fjobs, pl->d_f_items, st);
     }
     launch_far(T.far_lanes, T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
@@ -978,11 +1018,12 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     pl->cell_tot = cell_tot;
     pl->chk_tot = chk_tot;
     pl->inv_tot = inv_tot;
-    pl->tiles_tot = near_tot / kTile + 1;
     pl->cen_tot = cen_tot;
     pl->part_far_cap = pfar;
     pl->dec_tot = dec_tot;
     // host tables
+    std::vector<double> h_chk_t(chk_tot * 3);
+    std::vector<int> h_chk_slot(std::max<int64_t>(1, chk_tot));
     std::vector<double> h_img(img_tot * 3), h_chk(chk_tot * 3), h_pinv(pinv_tot), h_bm(coef_tot), h_rec(rec_tot);
     std::vector<double> h_cen(std::max<int64_t>(1, 3 * cen_tot), 1e3);  // padding: far from every box
     std::vector<int> h_imap(std::max<int64_t>(1, imap_tot), -1);
@@ -1005,6 +1046,16 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
                 h_chk[k * chk_tot + S.chk_off + l] = su.yc[l * 3 + k];
                 h_chk[k * chk_tot + S.chk_off + S.L + l] = su.yt[l * 3 + k];
             }
+        {
+            std::vector<double> pts(6 * static_cast<size_t>(S.L));
+            for (int l = 0; l < 2 * S.L; ++l)
+                for (int k = 0; k < 3; ++k) pts[l * 3 + k] = h_chk[k * chk_tot + S.chk_off + l];
+            const std::vector<int> ord = check_order(pts, 64);
+            for (int pos = 0; pos < 2 * S.L; ++pos) {
+                h_chk_slot[S.chk_off + ord[pos]] = pos;
+                for (int k = 0; k < 3; ++k) h_chk_t[k * chk_tot + S.chk_off + pos] = pts[ord[pos] * 3 + k];
+            }
+        }
         std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
         for (int64_t k = 0; k < 2 * static_cast<int64_t>(S.m2); ++k)
             for (int c = 0; c < 3; ++c) h_dpts[c * dec_tot + S.dec_off + k] = su.dec_pts[k * 3 + c];
@@ -1023,7 +1074,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     // capacities of the per-shape tables
     int64_t sort_cap = 0, near_items_cap = 0, far_cap = 0, tb_p = 0, tb_c = 0, chk_items_cap = 16;
     int64_t nt_sum = 0;
-    pl->bt_chk = pick_check_bt(pl->setups);
+    pl->bt_chk = pl->precision == PS_FP32_ACC64 ? 64 : pick_check_bt(pl->setups);
     for (int s = 0; s < nsys; ++s) {
         const SysDev& S = pl->base[s];
         const int64_t nt = std::max<int64_t>(prm[s].n_max, nsys == 1 ? prm[0].m_max : 0);
@@ -1034,7 +1085,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         const int64_t ntb_c = (2 * S.L + pl->bt_chk - 1) / pl->bt_chk;
         tb_c += ntb_c;
         // the split count grows with the particle count, so n_max bounds it
-        chk_items_cap += ntb_c * check_splits(ntb_c, pl->bt_chk,
+        chk_items_cap += ntb_c * check_splits(ntb_c, check_waves(pl),
                                               static_cast<int64_t>(near_expected(pl->setups[s], prm[s].n_max) / kTile) + 1,
                                               nsys);
         nt_sum += nt;
@@ -1046,7 +1097,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
             if (S.ndec == 0) continue;
             const int64_t nt = 2 * static_cast<int64_t>(S.m2);
             const int64_t ntb = (nt + kDecayBt - 1) / kDecayBt;
-            const int sp = check_splits(ntb, kDecayBt,
+            const int sp = check_splits(ntb, kDecayBt / 64,
                                         static_cast<int64_t>(near_expected(pl->setups[s], prm[s].n_max) / kTile) + 1,
                                         nsys);
             tb_d += ntb;
@@ -1074,6 +1125,8 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_sys, nsys)
     AL(pl->d_img, img_tot * 3)
     AL(pl->d_chk, chk_tot * 3)
+    AL(pl->d_chk_t, chk_tot * 3)
+    AL(pl->d_chk_slot, chk_tot)
     AL(pl->d_pinv, pinv_tot)
     AL(pl->d_bm, coef_tot)
     AL(pl->d_rec, rec_tot)
@@ -1098,7 +1151,6 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_nnear, nsys)
     AL(pl->d_ncount, near_items_cap)
     AL(pl->d_ioff, near_items_cap)
-    AL(pl->d_tile_bb, pl->tiles_tot * (kTile / kGroup) * 6)
     AL(pl->d_tblk_chk, tb_c * 4)
     AL(pl->d_tblk_p, tb_p * 4)
     AL(pl->d_part_chk, pl->part_chk_cap)
@@ -1132,7 +1184,6 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_d_items, std::max<int64_t>(1, pl->cap_d))
     AL(pl->d_f_items, pl->cap_t)
     AL(pl->d_cen, 3 * std::max<int64_t>(1, cen_tot))
-    AL(pl->d_cen_bb, (cen_tot / kTile + 1) * (kTile / kGroup) * 6)
     AL(pl->d_part_far, pfar)
 #undef AL
     if (e != hipSuccess) {
@@ -1148,6 +1199,8 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     if (e == hipSuccess && !(vec).empty()) e = hipMemcpy(dst, (vec).data(), sizeof((vec)[0]) * (vec).size(), hipMemcpyHostToDevice);
     UPS(pl->d_img, h_img)
     UPS(pl->d_chk, h_chk)
+    UPS(pl->d_chk_t, h_chk_t)
+    UPS(pl->d_chk_slot, h_chk_slot)
     UPS(pl->d_pinv, h_pinv)
     UPS(pl->d_bm, h_bm)
     UPS(pl->d_rec, h_rec)
@@ -1685,7 +1738,6 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_ay, ns)
     AL(pl->d_az, ns)
     AL(pl->d_aq, ns)
-    AL(pl->d_adj_bb, (ns / kTile + 1) * (kTile / kGroup) * 6)
     AL(pl->d_adj_tblk, pl->adj_tb_cap * 4)
     AL(pl->d_adj_part, pl->adj_part_cap)
     AL(pl->d_mom, (int64_t)std::max(kMomBlocks, kMomWaves) * S.P)
@@ -1772,7 +1824,6 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         J.sq = pl->d_aq;
         J.ns_dev = nullptr;
         J.ns_host = ns;
-        J.tile_bb = pl->d_adj_bb;
         J.tblk = pl->d_adj_tblk;
         J.part = pl->d_adj_part;
         J.ncomp = 4;
@@ -1803,7 +1854,6 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
             Mj.sz = pl->d_nz + S.near_off;
             Mj.sq = pl->d_nq + S.near_off;
             Mj.ns_host = n;
-            Mj.tile_bb = pl->d_tile_bb + (S.near_off / kTile) * (kTile / kGroup) * 6;
             Mj.tblk = pl->d_mom_tblk;
             Mj.part = pl->d_mom;
             Mj.ncomp = 1;
@@ -1837,7 +1887,6 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         launch_adjoint_sources(S.P, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mom, mom_blocks,
                                stride, toff, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az, pl->d_aq,
                                st);
-        launch_tile_bounds(1, 256, pl->d_adj_job, st);
         launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, static_cast<int64_t>(pl->adj_p.size()),
                    pl->d_adj_job, pl->d_adj_p, st);

@@ -5,15 +5,19 @@
 namespace ps {
 
 constexpr int kTile = 256;         // sources staged per LDS tile
-constexpr int kGroup = 32;         // sources per near/far decision (one bounding box each)
-// A group is "far" for a target block of radius rT (about its centre c) when
-// its bounding box is farther than kFarFactor * rT from c (both pair kernels).  A far
+constexpr int kGroup = 32;         // sources per near/far decision
+// A source is "far" for a target block of radius rT (about its centre c) when it
+// lies farther than kFarFactor * rT from c, and a group is far when all of its
+// sources are (both pair kernels).  A far
 // pair is then more than (kFarFactor - 1) rT apart, and the sum of the two
 // points' distances from c is at most (kFarFactor + 1)/(kFarFactor - 1) times
 // their separation.  That ratio (5 at 1.5) bounds the one-float coordinate
 // error relative to the separation, and its square the cancellation in the
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
+// Waves per workgroup of the FP32 check-point sums (k_chk_f32): they share one
+// block of 64 targets and split each staged source tile between them.
+constexpr int kChkWaves = 4;
 constexpr int kChunk = 1024;       // particles per chunk in the per-particle kernels
 // Lanes per target in the far-field/combine kernel: 8 when a shape has at most
 // kFarWideMax targets in all (spreading each target's work wider shortens a
@@ -78,7 +82,6 @@ struct PJob {
     const double* sq;
     const int64_t* ns_dev;  // device source count (or null)
     int64_t ns_host;        // host source count when ns_dev is null
-    const double* tile_bb;  // 6 doubles per tile of kTile sources: lo xyz, hi xyz
     double* tblk;           // 4 doubles per target block: centre xyz, radius
     double* part;           // partial sums [nsplit][ncomp][nt]
     int nsplit, ncomp, bt, pad;

@@ -16,15 +16,15 @@ void launch_sort(int nsys, int64_t ncitems, int64_t max_ncell, const SysDev* sys
 void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nitems, const double* img,
                  const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
                  int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st);
-void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st);
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st);
-void launch_bounds(int64_t nwitems, const PJob* pjobs, const CItem* witems, int64_t ntitems, const PJob* jobs,
-                   const TItem* titems, hipStream_t st);
 void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
+// FP32 check-point sums (potential only); every job has 64-target blocks and ncomp = 1.
+void launch_chk_f32(int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
 void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
                       const double* dw, const double* drows, double* f, hipStream_t st);
-void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
-                  double* coef, double* f, hipStream_t st);
+// slot[chk_off + k]: position of check target k of a system in its check job
+void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const int* slot,
+                  const double* pinv, double* coef, double* f, hipStream_t st);
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
                  const double* nx, const double* ny, const double* nz, const double* nq, double* part,
                  int64_t nmitems, int mcols, const MItem* mitems, const int* imap, const double* img,

@@ -386,53 +386,8 @@ __global__ __launch_bounds__(256) void k_near_write(const SysDev* __restrict__ s
 }
 
 // ----------------------------------------------------------------------------
-// tile bounds of a source set and centre/radius of each target block
+// centre and radius of each target block
 // ----------------------------------------------------------------------------
-// Bounding boxes of every group of kGroup consecutive sources (the unit of the
-// pair kernels' near/far decision): one workgroup per tile, one half-wave per group.
-__device__ __forceinline__ double half_min(double v)
-{
-    for (int o = 16; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ double half_max(double v)
-{
-    for (int o = 16; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-// Bounding box of every group of kGroup sources of job J, tiles first, first + stride, ...
-__device__ void tile_bounds(const PJob& J, int64_t first, int64_t stride)
-{
-    const int64_t ns = J.ns_dev ? *J.ns_dev : J.ns_host;
-    const int64_t ntiles = (ns + kTile - 1) / kTile;
-    double* bb = const_cast<double*>(J.tile_bb);
-    for (int64_t t = first; t < ntiles; t += stride)
-        for (int k = threadIdx.x; k < kTile; k += blockDim.x) {  // blockDim is a multiple of kGroup
-            const int64_t j = t * kTile + k;
-            const bool v = j < ns;
-            const double x = v ? J.sx[j] : 0.0, y = v ? J.sy[j] : 0.0, z = v ? J.sz[j] : 0.0;
-            const double lx = half_min(v ? x : 1e300), ly = half_min(v ? y : 1e300), lz = half_min(v ? z : 1e300);
-            const double hx = half_max(v ? x : -1e300), hy = half_max(v ? y : -1e300), hz = half_max(v ? z : -1e300);
-            if ((k & (kGroup - 1)) == 0) {
-                double* o = bb + (t * (kTile / kGroup) + k / kGroup) * 6;
-                o[0] = lx;
-                o[1] = ly;
-                o[2] = lz;
-                o[3] = hx;
-                o[4] = hy;
-                o[5] = hz;
-            }
-        }
-}
-
-// grid: blocks x jobs, the same number of workgroups per job
-__global__ __launch_bounds__(256) void k_tile_bounds(const PJob* __restrict__ jobs)
-{
-    tile_bounds(jobs[blockIdx.y], blockIdx.x, gridDim.x);
-}
-
-
 // Centre and radius of one target block (all threads of the workgroup call it).
 __device__ void target_block(const PJob* __restrict__ jobs, const TItem it)
 {
@@ -462,31 +417,15 @@ __global__ __launch_bounds__(256) void k_tblock(const PJob* __restrict__ jobs, c
     target_block(jobs, items[blockIdx.x]);
 }
 
-// Both bounding passes of a solve in one launch: workgroups [0, nw) take the
-// tile bounds of the particle jobs' near lists from the near-size-weighted
-// table (item (sys, count, start) is workgroup `start` of the `count` that
-// system `sys` has), the others one target block each (as k_tblock).
-__global__ __launch_bounds__(256) void k_bounds(const PJob* __restrict__ pjobs, const CItem* __restrict__ witems,
-                                                int64_t nw, const PJob* __restrict__ jobs,
-                                                const TItem* __restrict__ titems)
-{
-    if ((int64_t)blockIdx.x < nw) {
-        const CItem it = witems[blockIdx.x];
-        tile_bounds(pjobs[it.sys], it.start, it.count);
-    } else {
-        target_block(jobs, titems[blockIdx.x - nw]);
-    }
-}
-
 // ----------------------------------------------------------------------------
 // pair sums (the free-space finite sum of eq. (r2) over the near set)
 // ----------------------------------------------------------------------------
 // A workgroup owns BT consecutive targets (one per lane) and one split of the
 // source tiles.  Sources are staged kTile at a time in LDS and read as
-// broadcasts.  Each group of kGroup sources of a tile carries a bounding box;
-// a group farther than kFarFactor x (target-block radius) from the block
-// centre is "far": it cannot hold a source coinciding with a target, so its
-// loop has no K(0) = 0 test; other groups are "near" and apply K(0) = 0.
+// broadcasts.  A group of kGroup sources of a tile whose sources all lie
+// farther than kFarFactor x (target-block radius) from the block centre is
+// "far": it cannot hold a source coinciding with a target, so its loop has no
+// K(0) = 0 test; other groups are "near" and apply K(0) = 0.
 // Accumulation (FP32 kernel): the potential of every 8 pairs is summed as a
 // balanced FP32 tree, four such sums are added in FP32 and the result goes to
 // an FP64 accumulator; the field runs in FP32 chains flushed to FP64 every 32
@@ -820,12 +759,172 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
 }
 
 // ----------------------------------------------------------------------------
+// check-point sums in FP32 (step 3 at Y_c1 and Y_c2: potential only)
+// ----------------------------------------------------------------------------
+// The 2L check targets are few and the near set is large, so each target block
+// meets every source tile, and the blocks are kept small (64 targets, compact
+// by the order the plan gives the check targets) to keep the share of near
+// source groups low.  A workgroup of WS waves owns one such block (one target
+// per lane, the same in every wave): the waves stage each tile together
+// (kTile / (64 WS) sources per thread) and split every group of kGroup
+// sources, kGroup / WS to a wave, so the near/far decision stays per group and
+// the waves' work stays balanced; the per-target sums of the waves are added
+// in a fixed order at the end.  The global loads of the next tile are issued
+// before the current one is summed.  Far groups read |s_hi|^2 from an array of
+// its own, four sources per LDS read.  The pair arithmetic is group32_f32's
+// potential form, and so is the accumulation: a balanced FP32 tree per 8 pairs,
+// four trees added in FP32, then an FP64 accumulator.
+template <bool NEAR>
+__device__ __forceinline__ float pot8_f32(const float4* __restrict__ sA, const float4* __restrict__ sB,
+                                          const float* __restrict__ sW, float hx, float hy, float hz, float lx,
+                                          float ly, float lz, float tt)
+{
+    float qv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const float4 s = sA[u];
+        float r2;
+        if (NEAR) {
+            const float4 l = sB[u];
+            const float dx = __builtin_fmaf(0.5f, s.x, hx) + (lx - l.x);
+            const float dy = __builtin_fmaf(0.5f, s.y, hy) + (ly - l.y);
+            const float dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
+            r2 = dx * dx;
+            r2 = __builtin_fmaf(dy, dy, r2);
+            r2 = __builtin_fmaf(dz, dz, r2);
+        } else {
+            r2 = tt + sW[u];
+            r2 = __builtin_fmaf(hx, s.x, r2);
+            r2 = __builtin_fmaf(hy, s.y, r2);
+            r2 = __builtin_fmaf(hz, s.z, r2);
+        }
+        float ri = __builtin_amdgcn_rsqf(r2);
+        if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
+        qv[u] = s.w * ri;
+    }
+    return ((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7]));
+}
+
+// A load through the global address space: the source arrays of a job are
+// device memory, but a pointer read from a job descriptor is generic, and a
+// generic (flat) load also counts against the LDS counter, so every LDS wait
+// would wait for it as well.
+__device__ __forceinline__ double load_global(const double* p, int64_t j)
+{
+    return ((const __attribute__((address_space(1))) double*)p)[j];
+}
+
+template <int WS>
+__global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
+{
+    constexpr int NT = 64 * WS;     // threads of the workgroup
+    constexpr int PF = kTile / NT;  // sources each thread stages per tile
+    constexpr int SPW = kGroup / WS;  // sources of each group a wave takes
+    static_assert(SPW % 8 == 0 && PF >= 1, "WS must be 1, 2 or 4");
+    __shared__ float4 sA[kTile];
+    __shared__ float4 sB[kTile];
+    __shared__ float sW[kTile];  // |s_hi|^2 again, contiguous: far groups read it four sources at a time
+    __shared__ uint32_t sFar[kTile / kGroup];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const PItem it = items[blockIdx.x];
+    const PJob& J = jobs[it.job];
+    const SourceSplit sp = split_range(J, it.split);
+    const int64_t i = (int64_t)it.tb * 64 + lane;
+    const bool active = i < J.nt;
+    const double* tb = J.tblk + (int64_t)it.tb * 4;
+    const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
+    const double far2 = kFarFactor * kFarFactor * rT * rT;
+    double rx = 0.0, ry = 0.0, rz = 0.0;
+    if (active) {
+        rx = J.tx[i] - cx;
+        ry = J.ty[i] - cy;
+        rz = J.tz[i] - cz;
+    }
+    const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
+    const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
+    const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
+    const double* __restrict__ SX = J.sx;
+    const double* __restrict__ SY = J.sy;
+    const double* __restrict__ SZ = J.sz;
+    const double* __restrict__ SQ = J.sq;
+    double px[PF], py[PF], pz[PF], pq[PF];
+    auto fetch = [&](int64_t t) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int64_t j = t * kTile + u * NT + threadIdx.x;
+            const bool v = j < sp.ns;
+            px[u] = v ? load_global(SX, j) : 0.0;
+            py[u] = v ? load_global(SY, j) : 0.0;
+            pz[u] = v ? load_global(SZ, j) : 0.0;
+            pq[u] = v ? load_global(SQ, j) : 0.0;
+        }
+    };
+    auto stage = [&](int64_t t) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int k = u * NT + threadIdx.x;
+            // padding as in k_p2p_f32: charge 0, far from every target
+            float4 a = make_float4(-0x1p61f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0x1p120f);
+            bool far = true;
+            if (t * kTile + k < sp.ns) {
+                const double ux = px[u] - cx, uy = py[u] - cy, uz = pz[u] - cz;
+                far = ux * ux + uy * uy + uz * uz > far2;
+                const float ax = (float)ux, ay = (float)uy, az = (float)uz;
+                a = make_float4(-2.f * ax, -2.f * ay, -2.f * az, (float)pq[u]);
+                b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az),
+                                __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
+            }
+            sA[k] = a;
+            sB[k] = b;
+            sW[k] = b.w;
+            store_far_bits(sFar, k & ~63, far);
+        }
+    };
+    double aP = 0.0;
+    // the loads of tile t + 1 are in flight while tile t is summed
+    if (sp.t0 < sp.t1) fetch(sp.t0);
+    for (int64_t t = sp.t0; t < sp.t1; ++t) {
+        __syncthreads();
+        stage(t);
+        __syncthreads();
+        if (t + 1 < sp.t1) fetch(t + 1);
+        const uint32_t farm = load_far_mask(sFar);
+        // WS groups per FP64 flush: four trees of 8 pairs each
+#pragma unroll 1
+        for (int g0 = 0; g0 < kTile / kGroup; g0 += WS) {
+            float p32 = 0.f;
+#pragma unroll
+            for (int g = g0; g < g0 + WS; ++g) {
+                const int o = g * kGroup + w * SPW;
+#pragma unroll
+                for (int c = 0; c < SPW; c += 8)
+                    p32 += ((farm >> g) & 1)
+                               ? pot8_f32<false>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt)
+                               : pot8_f32<true>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt);
+            }
+            aP += (double)p32;
+        }
+    }
+    if (WS > 1) {
+        __syncthreads();
+        double* red = reinterpret_cast<double*>(sA);  // (WS - 1) x 64 doubles
+        if (w > 0) red[(w - 1) * 64 + lane] = aP;
+        __syncthreads();
+        if (w == 0)
+            for (int k = 1; k < WS; ++k) aP += red[(k - 1) * 64 + lane];
+    }
+    if (w == 0 && active) J.part[(int64_t)it.split * J.nt + i] = aP;
+}
+
+// ----------------------------------------------------------------------------
 // least-squares solve (steps 4-5): f = phi_near(Y_c2) - phi_near(Y_c1), C = A^+ f
 // ----------------------------------------------------------------------------
-// f_l = phi_near(y~_l) - phi_near(y_l) from the split partials: 64 check
-// points per workgroup, 16 lane groups over the splits, combined in fixed order.
+// f_l = phi_near(y~_l) - phi_near(y_l) from the split partials (the check job
+// holds the targets in its own order; slot maps a check target to its place):
+// 64 check points per workgroup, 16 lane groups over the splits, combined in
+// fixed order.
 __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ cjobs,
-                                              double* __restrict__ fout)
+                                              const int* __restrict__ slot, double* __restrict__ fout)
 {
     __shared__ double sa[16][64], sb[16][64];
     const SysDev& S = sys[blockIdx.y];
@@ -833,11 +932,13 @@ __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, co
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l = blockIdx.x * 64 + lane;
     double a = 0.0, b = 0.0;
-    if (l < S.L)
+    if (l < S.L) {
+        const int ia = slot[S.chk_off + l], ib = slot[S.chk_off + S.L + l];
         for (int s = g; s < J.nsplit; s += 16) {
-            a += J.part[(int64_t)s * J.nt + l];
-            b += J.part[(int64_t)s * J.nt + S.L + l];
+            a += J.part[(int64_t)s * J.nt + ia];
+            b += J.part[(int64_t)s * J.nt + ib];
         }
+    }
     sa[g][lane] = a;
     sb[g][lane] = b;
     __syncthreads();
@@ -1291,16 +1392,6 @@ void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nite
     PS_LAUNCH(k_near_write, dim3((unsigned)nnitems), dim3(256), 0, st, sys, nitems, ioff, img, sx, sy, sz, sq, nx, ny,
               nz, nq, nbase, inv);
 }
-void launch_tile_bounds(int njobs, int blocks_per_job, const PJob* jobs, hipStream_t st)
-{
-    PS_LAUNCH(k_tile_bounds, dim3(blocks_per_job, njobs), dim3(256), 0, st, jobs);
-}
-void launch_bounds(int64_t nwitems, const PJob* pjobs, const CItem* witems, int64_t ntitems, const PJob* jobs,
-                   const TItem* titems, hipStream_t st)
-{
-    if (nwitems + ntitems <= 0) return;
-    PS_LAUNCH(k_bounds, dim3((unsigned)(nwitems + ntitems)), dim3(256), 0, st, pjobs, witems, nwitems, jobs, titems);
-}
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st)
 {
     if (nitems <= 0) return;
@@ -1326,16 +1417,21 @@ void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, 
     P2P_CASE(256)
 #undef P2P_CASE
 }
+void launch_chk_f32(int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
+{
+    if (nitems <= 0) return;
+    PS_LAUNCH(k_chk_f32<kChkWaves>, dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
+}
 void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
                       const double* dw, const double* drows, double* f, hipStream_t st)
 {
     if (maxdec <= 0) return;
     PS_LAUNCH(k_decay_rhs, dim3(maxdec, nsys), dim3(256), 0, st, sys, djobs, dpts, dec_tot, dw, drows, f);
 }
-void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const double* pinv,
-                  double* coef, double* f, hipStream_t st)
+void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const int* slot,
+                  const double* pinv, double* coef, double* f, hipStream_t st)
 {
-    PS_LAUNCH(k_rhs, dim3((maxL + 63) / 64, nsys), dim3(1024), 0, st, sys, cjobs, f);
+    PS_LAUNCH(k_rhs, dim3((maxL + 63) / 64, nsys), dim3(1024), 0, st, sys, cjobs, slot, f);
     PS_LAUNCH(k_gemv, dim3((maxP - 1 + 3) / 4, nsys), dim3(256), 0, st, sys, pinv, f, coef);
 }
 void launch_mean(int nsys, int64_t nwitems, const SysDev* sys, const CItem* witems, const int64_t* nnear,
