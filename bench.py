@@ -363,7 +363,8 @@ def bench_batch(args):
             "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
             "config": {"workload": "512 boxes d_k~U[1,2], N~logU[200,20000] (sum %d), q~N(0,1)-mean, p=12, "
                                    "lambda=sqrt3, FP32 pairs, one graph launch" % int(off[-1]),
-                       "pairs_per_batch": pairs, "tile_targets": info["tile_targets"]},
+                       "pairs_per_batch": pairs, "check_pairs_per_batch": float(np.sum(2 * L * nb)),
+                       "near_entries": int(nb.sum()), "tile_targets": info["tile_targets"]},
             "pair_rate": pairs / (ms * 1e-3), "max_rel_l2_sampled": err32, "autotune_best_ms": tuned_ms,
             "plan_seconds": t_plan,
             "per_box_fp64": {"solves_per_s": nsys / (ms64 * 1e-3), "ms_per_batch": ms64, "max_rel_l2_sampled": err64},
