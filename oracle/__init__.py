@@ -19,6 +19,9 @@ Parts:
     rows on planes above and below the box fix the far field's x/y-periodic
     harmonic modes that periodicity alone leaves free;
   * ``ewald2d`` -- an independent Ewald sum for charges periodic in x and y;
+  * ``screened`` -- the method for the screened Coulomb kernel exp(-kappa r)/r
+    (the paper's "other kernels", Sec. 1) with the kernel-at-centres basis of
+    eq. (5), and an independent Ewald-type split of its periodic sum;
   * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
 
 Pins (tests/test_oracle_*.py): the basis against an independent assembly from
@@ -33,5 +36,8 @@ translation invariance; the adjoint against central finite differences; the
 slab Ewald sum against brute-force square-shell lattice sums (extrapolated), its
 splitting parameter and Gauss's law; the slab method against that Ewald sum
 (thin, thick and elongated cells, a dipolar cell), x/y periodicity and in-plane
-translation invariance.
+translation invariance; the screened direct sums against the modified Helmholtz
+equation, finite differences and the Coulomb limit; the screened split against
+its splitting parameter and brute-force lattice sums; the screened method
+against that split, periodicity and translation invariance.
 """

@@ -36,6 +36,10 @@ def lib():
         _lib.orc_ewald_real.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp,
                                         ctypes.c_double, ctypes.c_double, dp, dp, dp, dp]
         _lib.orc_ewald_recip.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, dp, dp, dp, dp, dp, dp]
+        D = ctypes.c_double
+        _lib.orc_direct_screened.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, dp, dp, dp, dp]
+        _lib.orc_ewald_screened_real.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, D, D,
+                                                 dp, dp, dp, dp]
     return _lib
 
 
@@ -99,4 +103,35 @@ def ewald_recip(targets, kvec, w, sre, sim):
     g = [np.zeros(n) for _ in range(3)]
     lib().orc_ewald_recip(n, _p(tx), _p(ty), _p(tz), kx.size, _p(kx), _p(ky), _p(kz), _p(w), _p(sre), _p(sim),
                           _p(phi), *(_p(a) for a in g))
+    return phi, np.stack(g, axis=1)
+
+
+def direct_screened(targets, sources, q, kappa, shifts=None, grad=True):
+    """phi(y) = sum_p sum_j q_j exp(-kappa r)/r, r = |y - x_j - p| (K(0) = 0), over
+    the given shifts (default: none, the free-space sum), and grad phi."""
+    tx, ty, tz = _cols(targets)
+    sx, sy, sz = _cols(sources)
+    px, py, pz = _cols(np.zeros((1, 3)) if shifts is None else shifts)
+    sq = np.ascontiguousarray(q, dtype=np.float64)
+    n = tx.size
+    phi = np.zeros(n)
+    g = [np.zeros(n) for _ in range(3)] if grad else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    lib().orc_direct_screened(n, _p(tx), _p(ty), _p(tz), sx.size, _p(sx), _p(sy), _p(sz), _p(sq),
+                              px.size, _p(px), _p(py), _p(pz), float(kappa), _p(phi),
+                              *(tuple(_p(a) for a in g) if grad else (null, null, null)))
+    return (phi, np.stack(g, axis=1)) if grad else phi
+
+
+def ewald_screened_real(targets, sources, q, shifts, kappa, alpha, rcut):
+    tx, ty, tz = _cols(targets)
+    sx, sy, sz = _cols(sources)
+    px, py, pz = _cols(shifts)
+    sq = np.ascontiguousarray(q, dtype=np.float64)
+    n = tx.size
+    phi = np.zeros(n)
+    g = [np.zeros(n) for _ in range(3)]
+    lib().orc_ewald_screened_real(n, _p(tx), _p(ty), _p(tz), sx.size, _p(sx), _p(sy), _p(sz), _p(sq),
+                                  px.size, _p(px), _p(py), _p(pz), float(kappa), float(alpha), float(rcut),
+                                  _p(phi), *(_p(a) for a in g))
     return phi, np.stack(g, axis=1)

@@ -151,3 +151,83 @@ void orc_ewald_recip(long nt, const double* tx, const double* ty, const double* 
         if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Screened Coulomb kernel K(r) = exp(-kappa r)/r (the Green's function of    */
+/* the modified Helmholtz operator, up to 4 pi), K(0) = 0.                    */
+/* grad_y K(y - x) = -(1 + kappa r) exp(-kappa r) (y - x) / r^3.              */
+
+/* phi(y) = sum_m sum_j q_j K(y - x_j - p_m) over a list of shifts p_m (one zero
+ * shift gives the free-space finite sum of eq. (r2)); gx may be NULL. */
+void orc_direct_screened(long nt, const double* tx, const double* ty, const double* tz,
+                         long ns, const double* sx, const double* sy, const double* sz, const double* sq,
+                         long nimg, const double* px, const double* py, const double* pz, double kappa,
+                         double* phi, double* gx, double* gy, double* gz)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nt; ++i) {
+        acc_t p = {0, 0}, ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (long m = 0; m < nimg; ++m) {
+            const double yx = tx[i] - px[m], yy = ty[i] - py[m], yz = tz[i] - pz[m];
+            for (long j = 0; j < ns; ++j) {
+                double dx = yx - sx[j], dy = yy - sy[j], dz = yz - sz[j];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2);
+                double k = sq[j] * exp(-kappa * r) / r;
+                acc_add(&p, k);
+                if (gx) {
+                    double g = k * (1.0 + kappa * r) / r2;
+                    acc_add(&ax, -g * dx);
+                    acc_add(&ay, -g * dy);
+                    acc_add(&az, -g * dz);
+                }
+            }
+        }
+        phi[i] = acc_get(&p);
+        if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
+    }
+}
+
+/* Real-space part of an Ewald split of the screened kernel.  With
+ * K(r) = (2/sqrt(pi)) int_0^inf exp(-r^2 t^2 - kappa^2/(4 t^2)) dt, the part
+ * t > alpha is
+ *   K1(r) = [exp(kappa r) erfc(alpha r + b) + exp(-kappa r) erfc(alpha r - b)] / (2 r),  b = kappa/(2 alpha),
+ * and dK1/dr = [kappa (A - B) - (4 alpha/sqrt(pi)) exp(-alpha^2 r^2 - b^2)]/(2 r) - K1/r with A, B the
+ * two products above.  Pairs beyond rcut and r = 0 are skipped. */
+void orc_ewald_screened_real(long nt, const double* tx, const double* ty, const double* tz,
+                             long ns, const double* sx, const double* sy, const double* sz, const double* sq,
+                             long nimg, const double* px, const double* py, const double* pz,
+                             double kappa, double alpha, double rcut,
+                             double* phi, double* gx, double* gy, double* gz)
+{
+    const double four_over_sqrtpi = 2.25675833419102514780;
+    const double rc2 = rcut * rcut, b = kappa / (2.0 * alpha);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nt; ++i) {
+        acc_t p = {0, 0}, ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (long m = 0; m < nimg; ++m) {
+            const double yx = tx[i] - px[m], yy = ty[i] - py[m], yz = tz[i] - pz[m];
+            for (long j = 0; j < ns; ++j) {
+                double dx = yx - sx[j], dy = yy - sy[j], dz = yz - sz[j];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0 || r2 > rc2) continue;
+                double r = sqrt(r2);
+                double A = exp(kappa * r) * erfc(alpha * r + b);
+                double B = exp(-kappa * r) * erfc(alpha * r - b);
+                double k1 = (A + B) / (2.0 * r);
+                acc_add(&p, sq[j] * k1);
+                if (gx) {
+                    double dk = (kappa * (A - B) - four_over_sqrtpi * alpha * exp(-alpha * alpha * r2 - b * b)) / (2.0 * r)
+                                - k1 / r;
+                    double g = sq[j] * dk / r;   /* grad_y = dK1/dr (y - x)/r */
+                    acc_add(&ax, g * dx);
+                    acc_add(&ay, g * dy);
+                    acc_add(&az, g * dz);
+                }
+            }
+        }
+        phi[i] = acc_get(&p);
+        if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
+    }
+}
