@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 FP32_TFLOPS = 157.3
 FP64_TFLOPS = 78.6
 FLOP_PER_PAIR = 20         # potential + field: 3 sub, r^2 (mul + 2 FMA), rsqrt, 3 mul, add, 3 FMA
+FLOP_PER_PAIR_SCREENED = 25  # the same plus r = r^2/r, kappa r, exp, the factor e, and 1/r + kappa
 
 
 def log(*a):
@@ -57,7 +58,7 @@ def measured_traffic(precision, record="p2p_f32_clustered_N1M_hbm_counters.json"
     """HBM bytes per launch of the pair kernel from the committed rocprofv3
     counter record of that workload, or None if the kernel source has changed
     since (or there is no record)."""
-    if precision != "fp32":
+    if precision != "fp32" or record is None:
         return None
     rec = os.path.join(ROOT, "profiles", record)
     if not os.path.exists(rec):
@@ -133,13 +134,13 @@ def accuracy(phi, field, names):
     return out
 
 
-def roofline(precision, n, nb, t_pairs_ms, kernel, record):
+def roofline(precision, n, nb, t_pairs_ms, kernel, record, flop_per_pair=FLOP_PER_PAIR):
     peak = FP32_TFLOPS if precision == "fp32" else FP64_TFLOPS
-    achieved = FLOP_PER_PAIR * n * nb / (t_pairs_ms * 1e-3) / 1e12
+    achieved = flop_per_pair * n * nb / (t_pairs_ms * 1e-3) / 1e12
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": measured_traffic(precision, record),
             "peak_basis": "published %s vector peak" % ("FP32" if precision == "fp32" else "FP64"),
-            "kernel": kernel, "flop_per_pair": FLOP_PER_PAIR, "pairs_per_launch": n * nb,
+            "kernel": kernel, "flop_per_pair": flop_per_pair, "pairs_per_launch": n * nb,
             "launch_ms": t_pairs_ms, "pair_rate": n * nb / (t_pairs_ms * 1e-3)}
 
 
@@ -153,7 +154,7 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="skip the uniform-cube figures of the default line")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--workload", default="clustered",
-                    choices=["clustered", "cube", "batch", "rocksalt", "bases", "aspect", "small", "select"],
+                    choices=["clustered", "cube", "screened", "batch", "rocksalt", "bases", "aspect", "small", "select"],
                     help="clustered (default): the headline solve; the others measure the uniform cube, the "
                          "batched, differentiated and paper-table workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -176,8 +177,8 @@ def main():
         log("calibration copy: %d MiB read, %d MiB written" % (args.copy_calibration_mib, args.copy_calibration_mib))
         del a, b
     if args.workload not in ("clustered", "cube"):
-        out = {"batch": bench_batch, "rocksalt": bench_rocksalt, "bases": bench_bases, "aspect": bench_aspect,
-               "small": bench_small, "select": bench_select}[args.workload](args)
+        out = {"screened": bench_screened, "batch": bench_batch, "rocksalt": bench_rocksalt, "bases": bench_bases,
+               "aspect": bench_aspect, "small": bench_small, "select": bench_select}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "cube":
@@ -285,6 +286,42 @@ def bench_cube(args):
             "roofline": roofline(args.precision, n, nb, st["pairs"],
                                  "k_p2p_%s<%d,field>" % ("f32" if f32 else "f64", info["tile_targets"]),
                                  "p2p_f32_uniform_cube_N100k_hbm_counters.json"),
+            "stage_ms": st, "accuracy": acc}
+
+
+def bench_screened(args):
+    """The screened kernel exp(-kappa r)/r (kappa = 2) on the uniform cube, N = 100,000
+    with a net charge, the kernel at 256 Thomson centres as the basis, p = 16, lambda = 1.5."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config_screened()
+    n = len(c["q"])
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
+    q = torch.tensor(c["q"], device=dev)
+    plan = ps.Plan(c["box"], c["p"], lam=c["lam"], precision=args.precision, n_max=n, centres=c["centres"],
+                   kernel="screened", kappa=c["kappa"], tile_targets=args.tile_targets)
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    steps = max(20, 2 * args.steps)
+    ms, st = timed_solves(plan, x, q, phi, field, steps, max(3, args.warmup))
+    info = plan.info()
+    nb, L = info["n_near_last"], info["L"]
+    pairs_per_step = (n + 2 * L) * nb
+    acc = accuracy(phi, field, ["ref_screened.npz"])
+    f32 = args.precision == "fp32"
+    return {"metric": METRIC, "value": pairs_per_step / (ms * 1e-3), "unit": "pair interactions/s",
+            "n_gpus": 1, "steps": steps, "warmup": max(3, args.warmup), "ms_per_step": ms, "solves_per_s": 1e3 / ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64",
+            "data": "synthetic (seeded uniform positions, Gaussian charges + 0.05)",
+            "config": {"workload": "screened kernel exp(-2r)/r, uniform cube 1x1x1, N=100000, 256 Thomson centres "
+                                   "at 1.5 R0, p=16 (L=496), lambda=1.5",
+                       "N": n, "p": c["p"], "L": L, "kappa": c["kappa"], "M": 256, "n_near": nb,
+                       "pairs_per_solve": pairs_per_step},
+            "roofline": roofline(args.precision, n, nb, st["pairs"],
+                                 "k_p2p_%s<%d,field,screened>" % ("f32" if f32 else "f64", info["tile_targets"]),
+                                 None, FLOP_PER_PAIR_SCREENED),
             "stage_ms": st, "accuracy": acc}
 
 

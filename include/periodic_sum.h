@@ -84,6 +84,16 @@ typedef enum {
     PS_MEAN_NONE = 1    /* C1 = 0 (remark after algorithm "get") */
 } ps_mean;
 
+typedef enum {
+    PS_KERNEL_COULOMB = 0,  /* K(r) = 1/r, eq. (2) */
+    PS_KERNEL_SCREENED = 1  /* K(r) = exp(-kappa r)/r, the screened Coulomb (Yukawa) kernel: one of the
+                               "other kernels" the method applies to (Sec. 1).  Its lattice sum converges
+                               absolutely, so the charges need not be neutral; Delta - kappa^2 has no nonzero
+                               bounded periodic solution, so the fit has no null space: every coefficient of the
+                               kernel-at-centres basis (eq. (5)) comes from A^+ f, and there is no constant C1
+                               (the mean setting is ignored).  Needs PS_BASIS_RBF, periodic = 7. */
+} ps_kernel;
+
 typedef struct {
     double  box[3];       /* d1, d2, d3 > 0 */
     int32_t p;            /* truncation number: degrees 0..p-1, P = p*p basis terms; 2 <= p <= 40 */
@@ -114,6 +124,8 @@ typedef struct {
                              <(d/dz + s|k|) phi, trig(k.rho)> = 0 (s = +1 above, -1 below; k = 0 is
                              Gauss's law), by m x m Gauss-Legendre points per plane,
                              m = max(2p + 8, ceil(40 max(d1, d2) / R0)).  Spherical basis only. */
+    int32_t kernel;       /* ps_kernel (PS_KERNEL_COULOMB when zero-initialised) */
+    double  kappa;        /* PS_KERNEL_SCREENED: the screening constant, 0 < kappa <= 64 / R0 */
 } ps_params;
 
 typedef struct {
@@ -132,6 +144,9 @@ typedef struct {
                                  batched eval); the pass the plan's workspace holds last */
     int32_t periodic;         /* periodic axes of system 0 (7 or 3) */
     int32_t n_rows;           /* rows of system 0's fit: L periodicity rows, then (slab) the decay rows */
+    double  kappa;            /* screening constant (0 for the Coulomb kernel) */
+    int32_t kernel;           /* ps_kernel of the plan (every system of a batch shares it) */
+    int32_t reserved;
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
@@ -215,8 +230,10 @@ ps_status periodic_sum_energy(ps_plan plan, int64_t n,
  *     dE/dq_i = 1/2 [phi(x_i) + sum_{p: (i,p) near} psi(x_i + p)],
  *     derived from eqs. (3), (8), (10), (pfx3)-(pfx4) (the paper gives no adjoint).
  *   exact = 0: the physical approximation dE/dx_i = -q_i field_i, dE/dq_i = phi_i.
- * dE/dq is returned projected onto sum dq = 0 (mean removed): the energy is only
- * defined for neutral charges.  Must follow a periodic_sum_energy (or eval at the
+ * dE/dq is returned projected onto sum dq = 0 (mean removed): the Coulomb energy is
+ * only defined for neutral charges.  Screened kernel: exact = 0 only (exact = 1
+ * returns PS_E_UNSUPPORTED), and dE/dq = phi without projection (any charges).
+ * Must follow a periodic_sum_energy (or eval at the
  * particles) with the same inputs on the same stream: it reuses that forward
  * pass's near set, coefficients and outputs kept in the plan.
  *   epoch : 0, or the forward_epoch (periodic_sum_plan_info) read right after
@@ -235,13 +252,14 @@ ps_status periodic_sum_energy_vjp(ps_plan plan, int64_t n,
  * mean and rcond are taken from prm[0]).  Same host steps as periodic_sum_plan
  * per system; device tables are packed per system. */
 ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int device, ps_plan* out);
+/* (kernel and kappa are taken from prm[0] as well.) */
 
 /* Saves the result of the "set" phase (Sec. 2.3; its cost grows like P^3 with
  * the SVD, Tables 2-4) so that a later process can skip it: for every system the
  * parameters, check points and partners, A^+, the box integrals R_t^(0), the
  * image list and the RBF centres, plus the plan's tuned launch shape.  Nothing
  * of the last eval is saved.  Format: little-endian binary, "PSPLAN01" magic,
- * version 1, a 64-bit FNV-1a checksum of all preceding bytes at the end.
+ * version 3, a 64-bit FNV-1a checksum of all preceding bytes at the end.
  *   path: host string, a file path; an existing file is replaced.
  * Errors: PS_E_INVALID (NULL plan or path), PS_E_IO (the file could not be
  * written completely). */
@@ -328,7 +346,8 @@ ps_status periodic_sum_near_counts(ps_plan plan, int64_t* out, int32_t nsys);
 
 /* Synchronizes `stream` and returns the data-dependent status of the last eval
  * or PS_OK, then clears it: PS_E_OUT_OF_BOX for a particle outside the box or
- * a NaN coordinate or charge (reported first), else PS_E_NOT_NEUTRAL. */
+ * a NaN coordinate or charge (reported first), else PS_E_NOT_NEUTRAL (Coulomb
+ * kernel only: screened plans accept any net charge). */
 ps_status periodic_sum_status(ps_plan plan, void* stream);
 
 /* Plan facts; n_near_last synchronizes the device. */

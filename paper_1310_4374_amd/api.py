@@ -14,6 +14,7 @@ from ._lib import check, lib, ps_params, ps_plan_info, ps_select_row
 _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
 _PERIODIC = {"xyz": 7, "xy": 3}
+_KERNEL = {"coulomb": 0, "screened": 1}
 
 
 def _host_points(a):
@@ -26,9 +27,11 @@ def _host_points(a):
 
 
 def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-            tile_targets=0, n_split=0, centres=None, check_points=None, keep=None, periodic="xyz"):
+            tile_targets=0, n_split=0, centres=None, check_points=None, keep=None, periodic="xyz", kernel="coulomb",
+            kappa=0.0):
     """keep: a list that receives the host arrays the struct points to.
-    periodic: "xyz" (three periodic axes) or "xy" (a slab, z free)."""
+    periodic: "xyz" (three periodic axes) or "xy" (a slab, z free).
+    kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r; needs centres)."""
     prm = ps_params()
     for k in range(3):
         prm.box[k] = float(box[k])
@@ -43,6 +46,8 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
     prm.tile_targets = int(tile_targets)
     prm.n_split = int(n_split)
     prm.periodic = _PERIODIC[periodic] if isinstance(periodic, str) else int(periodic)
+    prm.kernel = _KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
+    prm.kappa = float(kappa)
     dp = ctypes.POINTER(ctypes.c_double)
     if centres is not None:
         c = _host_points(centres)
@@ -103,15 +108,18 @@ class Plan:
     """One periodic box: algorithm "set" at construction, "get" on each eval."""
 
     def __init__(self, box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
-                 tile_targets=0, n_split=0, centres=None, check_points=None, periodic="xyz", device=0):
+                 tile_targets=0, n_split=0, centres=None, check_points=None, periodic="xyz", kernel="coulomb",
+                 kappa=0.0, device=0):
         """centres: (M, 3) RBF centres outside the box (eq. (5)); None for the
         spherical-harmonic basis.  check_points: (L, 3) points on the
         circumsphere; None for the Gauss spherical grid.  periodic: "xyz", or
-        "xy" for a slab (periodic in x and y, vacuum above and below)."""
+        "xy" for a slab (periodic in x and y, vacuum above and below).
+        kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r, any net charge,
+        RBF centres required, no constant term)."""
         self.device = torch.device("cuda", device)
         keep = []
         self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split,
-                            centres, check_points, keep, periodic)
+                            centres, check_points, keep, periodic, kernel, kappa)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan(ctypes.byref(self._prm), int(device), ctypes.byref(h)))
         self._h = h
@@ -302,16 +310,16 @@ class BatchedPlan:
     """Many independent boxes solved by one graph launch per eval."""
 
     def __init__(self, systems, p, lam=None, R_b=None, precision="fp32", mean="zero", rcond=1e-13, tile_targets=0,
-                 n_split=0, device=0):
+                 n_split=0, kernel="coulomb", kappa=0.0, device=0):
         """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam',
-        'centres', 'check_points', 'periodic')."""
+        'centres', 'check_points', 'periodic').  kernel and kappa hold for every system."""
         self.device = torch.device("cuda", device)
         arr = (ps_params * len(systems))()
         keep = []
         for k, s in enumerate(systems):
             arr[k] = _params(s["box"], s.get("p", p), s.get("R_b", R_b), s.get("lam", lam), precision, mean, rcond,
                              s["n_max"], 0, tile_targets, n_split, s.get("centres"), s.get("check_points"), keep,
-                             s.get("periodic", "xyz"))
+                             s.get("periodic", "xyz"), kernel, kappa)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan_batched(len(systems), arr, int(device), ctypes.byref(h)))
         self._h = h

@@ -151,6 +151,8 @@ struct ps_plan_s {
     std::vector<SysDev> base;        // per system, static part
     // device tables
     SysDev* d_sys = nullptr;
+    int kernel = 0;                     // ps_kernel, shared by every system of the plan
+    double kappa = 0.0;                 // screening constant of PS_KERNEL_SCREENED
     double* d_chk_t = nullptr;          // the check targets in the order of the check-point sums
     int* d_chk_slot = nullptr;          // position of check target k of a system in that order
     double *d_img = nullptr, *d_chk = nullptr, *d_pinv = nullptr, *d_bm = nullptr, *d_rec = nullptr;
@@ -290,6 +292,11 @@ void choose_grid(const double box[3], int64_t nmax, int g[3], int& gbits)
     for (int k = 0; k < 3; ++k) g[k] = static_cast<int>(std::min<double>(1 << gbits, std::max(1.0, std::ceil(box[k] / hc))));
 }
 
+// The C ABI's struct layouts (mirrored by the ctypes binding).
+static_assert(sizeof(ps_params) == 136 && offsetof(ps_params, periodic) == 120 && offsetof(ps_params, kappa) == 128,
+              "ps_params layout");
+static_assert(sizeof(ps_plan_info) == 112 && offsetof(ps_plan_info, kappa) == 96, "ps_plan_info layout");
+
 ps_status check_params(const ps_params* prm)
 {
     if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
@@ -310,11 +317,17 @@ ps_status check_params(const ps_params* prm)
         return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z) or 3 (x, y)");
     if (prm->periodic == 3 && prm->basis == PS_BASIS_RBF)
         return fail(PS_E_UNSUPPORTED, "the RBF basis is not supported with two periodic axes");
+    if (prm->kernel != PS_KERNEL_COULOMB && prm->kernel != PS_KERNEL_SCREENED)
+        return fail(PS_E_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == PS_KERNEL_SCREENED && (prm->basis != PS_BASIS_RBF || prm->periodic == 3))
+        return fail(PS_E_UNSUPPORTED, "the screened kernel needs the RBF basis and three periodic axes");
     for (int k = 0; k < 3; ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
     const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + prm->box[2] * prm->box[2]);
     const double Rb = prm->R_b > 0 ? prm->R_b : prm->lambda * R0;
     if (!(Rb > R0) || !std::isfinite(Rb)) return fail(PS_E_INVALID, "near radius must exceed the circumradius (lambda > 1)");
+    if (prm->kernel == PS_KERNEL_SCREENED && !(prm->kappa > 0.0 && prm->kappa * R0 <= 64.0))
+        return fail(PS_E_INVALID, "kappa must lie in (0, 64 / R0]");
     return PS_OK;
 }
 
@@ -475,6 +488,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         const SystemSetup& su = pl->setups[s];
         PJob& C = T.jobs[s];
         C = PJob{};
+        C.kappa = pl->kappa;
         C.tx = pl->d_chk_t + S.chk_off;
         C.ty = pl->d_chk_t + pl->chk_tot + S.chk_off;
         C.tz = pl->d_chk_t + 2 * pl->chk_tot + S.chk_off;
@@ -501,6 +515,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
 
         PJob& Pj = T.jobs[nsys + s];
         Pj = PJob{};
+        Pj.kappa = pl->kappa;
         if (separate) {
             Pj.tx = tx;
             Pj.ty = ty;
@@ -626,6 +641,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         const PJob& Pj = T.jobs[nsys + s];
         PJob& F = T.jobs[2 * nsys + s];
         F = PJob{};
+        F.kappa = pl->kappa;
         F.tx = Pj.tx;
         F.ty = Pj.ty;
         F.tz = Pj.tz;
@@ -796,26 +812,28 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     launch_tblock(T.nt_items, jobs, pl->d_t_items, st);
     mark(3);
     if (pl->precision == PS_FP32_ACC64)  // step 3 at the check points
-        launch_chk_f32(T.nchk, cjobs, pl->d_chk_items, st);
+        launch_chk_f32(pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
     else
-        launch_p2p(0, pl->bt_chk, false, T.nchk, cjobs, pl->d_chk_items, st);
+        launch_p2p(0, pl->bt_chk, false, pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
     if (T.nd > 0) {  // slab: near sums at the decay planes, then the decay rows of f
-        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
+        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, 0, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
         launch_decay_rhs(nsys, pl->max_dec, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot, pl->d_dw, pl->d_drows,
                          pl->d_f, st);
     }
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_chk_slot, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
     mark(5);
-    launch_mean(nsys, T.mean_entries ? T.nw : 0, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_nq, pl->d_mean_part,
-                T.nm, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
+    const bool need_mean = pl->mean == PS_MEAN_ZERO;   // with C1 = 0 only k_c1 runs (it writes the zero)
+    launch_mean(nsys, need_mean && T.mean_entries ? T.nw : 0, pl->d_sys, pl->d_w_items, pl->d_nnear, pl->d_nx, pl->d_ny,
+                pl->d_nz, pl->d_nq, pl->d_mean_part, need_mean ? T.nm : 0, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
                 pl->d_bm, pl->d_coef, st);  // step 6
     mark(6);
-    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, T.np, pjobs, pl->d_p_items, st);  // step 3 at Y0
+    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, pl->kernel, T.np, pjobs, pl->d_p_items,
+               st);  // step 3 at Y0
     mark(7);
     const PJob* fjobs = jobs + 2 * nsys;
     if (pl->any_rbf) {  // step 7 for the RBF basis: sum over the M centres
-        launch_p2p(0, pl->bt, true, T.nf, fjobs, pl->d_f_items, st);
+        launch_p2p(0, pl->bt, true, pl->kernel, T.nf, fjobs, pl->d_f_items, st);
     }
     launch_far(T.far_lanes, T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
                separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
@@ -843,6 +861,9 @@ ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
     pl->nsys = nsys;
     pl->precision = prm[0].precision;
     pl->mean = prm[0].mean;
+    pl->kernel = prm[0].kernel;
+    pl->kappa = prm[0].kernel == PS_KERNEL_SCREENED ? prm[0].kappa : 0.0;
+    if (pl->kernel == PS_KERNEL_SCREENED) pl->mean = PS_MEAN_NONE;   // no constant to fix
     pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
     pl->n_split_req = prm[0].n_split;
     pl->m_max = nsys == 1 ? prm[0].m_max : 0;
@@ -893,7 +914,10 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     if (nsys < 1) return fail(PS_E_INVALID, "nsys must be >= 1");
     if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
     for (int s = 0; s < nsys; ++s) {
-        ps_status st = check_params(&prm[s]);
+        ps_params q = prm[s];
+        q.kernel = prm[0].kernel;   // one kernel per plan, taken from prm[0]
+        q.kappa = prm[0].kappa;
+        ps_status st = check_params(&q);
         if (st != PS_OK) return st;
     }
     ps_status ds = check_device(device);
@@ -909,7 +933,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     for (int s = 0; s < nsys; ++s)
         errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
                                       prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points,
-                                      prm[s].periodic == 3 ? 3 : 7);
+                                      prm[s].periodic == 3 ? 3 : 7, prm[0].kernel, prm[0].kappa);
     for (int s = 0; s < nsys; ++s)
         if (!errs[s].empty()) {
             delete pl;
@@ -957,7 +981,9 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.P = su.P;
         S.L = su.L;
         S.nimg = static_cast<int>(su.images.size() / 3);
-        S.mean_mode = prm[0].mean;
+        S.mean_mode = pl->mean;
+        S.kernel = su.kernel;
+        S.kappa = su.kappa;
         S.basis = su.basis;
         S.M = su.basis == 1 ? static_cast<int>(su.centres.size() / 3) : 0;
         S.cen_off = cen_tot;
@@ -1225,7 +1251,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
 // Plan files: magic, version, system count, tuned launch shape, then per system
 // the scalar parameters and the set data, then a checksum of all prior bytes.
 const char kPlanMagic[8] = {'P', 'S', 'P', 'L', 'A', 'N', '0', '1'};
-const uint32_t kPlanVersion = 2;
+const uint32_t kPlanVersion = 3;
 
 template <typename T>
 void put_scalar(std::vector<unsigned char>& out, const T& v)
@@ -1279,6 +1305,8 @@ ps_status periodic_sum_plan_save(ps_plan pl, const char* path)
         put_scalar(buf, q.n_split);
         put_scalar(buf, q.basis);
         put_scalar(buf, q.periodic);
+        put_scalar(buf, q.kernel);
+        put_scalar(buf, q.kappa);
         pl->setups[s].serialize(buf);
     }
     put_scalar(buf, fnv1a64(buf.data(), buf.size()));
@@ -1334,12 +1362,14 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
              get_scalar(buf, pos, q.precision) && get_scalar(buf, pos, q.mean) && get_scalar(buf, pos, q.rcond) &&
              get_scalar(buf, pos, q.n_max) && get_scalar(buf, pos, q.m_max) &&
              get_scalar(buf, pos, q.tile_targets) && get_scalar(buf, pos, q.n_split) && get_scalar(buf, pos, q.basis) &&
-             get_scalar(buf, pos, q.periodic);
+             get_scalar(buf, pos, q.periodic) && get_scalar(buf, pos, q.kernel) && get_scalar(buf, pos, q.kappa);
         if (!ok) return fail(PS_E_IO, "%s: truncated parameters of system %d", path, s);
         const std::string why = setups[s].deserialize(buf.data(), buf.size(), pos);
         if (!why.empty()) return fail(PS_E_IO, "%s: system %d: %s", path, s, why.c_str());
         const SystemSetup& su = setups[s];
-        if (q.p != su.p || q.basis != su.basis || (q.periodic == 3 ? 3 : 7) != su.periodic)
+        if (q.p != su.p || q.basis != su.basis || (q.periodic == 3 ? 3 : 7) != su.periodic ||
+            q.kernel != su.kernel || (su.kernel == 1 && q.kappa != su.kappa) || q.kernel != prm[0].kernel ||
+            q.kappa != prm[0].kappa)
             return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
         for (int k = 0; k < 3; ++k)
             if (q.box[k] != su.box[k]) return fail(PS_E_IO, "%s: system %d: box does not match its tables", path, s);
@@ -1528,6 +1558,9 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
     out->forward_epoch = pl->fwd_epoch;
     out->periodic = su.periodic;
     out->n_rows = su.rows();
+    out->kappa = pl->kappa;
+    out->kernel = pl->kernel;
+    out->reserved = 0;
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
@@ -1804,6 +1837,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     const SysDev& S = pl->tab.sys[0];
     if (exact && S.ndec > 0)
         return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with two periodic axes (exact = 0 is)");
+    if (exact && pl->kernel == PS_KERNEL_SCREENED)
+        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the screened kernel (exact = 0 is)");
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
@@ -1878,7 +1913,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         HIPCHK(hipStreamSynchronize(st));
         if (S.basis == 1) {
             launch_tblock(static_cast<int64_t>(pl->mom_t.size()), pl->d_mom_job, pl->d_mom_t, st);
-            launch_p2p(0, 256, false, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p, st);
+            launch_p2p(0, 256, false, 0, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p, st);
         } else {
             mom_blocks = kMomWaves;
             launch_moments(S.P, S.p, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec, pl->d_mom, mom_blocks,
@@ -1888,7 +1923,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
                                stride, toff, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az, pl->d_aq,
                                st);
         launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
-        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, static_cast<int64_t>(pl->adj_p.size()),
+        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, 0, static_cast<int64_t>(pl->adj_p.size()),
                    pl->d_adj_job, pl->d_adj_p, st);
     } else {
         ps_status s = ensure_adjoint_workspace(pl);

@@ -68,6 +68,8 @@ struct SysDev {
     int64_t dec_off;             // slab: decay-plane points in the packed SoA arrays (2 m2 per system)
     int64_t dw_off;              // slab: their quadrature weights (m2, shared by both planes)
     int64_t drow_off;            // slab: decay rows, 5 doubles each (kx, ky, |k|, s, trig)
+    int kernel, pad2;            // 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (no neutrality, no C1)
+    double kappa;                // screening constant (screened kernel)
 };
 
 // A pair-sum job: every target of a set against every source of another.
@@ -85,6 +87,7 @@ struct PJob {
     double* tblk;           // 4 doubles per target block: centre xyz, radius
     double* part;           // partial sums [nsplit][ncomp][nt]
     int nsplit, ncomp, bt, pad;
+    double kappa;           // screened kernel: exp(-kappa r)/r (0 for the Coulomb kernel)
 };
 
 struct PItem { int job, tb, split, pad; };           // one workgroup of a pair sum

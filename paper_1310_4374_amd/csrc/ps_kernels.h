@@ -17,9 +17,11 @@ void launch_near(int nsys, int64_t nnitems, const SysDev* sys, const NItem* nite
                  const double* sx, const double* sy, const double* sz, const double* sq, int* ncount, int64_t* ioff,
                  int64_t* nnear, double* nx, double* ny, double* nz, double* nq, int* nbase, int* inv, hipStream_t st);
 void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStream_t st);
-void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
+// kern: 0 Coulomb 1/r, 1 screened exp(-kappa r)/r (kappa from each job)
+void launch_p2p(int prec, int bt, bool field, int kern, int64_t nitems, const PJob* jobs, const PItem* items,
+                hipStream_t st);
 // FP32 check-point sums (potential only); every job has 64-target blocks and ncomp = 1.
-void launch_chk_f32(int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
+void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
 void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
                       const double* dw, const double* drows, double* f, hipStream_t st);
 // slot[chk_off + k]: position of check target k of a system in its check job

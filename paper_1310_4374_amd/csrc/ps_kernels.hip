@@ -126,7 +126,9 @@ __global__ __launch_bounds__(256) void k_validate(const SysDev* __restrict__ sys
 }
 
 // One wave per system: lane-strided partial sums, then a butterfly (fixed order).
-__global__ __launch_bounds__(64) void k_validate_final(const double* __restrict__ part, int nblk, int* status)
+// The screened kernel's lattice sum converges for any net charge.
+__global__ __launch_bounds__(64) void k_validate_final(const SysDev* __restrict__ sys, const double* __restrict__ part,
+                                                       int nblk, int* status)
 {
     double sq = 0.0, sa = 0.0;
     const double* o = part + 2 * (int64_t)blockIdx.x * nblk;
@@ -136,7 +138,7 @@ __global__ __launch_bounds__(64) void k_validate_final(const double* __restrict_
     }
     sq = wave_sum(sq);
     sa = wave_sum(sa);
-    if (threadIdx.x == 0 && !(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
+    if (threadIdx.x == 0 && sys[blockIdx.x].kernel == 0 && !(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -459,10 +461,14 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
 // the field is t sum_j w_j + (1/2) (accumulators).  Far pairs are at least
 // (kFarFactor - 1) x (block radius) apart, so the cancellation in the expanded
 // r^2 stays a bounded multiple of the FP32 rounding.
-template <bool NEAR, bool FIELD>
+// KERN = 1, the screened kernel exp(-kappa r)/r: with ri = 1/r, r = r^2 ri and
+// e = 2^(r nk2) (nk2 = -kappa log2(e)), the potential term is q ri e and the
+// field weight q e (1 + kappa r)/r^3 = (q ri e) ri (ri + kappa).  A masked pair
+// (ri = 0) gives r = 0, e = 1 and zero terms; padding sources give e = 0.
+template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
-                                            float hy, float hz, float lx, float ly, float lz, float tt, double& aP,
-                                            double& aW, double& aX, double& aY, double& aZ)
+                                            float hy, float hz, float lx, float ly, float lz, float tt, float kap,
+                                            float nk2, double& aP, double& aW, double& aX, double& aY, double& aZ)
 {
     float fX = 0.f, fY = 0.f, fZ = 0.f, fW = 0.f;
     float p32 = 0.f;
@@ -489,9 +495,16 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
             }
             float ri = __builtin_amdgcn_rsqf(r2);
             if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
-            qv[u] = s.w * ri;
+            float qr3;
+            if constexpr (KERN == 1) {
+                const float e = __builtin_amdgcn_exp2f((r2 * ri) * nk2);
+                qv[u] = (s.w * ri) * e;
+                if (FIELD) qr3 = qv[u] * (ri * (ri + kap));
+            } else {
+                qv[u] = s.w * ri;
+                if (FIELD) qr3 = qv[u] * (ri * ri);
+            }
             if (FIELD) {
-                const float qr3 = qv[u] * (ri * ri);
                 if (NEAR) {
                     fX = __builtin_fmaf(qr3, dx, fX);
                     fY = __builtin_fmaf(qr3, dy, fY);
@@ -553,7 +566,7 @@ __device__ __forceinline__ uint32_t load_far_mask(const uint32_t* far_bits)
 template <int BT>
 constexpr int p2p_waves_hint() { return BT >= 128 ? 6 : 4; }
 
-template <int BT, bool FIELD>
+template <int BT, bool FIELD, int KERN>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hint<BT>()))) void k_p2p_f32(
     const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
@@ -578,6 +591,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
     const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
     const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
+    const float kap = (float)J.kappa, nk2 = (float)(-J.kappa * 1.4426950408889634);
     const double* __restrict__ SX = J.sx;
     const double* __restrict__ SY = J.sy;
     const double* __restrict__ SZ = J.sz;
@@ -628,11 +642,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f32<false, FIELD>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
-                                          aY, aZ);
+                group32_f32<false, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, kap,
+                                                nk2, aP, aW, aX, aY, aZ);
             else
-                group32_f32<true, FIELD>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, aP, aW, aX,
-                                         aY, aZ);
+                group32_f32<true, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, kap,
+                                               nk2, aP, aW, aX, aY, aZ);
         }
     }
     if (active) {
@@ -656,10 +670,12 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 // groups take differences of the absolute coordinates, exact for close pairs,
 // and apply K(0) = 0.  LDS per source: F = (-(x - c), |x - c|^2) for far groups
 // and N = (x, q/2) for near groups (which read the halved charge for both).
-template <bool NEAR, bool FIELD>
+// KERN = 1 (screened): r = r^2 u / 2, e = exp(-kappa r), the potential term
+// (q/2) u e = q e/r and the weight (q e/r) u (u + 2 kappa) = 4 q e (1 + kappa r)/r^3.
+template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, const double4* __restrict__ sN, double tx,
                                             double ty, double tz, double h2x, double h2y, double h2z, double tt,
-                                            double& aP, double& aW, double& aX, double& aY, double& aZ)
+                                            double kap, double& aP, double& aW, double& aX, double& aY, double& aZ)
 {
 #pragma unroll 2  // 90 VGPRs: five waves per SIMD hide the FP64 latency (unroll 8: 129, three waves, 5% slower)
     for (int k = 0; k < kGroup; ++k) {
@@ -680,10 +696,16 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
         const double y0 = __builtin_amdgcn_rsq(r2);
         double u = y0 * __builtin_fma(-(r2 * y0), y0, 3.0);  // 2/r
         if (NEAR) u = r2 > 0.0 ? u : 0.0;                     // K(0) = 0
-        const double qr = n.w * u;                            // q/r
+        double qr, w;
+        if constexpr (KERN == 1) {
+            qr = (n.w * u) * exp(-kap * (0.5 * (r2 * u)));        // q e/r
+            if (FIELD) w = qr * (u * (u + 2.0 * kap));            // 4 q e (1 + kappa r)/r^3
+        } else {
+            qr = n.w * u;                                         // q/r
+            if (FIELD) w = qr * (u * u);                          // 4 q/r^3
+        }
         aP += qr;
         if (FIELD) {
-            const double w = qr * (u * u);  // 4 q/r^3
             if (!NEAR) aW += w;
             aX = __builtin_fma(w, dx, aX);
             aY = __builtin_fma(w, dy, aY);
@@ -692,7 +714,7 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
     }
 }
 
-template <int BT, bool FIELD>
+template <int BT, bool FIELD, int KERN>
 __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
     __shared__ double4 sF[kTile];
@@ -740,11 +762,11 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f64<false, FIELD>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt, aP, aW,
-                                          aX, aY, aZ);
+                group32_f64<false, FIELD, KERN>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt,
+                                                J.kappa, aP, aW, aX, aY, aZ);
             else
-                group32_f64<true, FIELD>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt, aP, aW,
-                                         aX, aY, aZ);
+                group32_f64<true, FIELD, KERN>(sF + gq * kGroup, sN + gq * kGroup, tx, ty, tz, h2x, h2y, h2z, tt,
+                                               J.kappa, aP, aW, aX, aY, aZ);
         }
     }
     if (active) {
@@ -774,10 +796,10 @@ __global__ __launch_bounds__(BT) void k_p2p_f64(const PJob* __restrict__ jobs, c
 // its own, four sources per LDS read.  The pair arithmetic is group32_f32's
 // potential form, and so is the accumulation: a balanced FP32 tree per 8 pairs,
 // four trees added in FP32, then an FP64 accumulator.
-template <bool NEAR>
+template <bool NEAR, int KERN>
 __device__ __forceinline__ float pot8_f32(const float4* __restrict__ sA, const float4* __restrict__ sB,
                                           const float* __restrict__ sW, float hx, float hy, float hz, float lx,
-                                          float ly, float lz, float tt)
+                                          float ly, float lz, float tt, float nk2)
 {
     float qv[8];
 #pragma unroll
@@ -800,7 +822,10 @@ __device__ __forceinline__ float pot8_f32(const float4* __restrict__ sA, const f
         }
         float ri = __builtin_amdgcn_rsqf(r2);
         if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
-        qv[u] = s.w * ri;
+        if constexpr (KERN == 1)
+            qv[u] = (s.w * ri) * __builtin_amdgcn_exp2f((r2 * ri) * nk2);  // screened, as in group32_f32
+        else
+            qv[u] = s.w * ri;
     }
     return ((qv[0] + qv[1]) + (qv[2] + qv[3])) + ((qv[4] + qv[5]) + (qv[6] + qv[7]));
 }
@@ -814,7 +839,7 @@ __device__ __forceinline__ double load_global(const double* p, int64_t j)
     return ((const __attribute__((address_space(1))) double*)p)[j];
 }
 
-template <int WS>
+template <int WS, int KERN>
 __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jobs, const PItem* __restrict__ items)
 {
     constexpr int NT = 64 * WS;     // threads of the workgroup
@@ -843,6 +868,7 @@ __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jo
     const float hx = (float)rx, hy = (float)ry, hz = (float)rz;
     const float lx = (float)(rx - (double)hx), ly = (float)(ry - (double)hy), lz = (float)(rz - (double)hz);
     const float tt = __builtin_fmaf(hz, hz, __builtin_fmaf(hy, hy, hx * hx));
+    const float nk2 = (float)(-J.kappa * 1.4426950408889634);
     const double* __restrict__ SX = J.sx;
     const double* __restrict__ SY = J.sy;
     const double* __restrict__ SZ = J.sz;
@@ -899,8 +925,10 @@ __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jo
 #pragma unroll
                 for (int c = 0; c < SPW; c += 8)
                     p32 += ((farm >> g) & 1)
-                               ? pot8_f32<false>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt)
-                               : pot8_f32<true>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt);
+                               ? pot8_f32<false, KERN>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt,
+                                                       nk2)
+                               : pot8_f32<true, KERN>(sA + o + c, sB + o + c, sW + o + c, hx, hy, hz, lx, ly, lz, tt,
+                                                      nk2);
             }
             aP += (double)p32;
         }
@@ -1368,7 +1396,7 @@ void launch_validate(int nsys, int nblk, const SysDev* sys, const double* X, con
                      const double* Q, int* status, double* part, hipStream_t st)
 {
     PS_LAUNCH(k_validate, dim3(nblk, nsys), dim3(256), 0, st, sys, X, Y, Z, Q, status, part);
-    PS_LAUNCH(k_validate_final, dim3(nsys), dim3(64), 0, st, part, nblk, status);
+    PS_LAUNCH(k_validate_final, dim3(nsys), dim3(64), 0, st, sys, part, nblk, status);
 }
 void launch_sort(int nsys, int64_t ncitems, int64_t max_ncell, const SysDev* sys, const CItem* citems, const double* X,
                  const double* Y, const double* Z, const double* Q, int* keys, int* slots, int* cnt, int* start,
@@ -1397,30 +1425,37 @@ void launch_tblock(int64_t nitems, const PJob* jobs, const TItem* items, hipStre
     if (nitems <= 0) return;
     PS_LAUNCH(k_tblock, dim3((unsigned)nitems), dim3(256), 0, st, jobs, items);
 }
-void launch_p2p(int prec, int bt, bool field, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
+void launch_p2p(int prec, int bt, bool field, int kern, int64_t nitems, const PJob* jobs, const PItem* items,
+                hipStream_t st)
 {
     if (nitems <= 0) return;
     const dim3 g((unsigned)nitems);
-#define P2P_CASE(BT)                                                                                       \
-    if (bt == BT) {                                                                                        \
+#define P2P_CASE(BT, K)                                                                                    \
+    if (bt == BT && kern == K) {                                                                           \
         if (prec == 1) {                                                                                   \
-            if (field) PS_LAUNCH((k_p2p_f32<BT, true>), g, dim3(BT), 0, st, jobs, items);                  \
-            else PS_LAUNCH((k_p2p_f32<BT, false>), g, dim3(BT), 0, st, jobs, items);                       \
+            if (field) PS_LAUNCH((k_p2p_f32<BT, true, K>), g, dim3(BT), 0, st, jobs, items);               \
+            else PS_LAUNCH((k_p2p_f32<BT, false, K>), g, dim3(BT), 0, st, jobs, items);                    \
         } else {                                                                                           \
-            if (field) PS_LAUNCH((k_p2p_f64<BT, true>), g, dim3(BT), 0, st, jobs, items);                  \
-            else PS_LAUNCH((k_p2p_f64<BT, false>), g, dim3(BT), 0, st, jobs, items);                       \
+            if (field) PS_LAUNCH((k_p2p_f64<BT, true, K>), g, dim3(BT), 0, st, jobs, items);               \
+            else PS_LAUNCH((k_p2p_f64<BT, false, K>), g, dim3(BT), 0, st, jobs, items);                    \
         }                                                                                                  \
         return;                                                                                            \
     }
-    P2P_CASE(64)
-    P2P_CASE(128)
-    P2P_CASE(256)
+    P2P_CASE(64, 0)
+    P2P_CASE(128, 0)
+    P2P_CASE(256, 0)
+    P2P_CASE(64, 1)
+    P2P_CASE(128, 1)
+    P2P_CASE(256, 1)
 #undef P2P_CASE
 }
-void launch_chk_f32(int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
+void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
 {
     if (nitems <= 0) return;
-    PS_LAUNCH(k_chk_f32<kChkWaves>, dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
+    if (kern == 1)
+        PS_LAUNCH((k_chk_f32<kChkWaves, 1>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
+    else
+        PS_LAUNCH((k_chk_f32<kChkWaves, 0>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
 }
 void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
                       const double* dw, const double* drows, double* f, hipStream_t st)
@@ -1630,8 +1665,9 @@ __global__ __launch_bounds__(256) void k_adj_gather(const SysDev* __restrict__ s
     dx[2 * S.n + i] = 0.5 * q * (-o[3] - fz);
 }
 
-// Remove the mean of dq (neutral charges), scale by gE and store in the
-// original particle order.
+// Remove the mean of dq (neutral charges; not for the screened kernel, whose
+// energy is defined for any charges), scale by gE and store in the original
+// particle order.
 __global__ __launch_bounds__(1024) void k_adj_finish(const SysDev* __restrict__ sys, const int* __restrict__ perm,
                                                      const double* __restrict__ dq, const double* __restrict__ dx,
                                                      const double* __restrict__ gE, double* __restrict__ oq,
@@ -1643,7 +1679,7 @@ __global__ __launch_bounds__(1024) void k_adj_finish(const SysDev* __restrict__ 
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < S.n; i += 1024) acc += dq[i];
     acc = block_reduce<0>(acc, sh);
-    const double mean = acc / (double)S.n;
+    const double mean = S.kernel == 0 ? acc / (double)S.n : 0.0;
     const double g = gE[0];
     for (int64_t i = threadIdx.x; i < S.n; i += 1024) {
         const int64_t o = perm[S.n_off + i];
@@ -1693,8 +1729,8 @@ int p2p_blocks_per_cu(int prec, int bt)
     hipError_t e = hipErrorInvalidValue;
 #define OCC(BT)                                                                                               \
     if (bt == BT)                                                                                             \
-        e = prec == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f32<BT, true>, BT, 0)   \
-                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f64<BT, true>, BT, 0);
+        e = prec == 1 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f32<BT, true, 0>, BT, 0) \
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_p2p_f64<BT, true, 0>, BT, 0);
     OCC(64)
     OCC(128)
     OCC(256)

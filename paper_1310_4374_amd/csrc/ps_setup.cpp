@@ -331,11 +331,17 @@ void SystemSetup::build_decay()
 }
 
 std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond, int basis_,
-                               int n_centres, const double* cen, int n_check, const double* chk, int periodic_)
+                               int n_centres, const double* cen, int n_check, const double* chk, int periodic_,
+                               int kernel_, double kappa_)
 {
     basis = basis_;
     if (periodic_ != 7 && periodic_ != 3) return "periodic axes must be 7 (x, y, z) or 3 (x, y)";
     if (periodic_ == 3 && basis_ != 0) return "the RBF basis is not supported with two periodic axes";
+    if (kernel_ != 0 && kernel_ != 1) return "kernel must be 0 (Coulomb) or 1 (screened)";
+    if (kernel_ == 1 && (basis_ != 1 || periodic_ != 7))
+        return "the screened kernel needs the RBF basis and three periodic axes";
+    kernel = kernel_;
+    kappa = kernel_ == 1 ? kappa_ : 0.0;
     periodic = periodic_;
     const int nper = periodic == 7 ? 3 : 2;   // axes a partner may be shifted along
     for (int k = 0; k < 3; ++k) {
@@ -349,6 +355,7 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     R0 = 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1] + box[2] * box[2]);   // step 1
     R_b = Rb > 0 ? Rb : lambda * R0;
     if (!(R_b > R0) || !std::isfinite(R_b)) return "the near radius must exceed the circumradius (lambda > 1)";
+    if (kernel == 1 && !(kappa > 0.0 && kappa * R0 <= 64.0)) return "kappa must lie in (0, 64 / R0]";
     thr = R_b * R_b * (1.0 + 1e-12);
     if (rcond <= 0) rcond = 1e-13;
 
@@ -448,8 +455,9 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 const double* c = &centres[static_cast<size_t>(j) * 3];
                 const double a0 = y[0] - c[0], a1 = y[1] - c[1], a2 = y[2] - c[2];
                 const double b0 = t[0] - c[0], b1 = t[1] - c[1], b2 = t[2] - c[2];
+                const double ra = std::sqrt(a0 * a0 + a1 * a1 + a2 * a2), rb = std::sqrt(b0 * b0 + b1 * b1 + b2 * b2);
                 A[static_cast<size_t>(j) * Lf + l] =
-                    1.0 / std::sqrt(a0 * a0 + a1 * a1 + a2 * a2) - 1.0 / std::sqrt(b0 * b0 + b1 * b1 + b2 * b2);
+                    kernel == 1 ? std::exp(-kappa * ra) / ra - std::exp(-kappa * rb) / rb : 1.0 / ra - 1.0 / rb;
             }
         } else {
             rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
@@ -490,6 +498,7 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     // (App. C), or tensor Gauss-Legendre with N_q = floor((p-1)/2) + 1 nodes (App. B)
     if (basis == 1) {
         box_means.assign(P, 0.0);
+        if (kernel == 1) return std::string();   // no constant to fix: nothing uses the box integrals
         box_means[0] = 1.0;
         for (int t = 1; t < P; ++t) {
             const double* c = &centres[static_cast<size_t>(t - 1) * 3];
@@ -572,6 +581,8 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
     put(out, static_cast<int32_t>(images.size() / 3));
     put(out, static_cast<int32_t>(centres.size() / 3));
     put(out, static_cast<int32_t>(periodic));
+    put(out, static_cast<int32_t>(kernel));
+    put(out, kappa);
     put_vec(out, yc);
     put_vec(out, yt);
     put_vec(out, pinv);
@@ -582,17 +593,20 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
 
 std::string SystemSetup::deserialize(const unsigned char* data, size_t size, size_t& pos)
 {
-    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0, per = 0;
+    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0, per = 0, ker = 0;
+    double kap = 0.0;
     bool ok = true;
     for (int k = 0; k < 3; ++k) ok = ok && get(data, size, pos, box[k]);
     ok = ok && get(data, size, pos, b) && get(data, size, pos, R0) && get(data, size, pos, R_b) &&
          get(data, size, pos, thr) && get(data, size, pos, V0) && get(data, size, pos, p_) &&
          get(data, size, pos, P_) && get(data, size, pos, L_) && get(data, size, pos, rank_) &&
          get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M) &&
-         get(data, size, pos, per);
+         get(data, size, pos, per) && get(data, size, pos, ker) && get(data, size, pos, kap);
     if (!ok) return "truncated system record";
     if (per != 7 && per != 3) return "bad periodic axes";
     if (per == 3 && b != 0) return "the RBF basis is not supported with two periodic axes";
+    if (ker != 0 && ker != 1) return "bad kernel";
+    if (ker == 1 && (b != 1 || per != 7 || !(kap > 0.0) || !std::isfinite(kap))) return "bad screened-kernel record";
     for (int k = 0; k < 3; ++k)
         if (!(box[k] > 0.0) || !std::isfinite(box[k])) return "bad box lengths";
     if (b != 0 && b != 1) return "bad basis";
@@ -609,6 +623,9 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
     L = L_;
     rank = rank_;
     periodic = per;
+    kernel = ker;
+    kappa = ker == 1 ? kap : 0.0;
+    if (kernel == 1 && !(kappa * R0 <= 64.0)) return "kappa out of range";
     build_decay();
     if (rows() < P - 1) return "bad check-point count";
     const size_t l3 = static_cast<size_t>(L) * 3;

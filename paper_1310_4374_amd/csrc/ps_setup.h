@@ -56,10 +56,14 @@ struct SystemSetup {
     std::vector<double> dec_w;         // [m^2] quadrature weights (sum 1), shared by both planes
     std::vector<double> dec_rows;      // [n_dec * 5]: kx, ky, |k|, s (+1 top, -1 bottom), trig (0 cos, 1 sin)
     int rows() const { return L + n_dec; }   // rows of the fit (columns of pinv)
+    // Kernel: 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (RBF basis, three periodic
+    // axes; no constant basis function to fix: box_means stay zero).
+    int kernel = 0;
+    double kappa = 0;
     // Returns an empty string on success, or the reason for failure.
     std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
                       int n_centres = 0, const double* centres = nullptr, int n_check = 0,
-                      const double* check_points = nullptr, int periodic = 7);
+                      const double* check_points = nullptr, int periodic = 7, int kernel = 0, double kappa = 0);
     // The slab's decay planes and rows (a function of box, p and R0 alone).
     void build_decay();
     // Binary form of the set data (little-endian scalars and arrays; the

@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened]
 """
 import os
 import sys
@@ -165,6 +165,17 @@ def table3():
 
 
 TABLE3_CASES = ((1.3, 34), (1.5, 25), (1.7, 19))
+
+
+def screened():
+    """The screened-kernel workload (workloads.config_screened) at its sampled particles."""
+    from oracle.screened import ScreenedPlan
+    c = W.config_screened()
+    pl = ScreenedPlan(c["box"], c["kappa"], c["centres"], c["p"], lam=c["lam"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save("ref_screened.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"],
+          n_near=parts["n_near"])
 
 
 if __name__ == "__main__":

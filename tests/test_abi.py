@@ -34,9 +34,12 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layout_matches_header():
     """The ctypes mirror of ps_params has the C layout (no torch types cross)."""
-    assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8 + 8
+    assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8 \
+        + 4 + 4 + 8
     assert _lib.ps_params.n_max.offset == 64
     assert _lib.ps_params.periodic.offset == 120
+    assert _lib.ps_params.kernel.offset == 124 and _lib.ps_params.kappa.offset == 128
+    assert ctypes.sizeof(_lib.ps_plan_info) == 112 and _lib.ps_plan_info.kappa.offset == 96
 
 
 def _params(**kw):
@@ -75,6 +78,24 @@ def test_null_arguments_rejected():
     assert L.periodic_sum_forward_epoch(None, ctypes.byref(e)) == _lib.PS_E_INVALID
     assert L.periodic_sum_energy_vjp(None, 10, *([None] * 4), None, *([None] * 4), 1, 0, None) == _lib.PS_E_INVALID
     L.periodic_sum_destroy(None)
+
+
+def test_screened_kernel_parameters_checked_on_host():
+    """Unknown kernel, the screened kernel without the RBF basis or on a slab,
+    and kappa outside (0, 64/R0] are refused before any device work."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    cen = (ctypes.c_double * 3)(2.0, 0.0, 0.0)
+    dp = ctypes.cast(cen, ctypes.POINTER(ctypes.c_double))
+    cases = [(dict(kernel=2), _lib.PS_E_INVALID),
+             (dict(kernel=1, kappa=1.0), _lib.PS_E_UNSUPPORTED),
+             (dict(kernel=1, kappa=1.0, basis=1, n_centres=1, centres=dp, periodic=3), _lib.PS_E_UNSUPPORTED),
+             (dict(kernel=1, kappa=0.0, basis=1, n_centres=1, centres=dp), _lib.PS_E_INVALID),
+             (dict(kernel=1, kappa=-1.0, basis=1, n_centres=1, centres=dp), _lib.PS_E_INVALID),
+             (dict(kernel=1, kappa=1e3, basis=1, n_centres=1, centres=dp), _lib.PS_E_INVALID)]
+    for kw, status in cases:
+        assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == status, kw
+        assert h.value is None
 
 
 @pytest.mark.parametrize("kw", [dict(R_b=0.5), dict(R_b=0.0, lambda_=0.9)])
@@ -122,11 +143,11 @@ def test_plan_file_with_valid_checksum_but_bad_contents_is_refused(tmp_path):
     whose system record claims p = 99 is refused with PS_E_IO."""
     import struct
     L = _lib.lib()
-    head = b"PSPLAN01" + struct.pack("<Iiid", 2, 1, 256, 1.0)
+    head = b"PSPLAN01" + struct.pack("<Iiid", 3, 1, 256, 1.0)
     prm = struct.pack("<3didd", 1.0, 1.0, 1.0, 99, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
-        + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7)
+        + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<id", 0, 0.0)
     setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) + struct.pack("<4id", 99, 99 * 99, 10, 5, 1.0) \
-        + struct.pack("<iii", 1, 0, 7)
+        + struct.pack("<iii", 1, 0, 7) + struct.pack("<id", 0, 0.0)
     body = head + prm + setup
     f = tmp_path / "bad_p.plan"
     f.write_bytes(body + struct.pack("<Q", _fnv1a64(body)))
@@ -144,11 +165,12 @@ def test_plan_file_with_bad_image_list_is_refused(tmp_path):
     p, P, Lc = 2, 4, 6
 
     def plan_file(images):
-        head = b"PSPLAN01" + struct.pack("<Iiid", 2, 1, 256, 1.0)
+        head = b"PSPLAN01" + struct.pack("<Iiid", 3, 1, 256, 1.0)
         prm = struct.pack("<3didd", 1.0, 1.0, 1.0, p, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
-            + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7)
+            + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<id", 0, 0.0)
         setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) \
-            + struct.pack("<4id", p, P, Lc, P - 1, 1.0) + struct.pack("<iii", len(images), 0, 7)
+            + struct.pack("<4id", p, P, Lc, P - 1, 1.0) + struct.pack("<iii", len(images), 0, 7) \
+            + struct.pack("<id", 0, 0.0)
         arrays = struct.pack("<%dd" % (2 * 3 * Lc + (P - 1) * Lc + P), *([0.1] * (2 * 3 * Lc + (P - 1) * Lc + P)))
         arrays += struct.pack("<%di" % (3 * len(images)), *[v for im in images for v in im])
         body = head + prm + setup + arrays

@@ -94,6 +94,20 @@ def config3(n=1_000_000, nblob=64, nsub=2000):
     return dict(box=d, x=x, q=q, p=20, lam=1.5, subset=sub)
 
 
+def config_screened(n=100_000, nsub=2000):
+    """Screened-kernel workload (exp(-kappa r)/r, kappa = 2): N uniform in the unit
+    cube, Gaussian charges plus 0.05 (a net charge, which this kernel allows),
+    the kernel at M = 256 Thomson centres on the sphere of radius 1.5 R0,
+    R0 = |d|/2, as the basis (eq. (5)); p = 16 sets the Gauss check grid."""
+    g = rng(6)
+    d = np.array([1.0, 1.0, 1.0])
+    x = wrap((g.random((n, 3)) - 0.5) * d, d)
+    q = g.standard_normal(n) + 0.05
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    centres = thomson_points(256, 1.5 * 0.5 * float(np.linalg.norm(d)))
+    return dict(box=d, x=x, q=q, p=16, lam=1.5, kappa=2.0, centres=centres, subset=sub)
+
+
 def config4(nsys=512, nmin=200, nmax=20000):
     g = rng(4)
     systems = []
