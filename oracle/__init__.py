@@ -22,6 +22,10 @@ Parts:
   * ``screened`` -- the method for the screened Coulomb kernel exp(-kappa r)/r
     (the paper's "other kernels", Sec. 1) with the kernel-at-centres basis of
     eq. (5), and an independent Ewald-type split of its periodic sum;
+  * ``wire``    -- the method with the periodic extension along x only (Sec. 1,
+    closing paragraph), completed by decay rows on a cylinder around the
+    box that fix the far field's Fourier modes (K_m Bessel and rho^-m
+    decay), and a brute-force row sum with Richardson extrapolation;
   * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
 
 Pins (tests/test_oracle_*.py): the basis against an independent assembly from
@@ -39,5 +43,10 @@ splitting parameter and Gauss's law; the slab method against that Ewald sum
 translation invariance; the screened direct sums against the modified Helmholtz
 equation, finite differences and the Coulomb limit; the screened split against
 its splitting parameter and brute-force lattice sums; the screened method
-against that split, periodicity and translation invariance.
+against that split, periodicity and translation invariance; the wire row sum
+against its K_0 Fourier series (Poisson summation along x), the exact
+potential against the decay rows, the periodicity rows' exact null space
+(rho^m e^{i m theta}), and the wire method against the row sum (thin and long
+cells, charges next to the cylinder, a transverse dipole), x periodicity and
+translation invariance along x.
 """
