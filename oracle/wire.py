@@ -48,7 +48,7 @@ Reading (every step is the 3-D method's unless stated):
 import math
 
 import numpy as np
-from scipy.special import kv, kvp
+from scipy.special import kve
 
 from . import _native
 from .basis import basis as basis_fn
@@ -80,11 +80,14 @@ def wire_near_set(x, q, box, R_b):
 
 
 def decay_beta(k, m, rho):
-    """d/drho log of the decaying radial factor of mode (k, m) at rho."""
+    """d/drho log of the decaying radial factor of mode (k, m) at rho:
+    k K_m'(k rho) / K_m(k rho), with K_m' = -(K_{m-1} + K_{m+1}) / 2 and the
+    exponentially scaled K (the scale cancels), so that thin periods (k rho in
+    the hundreds, where K itself underflows) stay finite."""
     if k == 0.0:
         return -m / rho
     z = k * rho
-    return k * kvp(m, z) / kv(m, z)
+    return -k * (kve(abs(m - 1), z) + kve(m + 1, z)) / (2.0 * kve(m, z))
 
 
 class WirePlan:

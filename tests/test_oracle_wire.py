@@ -12,10 +12,10 @@ periodicity in x and translation invariance along x.
 import math
 
 import numpy as np
-from scipy.special import k0, k1
+from scipy.special import k0, k1, kv, kvp
 
 import workloads as W
-from oracle.wire import WirePlan, line_sum, wire_near_set
+from oracle.wire import WirePlan, decay_beta, line_sum, wire_near_set
 
 BOX = np.array([1.0, 1.2, 0.8])
 
@@ -72,6 +72,19 @@ def test_brute_force_row_sum_equals_the_fourier_series():
     pf, ff = _fourier_row(x, q, BOX[0], y)
     assert _worst(pb - pb.mean(), pf - pf.mean()) < 1e-8
     assert _worst(fb, ff) < 1e-8
+
+
+def test_decay_ratio_against_the_bessel_derivative_and_its_asymptote():
+    """k K_m'(k rho)/K_m(k rho) against scipy's K_m and K_m' where they are finite,
+    and against the large-argument expansion -1 - 1/(2z) - (4m^2 - 1)/(8z^2) where
+    K_m underflows; k = 0 gives -m/rho."""
+    for z in (0.01, 0.3, 2.0, 20.0, 100.0):
+        for m in (0, 1, 5, 39):
+            assert abs(decay_beta(z, m, 1.0) / (z * kvp(m, z) / kv(m, z)) - 1.0) < 1e-14
+    for m in (0, 1, 2):
+        z = 2000.0
+        assert abs(decay_beta(z, m, 1.0) / z - (-1.0 - 0.5 / z - (4 * m * m - 1) / (8 * z * z))) < 1e-9
+    assert decay_beta(0.0, 3, 0.5) == -6.0
 
 
 def test_exact_potential_satisfies_the_decay_rows():
