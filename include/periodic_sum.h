@@ -123,7 +123,17 @@ typedef struct {
                              mode k = 2 pi (n1/d1, n2/d2), |n1|, |n2| <= ceil(p/4) + 1, satisfies
                              <(d/dz + s|k|) phi, trig(k.rho)> = 0 (s = +1 above, -1 below; k = 0 is
                              Gauss's law), by m x m Gauss-Legendre points per plane,
-                             m = max(2p + 8, ceil(40 max(d1, d2) / R0)).  Spherical basis only. */
+                             m = max(2p + 8, ceil(40 max(d1, d2) / R0)).  1 = x only (a wire, y and z
+                             free): images along x only; the Gauss check points with |y_1| > d1/2,
+                             partners along x; decay rows on the cylinder rho = rho_d around the x axis,
+                             rho_d = |(d2, d3)|/2 + R0/10 (rho, theta polar in the y-z plane): outside it
+                             each Fourier mode (k = 2 pi n/d1, m) of the potential is the decaying one,
+                             so <(d/drho - beta) phi, trig(k x) trig(m theta)> = 0 for n = 0..ceil(p/4)+1,
+                             m = 0..p-1, with beta = k K_m'(k rho_d)/K_m(k rho_d) for n > 0 and -m/rho_d
+                             for n = 0, by mx Gauss-Legendre points in x, mx = max(2p + 8,
+                             ceil(40 d1 / R0)), times mt equispaced angles, mt = max(4p,
+                             ceil(80 pi rho_d / R0)).  With fewer than three axes: spherical basis,
+                             Coulomb kernel; the exact adjoint is not available. */
     int32_t kernel;       /* ps_kernel (PS_KERNEL_COULOMB when zero-initialised) */
     double  kappa;        /* PS_KERNEL_SCREENED: the screening constant, 0 < kappa <= 64 / R0 */
 } ps_params;
@@ -142,8 +152,8 @@ typedef struct {
                                  graph launches of the batched path never record events */
     int64_t forward_epoch;    /* count of "get" passes enqueued or launched on this plan (eval, energy,
                                  batched eval); the pass the plan's workspace holds last */
-    int32_t periodic;         /* periodic axes of system 0 (7 or 3) */
-    int32_t n_rows;           /* rows of system 0's fit: L periodicity rows, then (slab) the decay rows */
+    int32_t periodic;         /* periodic axes of system 0 (7, 3 or 1) */
+    int32_t n_rows;           /* rows of system 0's fit: L periodicity rows, then (slab, wire) the decay rows */
     double  kappa;            /* screening constant (0 for the Coulomb kernel) */
     int32_t kernel;           /* ps_kernel of the plan (every system of a batch shares it) */
     int32_t reserved;

@@ -13,7 +13,7 @@ from ._lib import check, lib, ps_params, ps_plan_info, ps_select_row
 
 _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
-_PERIODIC = {"xyz": 7, "xy": 3}
+_PERIODIC = {"xyz": 7, "xy": 3, "x": 1}
 _KERNEL = {"coulomb": 0, "screened": 1}
 
 
@@ -30,7 +30,7 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
             tile_targets=0, n_split=0, centres=None, check_points=None, keep=None, periodic="xyz", kernel="coulomb",
             kappa=0.0):
     """keep: a list that receives the host arrays the struct points to.
-    periodic: "xyz" (three periodic axes) or "xy" (a slab, z free).
+    periodic: "xyz" (three periodic axes), "xy" (a slab, z free) or "x" (a wire, y and z free).
     kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r; needs centres)."""
     prm = ps_params()
     for k in range(3):
@@ -113,7 +113,8 @@ class Plan:
         """centres: (M, 3) RBF centres outside the box (eq. (5)); None for the
         spherical-harmonic basis.  check_points: (L, 3) points on the
         circumsphere; None for the Gauss spherical grid.  periodic: "xyz", or
-        "xy" for a slab (periodic in x and y, vacuum above and below).
+        "xy" for a slab (periodic in x and y, vacuum above and below), or "x" for
+        a wire (periodic in x, vacuum around it).
         kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r, any net charge,
         RBF centres required, no constant term)."""
         self.device = torch.device("cuda", device)

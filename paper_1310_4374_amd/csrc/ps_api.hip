@@ -101,7 +101,7 @@ struct EventPair {
 };
 
 constexpr int kEvRing = 16;         // profiled evals whose stage events are kept until read
-constexpr int kDecayBt = 256;       // targets per workgroup of the slab decay-plane sums
+constexpr int kDecayBt = 256;       // targets per workgroup of the decay-surface sums
 constexpr int kItemTarget = 8192;   // batched pair sums: aim for this many workgroups
 constexpr int kCheckWaveTarget = 16384;  // check-point sums of one system: aim for this many waves
 constexpr int kMaxSplit = 256;
@@ -122,7 +122,7 @@ struct Tables {                     // per-shape item tables (depend on the part
     std::vector<TItem> t_items;
     std::vector<PItem> chk_items, p_items, f_items, d_items;
     std::vector<PJob> jobs;         // [0, nsys): check jobs; [nsys, 2 nsys): particle jobs; [2 nsys, 3 nsys): RBF far jobs;
-                                    // [3 nsys, 4 nsys): slab decay-plane jobs
+                                    // [3 nsys, 4 nsys): decay-surface jobs (slab, wire)
     std::vector<PJob> jobs_s;       // the same jobs with their partial sums in the static scratch
     bool scratch_fits = false;      // jobs_s is valid: the partial sums fit in kScratchDoubles
     int64_t scratch_need = 0;       // doubles of partial sums one eval writes
@@ -194,8 +194,8 @@ struct ps_plan_s {
     PItem *d_chk_items = nullptr, *d_p_items = nullptr, *d_f_items = nullptr;
     PJob* d_jobs = nullptr;
     PJob* d_jobs_s = nullptr;           // jobs whose partial sums live in the static scratch
-    // slab (two periodic axes): decay planes and rows
-    bool any_slab = false;
+    // fewer than three periodic axes (slab, wire): decay surfaces and rows
+    bool any_decay = false;
     int max_dec = 0;                    // most decay rows of any system
     int64_t dec_tot = 0;                // decay-plane points over all systems
     double *d_dpts = nullptr, *d_dw = nullptr, *d_drows = nullptr;
@@ -297,6 +297,9 @@ static_assert(sizeof(ps_params) == 136 && offsetof(ps_params, periodic) == 120 &
               "ps_params layout");
 static_assert(sizeof(ps_plan_info) == 112 && offsetof(ps_plan_info, kappa) == 96, "ps_plan_info layout");
 
+// The periodic-axes mask of a parameter block as the set phase takes it (0 means 7).
+int periodic_axes(int32_t periodic) { return periodic == 0 ? 7 : periodic; }
+
 ps_status check_params(const ps_params* prm)
 {
     if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
@@ -313,13 +316,13 @@ ps_status check_params(const ps_params* prm)
     if (prm->basis == PS_BASIS_RBF && (prm->n_centres < 1 || prm->n_centres > 4096 || !prm->centres))
         return fail(PS_E_INVALID, "the RBF basis needs 1..4096 centres");
     if (prm->n_check < 0 || (prm->n_check > 0 && !prm->check_points)) return fail(PS_E_INVALID, "bad check-point arguments");
-    if (prm->periodic != 0 && prm->periodic != 7 && prm->periodic != 3)
-        return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z) or 3 (x, y)");
-    if (prm->periodic == 3 && prm->basis == PS_BASIS_RBF)
-        return fail(PS_E_UNSUPPORTED, "the RBF basis is not supported with two periodic axes");
+    if (prm->periodic != 0 && prm->periodic != 7 && prm->periodic != 3 && prm->periodic != 1)
+        return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z), 3 (x, y) or 1 (x)");
+    if (periodic_axes(prm->periodic) != 7 && prm->basis == PS_BASIS_RBF)
+        return fail(PS_E_UNSUPPORTED, "the RBF basis needs three periodic axes");
     if (prm->kernel != PS_KERNEL_COULOMB && prm->kernel != PS_KERNEL_SCREENED)
         return fail(PS_E_INVALID, "unknown kernel %d", prm->kernel);
-    if (prm->kernel == PS_KERNEL_SCREENED && (prm->basis != PS_BASIS_RBF || prm->periodic == 3))
+    if (prm->kernel == PS_KERNEL_SCREENED && (prm->basis != PS_BASIS_RBF || periodic_axes(prm->periodic) != 7))
         return fail(PS_E_UNSUPPORTED, "the screened kernel needs the RBF basis and three periodic axes");
     for (int k = 0; k < 3; ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
@@ -478,7 +481,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     const bool separate = m > 0;
     const int bt = pl->bt;
     // jobs: check-point sums (potential only), then particle sums, then RBF far
-    // fields, then the slab decay-plane sums (potential and field)
+    // fields, then the decay-surface sums (potential and field)
     T.jobs.resize(4 * nsys);
     int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
     struct Est { int64_t ntb, nbexp; };
@@ -666,7 +669,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         }
     }
     if (pf_off > pl->part_far_cap) { why = "far-field partial workspace too small"; return false; }
-    // slab decay planes: near sums with the field at the 2 m^2 plane points
+    // decay surfaces (slab planes, wire cylinder): near sums with the field at their points
     int64_t pd_off = 0, tb_d_off = 0;
     for (int s = 0; s < nsys; ++s) {
         const SysDev& S = T.sys[s];
@@ -680,7 +683,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         D.tx = pl->d_dpts + S.dec_off;
         D.ty = pl->d_dpts + pl->dec_tot + S.dec_off;
         D.tz = pl->d_dpts + 2 * pl->dec_tot + S.dec_off;
-        D.nt = 2 * static_cast<int64_t>(S.m2);
+        D.nt = static_cast<int64_t>(S.nsurf) * S.m2;
         D.sx = C.sx;
         D.sy = C.sy;
         D.sz = C.sz;
@@ -717,7 +720,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T.np = T.p_items.size();
     // the same jobs with the partial-sum layout in the static scratch
     // (periodic_sum_eval_noalloc): check partials first, then the particle partials
-    T.scratch_fits = pl->d_scratch && !pl->any_rbf && !pl->any_slab && T.scratch_need <= kScratchDoubles;
+    T.scratch_fits = pl->d_scratch && !pl->any_rbf && !pl->any_decay && T.scratch_need <= kScratchDoubles;
     T.jobs_s = T.jobs;
     if (T.scratch_fits) {
         const int64_t pc_tot = T.scratch_need - pp_off;
@@ -815,7 +818,7 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
         launch_chk_f32(pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
     else
         launch_p2p(0, pl->bt_chk, false, pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
-    if (T.nd > 0) {  // slab: near sums at the decay planes, then the decay rows of f
+    if (T.nd > 0) {  // fewer than three periodic axes: near sums at the decay surfaces, then the decay rows of f
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, 0, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
         launch_decay_rhs(nsys, pl->max_dec, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot, pl->d_dw, pl->d_drows,
                          pl->d_f, st);
@@ -933,7 +936,7 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     for (int s = 0; s < nsys; ++s)
         errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
                                       prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points,
-                                      prm[s].periodic == 3 ? 3 : 7, prm[0].kernel, prm[0].kappa);
+                                      periodic_axes(prm[s].periodic), prm[0].kernel, prm[0].kappa);
     for (int s = 0; s < nsys; ++s)
         if (!errs[s].empty()) {
             delete pl;
@@ -959,14 +962,15 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.periodic = su.periodic;
         S.Lf = su.rows();
         S.ndec = su.n_dec;
-        S.m2 = su.m * su.m;
+        S.m2 = su.npts;
+        S.nsurf = su.nsurf;
         S.dec_off = dec_tot;
         S.dw_off = dw_tot;
         S.drow_off = drow_tot;
-        dec_tot += 2 * static_cast<int64_t>(S.m2);
+        dec_tot += static_cast<int64_t>(S.nsurf) * S.m2;
         dw_tot += S.m2;
         drow_tot += 5 * static_cast<int64_t>(S.ndec);
-        pl->any_slab = pl->any_slab || su.n_dec > 0;
+        pl->any_decay = pl->any_decay || su.n_dec > 0;
         pl->max_dec = std::max(pl->max_dec, su.n_dec);
         pl->n_max[s] = prm[s].n_max;
         for (int k = 0; k < 3; ++k) {
@@ -1083,7 +1087,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
             }
         }
         std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
-        for (int64_t k = 0; k < 2 * static_cast<int64_t>(S.m2); ++k)
+        for (int64_t k = 0; k < static_cast<int64_t>(S.nsurf) * S.m2; ++k)
             for (int c = 0; c < 3; ++c) h_dpts[c * dec_tot + S.dec_off + k] = su.dec_pts[k * 3 + c];
         std::copy(su.dec_w.begin(), su.dec_w.end(), h_dw.begin() + S.dw_off);
         std::copy(su.dec_rows.begin(), su.dec_rows.end(), h_drows.begin() + S.drow_off);
@@ -1116,12 +1120,12 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
                                               nsys);
         nt_sum += nt;
     }
-    {   // slab decay planes: target blocks, items, partials (the split count grows with n, so n_max bounds it)
+    {   // decay surfaces: target blocks, items, partials (the split count grows with n, so n_max bounds it)
         int64_t tb_d = 0, items_d = 0, part_d = 0;
         for (int s = 0; s < nsys; ++s) {
             const SysDev& S = pl->base[s];
             if (S.ndec == 0) continue;
-            const int64_t nt = 2 * static_cast<int64_t>(S.m2);
+            const int64_t nt = static_cast<int64_t>(S.nsurf) * S.m2;
             const int64_t ntb = (nt + kDecayBt - 1) / kDecayBt;
             const int sp = check_splits(ntb, kDecayBt / 64,
                                         static_cast<int64_t>(near_expected(pl->setups[s], prm[s].n_max) / kTile) + 1,
@@ -1367,7 +1371,7 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
         const std::string why = setups[s].deserialize(buf.data(), buf.size(), pos);
         if (!why.empty()) return fail(PS_E_IO, "%s: system %d: %s", path, s, why.c_str());
         const SystemSetup& su = setups[s];
-        if (q.p != su.p || q.basis != su.basis || (q.periodic == 3 ? 3 : 7) != su.periodic ||
+        if (q.p != su.p || q.basis != su.basis || periodic_axes(q.periodic) != su.periodic ||
             q.kernel != su.kernel || (su.kernel == 1 && q.kappa != su.kappa) || q.kernel != prm[0].kernel ||
             q.kappa != prm[0].kappa)
             return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
@@ -1436,7 +1440,7 @@ ps_status periodic_sum_eval_noalloc(ps_plan pl, int64_t n, const double* x, cons
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_INVALID, "batched plan: the allocation-free eval takes single-system plans");
-    if (pl->any_rbf || pl->any_slab)
+    if (pl->any_rbf || pl->any_decay)
         return fail(PS_E_UNSUPPORTED, "the allocation-free eval covers the spherical basis with three periodic axes");
     if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max=%lld]", (long long)n, (long long)pl->n_max[0]);
     if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
@@ -1836,7 +1840,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
     if (exact && S.ndec > 0)
-        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with two periodic axes (exact = 0 is)");
+        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with fewer than three periodic axes (exact = 0 is)");
     if (exact && pl->kernel == PS_KERNEL_SCREENED)
         return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the screened kernel (exact = 0 is)");
     if (exact) {

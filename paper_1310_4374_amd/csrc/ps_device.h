@@ -62,13 +62,16 @@ struct SysDev {
     int mr[3], mcorner;          // box mean by corners: image ranges |i_k| <= mr[k]; 1 if used
     int64_t imap_off;            // dense image map over the ranges (image index or -1)
     int64_t mitem_off, mitem_n;  // this system's workgroups of the corner box mean
-    int periodic;                // periodic axes: 7 (x, y, z) or 3 (x, y: a slab)
-    int Lf;                      // rows of the fit: L periodicity rows, then ndec decay rows (slab)
-    int ndec, m2;                // slab: decay rows; points per decay plane (two planes, top first)
-    int64_t dec_off;             // slab: decay-plane points in the packed SoA arrays (2 m2 per system)
-    int64_t dw_off;              // slab: their quadrature weights (m2, shared by both planes)
-    int64_t drow_off;            // slab: decay rows, 5 doubles each (kx, ky, |k|, s, trig)
-    int kernel, pad2;            // 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (no neutrality, no C1)
+    int periodic;                // periodic axes: 7 (x, y, z), 3 (x, y: a slab) or 1 (x: a wire)
+    int Lf;                      // rows of the fit: L periodicity rows, then ndec decay rows (slab, wire)
+    int ndec, m2;                // decay rows; points per decay surface (slab: two planes, top first;
+                                 // wire: one cylinder, x-major)
+    int64_t dec_off;             // decay-surface points in the packed SoA arrays (nsurf m2 per system)
+    int64_t dw_off;              // their quadrature weights (m2, shared by the surfaces)
+    int64_t drow_off;            // decay rows, 5 doubles each (slab: kx, ky, |k|, s, trig;
+                                 // wire: k, m, beta, trig in x, trig in theta)
+    int kernel, nsurf;           // kernel: 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (no neutrality, no C1);
+                                 // nsurf: decay surfaces (2 slab, 1 wire, 0 otherwise)
     double kappa;                // screening constant (screened kernel)
 };
 

@@ -980,9 +980,12 @@ __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, co
     }
 }
 
-// Slab decay rows (two periodic axes): f[L + r] = <(E_z - s|k| phi_near) trig(k.rho)>
-// over decay plane s, i.e. -<(d phi_near/dz + s|k| phi_near) trig(k.rho)>, from the
-// split partials of the near sums at the plane points (potential and field).
+// Decay rows (fewer than three periodic axes), from the split partials of the
+// near sums at the decay-surface points (potential and field E = -grad phi):
+//   slab: f[L + r] = <(E_z - s|k| phi_near) trig(k.rho)> over decay plane s,
+//         i.e. -<(d phi_near/dz + s|k| phi_near) trig(k.rho)>;
+//   wire: f[L + r] = <(E_rho + beta phi_near) trig(k x) trig(m theta)> over the
+//         cylinder, i.e. -<(d phi_near/drho - beta phi_near) trig(k x) trig(m theta)>.
 // One workgroup per (row, system); fixed-order reduction.
 __global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ djobs,
                                                    const double* __restrict__ dpts, int64_t dec_tot,
@@ -995,6 +998,33 @@ __global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sy
     if (r >= S.ndec) return;  // uniform over the workgroup
     const PJob& J = djobs[blockIdx.y];
     const double* row = drows + S.drow_off + (int64_t)r * 5;
+    if (S.periodic == 1) {
+        const double k = row[0], mm = row[1], beta = row[2];
+        const bool sin_x = row[3] != 0.0, sin_t = row[4] != 0.0;
+        const double* px = dpts + S.dec_off;
+        const double* py = dpts + dec_tot + S.dec_off;
+        const double* pz = dpts + 2 * dec_tot + S.dec_off;
+        double acc = 0.0;
+        for (int i = threadIdx.x; i < S.m2; i += 256) {
+            double phi = 0.0, ey = 0.0, ez = 0.0;
+            for (int sp = 0; sp < J.nsplit; ++sp) {
+                const double* P_ = J.part + (int64_t)sp * 4 * J.nt;
+                phi += P_[i];
+                ey += P_[2 * J.nt + i];
+                ez += P_[3 * J.nt + i];
+            }
+            const double th = atan2(pz[i], py[i]);
+            double st, ct;
+            sincos(th, &st, &ct);
+            const double erho = ey * ct + ez * st;
+            const double tx = sin_x ? sin(k * px[i]) : cos(k * px[i]);
+            const double tt = sin_t ? sin(mm * th) : cos(mm * th);
+            acc = __builtin_fma(dw[S.dw_off + i] * (tx * tt), erho + beta * phi, acc);
+        }
+        acc = block_reduce<0>(acc, sh);
+        if (threadIdx.x == 0) fout[S.f_off + S.L + r] = acc;
+        return;
+    }
     const double kx = row[0], ky = row[1], kk = row[2], sg = row[3];
     const bool use_sin = row[4] != 0.0;
     const int plane = sg > 0.0 ? 0 : 1;

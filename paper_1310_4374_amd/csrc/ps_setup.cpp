@@ -82,6 +82,42 @@ void Recurrence::eval_dz(double x, double y, double z, double* out, double* dout
     }
 }
 
+void Recurrence::eval_dir(double x, double y, double z, double u, double v, double w, double* out, double* dout) const
+{
+    const double r2 = x * x + y * y + z * z;
+    const double dr2 = 2.0 * (x * u + y * v + z * w);
+    double dA = 1.0, dB = 0.0, gA = 0.0, gB = 0.0;   // diagonal R^_m^{+-m} and their derivatives
+    for (int m = 0; m < p; ++m) {
+        if (m > 0) {
+            const double nA = -c[m] * (x * dA + y * dB);
+            const double nB = c[m] * (y * dA - x * dB);
+            const double ngA = -c[m] * (u * dA + x * gA + v * dB + y * gB);
+            const double ngB = c[m] * (v * dA + y * gA - u * dB - x * gB);
+            dA = nA;
+            dB = nB;
+            gA = ngA;
+            gB = ngB;
+        }
+        for (int s = 0; s < (m ? 2 : 1); ++s) {
+            const int mm = s ? -m : m;
+            double prev2 = 0.0, prev1 = s ? dB : dA, dprev2 = 0.0, dprev1 = s ? gB : gA;
+            out[m * m + m + mm] = prev1;
+            dout[m * m + m + mm] = dprev1;
+            for (int n = m + 1; n < p; ++n) {
+                const int t = n * n + n + mm;
+                const double val = -a[t] * z * prev1 - b[t] * r2 * prev2;
+                const double dv = -a[t] * (w * prev1 + z * dprev1) - b[t] * (dr2 * prev2 + r2 * dprev2);
+                out[t] = val;
+                dout[t] = dv;
+                prev2 = prev1;
+                prev1 = val;
+                dprev2 = dprev1;
+                dprev1 = dv;
+            }
+        }
+    }
+}
+
 // Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1], ascending:
 // Newton's method on P_n evaluated by the three-term recurrence.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
@@ -292,18 +328,95 @@ void pseudo_inverse(int L, int n, std::vector<double> A, double rcond, std::vect
 
 }  // namespace
 
+namespace {
+
+// exp(z) K_nu(z) for nu = 0, 1 and z > 0, from K_nu(z) = int_0^inf exp(-z cosh t) cosh(nu t) dt
+// by the trapezoidal rule (exponentially convergent for this analytic, even
+// integrand; the step shrinks as 1/sqrt(z) where the integrand narrows).
+void scaled_bessel_k01(double z, double& k0, double& k1)
+{
+    const double h = std::min(0.1, 0.4 / std::sqrt(z));
+    double s0 = 0.5, s1 = 0.5;   // the t = 0 terms, half weight
+    for (int i = 1; i < 100000; ++i) {
+        const double t = i * h, sh = std::sinh(0.5 * t);
+        const double e = std::exp(-2.0 * z * sh * sh);   // exp(-z (cosh t - 1))
+        s0 += e;
+        s1 += e * std::cosh(t);
+        if (e * std::cosh(t) < 1e-20 * s0 && t > 1.0) break;
+    }
+    k0 = h * s0;
+    k1 = h * s1;
+}
+
+// beta_m = k K_m'(k rho) / K_m(k rho), m = 0..p-1, for k > 0: the ratio
+// u_m = K_{m+1}/K_m grows by the (stable, upward) recurrence
+// u_m = 1/u_{m-1} + 2m/z, and K_m' = -K_{m-1} - (m/z) K_m, K_0' = -K_1.
+void decay_betas(double k, double rho, int p, std::vector<double>& beta)
+{
+    const double z = k * rho;
+    double k0, k1;
+    scaled_bessel_k01(z, k0, k1);
+    beta.assign(p, 0.0);
+    double u = k1 / k0;   // K_1 / K_0
+    beta[0] = -k * u;
+    for (int m = 1; m < p; ++m) {
+        beta[m] = k * (-1.0 / u - m / z);
+        u = 1.0 / u + 2.0 * m / z;
+    }
+}
+
+}  // namespace
+
 void SystemSetup::build_decay()
 {
     dec_pts.clear();
     dec_w.clear();
     dec_rows.clear();
-    n_dec = nk = m = 0;
-    zd = 0.0;
+    n_dec = nk = m = mx = mt = nsurf = npts = 0;
+    zd = rho_d = 0.0;
     if (periodic == 7) return;
     const double h = R0 / 10.0;
-    zd = 0.5 * box[2] + h;
     nk = (p + 3) / 4 + 1;
+    if (periodic == 1) {
+        // wire: the cylinder rho = rho_d over one period, mx Gauss-Legendre points
+        // in x times mt equispaced angles; rows over n = 0..nk, m = 0..p-1
+        rho_d = std::hypot(0.5 * box[1], 0.5 * box[2]) + h;
+        mx = std::max(2 * p + 8, static_cast<int>(std::ceil(4.0 * box[0] / h)));
+        mt = std::max(4 * p, static_cast<int>(std::ceil(8.0 * M_PI * rho_d / h)));
+        nsurf = 1;
+        npts = mx * mt;
+        std::vector<double> g, w;
+        gauss_legendre(mx, g, w);
+        dec_w.resize(static_cast<size_t>(npts));
+        dec_pts.resize(static_cast<size_t>(npts) * 3);
+        for (int i = 0; i < mx; ++i)
+            for (int j = 0; j < mt; ++j) {
+                const size_t k = static_cast<size_t>(i) * mt + j;
+                const double th = 2.0 * M_PI * j / mt;
+                dec_w[k] = w[i] / 2.0 * (1.0 / mt);
+                dec_pts[k * 3 + 0] = 0.5 * box[0] * g[i];
+                dec_pts[k * 3 + 1] = rho_d * std::cos(th);
+                dec_pts[k * 3 + 2] = rho_d * std::sin(th);
+            }
+        std::vector<double> beta;
+        for (int n = 0; n <= nk; ++n) {
+            const double k = 2.0 * M_PI * n / box[0];
+            if (n > 0) decay_betas(k, rho_d, p, beta);
+            for (int mm = 0; mm < p; ++mm) {
+                const double b = n > 0 ? beta[mm] : -mm / rho_d;
+                for (int tx = 0; tx < (n == 0 ? 1 : 2); ++tx)
+                    for (int tt = 0; tt < (mm == 0 ? 1 : 2); ++tt)
+                        dec_rows.insert(dec_rows.end(),
+                                        {k, static_cast<double>(mm), b, static_cast<double>(tx), static_cast<double>(tt)});
+            }
+        }
+        n_dec = static_cast<int>(dec_rows.size() / 5);
+        return;
+    }
+    zd = 0.5 * box[2] + h;
     m = std::max(2 * p + 8, static_cast<int>(std::ceil(4.0 * std::max(box[0], box[1]) / h)));
+    nsurf = 2;
+    npts = m * m;
     std::vector<double> g, w;
     gauss_legendre(m, g, w);
     dec_w.resize(static_cast<size_t>(m) * m);
@@ -335,15 +448,15 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                                int kernel_, double kappa_)
 {
     basis = basis_;
-    if (periodic_ != 7 && periodic_ != 3) return "periodic axes must be 7 (x, y, z) or 3 (x, y)";
-    if (periodic_ == 3 && basis_ != 0) return "the RBF basis is not supported with two periodic axes";
+    if (periodic_ != 7 && periodic_ != 3 && periodic_ != 1) return "periodic axes must be 7 (x, y, z), 3 (x, y) or 1 (x)";
+    if (periodic_ != 7 && basis_ != 0) return "the RBF basis needs three periodic axes";
     if (kernel_ != 0 && kernel_ != 1) return "kernel must be 0 (Coulomb) or 1 (screened)";
     if (kernel_ == 1 && (basis_ != 1 || periodic_ != 7))
         return "the screened kernel needs the RBF basis and three periodic axes";
     kernel = kernel_;
     kappa = kernel_ == 1 ? kappa_ : 0.0;
     periodic = periodic_;
-    const int nper = periodic == 7 ? 3 : 2;   // axes a partner may be shifted along
+    const int nper = periodic == 7 ? 3 : (periodic == 3 ? 2 : 1);   // axes a partner may be shifted along
     for (int k = 0; k < 3; ++k) {
         if (!(bx[k] > 0.0) || !std::isfinite(bx[k])) return "box lengths must be positive and finite";
         box[k] = bx[k];
@@ -406,11 +519,13 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 y[2] = R0 * mu[a];
             }
         }
-        if (periodic == 3) {   // a slab keeps the points that an in-plane shift moves into S0
+        if (periodic != 7) {   // keep the points that a shift along a periodic axis moves into S0
             std::vector<double> kept;
             for (int l = 0; l < L; ++l) {
                 const double* y = &yc[static_cast<size_t>(l) * 3];
-                if (std::fabs(y[0]) > 0.5 * box[0] || std::fabs(y[1]) > 0.5 * box[1]) kept.insert(kept.end(), y, y + 3);
+                bool outside = false;
+                for (int k = 0; k < nper; ++k) outside = outside || std::fabs(y[k]) > 0.5 * box[k];
+                if (outside) kept.insert(kept.end(), y, y + 3);
             }
             yc.swap(kept);
             L = static_cast<int>(yc.size() / 3);
@@ -465,7 +580,55 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
             for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + l] = r1[j + 1] - r2[j + 1];
         }
     }
-    if (n_dec > 0) {
+    if (n_dec > 0 && periodic == 1) {
+        // wire decay rows: <(dR_t/drho - beta R_t) trig(k x) trig(m theta)> over the
+        // cylinder, R_t at y/R0.  Separable: first, per x node i and angular
+        // harmonic (m, trig), the angular means G_V = <trig(m theta) R_t>_theta and
+        // G_D = <trig(m theta) dR_t/drho>_theta; then each row is a sum over i.
+        const int nh = 2 * p - 1;   // angular harmonics: cos(0), then cos(m .), sin(m .) for m >= 1
+        std::vector<double> GV(static_cast<size_t>(mx) * nh * P, 0.0), GD(GV.size(), 0.0);
+#pragma omp parallel
+        {
+            std::vector<double> V(P), D(P);
+#pragma omp for schedule(dynamic, 1)
+            for (int i = 0; i < mx; ++i) {
+                double* gv = &GV[static_cast<size_t>(i) * nh * P];
+                double* gd = &GD[static_cast<size_t>(i) * nh * P];
+                for (int j = 0; j < mt; ++j) {
+                    const double* q = &dec_pts[(static_cast<size_t>(i) * mt + j) * 3];
+                    const double th = 2.0 * M_PI * j / mt;
+                    rec.eval_dir(q[0] / R0, q[1] / R0, q[2] / R0, 0.0, std::cos(th), std::sin(th), V.data(), D.data());
+                    for (int hh = 0; hh < nh; ++hh) {
+                        const int mm = (hh + 1) / 2;
+                        const double c = (hh == 0 || (hh & 1) ? std::cos(mm * th) : std::sin(mm * th)) / mt;
+                        double* a = gv + static_cast<size_t>(hh) * P;
+                        double* d = gd + static_cast<size_t>(hh) * P;
+                        for (int t = 1; t < P; ++t) {
+                            a[t] += c * V[t];
+                            d[t] += c * (D[t] / R0);
+                        }
+                    }
+                }
+            }
+        }
+        std::vector<double> gq, wq;
+        gauss_legendre(mx, gq, wq);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int r = 0; r < n_dec; ++r) {
+            const double* row = &dec_rows[static_cast<size_t>(r) * 5];
+            const int mm = static_cast<int>(row[1]);
+            const int hh = mm == 0 ? 0 : 2 * mm - 1 + static_cast<int>(row[4]);
+            std::vector<double> acc(n, 0.0);
+            for (int i = 0; i < mx; ++i) {
+                const double x = dec_pts[static_cast<size_t>(i) * mt * 3];
+                const double wt = wq[i] / 2.0 * (row[3] == 0.0 ? std::cos(row[0] * x) : std::sin(row[0] * x));
+                const double* gv = &GV[(static_cast<size_t>(i) * nh + hh) * P];
+                const double* gd = &GD[(static_cast<size_t>(i) * nh + hh) * P];
+                for (int j = 0; j < n; ++j) acc[j] += wt * (gd[j + 1] - row[2] * gv[j + 1]);
+            }
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + L + r] = acc[j];
+        }
+    } else if (n_dec > 0) {
         // decay rows: <(dR_t/dz + s|k| R_t) trig(k.rho)> over a plane, R_t at y/R0
         const int m2 = m * m;
         std::vector<double> V(static_cast<size_t>(2) * m2 * P), D(static_cast<size_t>(2) * m2 * P);
@@ -603,8 +766,8 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
          get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M) &&
          get(data, size, pos, per) && get(data, size, pos, ker) && get(data, size, pos, kap);
     if (!ok) return "truncated system record";
-    if (per != 7 && per != 3) return "bad periodic axes";
-    if (per == 3 && b != 0) return "the RBF basis is not supported with two periodic axes";
+    if (per != 7 && per != 3 && per != 1) return "bad periodic axes";
+    if (per != 7 && b != 0) return "the RBF basis needs three periodic axes";
     if (ker != 0 && ker != 1) return "bad kernel";
     if (ker == 1 && (b != 1 || per != 7 || !(kap > 0.0) || !std::isfinite(kap))) return "bad screened-kernel record";
     for (int k = 0; k < 3; ++k)

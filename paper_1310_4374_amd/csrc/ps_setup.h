@@ -24,6 +24,8 @@ struct Recurrence {
     // R^_t and dR^_t/dz (forward-mode differentiation of the same recurrence;
     // the diagonal terms do not depend on z).
     void eval_dz(double x, double y, double z, double* out, double* dout) const;
+    // R^_t and its derivative along the direction (u, v, w) (forward mode).
+    void eval_dir(double x, double y, double z, double u, double v, double w, double* out, double* dout) const;
 };
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
@@ -45,16 +47,27 @@ struct SystemSetup {
     std::vector<double> box_means;     // [P]: R_t^(0), App. B
     std::vector<int> images;           // [nimg*3] lattice integers, (0,0,0) first
     Recurrence rec;
-    // Periodic axes: 7 (x, y and z) or 3 (x and y: a slab, z free).  For a slab
-    // the fit has n_dec decay rows after the L periodicity rows: on the planes
-    // z = +-zd (zd = d3/2 + R0/10) the in-plane Fourier modes of the potential
-    // decay away from the charges, <(d/dz + s|k|) phi, trig(k.rho)> = 0.
+    // Periodic axes: 7 (x, y and z), 3 (x and y: a slab, z free) or 1 (x only: a
+    // wire, y and z free).  With fewer than three axes the fit has n_dec decay
+    // rows after the L periodicity rows, which fix the far field's modes that
+    // periodicity alone leaves free:
+    //   slab: on the planes z = +-zd (zd = d3/2 + R0/10) the in-plane Fourier
+    //     modes of the potential decay away from the charges,
+    //     <(d/dz + s|k|) phi, trig(k.rho)> = 0;
+    //   wire: on the cylinder rho = rho_d (rho_d = |(d2, d3)|/2 + R0/10) each
+    //     Fourier mode in (x, theta) is the decaying one,
+    //     <(d/drho - beta_{k,m}) phi, trig(k x) trig(m theta)> = 0,
+    //     beta = |k| K_m'(|k| rho_d) / K_m(|k| rho_d) (k != 0), -m / rho_d (k = 0).
     int periodic = 7;
-    int n_dec = 0, nk = 0, m = 0;      // decay rows, mode range |n1|,|n2| <= nk, m x m points per plane
-    double zd = 0;
-    std::vector<double> dec_pts;       // [2 m^2 * 3]: the top plane's points, then the bottom plane's
-    std::vector<double> dec_w;         // [m^2] quadrature weights (sum 1), shared by both planes
-    std::vector<double> dec_rows;      // [n_dec * 5]: kx, ky, |k|, s (+1 top, -1 bottom), trig (0 cos, 1 sin)
+    int n_dec = 0, nk = 0;             // decay rows; wave numbers 2 pi n / d, |n| <= nk
+    int m = 0;                         // slab: m x m Gauss points per plane
+    int mx = 0, mt = 0;                // wire: Gauss points along x, equispaced angles
+    int nsurf = 0, npts = 0;           // decay surfaces (2 planes, 1 cylinder), points per surface
+    double zd = 0, rho_d = 0;
+    std::vector<double> dec_pts;       // [nsurf * npts * 3]: slab top plane then bottom; wire x-major, theta minor
+    std::vector<double> dec_w;         // [npts] quadrature weights (sum 1), shared by the surfaces
+    std::vector<double> dec_rows;      // [n_dec * 5]: slab kx, ky, |k|, s (+1 top, -1 bottom), trig (0 cos, 1 sin);
+                                       // wire k, m, beta, trig in x, trig in theta
     int rows() const { return L + n_dec; }   // rows of the fit (columns of pinv)
     // Kernel: 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (RBF basis, three periodic
     // axes; no constant basis function to fix: box_means stay zero).
@@ -64,7 +77,7 @@ struct SystemSetup {
     std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
                       int n_centres = 0, const double* centres = nullptr, int n_check = 0,
                       const double* check_points = nullptr, int periodic = 7, int kernel = 0, double kappa = 0);
-    // The slab's decay planes and rows (a function of box, p and R0 alone).
+    // The decay surfaces and rows (a function of the periodic axes, box, p and R0 alone).
     void build_decay();
     // Binary form of the set data (little-endian scalars and arrays; the
     // recurrence coefficients and the decay tables are rebuilt on reading).

@@ -98,6 +98,21 @@ def test_screened_kernel_parameters_checked_on_host():
         assert h.value is None
 
 
+def test_periodic_axes_checked_on_host():
+    """Masks other than 0, 7, 3 and 1, the RBF basis with fewer than three axes
+    and the screened kernel on a wire are refused before any device work."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    cen = (ctypes.c_double * 3)(2.0, 0.0, 0.0)
+    dp = ctypes.cast(cen, ctypes.POINTER(ctypes.c_double))
+    cases = [dict(periodic=p) for p in (2, 4, 5, 6, 8, -1)]
+    cases += [dict(periodic=1, basis=1, n_centres=1, centres=dp), dict(periodic=3, basis=1, n_centres=1, centres=dp),
+              dict(periodic=1, kernel=1, kappa=1.0, basis=1, n_centres=1, centres=dp)]
+    for kw in cases:
+        assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == _lib.PS_E_UNSUPPORTED, kw
+        assert h.value is None
+
+
 @pytest.mark.parametrize("kw", [dict(R_b=0.5), dict(R_b=0.0, lambda_=0.9)])
 def test_near_radius_must_exceed_circumradius(kw):
     L = _lib.lib()
