@@ -154,7 +154,8 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="skip the uniform-cube figures of the default line")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--workload", default="clustered",
-                    choices=["clustered", "cube", "screened", "batch", "rocksalt", "bases", "aspect", "small", "select"],
+                    choices=["clustered", "cube", "screened", "slab", "wire", "batch", "rocksalt", "bases", "aspect",
+                             "small", "select"],
                     help="clustered (default): the headline solve; the others measure the uniform cube, the "
                          "batched, differentiated and paper-table workloads")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -178,7 +179,8 @@ def main():
         del a, b
     if args.workload not in ("clustered", "cube"):
         out = {"screened": bench_screened, "batch": bench_batch, "rocksalt": bench_rocksalt, "bases": bench_bases,
-               "aspect": bench_aspect, "small": bench_small, "select": bench_select}[args.workload](args)
+               "aspect": bench_aspect, "small": bench_small, "select": bench_select,
+               "slab": lambda a: bench_partial(a, "xy"), "wire": lambda a: bench_partial(a, "x")}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "cube":
@@ -323,6 +325,45 @@ def bench_screened(args):
                                  "k_p2p_%s<%d,field,screened>" % ("f32" if f32 else "f64", info["tile_targets"]),
                                  None, FLOP_PER_PAIR_SCREENED),
             "stage_ms": st, "accuracy": acc}
+
+
+def bench_partial(args, periodic):
+    """The uniform-cube workload with fewer periodic axes (workloads.config_partial):
+    a slab ("xy") or a wire ("x"), N = 100,000, p = 16, lambda = 1.5.  The check
+    stage includes the near sums at the decay surfaces and the decay rows."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config_partial(periodic)
+    n = len(c["q"])
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
+    q = torch.tensor(c["q"], device=dev)
+    t_set = time.perf_counter()
+    plan = ps.Plan(c["box"], c["p"], lam=c["lam"], precision=args.precision, n_max=n, periodic=periodic,
+                   tile_targets=args.tile_targets)
+    t_set = time.perf_counter() - t_set
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    steps = max(20, 2 * args.steps)
+    ms, st = timed_solves(plan, x, q, phi, field, steps, max(3, args.warmup))
+    info = plan.info()
+    nb, L = info["n_near_last"], info["L"]
+    pairs_per_step = (n + 2 * L) * nb
+    name = {"xy": "slab", "x": "wire"}[periodic]
+    acc = accuracy(phi, field, ["ref_%s.npz" % name])
+    f32 = args.precision == "fp32"
+    shape = {"xy": "slab (x, y periodic, z free)", "x": "wire (x periodic, y, z free)"}[periodic]
+    return {"metric": METRIC, "value": pairs_per_step / (ms * 1e-3), "unit": "pair interactions/s",
+            "n_gpus": 1, "steps": steps, "warmup": max(3, args.warmup), "ms_per_step": ms, "solves_per_s": 1e3 / ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64",
+            "data": "synthetic (seeded uniform positions, Gaussian charges minus their mean)",
+            "config": {"workload": "%s, unit cube, N=100000, q~N(0,1)-mean, p=16, lambda=1.5" % shape,
+                       "N": n, "p": c["p"], "L": L, "n_rows": info["n_rows"], "n_images": info["n_images"],
+                       "n_near": nb, "pairs_per_solve": pairs_per_step},
+            "roofline": roofline(args.precision, n, nb, st["pairs"],
+                                 "k_p2p_%s<%d,field>" % ("f32" if f32 else "f64", info["tile_targets"]), None),
+            "stage_ms": st, "set_s": t_set, "accuracy": acc}
 
 
 def _rel(a, b):

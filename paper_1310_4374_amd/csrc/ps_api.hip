@@ -199,6 +199,8 @@ struct ps_plan_s {
     int max_dec = 0;                    // most decay rows of any system
     int64_t dec_tot = 0;                // decay-plane points over all systems
     double *d_dpts = nullptr, *d_dw = nullptr, *d_drows = nullptr;
+    double* d_dfield = nullptr;         // 3 x dec_tot: decay-surface near sums reduced over splits
+    int64_t max_dpts = 0;               // most decay-surface points of any system
     double *d_part_dec = nullptr, *d_tblk_dec = nullptr;
     int64_t part_dec_cap = 0, tblk_dec_cap = 0, cap_d = 0;
     PItem* d_d_items = nullptr;
@@ -820,8 +822,8 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
         launch_p2p(0, pl->bt_chk, false, pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
     if (T.nd > 0) {  // fewer than three periodic axes: near sums at the decay surfaces, then the decay rows of f
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, 0, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
-        launch_decay_rhs(nsys, pl->max_dec, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot, pl->d_dw, pl->d_drows,
-                         pl->d_f, st);
+        launch_decay_rhs(nsys, pl->max_dec, pl->max_dpts, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot,
+                         pl->d_dfield, pl->d_dw, pl->d_drows, pl->d_f, st);
     }
     mark(4);
     launch_solve(nsys, pl->maxL, pl->maxP, pl->d_sys, cjobs, pl->d_chk_slot, pl->d_pinv, pl->d_coef, pl->d_f, st);  // steps 4-5
@@ -972,6 +974,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         drow_tot += 5 * static_cast<int64_t>(S.ndec);
         pl->any_decay = pl->any_decay || su.n_dec > 0;
         pl->max_dec = std::max(pl->max_dec, su.n_dec);
+        pl->max_dpts = std::max<int64_t>(pl->max_dpts, static_cast<int64_t>(su.nsurf) * su.npts);
         pl->n_max[s] = prm[s].n_max;
         for (int k = 0; k < 3; ++k) {
             S.box[k] = su.box[k];
@@ -1087,9 +1090,20 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
             }
         }
         std::copy(su.pinv.begin(), su.pinv.end(), h_pinv.begin() + S.pinv_off);
-        for (int64_t k = 0; k < static_cast<int64_t>(S.nsurf) * S.m2; ++k)
-            for (int c = 0; c < 3; ++c) h_dpts[c * dec_tot + S.dec_off + k] = su.dec_pts[k * 3 + c];
-        std::copy(su.dec_w.begin(), su.dec_w.end(), h_dw.begin() + S.dw_off);
+        if (S.nsurf > 0) {
+            // kd order of the first surface's points (the slab's two planes share their
+            // x/y layout and weights): each 256-target block of the decay-surface sums is
+            // a compact patch, so most sources are far from its centre (cheaper pairs)
+            const std::vector<double> first(su.dec_pts.begin(), su.dec_pts.begin() + 3 * static_cast<size_t>(S.m2));
+            const std::vector<int> ord = check_order(first, kDecayBt);
+            for (int sf = 0; sf < S.nsurf; ++sf)
+                for (int k = 0; k < S.m2; ++k) {
+                    const size_t src = static_cast<size_t>(sf) * S.m2 + ord[k];
+                    const int64_t dst = S.dec_off + static_cast<int64_t>(sf) * S.m2 + k;
+                    for (int c = 0; c < 3; ++c) h_dpts[c * dec_tot + dst] = su.dec_pts[src * 3 + c];
+                }
+            for (int k = 0; k < S.m2; ++k) h_dw[S.dw_off + k] = su.dec_w[ord[k]];
+        }
         std::copy(su.dec_rows.begin(), su.dec_rows.end(), h_drows.begin() + S.drow_off);
         std::copy(su.box_means.begin(), su.box_means.end(), h_bm.begin() + S.bm_off);
         if (su.basis == 1) {
@@ -1208,6 +1222,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_jobs_s, 4 * nsys)
     AL(pl->d_dpts, 3 * std::max<int64_t>(1, dec_tot))
     AL(pl->d_dw, std::max<int64_t>(1, dw_tot))
+    AL(pl->d_dfield, 3 * std::max<int64_t>(1, dec_tot))
     AL(pl->d_drows, std::max<int64_t>(1, drow_tot))
     AL(pl->d_part_dec, std::max<int64_t>(1, pl->part_dec_cap))
     AL(pl->d_tblk_dec, 4 * std::max<int64_t>(1, pl->tblk_dec_cap))

@@ -22,8 +22,9 @@ void launch_p2p(int prec, int bt, bool field, int kern, int64_t nitems, const PJ
                 hipStream_t st);
 // FP32 check-point sums (potential only); every job has 64-target blocks and ncomp = 1.
 void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st);
-void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
-                      const double* dw, const double* drows, double* f, hipStream_t st);
+// dfield: 3 x dec_tot scratch for the decay-surface near sums reduced over splits
+void launch_decay_rhs(int nsys, int maxdec, int64_t maxpts, const SysDev* sys, const PJob* djobs, const double* dpts,
+                      int64_t dec_tot, double* dfield, const double* dw, const double* drows, double* f, hipStream_t st);
 // slot[chk_off + k]: position of check target k of a system in its check job
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const int* slot,
                   const double* pinv, double* coef, double* f, hipStream_t st);

@@ -980,15 +980,47 @@ __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, co
     }
 }
 
-// Decay rows (fewer than three periodic axes), from the split partials of the
-// near sums at the decay-surface points (potential and field E = -grad phi):
+// Near sums at the decay-surface points, reduced once over the source splits
+// (in split order) so that the rows below read two or three values per point
+// instead of re-reading every split for every row:
+//   dfield[0][i] = phi_near, dfield[1][i] = the normal field (slab: E_z; wire:
+//   E_rho = E_y cos(theta) + E_z sin(theta)), dfield[2][i] = theta (wire).
+__global__ __launch_bounds__(256) void k_decay_fields(const SysDev* __restrict__ sys, const PJob* __restrict__ djobs,
+                                                      const double* __restrict__ dpts, int64_t dec_tot,
+                                                      double* __restrict__ dfield)
+{
+    const SysDev& S = sys[blockIdx.y];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (S.ndec == 0 || i >= (int64_t)S.nsurf * S.m2) return;
+    const PJob& J = djobs[blockIdx.y];
+    double phi = 0.0, ey = 0.0, ez = 0.0;
+    for (int sp = 0; sp < J.nsplit; ++sp) {
+        const double* P_ = J.part + (int64_t)sp * 4 * J.nt;
+        phi += P_[i];
+        ey += P_[2 * J.nt + i];
+        ez += P_[3 * J.nt + i];
+    }
+    double en = ez, th = 0.0;
+    if (S.periodic == 1) {
+        th = atan2(dpts[2 * dec_tot + S.dec_off + i], dpts[dec_tot + S.dec_off + i]);
+        double st, ct;
+        sincos(th, &st, &ct);
+        en = ey * ct + ez * st;
+    }
+    dfield[S.dec_off + i] = phi;
+    dfield[dec_tot + S.dec_off + i] = en;
+    dfield[2 * dec_tot + S.dec_off + i] = th;
+}
+
+// Decay rows (fewer than three periodic axes), from the reduced near sums at the
+// decay-surface points (potential and field E = -grad phi):
 //   slab: f[L + r] = <(E_z - s|k| phi_near) trig(k.rho)> over decay plane s,
 //         i.e. -<(d phi_near/dz + s|k| phi_near) trig(k.rho)>;
 //   wire: f[L + r] = <(E_rho + beta phi_near) trig(k x) trig(m theta)> over the
 //         cylinder, i.e. -<(d phi_near/drho - beta phi_near) trig(k x) trig(m theta)>.
 // One workgroup per (row, system); fixed-order reduction.
-__global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ djobs,
-                                                   const double* __restrict__ dpts, int64_t dec_tot,
+__global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sys, const double* __restrict__ dpts,
+                                                   int64_t dec_tot, const double* __restrict__ dfield,
                                                    const double* __restrict__ dw, const double* __restrict__ drows,
                                                    double* __restrict__ fout)
 {
@@ -996,52 +1028,31 @@ __global__ __launch_bounds__(256) void k_decay_rhs(const SysDev* __restrict__ sy
     const SysDev& S = sys[blockIdx.y];
     const int r = blockIdx.x;
     if (r >= S.ndec) return;  // uniform over the workgroup
-    const PJob& J = djobs[blockIdx.y];
     const double* row = drows + S.drow_off + (int64_t)r * 5;
+    const double* px = dpts + S.dec_off;
+    const double* fphi = dfield + S.dec_off;
+    const double* fn = dfield + dec_tot + S.dec_off;
+    double acc = 0.0;
     if (S.periodic == 1) {
         const double k = row[0], mm = row[1], beta = row[2];
         const bool sin_x = row[3] != 0.0, sin_t = row[4] != 0.0;
-        const double* px = dpts + S.dec_off;
-        const double* py = dpts + dec_tot + S.dec_off;
-        const double* pz = dpts + 2 * dec_tot + S.dec_off;
-        double acc = 0.0;
+        const double* fth = dfield + 2 * dec_tot + S.dec_off;
         for (int i = threadIdx.x; i < S.m2; i += 256) {
-            double phi = 0.0, ey = 0.0, ez = 0.0;
-            for (int sp = 0; sp < J.nsplit; ++sp) {
-                const double* P_ = J.part + (int64_t)sp * 4 * J.nt;
-                phi += P_[i];
-                ey += P_[2 * J.nt + i];
-                ez += P_[3 * J.nt + i];
-            }
-            const double th = atan2(pz[i], py[i]);
-            double st, ct;
-            sincos(th, &st, &ct);
-            const double erho = ey * ct + ez * st;
             const double tx = sin_x ? sin(k * px[i]) : cos(k * px[i]);
-            const double tt = sin_t ? sin(mm * th) : cos(mm * th);
-            acc = __builtin_fma(dw[S.dw_off + i] * (tx * tt), erho + beta * phi, acc);
+            const double tt = sin_t ? sin(mm * fth[i]) : cos(mm * fth[i]);
+            acc = __builtin_fma(dw[S.dw_off + i] * (tx * tt), fn[i] + beta * fphi[i], acc);
         }
-        acc = block_reduce<0>(acc, sh);
-        if (threadIdx.x == 0) fout[S.f_off + S.L + r] = acc;
-        return;
-    }
-    const double kx = row[0], ky = row[1], kk = row[2], sg = row[3];
-    const bool use_sin = row[4] != 0.0;
-    const int plane = sg > 0.0 ? 0 : 1;
-    const double* px = dpts + S.dec_off;
-    const double* py = dpts + dec_tot + S.dec_off;
-    double acc = 0.0;
-    for (int k = threadIdx.x; k < S.m2; k += 256) {
-        const int64_t i = (int64_t)plane * S.m2 + k;
-        double phi = 0.0, ez = 0.0;
-        for (int sp = 0; sp < J.nsplit; ++sp) {
-            const double* P_ = J.part + (int64_t)sp * 4 * J.nt;
-            phi += P_[i];
-            ez += P_[3 * J.nt + i];
+    } else {
+        const double kx = row[0], ky = row[1], kk = row[2], sg = row[3];
+        const bool use_sin = row[4] != 0.0;
+        const int plane = sg > 0.0 ? 0 : 1;
+        const double* py = dpts + dec_tot + S.dec_off;
+        for (int k = threadIdx.x; k < S.m2; k += 256) {
+            const int64_t i = (int64_t)plane * S.m2 + k;
+            const double ph = kx * px[i] + ky * py[i];
+            const double tr = use_sin ? sin(ph) : cos(ph);
+            acc = __builtin_fma(dw[S.dw_off + k] * tr, fn[i] - sg * kk * fphi[i], acc);
         }
-        const double ph = kx * px[i] + ky * py[i];
-        const double tr = use_sin ? sin(ph) : cos(ph);
-        acc = __builtin_fma(dw[S.dw_off + k] * tr, ez - sg * kk * phi, acc);
     }
     acc = block_reduce<0>(acc, sh);
     if (threadIdx.x == 0) fout[S.f_off + S.L + r] = acc;
@@ -1487,11 +1498,13 @@ void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* ite
     else
         PS_LAUNCH((k_chk_f32<kChkWaves, 0>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
 }
-void launch_decay_rhs(int nsys, int maxdec, const SysDev* sys, const PJob* djobs, const double* dpts, int64_t dec_tot,
-                      const double* dw, const double* drows, double* f, hipStream_t st)
+void launch_decay_rhs(int nsys, int maxdec, int64_t maxpts, const SysDev* sys, const PJob* djobs, const double* dpts,
+                      int64_t dec_tot, double* dfield, const double* dw, const double* drows, double* f, hipStream_t st)
 {
     if (maxdec <= 0) return;
-    PS_LAUNCH(k_decay_rhs, dim3(maxdec, nsys), dim3(256), 0, st, sys, djobs, dpts, dec_tot, dw, drows, f);
+    PS_LAUNCH(k_decay_fields, dim3(static_cast<unsigned>((maxpts + 255) / 256), nsys), dim3(256), 0, st, sys, djobs,
+              dpts, dec_tot, dfield);
+    PS_LAUNCH(k_decay_rhs, dim3(maxdec, nsys), dim3(256), 0, st, sys, dpts, dec_tot, dfield, dw, drows, f);
 }
 void launch_solve(int nsys, int maxL, int maxP, const SysDev* sys, const PJob* cjobs, const int* slot,
                   const double* pinv, double* coef, double* f, hipStream_t st)

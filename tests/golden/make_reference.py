@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened slab wire]
 """
 import os
 import sys
@@ -176,6 +176,26 @@ def screened():
     parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
     _save("ref_screened.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"],
           n_near=parts["n_near"])
+
+
+def _partial(periodic, name):
+    from oracle.slab import SlabPlan
+    from oracle.wire import WirePlan
+    c = W.config_partial(periodic)
+    pl = (SlabPlan if periodic == "xy" else WirePlan)(c["box"], c["p"], lam=c["lam"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save(name, subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
+
+
+def slab():
+    """The slab workload (workloads.config_partial("xy")) at its sampled particles."""
+    _partial("xy", "ref_slab.npz")
+
+
+def wire():
+    """The wire workload (workloads.config_partial("x")) at its sampled particles."""
+    _partial("x", "ref_wire.npz")
 
 
 if __name__ == "__main__":

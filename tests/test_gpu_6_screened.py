@@ -137,3 +137,17 @@ def test_screened_plan_file_and_gradients(ps, tmp_path):
     assert abs(float(e.item()) - 0.5 * float(q @ phi0.cpu().numpy())) < 1e-10 * abs(float(e.item()))
     with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
         pl.energy_vjp(X, Q, one, exact=True)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_screened_full_size_workload(ps, prec):
+    """The benchmark's screened workload (N = 100,000, kappa = 2, 256 centres,
+    p = 16, the default launch shape it times): 2,000 sampled particles against
+    the oracle's stored values (tests/golden/ref_screened.npz), near-set size exact."""
+    from gpu_common import golden
+    c = W.config_screened()
+    ref = golden("ref_screened.npz")
+    pl, phi, field = _solve(ps, c["box"], c["p"], c["x"], c["q"], prec, c["kappa"], c["centres"], lam=c["lam"])
+    sub = ref["subset"]
+    assert pl.info()["n_near_last"] == int(ref["n_near"])
+    assert err(phi[sub], ref["phi"]) <= TOL[prec] and err(field[sub], ref["field"]) <= TOL[prec]

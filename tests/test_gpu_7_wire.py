@@ -136,3 +136,17 @@ def test_wire_plan_file_and_adjoint_modes(ps, tmp_path):
     with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
         pl.energy_vjp(X, Q, one, exact=True)
     del e
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_wire_full_size_workload(ps, prec):
+    """The benchmark's wire workload (N = 100,000, p = 16, lambda = 1.5, the
+    default launch shape it times): 2,000 sampled particles against the oracle's
+    stored values (tests/golden/ref_wire.npz), near-set size exact."""
+    from gpu_common import golden
+    c = W.config_partial("x")
+    ref = golden("ref_wire.npz")
+    pl, phi, field = _wire(ps, c["box"], c["p"], c["x"], c["q"], prec, lam=c["lam"])
+    sub = ref["subset"]
+    assert pl.info()["n_near_last"] == int(ref["n_near"])
+    assert err(phi[sub], ref["phi"]) <= TOL[prec] and err(field[sub], ref["field"]) <= TOL[prec]

@@ -108,6 +108,18 @@ def config_screened(n=100_000, nsub=2000):
     return dict(box=d, x=x, q=q, p=16, lam=1.5, kappa=2.0, centres=centres, subset=sub)
 
 
+def config_partial(periodic, n=100_000, nsub=2000):
+    """The uniform-cube workload with fewer periodic axes: "xy" (a slab, z free)
+    or "x" (a wire, y and z free).  N uniform in the unit cube, Gaussian charges
+    minus their mean, p = 16, lambda = 1.5."""
+    g = rng({"xy": 7, "x": 8}[periodic])
+    d = np.array([1.0, 1.0, 1.0])
+    x = wrap((g.random((n, 3)) - 0.5) * d, d)
+    q = _neutral_gauss(g, n)
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    return dict(box=d, x=x, q=q, p=16, lam=1.5, periodic=periodic, subset=sub)
+
+
 def config4(nsys=512, nmin=200, nmax=20000):
     g = rng(4)
     systems = []
