@@ -26,6 +26,10 @@ Parts:
     closing paragraph), completed by decay rows on a cylinder around the
     box that fix the far field's Fourier modes (K_m Bessel and rho^-m
     decay), and a brute-force row sum with Richardson extrapolation;
+  * ``twod``    -- the method in two dimensions (Sec. 1: it applies to 2-D problems)
+    for K = -log r: harmonic-polynomial basis, check points on the
+    circumcircle, the uniform-rectangle box mean; an independent 2-D Ewald
+    split, the Jacobi theta-function closed form and brute-force squares;
   * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
 
 Pins (tests/test_oracle_*.py): the basis against an independent assembly from
@@ -48,5 +52,9 @@ against its K_0 Fourier series (Poisson summation along x), the exact
 potential against the decay rows, the periodicity rows' exact null space
 (rho^m e^{i m theta}), and the wire method against the row sum (thin and long
 cells, charges next to the cylinder, a transverse dipole), x periodicity and
-translation invariance along x.
+translation invariance along x; the 2-D basis against closed forms, harmonicity
+and differences, the rectangle potential against quadrature and its Laplacian,
+the 2-D Ewald split against its parameter, the theta-function closed form and
+brute-force squares of images, and the 2-D method against Ewald (other cells,
+a strong dipole, targets on particles), periodicity and translation invariance.
 """

@@ -40,6 +40,7 @@ def lib():
         _lib.orc_direct_screened.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, dp, dp, dp, dp]
         _lib.orc_ewald_screened_real.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, D, D,
                                                  dp, dp, dp, dp]
+        _lib.orc_direct_log2d.argtypes = [L, dp, dp, L, dp, dp, dp, L, dp, dp, dp, dp, dp]
     return _lib
 
 
@@ -135,3 +136,23 @@ def ewald_screened_real(targets, sources, q, shifts, kappa, alpha, rcut):
                                   px.size, _p(px), _p(py), _p(pz), float(kappa), float(alpha), float(rcut),
                                   _p(phi), *(_p(a) for a in g))
     return phi, np.stack(g, axis=1)
+
+
+def direct_log2d(targets, sources, q, shifts=None, grad=True):
+    """Two dimensions: phi(y) = sum_p sum_j q_j (-log |y - x_j - p|) (K(0) = 0) over
+    the given 2-D shifts (default: none, the free-space sum), and grad phi.
+    targets, sources: (n, 2)."""
+    t = np.asarray(targets, dtype=np.float64)
+    s = np.asarray(sources, dtype=np.float64)
+    sh = np.zeros((1, 2)) if shifts is None else np.asarray(shifts, dtype=np.float64)
+    tx, ty = (np.ascontiguousarray(t[:, k]) for k in range(2))
+    sx, sy = (np.ascontiguousarray(s[:, k]) for k in range(2))
+    px, py = (np.ascontiguousarray(sh[:, k]) for k in range(2))
+    sq = np.ascontiguousarray(q, dtype=np.float64)
+    n = tx.size
+    phi = np.zeros(n)
+    g = [np.zeros(n) for _ in range(2)] if grad else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    lib().orc_direct_log2d(n, _p(tx), _p(ty), sx.size, _p(sx), _p(sy), _p(sq), px.size, _p(px), _p(py), _p(phi),
+                           *(tuple(_p(a) for a in g) if grad else (null, null)))
+    return (phi, np.stack(g, axis=1)) if grad else phi

@@ -231,3 +231,36 @@ void orc_ewald_screened_real(long nt, const double* tx, const double* ty, const 
         if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Two dimensions: K(r) = -log r (the Green's function of the 2-D Laplacian, */
+/* up to 2 pi), K(0) = 0.  grad_y K(y - x) = -(y - x) / r^2.                 */
+
+/* phi(y) = sum_m sum_j q_j K(y - x_j - p_m) over a list of 2-D shifts p_m (one
+ * zero shift gives the free-space finite sum), and grad phi; gx may be NULL. */
+void orc_direct_log2d(long nt, const double* tx, const double* ty,
+                      long ns, const double* sx, const double* sy, const double* sq,
+                      long nimg, const double* px, const double* py,
+                      double* phi, double* gx, double* gy)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nt; ++i) {
+        acc_t p = {0, 0}, ax = {0, 0}, ay = {0, 0};
+        for (long m = 0; m < nimg; ++m) {
+            const double yx = tx[i] - px[m], yy = ty[i] - py[m];
+            for (long j = 0; j < ns; ++j) {
+                double dx = yx - sx[j], dy = yy - sy[j];
+                double r2 = dx * dx + dy * dy;
+                if (r2 == 0.0) continue;
+                acc_add(&p, -0.5 * sq[j] * log(r2));
+                if (gx) {
+                    double g = sq[j] / r2;
+                    acc_add(&ax, -g * dx);
+                    acc_add(&ay, -g * dy);
+                }
+            }
+        }
+        phi[i] = acc_get(&p);
+        if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); }
+    }
+}
