@@ -136,6 +136,19 @@ typedef struct {
                              Coulomb kernel; the exact adjoint is not available. */
     int32_t kernel;       /* ps_kernel (PS_KERNEL_COULOMB when zero-initialised) */
     double  kappa;        /* PS_KERNEL_SCREENED: the screening constant, 0 < kappa <= 64 / R0 */
+    int32_t dim;          /* 0 or 3: three dimensions.  2: the method in the plane (Sec. 1 says it applies to
+                             2-D problems): charges at (x, y) in the d1 x d2 rectangle (box[2] is ignored),
+                             periodic along x and y, kernel K(r) = -log r (the 2-D Coulomb kernel; kernel must be
+                             PS_KERNEL_COULOMB), neutral charges.  R0 = |(d1, d2)|/2; near set = images
+                             (i d1, j d2) in the disc R_b; basis 1, Re w^n, Im w^n, w = (x + iy)/R0,
+                             n = 1..p-1 (P = 2p - 1), 2 <= p <= 128; L = 4p check points equispaced on the
+                             circumcircle (theta_l = 2 pi l / L; n_check must be 0), partners as in 3-D over
+                             the two axes; C1 from the zero box mean with the closed-form potential of a
+                             uniform rectangle.  z and target z pointers may be NULL (they are not read);
+                             ez outputs, when given, receive zeros.  Spherical basis (meaning the plane's
+                             harmonic polynomials) only; periodic must be 0, 7 or 3; the exact adjoint is
+                             not available. */
+    int32_t reserved;     /* 0 */
 } ps_params;
 
 typedef struct {
@@ -156,7 +169,7 @@ typedef struct {
     int32_t n_rows;           /* rows of system 0's fit: L periodicity rows, then (slab, wire) the decay rows */
     double  kappa;            /* screening constant (0 for the Coulomb kernel) */
     int32_t kernel;           /* ps_kernel of the plan (every system of a batch shares it) */
-    int32_t reserved;
+    int32_t dim;              /* 3, or 2 for a plan in the plane (every system of a batch shares it) */
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
@@ -269,7 +282,7 @@ ps_status periodic_sum_plan_batched(int32_t nsys, const ps_params* prm, int devi
  * parameters, check points and partners, A^+, the box integrals R_t^(0), the
  * image list and the RBF centres, plus the plan's tuned launch shape.  Nothing
  * of the last eval is saved.  Format: little-endian binary, "PSPLAN01" magic,
- * version 3, a 64-bit FNV-1a checksum of all preceding bytes at the end.
+ * version 4, a 64-bit FNV-1a checksum of all preceding bytes at the end.
  *   path: host string, a file path; an existing file is replaced.
  * Errors: PS_E_INVALID (NULL plan or path), PS_E_IO (the file could not be
  * written completely). */

@@ -35,7 +35,8 @@ class ps_params(ctypes.Structure):
                 ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32), ("basis", ctypes.c_int32),
                 ("n_centres", ctypes.c_int32), ("centres", ctypes.POINTER(ctypes.c_double)),
                 ("n_check", ctypes.c_int32), ("check_points", ctypes.POINTER(ctypes.c_double)),
-                ("periodic", ctypes.c_int32), ("kernel", ctypes.c_int32), ("kappa", ctypes.c_double)]
+                ("periodic", ctypes.c_int32), ("kernel", ctypes.c_int32), ("kappa", ctypes.c_double),
+                ("dim", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class ps_plan_info(ctypes.Structure):
@@ -44,7 +45,7 @@ class ps_plan_info(ctypes.Structure):
                 ("n_near_last", ctypes.c_int64), ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32),
                 ("nsys", ctypes.c_int32), ("mean_corners", ctypes.c_int32), ("profiled_evals", ctypes.c_int64),
                 ("forward_epoch", ctypes.c_int64), ("periodic", ctypes.c_int32), ("n_rows", ctypes.c_int32),
-                ("kappa", ctypes.c_double), ("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("kappa", ctypes.c_double), ("kernel", ctypes.c_int32), ("dim", ctypes.c_int32)]
 
 
 class ps_select_row(ctypes.Structure):

@@ -28,12 +28,13 @@ def _host_points(a):
 
 def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
             tile_targets=0, n_split=0, centres=None, check_points=None, keep=None, periodic="xyz", kernel="coulomb",
-            kappa=0.0):
+            kappa=0.0, dim=3):
     """keep: a list that receives the host arrays the struct points to.
     periodic: "xyz" (three periodic axes), "xy" (a slab, z free) or "x" (a wire, y and z free).
-    kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r; needs centres)."""
+    kernel: "coulomb" (1/r; -log r in the plane) or "screened" (exp(-kappa r)/r; needs centres).
+    dim: 3, or 2 for the method in the plane (box (d1, d2))."""
     prm = ps_params()
-    for k in range(3):
+    for k in range(len(box) if int(dim) == 2 else 3):
         prm.box[k] = float(box[k])
     prm.p = int(p)
     prm.R_b = float(R_b) if R_b is not None else 0.0
@@ -48,6 +49,7 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
     prm.periodic = _PERIODIC[periodic] if isinstance(periodic, str) else int(periodic)
     prm.kernel = _KERNEL[kernel] if isinstance(kernel, str) else int(kernel)
     prm.kappa = float(kappa)
+    prm.dim = int(dim)
     dp = ctypes.POINTER(ctypes.c_double)
     if centres is not None:
         c = _host_points(centres)
@@ -67,15 +69,24 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _soa(x, device):
-    """(3, N) or (N, 3) float64 positions -> contiguous (3, N) on the device."""
-    if x.dim() != 2 or 3 not in x.shape:
-        raise ValueError("positions must be (3, N) or (N, 3)")
-    if x.shape[0] != 3 or (x.shape[1] == 3 and not x.is_contiguous()):
+def _soa(x, device, dim=3):
+    """(3, N) or (N, 3) float64 positions -> contiguous (3, N) on the device.
+    dim 2 (the plane): (2, N) or (N, 2) -> contiguous (2, N); a (3, N) or (N, 3)
+    array gives its first two coordinates."""
+    rows = (2, 3) if dim == 2 else (3,)
+    if x.dim() != 2 or not any(r in x.shape for r in rows):
+        r = "2|3" if dim == 2 else "3"
+        raise ValueError("positions must be (%s, N) or (N, %s)" % (r, r))
+    if x.shape[0] not in rows or (x.shape[1] in rows and not x.is_contiguous()):
         x = x.t()
     if x.dtype != torch.float64 or x.device != device:
         raise ValueError("positions must be float64 on %s" % device)
-    return x.contiguous()
+    return x[:dim].contiguous()
+
+
+def _xyz(x):
+    """Pointers to the coordinate rows; None for z in the plane."""
+    return [_ptr(x[0]), _ptr(x[1]), _ptr(x[2]) if x.shape[0] > 2 else None]
 
 
 def _vec(t, n, device, name):
@@ -91,12 +102,12 @@ def _vec(t, n, device, name):
     return t.reshape(n).contiguous()
 
 
-def _field_out(t, n, device, name):
-    """A (3, n) float64 device output whose rows are contiguous."""
+def _field_out(t, n, device, name, rows=3):
+    """A (rows, n) float64 device output whose rows are contiguous."""
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device != device:
         raise ValueError("%s must be a float64 tensor on %s" % (name, device))
-    if tuple(t.shape) != (3, n) or not t.is_contiguous():
-        raise ValueError("%s must be a contiguous (3, %d) tensor" % (name, n))
+    if tuple(t.shape) != (rows, n) or not t.is_contiguous():
+        raise ValueError("%s must be a contiguous (%d, %d) tensor" % (name, rows, n))
     return t
 
 
@@ -109,18 +120,20 @@ class Plan:
 
     def __init__(self, box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-13, n_max=1, m_max=0,
                  tile_targets=0, n_split=0, centres=None, check_points=None, periodic="xyz", kernel="coulomb",
-                 kappa=0.0, device=0):
+                 kappa=0.0, dim=3, device=0):
         """centres: (M, 3) RBF centres outside the box (eq. (5)); None for the
         spherical-harmonic basis.  check_points: (L, 3) points on the
         circumsphere; None for the Gauss spherical grid.  periodic: "xyz", or
         "xy" for a slab (periodic in x and y, vacuum above and below), or "x" for
         a wire (periodic in x, vacuum around it).
         kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r, any net charge,
-        RBF centres required, no constant term)."""
+        RBF centres required, no constant term).  dim=2: the method in the plane
+        (box (d1, d2), kernel -log r, positions (2, N), field (2, N))."""
         self.device = torch.device("cuda", device)
+        self.dim = int(dim) if int(dim) == 2 else 3
         keep = []
         self._prm = _params(box, p, R_b, lam, precision, mean, rcond, n_max, m_max, tile_targets, n_split,
-                            centres, check_points, keep, periodic, kernel, kappa)
+                            centres, check_points, keep, periodic, kernel, kappa, dim)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan(ctypes.byref(self._prm), int(device), ctypes.byref(h)))
         self._h = h
@@ -144,6 +157,7 @@ class Plan:
         obj.device = torch.device("cuda", device)
         obj._h = _load(path, device)
         obj.n_max = None
+        obj.dim = obj.info()["dim"]
         return obj
 
     def info(self):
@@ -173,27 +187,26 @@ class Plan:
     def eval(self, x, q, targets=None, out=None):
         """phi (N,) and field -grad phi (3, N) at the particles, or at separate
         targets (3, M).  Returns device tensors; enqueued on the current stream."""
-        x = _soa(x, self.device)
+        x = _soa(x, self.device, self.dim)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")
         if targets is not None:
-            t = _soa(targets, self.device)
+            t = _soa(targets, self.device, self.dim)
             m = t.shape[1]
-            tp = [_ptr(t[0]), _ptr(t[1]), _ptr(t[2])]
+            tp = _xyz(t)
         else:
             m = 0
             tp = [None, None, None]
         cnt = m if m else n
         if out is None:
             phi = torch.empty(cnt, dtype=torch.float64, device=self.device)
-            field = torch.empty(3, cnt, dtype=torch.float64, device=self.device)
+            field = torch.empty(self.dim, cnt, dtype=torch.float64, device=self.device)
         else:
             phi, field = out
             if phi.data_ptr() != _vec(phi, cnt, self.device, "phi").data_ptr():
                 raise ValueError("phi must be contiguous")
-            _field_out(field, cnt, self.device, "field")
-        check(lib().periodic_sum_eval(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), m, *tp,
-                                      _ptr(phi), _ptr(field[0]), _ptr(field[1]), _ptr(field[2]),
+            _field_out(field, cnt, self.device, "field", self.dim)
+        check(lib().periodic_sum_eval(self._h, n, *_xyz(x), _ptr(q), m, *tp, _ptr(phi), *_xyz(field),
                                       _stream(self.device)))
         return phi, field
 
@@ -209,7 +222,7 @@ class Plan:
 
     def autotune(self, x, q):
         """Pick targets per workgroup and the split scale by timing them on these inputs; returns ms per eval."""
-        return _autotune(self, x, q, [0, _soa(x, self.device).shape[1]])
+        return _autotune(self, x, q, [0, _soa(x, self.device, self.dim).shape[1]])
 
     def near_counts(self):
         return _near_counts(self, 1)
@@ -219,18 +232,17 @@ class Plan:
         check(lib().periodic_sum_status(self._h, _stream(self.device)))
 
     def energy(self, x, q, phi=None, field=None):
-        x = _soa(x, self.device)
+        x = _soa(x, self.device, self.dim)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")
         if phi is not None and phi.data_ptr() != _vec(phi, n, self.device, "phi").data_ptr():
             raise ValueError("phi must be contiguous")
         if field is not None:
-            _field_out(field, n, self.device, "field")
+            _field_out(field, n, self.device, "field", self.dim)
         e = torch.empty(1, dtype=torch.float64, device=self.device)
-        f = field if field is not None else None
-        check(lib().periodic_sum_energy(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(e), _ptr(phi),
-                                        _ptr(f[0]) if f is not None else None, _ptr(f[1]) if f is not None else None,
-                                        _ptr(f[2]) if f is not None else None, _stream(self.device)))
+        fp = _xyz(field) if field is not None else [None, None, None]
+        check(lib().periodic_sum_energy(self._h, n, *_xyz(x), _ptr(q), _ptr(e), _ptr(phi), *fp,
+                                        _stream(self.device)))
         return e
 
     def forward_epoch(self):
@@ -244,29 +256,27 @@ class Plan:
         """Gradient of the last energy pass at these particles; epoch (from
         forward_epoch right after that pass, 0 = unchecked) makes the library
         refuse the call if another pass has run on the plan since."""
-        x = _soa(x, self.device)
+        x = _soa(x, self.device, self.dim)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")
-        dx = torch.empty(3, n, dtype=torch.float64, device=self.device)
+        dx = torch.empty(self.dim, n, dtype=torch.float64, device=self.device)
         dq = torch.empty(n, dtype=torch.float64, device=self.device)
         gE = torch.as_tensor(gE).to(device=self.device, dtype=torch.float64).reshape(1).contiguous()
-        check(lib().periodic_sum_energy_vjp(self._h, n, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(gE),
-                                            _ptr(dx[0]), _ptr(dx[1]), _ptr(dx[2]), _ptr(dq), int(bool(exact)),
-                                            int(epoch), _stream(self.device)))
+        check(lib().periodic_sum_energy_vjp(self._h, n, *_xyz(x), _ptr(q), _ptr(gE), *_xyz(dx), _ptr(dq),
+                                            int(bool(exact)), int(epoch), _stream(self.device)))
         return dx, dq
 
 
 def _autotune(obj, x, q, offsets):
-    x = _soa(x, obj.device)
+    x = _soa(x, obj.device, obj.dim)
     n = x.shape[1]
     q = _vec(q, n, obj.device, "q")
     _check_offsets(offsets, n)
     off = (ctypes.c_int64 * len(offsets))(*[int(v) for v in offsets])
     phi = torch.empty(n, dtype=torch.float64, device=obj.device)
-    field = torch.empty(3, n, dtype=torch.float64, device=obj.device)
+    field = torch.empty(obj.dim, n, dtype=torch.float64, device=obj.device)
     best = ctypes.c_double()
-    check(lib().periodic_sum_autotune(obj._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
-                                      _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), ctypes.byref(best),
+    check(lib().periodic_sum_autotune(obj._h, off, *_xyz(x), _ptr(q), _ptr(phi), *_xyz(field), ctypes.byref(best),
                                       _stream(obj.device)))
     return best.value
 
@@ -311,16 +321,17 @@ class BatchedPlan:
     """Many independent boxes solved by one graph launch per eval."""
 
     def __init__(self, systems, p, lam=None, R_b=None, precision="fp32", mean="zero", rcond=1e-13, tile_targets=0,
-                 n_split=0, kernel="coulomb", kappa=0.0, device=0):
+                 n_split=0, kernel="coulomb", kappa=0.0, dim=3, device=0):
         """systems: list of dicts with 'box' and 'n_max' (and optional 'R_b'/'lam',
-        'centres', 'check_points', 'periodic').  kernel and kappa hold for every system."""
+        'centres', 'check_points', 'periodic').  kernel, kappa and dim hold for every system."""
         self.device = torch.device("cuda", device)
+        self.dim = int(dim) if int(dim) == 2 else 3
         arr = (ps_params * len(systems))()
         keep = []
         for k, s in enumerate(systems):
             arr[k] = _params(s["box"], s.get("p", p), s.get("R_b", R_b), s.get("lam", lam), precision, mean, rcond,
                              s["n_max"], 0, tile_targets, n_split, s.get("centres"), s.get("check_points"), keep,
-                             s.get("periodic", "xyz"), kernel, kappa)
+                             s.get("periodic", "xyz"), kernel, kappa, dim)
         h = ctypes.c_void_p()
         check(lib().periodic_sum_plan_batched(len(systems), arr, int(device), ctypes.byref(h)))
         self._h = h
@@ -341,13 +352,14 @@ class BatchedPlan:
         obj.device = torch.device("cuda", device)
         obj._h = _load(path, device)
         obj.nsys = obj.info()["nsys"]
+        obj.dim = obj.info()["dim"]
         return obj
 
     def eval(self, x, q, offsets, out=None):
         """x: (3, sum N) packed positions, q: (sum N,), offsets: host sequence of nsys+1 ints.
         The captured graph is replayed while the particle counts and the buffers
         stay the same: in a loop, pass the same out=(phi, field) each time."""
-        x = _soa(x, self.device)
+        x = _soa(x, self.device, self.dim)
         n = x.shape[1]
         q = _vec(q, n, self.device, "q")
         if len(offsets) != self.nsys + 1:
@@ -356,14 +368,14 @@ class BatchedPlan:
         off = (ctypes.c_int64 * (self.nsys + 1))(*[int(v) for v in offsets])
         if out is None:
             phi = torch.empty(n, dtype=torch.float64, device=self.device)
-            field = torch.empty(3, n, dtype=torch.float64, device=self.device)
+            field = torch.empty(self.dim, n, dtype=torch.float64, device=self.device)
         else:
             phi, field = out
             if phi.data_ptr() != _vec(phi, n, self.device, "phi").data_ptr():
                 raise ValueError("phi must be contiguous")
-            _field_out(field, n, self.device, "field")
-        check(lib().periodic_sum_eval_batched(self._h, off, _ptr(x[0]), _ptr(x[1]), _ptr(x[2]), _ptr(q), _ptr(phi),
-                                              _ptr(field[0]), _ptr(field[1]), _ptr(field[2]), _stream(self.device)))
+            _field_out(field, n, self.device, "field", self.dim)
+        check(lib().periodic_sum_eval_batched(self._h, off, *_xyz(x), _ptr(q), _ptr(phi), *_xyz(field),
+                                              _stream(self.device)))
         return phi, field
 
     def autotune(self, x, q, offsets):
@@ -412,11 +424,13 @@ class PeriodicEnergy(torch.autograd.Function):
     def forward(ctx, x, q, plan, exact=True):
         # the adjoint checks that it follows a pass at the same device arrays, so
         # the (3, N) contiguous form the library reads is kept for backward
-        xs = _soa(x.detach(), plan.device)
+        xs = _soa(x.detach(), plan.device, getattr(plan, "dim", 3))
         qs = _vec(q.detach(), xs.shape[1], plan.device, "q")
         e = plan.energy(xs, qs)
         ctx.save_for_backward(xs, qs)
-        ctx.x_rows = not (x.shape[0] != 3 or (x.shape[1] == 3 and not x.is_contiguous()))  # as _soa reads it
+        rows = (2, 3) if getattr(plan, "dim", 3) == 2 else (3,)
+        ctx.x_rows = x.shape[0] in rows and not (x.shape[1] in rows and not x.is_contiguous())  # as _soa reads it
+        ctx.x_shape = tuple(x.shape)
         ctx.plan = plan
         ctx.exact = exact
         ctx.epoch = plan.forward_epoch()
@@ -434,6 +448,8 @@ class PeriodicEnergy(torch.autograd.Function):
             plan.energy(x, q)
             epoch = plan.forward_epoch()
         dx, dq = plan.energy_vjp(x, q, gE, exact=ctx.exact, epoch=epoch)
+        if dx.shape[0] == 2 and 3 in ctx.x_shape and 2 not in ctx.x_shape:   # plane positions given with a z row
+            dx = torch.cat([dx, torch.zeros_like(dx[:1])])
         if not ctx.x_rows:
             dx = dx.t()
         return dx, dq, None, None

@@ -153,6 +153,9 @@ struct ps_plan_s {
     SysDev* d_sys = nullptr;
     int kernel = 0;                     // ps_kernel, shared by every system of the plan
     double kappa = 0.0;                 // screening constant of PS_KERNEL_SCREENED
+    int dim = 3;                        // 3, or 2 for a plan in the plane (every system)
+    int pair_kern = 0;                  // the pair kernels' form: 0 1/r, 1 screened, 2 the plane's -log r
+    double* d_zero = nullptr;           // the plane: zeros read as every z coordinate
     double* d_chk_t = nullptr;          // the check targets in the order of the check-point sums
     int* d_chk_slot = nullptr;          // position of check target k of a system in that order
     double *d_img = nullptr, *d_chk = nullptr, *d_pinv = nullptr, *d_bm = nullptr, *d_rec = nullptr;
@@ -282,22 +285,27 @@ int ceil_log2(int64_t v)
 // Cell grid for the spatial ordering: cubic cells of side d_max / 2^gbits with
 // about two to four particles each (at most 128 per axis), so that the Morton
 // key space 2^(3 gbits) stays close to the number of occupied cells.
-void choose_grid(const double box[3], int64_t nmax, int g[3], int& gbits)
+// In the plane (every z is 0) the cells are squares and g[2] = 1.
+void choose_grid(const double box[3], int64_t nmax, int dim, int g[3], int& gbits)
 {
-    const double V = box[0] * box[1] * box[2];
-    const double dmax = std::max(box[0], std::max(box[1], box[2]));
-    const double h = std::cbrt(V / std::max<double>(1.0, nmax / 2.0));
+    const double V = dim == 2 ? box[0] * box[1] : box[0] * box[1] * box[2];
+    const double dmax = dim == 2 ? std::max(box[0], box[1]) : std::max(box[0], std::max(box[1], box[2]));
+    const double h = dim == 2 ? std::sqrt(V / std::max<double>(1.0, nmax / 2.0))
+                              : std::cbrt(V / std::max<double>(1.0, nmax / 2.0));
     const double graw = std::max(1.0, std::ceil(dmax / h));
     gbits = std::min(7, ceil_log2(static_cast<int64_t>(graw)));
     if (gbits > 0 && (double)(1 << gbits) > 1.5 * graw) --gbits;
     const double hc = dmax / (1 << gbits);
     for (int k = 0; k < 3; ++k) g[k] = static_cast<int>(std::min<double>(1 << gbits, std::max(1.0, std::ceil(box[k] / hc))));
+    if (dim == 2) g[2] = 1;
 }
 
 // The C ABI's struct layouts (mirrored by the ctypes binding).
-static_assert(sizeof(ps_params) == 136 && offsetof(ps_params, periodic) == 120 && offsetof(ps_params, kappa) == 128,
+static_assert(sizeof(ps_params) == 144 && offsetof(ps_params, periodic) == 120 && offsetof(ps_params, kappa) == 128 &&
+                  offsetof(ps_params, dim) == 136,
               "ps_params layout");
-static_assert(sizeof(ps_plan_info) == 112 && offsetof(ps_plan_info, kappa) == 96, "ps_plan_info layout");
+static_assert(sizeof(ps_plan_info) == 112 && offsetof(ps_plan_info, kappa) == 96 && offsetof(ps_plan_info, dim) == 108,
+              "ps_plan_info layout");
 
 // The periodic-axes mask of a parameter block as the set phase takes it (0 means 7).
 int periodic_axes(int32_t periodic) { return periodic == 0 ? 7 : periodic; }
@@ -313,11 +321,18 @@ ps_status check_params(const ps_params* prm)
         return fail(PS_E_INVALID, "tile_targets must be 0, 64, 128 or 256");
     if (prm->n_split < 0 || prm->n_split > kMaxSplit) return fail(PS_E_INVALID, "n_split must be in [0, %d]", kMaxSplit);
 
-    if (prm->p < 2 || prm->p > 40) return fail(PS_E_INVALID, "p must be in [2, 40]");
+    if (prm->p < 2 || prm->p > (prm->dim == 2 ? 128 : 40))
+        return fail(PS_E_INVALID, "p must be in [2, %d]", prm->dim == 2 ? 128 : 40);
     if (prm->basis != PS_BASIS_SPHERICAL && prm->basis != PS_BASIS_RBF) return fail(PS_E_INVALID, "unknown basis %d", prm->basis);
     if (prm->basis == PS_BASIS_RBF && (prm->n_centres < 1 || prm->n_centres > 4096 || !prm->centres))
         return fail(PS_E_INVALID, "the RBF basis needs 1..4096 centres");
     if (prm->n_check < 0 || (prm->n_check > 0 && !prm->check_points)) return fail(PS_E_INVALID, "bad check-point arguments");
+    if (prm->dim != 0 && prm->dim != 3 && prm->dim != 2) return fail(PS_E_INVALID, "dim must be 0, 3 or 2");
+    const bool plane = prm->dim == 2;
+    if (plane && (prm->basis != PS_BASIS_SPHERICAL || prm->kernel != PS_KERNEL_COULOMB || prm->n_check != 0 ||
+                  periodic_axes(prm->periodic) == 1))
+        return fail(PS_E_UNSUPPORTED, "the plane takes its own basis and check points, the kernel -log r (coulomb) and "
+                                      "both axes periodic");
     if (prm->periodic != 0 && prm->periodic != 7 && prm->periodic != 3 && prm->periodic != 1)
         return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z), 3 (x, y) or 1 (x)");
     if (periodic_axes(prm->periodic) != 7 && prm->basis == PS_BASIS_RBF)
@@ -326,9 +341,10 @@ ps_status check_params(const ps_params* prm)
         return fail(PS_E_INVALID, "unknown kernel %d", prm->kernel);
     if (prm->kernel == PS_KERNEL_SCREENED && (prm->basis != PS_BASIS_RBF || periodic_axes(prm->periodic) != 7))
         return fail(PS_E_UNSUPPORTED, "the screened kernel needs the RBF basis and three periodic axes");
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < (plane ? 2 : 3); ++k)
         if (!(prm->box[k] > 0.0) || !std::isfinite(prm->box[k])) return fail(PS_E_INVALID, "box lengths must be positive");
-    const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + prm->box[2] * prm->box[2]);
+    const double d2 = plane ? 0.0 : prm->box[2];
+    const double R0 = 0.5 * std::sqrt(prm->box[0] * prm->box[0] + prm->box[1] * prm->box[1] + d2 * d2);
     const double Rb = prm->R_b > 0 ? prm->R_b : prm->lambda * R0;
     if (!(Rb > R0) || !std::isfinite(Rb)) return fail(PS_E_INVALID, "near radius must exceed the circumradius (lambda > 1)");
     if (prm->kernel == PS_KERNEL_SCREENED && !(prm->kappa > 0.0 && prm->kappa * R0 <= 64.0))
@@ -817,9 +833,9 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     launch_tblock(T.nt_items, jobs, pl->d_t_items, st);
     mark(3);
     if (pl->precision == PS_FP32_ACC64)  // step 3 at the check points
-        launch_chk_f32(pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
+        launch_chk_f32(pl->pair_kern, T.nchk, cjobs, pl->d_chk_items, st);
     else
-        launch_p2p(0, pl->bt_chk, false, pl->kernel, T.nchk, cjobs, pl->d_chk_items, st);
+        launch_p2p(0, pl->bt_chk, false, pl->pair_kern, T.nchk, cjobs, pl->d_chk_items, st);
     if (T.nd > 0) {  // fewer than three periodic axes: near sums at the decay surfaces, then the decay rows of f
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, kDecayBt, true, 0, T.nd, jobs + 3 * nsys, pl->d_d_items, st);
         launch_decay_rhs(nsys, pl->max_dec, pl->max_dpts, pl->d_sys, jobs + 3 * nsys, pl->d_dpts, pl->dec_tot,
@@ -833,12 +849,12 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
                 pl->d_nz, pl->d_nq, pl->d_mean_part, need_mean ? T.nm : 0, pl->mcols, pl->d_m_items, pl->d_imap, pl->d_img, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mpart,
                 pl->d_bm, pl->d_coef, st);  // step 6
     mark(6);
-    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, pl->kernel, T.np, pjobs, pl->d_p_items,
+    launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, pl->bt, true, pl->pair_kern, T.np, pjobs, pl->d_p_items,
                st);  // step 3 at Y0
     mark(7);
     const PJob* fjobs = jobs + 2 * nsys;
     if (pl->any_rbf) {  // step 7 for the RBF basis: sum over the M centres
-        launch_p2p(0, pl->bt, true, pl->kernel, T.nf, fjobs, pl->d_f_items, st);
+        launch_p2p(0, pl->bt, true, pl->pair_kern, T.nf, fjobs, pl->d_f_items, st);
     }
     launch_far(T.far_lanes, T.nfar, pl->maxP_sph, pl->maxp, pl->d_sys, pl->d_far_items, pjobs, fjobs, pl->d_coef, pl->d_rec,
                separate ? nullptr : pl->d_perm, phi, ex, ey, ez, separate ? nullptr : pl->d_osort, st);  // steps 7-8
@@ -868,6 +884,8 @@ ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
     pl->mean = prm[0].mean;
     pl->kernel = prm[0].kernel;
     pl->kappa = prm[0].kernel == PS_KERNEL_SCREENED ? prm[0].kappa : 0.0;
+    pl->dim = prm[0].dim == 2 ? 2 : 3;
+    pl->pair_kern = pl->dim == 2 ? 2 : pl->kernel;
     if (pl->kernel == PS_KERNEL_SCREENED) pl->mean = PS_MEAN_NONE;   // no constant to fix
     pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
     pl->n_split_req = prm[0].n_split;
@@ -920,8 +938,9 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     if (!prm) return fail(PS_E_INVALID, "params pointer is NULL");
     for (int s = 0; s < nsys; ++s) {
         ps_params q = prm[s];
-        q.kernel = prm[0].kernel;   // one kernel per plan, taken from prm[0]
+        q.kernel = prm[0].kernel;   // one kernel and dimension per plan, taken from prm[0]
         q.kappa = prm[0].kappa;
+        q.dim = prm[0].dim;
         ps_status st = check_params(&q);
         if (st != PS_OK) return st;
     }
@@ -938,7 +957,8 @@ ps_status make_plan(int nsys, const ps_params* prm, int device, ps_plan* out)
     for (int s = 0; s < nsys; ++s)
         errs[s] = pl->setups[s].build(prm[s].box, prm[s].p, prm[s].R_b, prm[s].lambda, prm[0].rcond, prm[s].basis,
                                       prm[s].n_centres, prm[s].centres, prm[s].n_check, prm[s].check_points,
-                                      periodic_axes(prm[s].periodic), prm[0].kernel, prm[0].kappa);
+                                      prm[0].dim == 2 ? 3 : periodic_axes(prm[s].periodic), prm[0].kernel, prm[0].kappa,
+                                      prm[0].dim == 2 ? 2 : 3);
     for (int s = 0; s < nsys; ++s)
         if (!errs[s].empty()) {
             delete pl;
@@ -989,9 +1009,10 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.L = su.L;
         S.nimg = static_cast<int>(su.images.size() / 3);
         S.mean_mode = pl->mean;
-        S.kernel = su.kernel;
+        S.kernel = su.dim == 2 ? 2 : su.kernel;
         S.kappa = su.kappa;
         S.basis = su.basis;
+        S.dim = su.dim;
         S.M = su.basis == 1 ? static_cast<int>(su.centres.size() / 3) : 0;
         S.cen_off = cen_tot;
         if (su.basis == 1) {
@@ -1001,7 +1022,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         } else {
             pl->maxP_sph = std::max(pl->maxP_sph, su.P);
         }
-        choose_grid(su.box, prm[s].n_max, S.g, S.gbits);
+        choose_grid(su.box, prm[s].n_max, su.dim, S.g, S.gbits);
         for (int k = 0; k < 3; ++k) S.inv_cell[k] = S.g[k] / su.box[k];
         S.ncell = int64_t(1) << (3 * S.gbits);
         S.cell_off = cell_tot;
@@ -1021,7 +1042,8 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         for (int k = 0; k < 3; ++k) S.mr[k] = 0;
         for (size_t mi = 0; mi < su.images.size(); ++mi)
             S.mr[mi % 3] = std::max(S.mr[mi % 3], std::abs(su.images[mi]));
-        S.mcorner = 2 * S.mr[2] + 1 <= kMeanZ && (2 * int64_t(S.mr[0]) + 1) * (2 * int64_t(S.mr[1]) + 1) <= kMeanCols;
+        S.mcorner = su.dim == 3 && 2 * S.mr[2] + 1 <= kMeanZ &&
+                    (2 * int64_t(S.mr[0]) + 1) * (2 * int64_t(S.mr[1]) + 1) <= kMeanCols;
         S.imap_off = imap_tot;
         if (S.mcorner) {
             imap_tot += static_cast<int64_t>(2 * S.mr[0] + 1) * (2 * S.mr[1] + 1) * (2 * S.mr[2] + 1);
@@ -1036,7 +1058,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.bm_off = coef_tot;
         coef_tot += S.P;
         S.rec_off = rec_tot;
-        rec_tot += su.basis == 1 ? 0 : 2 * S.P + S.p;
+        rec_tot += su.basis == 1 || su.dim == 2 ? 0 : 2 * S.P + S.p;   // the plane's far field needs no table
         S.f_off = f_tot;
         f_tot += S.Lf;
         S.inv_off = inv_tot;
@@ -1109,7 +1131,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         if (su.basis == 1) {
             for (int t = 0; t < S.M; ++t)
                 for (int k = 0; k < 3; ++k) h_cen[k * cen_tot + S.cen_off + t] = su.centres[t * 3 + k];
-        } else {
+        } else if (su.dim == 3) {
             std::copy(su.rec.a.begin(), su.rec.a.end(), h_rec.begin() + S.rec_off);
             std::copy(su.rec.b.begin(), su.rec.b.end(), h_rec.begin() + S.rec_off + S.P);
             std::copy(su.rec.c.begin(), su.rec.c.end(), h_rec.begin() + S.rec_off + 2 * S.P);
@@ -1223,6 +1245,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     AL(pl->d_dpts, 3 * std::max<int64_t>(1, dec_tot))
     AL(pl->d_dw, std::max<int64_t>(1, dw_tot))
     AL(pl->d_dfield, 3 * std::max<int64_t>(1, dec_tot))
+    if (pl->dim == 2) AL(pl->d_zero, std::max<int64_t>(std::max<int64_t>(1, n_tot), pl->m_max))
     AL(pl->d_drows, std::max<int64_t>(1, drow_tot))
     AL(pl->d_part_dec, std::max<int64_t>(1, pl->part_dec_cap))
     AL(pl->d_tblk_dec, 4 * std::max<int64_t>(1, pl->tblk_dec_cap))
@@ -1256,6 +1279,8 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     UPS(pl->d_drows, h_drows)
 #undef UPS
     if (e == hipSuccess) e = hipMemset(pl->d_status, 0, sizeof(int));
+    if (e == hipSuccess && pl->d_zero)
+        e = hipMemset(pl->d_zero, 0, sizeof(double) * std::max<int64_t>(std::max<int64_t>(1, n_tot), pl->m_max));
     if (e == hipSuccess) e = hipMemset(pl->d_coef, 0, sizeof(double) * coef_tot);
     if (e == hipSuccess) e = hipMemset(pl->d_nnear, 0, sizeof(int64_t) * nsys);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -1270,7 +1295,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
 // Plan files: magic, version, system count, tuned launch shape, then per system
 // the scalar parameters and the set data, then a checksum of all prior bytes.
 const char kPlanMagic[8] = {'P', 'S', 'P', 'L', 'A', 'N', '0', '1'};
-const uint32_t kPlanVersion = 3;
+const uint32_t kPlanVersion = 4;
 
 template <typename T>
 void put_scalar(std::vector<unsigned char>& out, const T& v)
@@ -1326,6 +1351,7 @@ ps_status periodic_sum_plan_save(ps_plan pl, const char* path)
         put_scalar(buf, q.periodic);
         put_scalar(buf, q.kernel);
         put_scalar(buf, q.kappa);
+        put_scalar(buf, q.dim);
         pl->setups[s].serialize(buf);
     }
     put_scalar(buf, fnv1a64(buf.data(), buf.size()));
@@ -1381,16 +1407,18 @@ ps_status periodic_sum_plan_load(const char* path, int device, ps_plan* out)
              get_scalar(buf, pos, q.precision) && get_scalar(buf, pos, q.mean) && get_scalar(buf, pos, q.rcond) &&
              get_scalar(buf, pos, q.n_max) && get_scalar(buf, pos, q.m_max) &&
              get_scalar(buf, pos, q.tile_targets) && get_scalar(buf, pos, q.n_split) && get_scalar(buf, pos, q.basis) &&
-             get_scalar(buf, pos, q.periodic) && get_scalar(buf, pos, q.kernel) && get_scalar(buf, pos, q.kappa);
+             get_scalar(buf, pos, q.periodic) && get_scalar(buf, pos, q.kernel) && get_scalar(buf, pos, q.kappa) &&
+             get_scalar(buf, pos, q.dim);
         if (!ok) return fail(PS_E_IO, "%s: truncated parameters of system %d", path, s);
         const std::string why = setups[s].deserialize(buf.data(), buf.size(), pos);
         if (!why.empty()) return fail(PS_E_IO, "%s: system %d: %s", path, s, why.c_str());
         const SystemSetup& su = setups[s];
-        if (q.p != su.p || q.basis != su.basis || periodic_axes(q.periodic) != su.periodic ||
+        const int qdim = q.dim == 2 ? 2 : 3;
+        if (q.p != su.p || q.basis != su.basis || (qdim == 2 ? 3 : periodic_axes(q.periodic)) != su.periodic ||
             q.kernel != su.kernel || (su.kernel == 1 && q.kappa != su.kappa) || q.kernel != prm[0].kernel ||
-            q.kappa != prm[0].kappa)
+            q.kappa != prm[0].kappa || qdim != su.dim || q.dim != prm[0].dim)
             return fail(PS_E_IO, "%s: system %d: parameters do not match its tables", path, s);
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < qdim; ++k)
             if (q.box[k] != su.box[k]) return fail(PS_E_IO, "%s: system %d: box does not match its tables", path, s);
         if (su.basis == PS_BASIS_RBF) {
             q.n_centres = static_cast<int32_t>(su.centres.size() / 3);
@@ -1427,6 +1455,7 @@ ps_status periodic_sum_eval(ps_plan pl, int64_t n, const double* x, const double
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_INVALID, "batched plan: use periodic_sum_eval_batched");
     if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max=%lld]", (long long)n, (long long)pl->n_max[0]);
+    if (pl->dim == 2) z = tz = pl->d_zero;   // the plane: every z is 0, the caller's z is not read
     if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
     if (m < 0 || m > pl->m_max) return fail(PS_E_INVALID, "m=%lld outside [0, m_max=%lld]", (long long)m, (long long)pl->m_max);
     if (m > 0 && (!tx || !ty || !tz)) return fail(PS_E_INVALID, "target arrays must not be NULL when m > 0");
@@ -1455,7 +1484,7 @@ ps_status periodic_sum_eval_noalloc(ps_plan pl, int64_t n, const double* x, cons
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_INVALID, "batched plan: the allocation-free eval takes single-system plans");
-    if (pl->any_rbf || pl->any_decay)
+    if (pl->any_rbf || pl->any_decay || pl->dim == 2)
         return fail(PS_E_UNSUPPORTED, "the allocation-free eval covers the spherical basis with three periodic axes");
     if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max=%lld]", (long long)n, (long long)pl->n_max[0]);
     if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
@@ -1488,6 +1517,7 @@ ps_status periodic_sum_eval_batched(ps_plan pl, const int64_t* offsets, const do
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (!offsets) return fail(PS_E_INVALID, "offsets is NULL");
+    if (pl->dim == 2) z = pl->d_zero;
     if (!x || !y || !z || !q) return fail(PS_E_INVALID, "particle arrays must not be NULL");
     if (!phi && !ex && !ey && !ez) return fail(PS_E_INVALID, "no output array given");
     std::vector<int64_t> n(pl->nsys);
@@ -1579,7 +1609,7 @@ ps_status periodic_sum_plan_info(ps_plan pl, ps_plan_info* out)
     out->n_rows = su.rows();
     out->kappa = pl->kappa;
     out->kernel = pl->kernel;
-    out->reserved = 0;
+    out->dim = pl->dim;
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
     HIPCHK(hipDeviceSynchronize());
@@ -1819,6 +1849,7 @@ ps_status periodic_sum_energy(ps_plan pl, int64_t n, const double* x, const doub
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy is available for single-system plans");
     if (n < 1 || n > pl->n_max[0]) return fail(PS_E_INVALID, "n=%lld outside [1, n_max]", (long long)n);
+    if (pl->dim == 2) z = pl->d_zero;
     if (!x || !y || !z || !q || !energy) return fail(PS_E_INVALID, "NULL argument");
     DeviceGuard dev_guard(pl->device);
     HIPCHK(dev_guard.err);
@@ -1838,6 +1869,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
 {
     if (!pl) return fail(PS_E_INVALID, "plan is NULL");
     if (pl->nsys != 1) return fail(PS_E_UNSUPPORTED, "energy_vjp is available for single-system plans");
+    if (pl->dim == 2) z = pl->d_zero;
     if (!x || !y || !z || !q || !gE) return fail(PS_E_INVALID, "NULL argument");
     if (epoch < 0) return fail(PS_E_INVALID, "epoch must be >= 0");
     const std::vector<int64_t> key = {n, 0, 0, 0, 0};
@@ -1858,6 +1890,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with fewer than three periodic axes (exact = 0 is)");
     if (exact && pl->kernel == PS_KERNEL_SCREENED)
         return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the screened kernel (exact = 0 is)");
+    if (exact && pl->dim == 2)
+        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available in the plane (exact = 0 is)");
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
@@ -2093,8 +2127,8 @@ ps_status periodic_sum_select(const ps_params* base, int device, int64_t n, cons
     if (p_ref == 0) p_ref = 36;
     if (p_ref < kSelectCal + 2 || p_ref > kSelectPMax)
         return fail(PS_E_INVALID, "p_ref must be in [%d, %d]", kSelectCal + 2, kSelectPMax);
-    if (base->basis != PS_BASIS_SPHERICAL || base->n_check != 0)
-        return fail(PS_E_UNSUPPORTED, "selection covers the spherical basis with the Gauss check points");
+    if (base->basis != PS_BASIS_SPHERICAL || base->n_check != 0 || base->dim == 2)
+        return fail(PS_E_UNSUPPORTED, "selection covers the spherical basis with the Gauss check points in 3-D");
     if (base->precision != PS_FP64 && base->precision != PS_FP32_ACC64)
         return fail(PS_E_INVALID, "unknown precision %d", base->precision);
     double lam_ref = 0.0;

@@ -15,6 +15,8 @@ constexpr int kGroup = 32;         // sources per near/far decision
 // error relative to the separation, and its square the cancellation in the
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
+// -ln(2)/2: the plane's potential term -log(r) = kLog2Half log2(r^2)
+constexpr double kLog2Half = -0.34657359027997265471;
 // Waves per workgroup of the FP32 check-point sums (k_chk_f32): they share one
 // block of 64 targets and split each staged source tile between them.
 constexpr int kChkWaves = 4;
@@ -44,7 +46,8 @@ struct SysDev {
     int g[3], gbits;
     int p, P, L, nimg;
     int mean_mode, basis;        // basis: 0 spherical harmonics, 1 RBF centres
-    int M, pad1;                 // RBF: number of centres (P = M + 1)
+    int M, dim;                  // RBF: number of centres (P = M + 1); dim: 3, or 2 (the plane: every z is 0,
+                                 // basis 1, Re w^n, Im w^n, P = 2p - 1, box mean over the rectangle)
     int64_t cen_off;             // RBF: centres in the packed SoA arrays
     int64_t n_off, n;            // particles in the packed input / sorted arrays
     int64_t cell_off, ncell;     // cell counters (ncell + 1 entries)
@@ -71,6 +74,7 @@ struct SysDev {
     int64_t drow_off;            // decay rows, 5 doubles each (slab: kx, ky, |k|, s, trig;
                                  // wire: k, m, beta, trig in x, trig in theta)
     int kernel, nsurf;           // kernel: 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (no neutrality, no C1);
+                                 // 2 the plane's -log r;
                                  // nsurf: decay surfaces (2 slab, 1 wire, 0 otherwise)
     double kappa;                // screening constant (screened kernel)
 };

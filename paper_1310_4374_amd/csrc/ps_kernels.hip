@@ -138,7 +138,7 @@ __global__ __launch_bounds__(64) void k_validate_final(const SysDev* __restrict_
     }
     sq = wave_sum(sq);
     sa = wave_sum(sa);
-    if (threadIdx.x == 0 && sys[blockIdx.x].kernel == 0 && !(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
+    if (threadIdx.x == 0 && sys[blockIdx.x].kernel != 1 && !(fabs(sq) <= 1e-12 * sa)) atomicOr(status, 1);
 }
 
 // ----------------------------------------------------------------------------
@@ -465,6 +465,10 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
 // e = 2^(r nk2) (nk2 = -kappa log2(e)), the potential term is q ri e and the
 // field weight q e (1 + kappa r)/r^3 = (q ri e) ri (ri + kappa).  A masked pair
 // (ri = 0) gives r = 0, e = 1 and zero terms; padding sources give e = 0.
+// KERN = 2, the plane's -log r (every z is 0): the potential accumulates
+// q log2(r^2), scaled by -ln(2)/2 once at the end, and the field weight is
+// q / r^2; a masked pair gives zero terms, padding (r^2 = 2^120) finite ones
+// times q = 0.
 template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
                                             float hy, float hz, float lx, float ly, float lz, float tt, float kap,
@@ -496,7 +500,16 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
             float ri = __builtin_amdgcn_rsqf(r2);
             if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
             float qr3;
-            if constexpr (KERN == 1) {
+            if constexpr (KERN == 2) {
+                float lg = __builtin_amdgcn_logf(r2);
+                float inv = __builtin_amdgcn_rcpf(r2);
+                if (NEAR) {
+                    lg = r2 > 0.f ? lg : 0.f;  // K(0) = 0
+                    inv = r2 > 0.f ? inv : 0.f;
+                }
+                qv[u] = s.w * lg;
+                if (FIELD) qr3 = s.w * inv;
+            } else if constexpr (KERN == 1) {
                 const float e = __builtin_amdgcn_exp2f((r2 * ri) * nk2);
                 qv[u] = (s.w * ri) * e;
                 if (FIELD) qr3 = qv[u] * (ri * (ri + kap));
@@ -651,7 +664,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
     }
     if (active) {
         double* P_ = J.part + (int64_t)it.split * J.ncomp * J.nt;
-        P_[i] = aP;
+        P_[i] = KERN == 2 ? kLog2Half * aP : aP;
         if (FIELD) {
             P_[J.nt + i] = __builtin_fma((double)hx, aW, 0.5 * aX);
             P_[2 * J.nt + i] = __builtin_fma((double)hy, aW, 0.5 * aY);
@@ -672,6 +685,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 // and N = (x, q/2) for near groups (which read the halved charge for both).
 // KERN = 1 (screened): r = r^2 u / 2, e = exp(-kappa r), the potential term
 // (q/2) u e = q e/r and the weight (q e/r) u (u + 2 kappa) = 4 q e (1 + kappa r)/r^3.
+// KERN = 2 (the plane's -log r): the potential term -(q/2) log(r^2) and the
+// weight 8 (q/2) / r^2 = 4 q / r^2.
 template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, const double4* __restrict__ sN, double tx,
                                             double ty, double tz, double h2x, double h2y, double h2z, double tt,
@@ -697,7 +712,11 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
         double u = y0 * __builtin_fma(-(r2 * y0), y0, 3.0);  // 2/r
         if (NEAR) u = r2 > 0.0 ? u : 0.0;                     // K(0) = 0
         double qr, w;
-        if constexpr (KERN == 1) {
+        if constexpr (KERN == 2) {
+            const bool live = !NEAR || r2 > 0.0;              // K(0) = 0
+            qr = live ? -n.w * log(r2) : 0.0;
+            if (FIELD) w = live ? 8.0 * n.w / r2 : 0.0;
+        } else if constexpr (KERN == 1) {
             qr = (n.w * u) * exp(-kap * (0.5 * (r2 * u)));        // q e/r
             if (FIELD) w = qr * (u * (u + 2.0 * kap));            // 4 q e (1 + kappa r)/r^3
         } else {
@@ -822,7 +841,10 @@ __device__ __forceinline__ float pot8_f32(const float4* __restrict__ sA, const f
         }
         float ri = __builtin_amdgcn_rsqf(r2);
         if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
-        if constexpr (KERN == 1)
+        if constexpr (KERN == 2) {
+            const float lg = __builtin_amdgcn_logf(r2);  // the plane, as in group32_f32
+            qv[u] = s.w * (NEAR ? (r2 > 0.f ? lg : 0.f) : lg);
+        } else if constexpr (KERN == 1)
             qv[u] = (s.w * ri) * __builtin_amdgcn_exp2f((r2 * ri) * nk2);  // screened, as in group32_f32
         else
             qv[u] = s.w * ri;
@@ -941,7 +963,7 @@ __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jo
         if (w == 0)
             for (int k = 1; k < WS; ++k) aP += red[(k - 1) * 64 + lane];
     }
-    if (w == 0 && active) J.part[(int64_t)it.split * J.nt + i] = aP;
+    if (w == 0 && active) J.part[(int64_t)it.split * J.nt + i] = KERN == 2 ? kLog2Half * aP : aP;
 }
 
 // ----------------------------------------------------------------------------
@@ -1102,9 +1124,29 @@ __device__ double prism_corner(double a, double b, double c)
     return F;
 }
 
+// The plane's rectangle primitive F with d^2F/du dv = log(u^2 + v^2):
+// F = u v (log(u^2 + v^2) - 3) + u^2 atan(v/u) + v^2 atan(u/v), a term taken as
+// zero where its prefactor vanishes.
+__device__ double rect_corner(double u, double v)
+{
+    const double r2 = u * u + v * v;
+    if (r2 == 0.0) return 0.0;
+    double F = u * v * (log(r2) - 3.0);
+    if (u != 0.0) F += u * u * atan(v / u);
+    if (v != 0.0) F += v * v * atan(u / v);
+    return F;
+}
+
 // Corner k (bit 0: +x side, bit 1: +y, bit 2: +z) of Phi0(x): its signed term over V0.
+// In the plane (V0 is the rectangle's area) the four corners k < 4 give
+// Phi0 = -(1/(2 V0)) sum_k s_k F(corner_k - x), the potential of a uniform rectangle.
 __device__ double box_mean_corner(const SysDev& S, int k, double x, double y, double z)
 {
+    if (S.dim == 2) {
+        if (k >= 4) return 0.0;
+        const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0;
+        return -0.5 * sx * sy * rect_corner(sx * S.half[0] - x, sy * S.half[1] - y) / S.V0;
+    }
     const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
     return sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z) / S.V0;
 }
@@ -1326,6 +1368,43 @@ __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const
     gz = Z0;
 }
 
+// The plane's far field at the scaled point w = x + iy, lane g of FL: with
+// c_n = C[2n-1] - i C[2n], sum_t C_t R_t = Re S and its gradient (Re D, -Im D),
+// S = sum_n c_n w^n, D = sum_n n c_n w^(n-1) (Cauchy-Riemann), n = 1..p-1.  Lane
+// g takes n = g + 1, g + 1 + FL, ...: it forms w^g by repeated products, then
+// steps by w^FL.
+template <int FL>
+__device__ __forceinline__ void far_field_plane_lane(int p, int g, const double* C, double x, double y, double& phi,
+                                                     double& gx, double& gy)
+{
+    double pr = 1.0, pi = 0.0;  // w^(n-1) for the lane's first n = g + 1
+    for (int k = 0; k < g; ++k) {
+        const double a = pr * x - pi * y, b = pr * y + pi * x;
+        pr = a;
+        pi = b;
+    }
+    double sr = 1.0, si = 0.0;  // w^FL
+    for (int k = 0; k < FL; ++k) {
+        const double a = sr * x - si * y, b = sr * y + si * x;
+        sr = a;
+        si = b;
+    }
+    double Sr = 0.0, Dr = 0.0, Di = 0.0;
+    for (int n = g + 1; n < p; n += FL) {
+        const double cr = C[2 * n - 1], ci = -C[2 * n];
+        const double wr = pr * x - pi * y, wi = pr * y + pi * x;  // w^n
+        Sr += cr * wr - ci * wi;
+        Dr += n * (cr * pr - ci * pi);
+        Di += n * (cr * pi + ci * pr);
+        const double a = pr * sr - pi * si, b = pr * si + pi * sr;
+        pr = a;
+        pi = b;
+    }
+    phi = Sr;
+    gx = Dr;
+    gy = -Di;
+}
+
 // Sum over the FL adjacent lanes of one target (butterfly: the same
 // value in each of them, in a fixed order).
 template <int FL>
@@ -1358,11 +1437,14 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
     const PJob& J = pjobs[it.sys];
     const int P = S.P, p = S.p;
     const bool rbf = S.basis == 1;
+    const bool plane = S.dim == 2;
     double* C = lds;
     double* A = lds + P;
     double* B = lds + 2 * P;
     double* Cd = lds + 3 * P;
-    if (!rbf) {
+    if (plane) {
+        for (int t = threadIdx.x; t < P; t += 256) C[t] = coef[S.coef_off + t];
+    } else if (!rbf) {
         for (int t = threadIdx.x; t < P; t += 256) {
             C[t] = coef[S.coef_off + t];
             A[t] = rec[S.rec_off + t];
@@ -1392,6 +1474,12 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
                 fy += F.part[2 * F.nt + i];
                 fz += F.part[3 * F.nt + i];
             }
+        } else if (plane) {
+            double pf, gx, gy;
+            far_field_plane_lane<FL>(p, g, C, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, pf, gx, gy);
+            ph += pf + (g == 0 ? C[0] : 0.0);
+            fx -= gx * S.inv_R0;
+            fy -= gy * S.inv_R0;
         } else {
             double pf, gx, gy, gz;
             far_field_lane<FL>(p, g, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy,
@@ -1488,6 +1576,9 @@ void launch_p2p(int prec, int bt, bool field, int kern, int64_t nitems, const PJ
     P2P_CASE(64, 1)
     P2P_CASE(128, 1)
     P2P_CASE(256, 1)
+    P2P_CASE(64, 2)
+    P2P_CASE(128, 2)
+    P2P_CASE(256, 2)
 #undef P2P_CASE
 }
 void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)
@@ -1495,6 +1586,8 @@ void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* ite
     if (nitems <= 0) return;
     if (kern == 1)
         PS_LAUNCH((k_chk_f32<kChkWaves, 1>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
+    else if (kern == 2)
+        PS_LAUNCH((k_chk_f32<kChkWaves, 2>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
     else
         PS_LAUNCH((k_chk_f32<kChkWaves, 0>), dim3((unsigned)nitems), dim3(64 * kChkWaves), 0, st, jobs, items);
 }
@@ -1722,7 +1815,7 @@ __global__ __launch_bounds__(1024) void k_adj_finish(const SysDev* __restrict__ 
     double acc = 0.0;
     for (int64_t i = threadIdx.x; i < S.n; i += 1024) acc += dq[i];
     acc = block_reduce<0>(acc, sh);
-    const double mean = S.kernel == 0 ? acc / (double)S.n : 0.0;
+    const double mean = S.kernel != 1 ? acc / (double)S.n : 0.0;
     const double g = gE[0];
     for (int64_t i = threadIdx.x; i < S.n; i += 1024) {
         const int64_t o = perm[S.n_off + i];

@@ -118,6 +118,19 @@ void Recurrence::eval_dir(double x, double y, double z, double u, double v, doub
     }
 }
 
+void basis2d(int p, double x, double y, double* out)
+{
+    out[0] = 1.0;
+    double re = 1.0, im = 0.0;   // w^(n-1)
+    for (int n = 1; n < p; ++n) {
+        const double r2 = re * x - im * y, i2 = re * y + im * x;
+        re = r2;
+        im = i2;
+        out[2 * n - 1] = re;
+        out[2 * n] = im;
+    }
+}
+
 // Nodes and weights of n-point Gauss-Legendre quadrature on [-1, 1], ascending:
 // Newton's method on P_n evaluated by the three-term recurrence.
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w)
@@ -374,7 +387,7 @@ void SystemSetup::build_decay()
     dec_rows.clear();
     n_dec = nk = m = mx = mt = nsurf = npts = 0;
     zd = rho_d = 0.0;
-    if (periodic == 7) return;
+    if (periodic == 7 || dim == 2) return;   // the plane's torus has no free direction
     const double h = R0 / 10.0;
     nk = (p + 3) / 4 + 1;
     if (periodic == 1) {
@@ -445,9 +458,18 @@ void SystemSetup::build_decay()
 
 std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond, int basis_,
                                int n_centres, const double* cen, int n_check, const double* chk, int periodic_,
-                               int kernel_, double kappa_)
+                               int kernel_, double kappa_, int dim_)
 {
     basis = basis_;
+    if (dim_ != 3 && dim_ != 2) return "dim must be 3 or 2";
+    dim = dim_;
+    if (dim == 2) {
+        if (basis_ != 0) return "the plane has only its harmonic-polynomial basis";
+        if (periodic_ != 3) return "in the plane both axes are periodic";
+        if (kernel_ != 0) return "the plane takes the Coulomb kernel only (-log r)";
+        if (n_check != 0) return "the plane uses its own check points (n_check must be 0)";
+        if (p_ < 2 || p_ > 128) return "p must be in [2, 128] in the plane";
+    }
     if (periodic_ != 7 && periodic_ != 3 && periodic_ != 1) return "periodic axes must be 7 (x, y, z), 3 (x, y) or 1 (x)";
     if (periodic_ != 7 && basis_ != 0) return "the RBF basis needs three periodic axes";
     if (kernel_ != 0 && kernel_ != 1) return "kernel must be 0 (Coulomb) or 1 (screened)";
@@ -457,15 +479,17 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     kappa = kernel_ == 1 ? kappa_ : 0.0;
     periodic = periodic_;
     const int nper = periodic == 7 ? 3 : (periodic == 3 ? 2 : 1);   // axes a partner may be shifted along
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < dim; ++k) {
         if (!(bx[k] > 0.0) || !std::isfinite(bx[k])) return "box lengths must be positive and finite";
         box[k] = bx[k];
     }
-    if (p_ < 2 || p_ > 40) return "p must be in [2, 40]";
+    if (dim == 2) box[2] = 1.0;   // every z is 0: the slab of unit height holds them
+    if (dim == 3 && (p_ < 2 || p_ > 40)) return "p must be in [2, 40]";
     p = p_;
-    P = p * p;
+    P = dim == 2 ? 2 * p - 1 : p * p;
     V0 = box[0] * box[1] * box[2];
-    R0 = 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1] + box[2] * box[2]);   // step 1
+    R0 = dim == 2 ? 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1])
+                  : 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1] + box[2] * box[2]);   // step 1
     R_b = Rb > 0 ? Rb : lambda * R0;
     if (!(R_b > R0) || !std::isfinite(R_b)) return "the near radius must exceed the circumradius (lambda > 1)";
     if (kernel == 1 && !(kappa > 0.0 && kappa * R0 <= 64.0)) return "kappa must lie in (0, 64 / R0]";
@@ -502,6 +526,16 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
             for (int k = 0; k < nper; ++k) outside = outside || std::fabs(y[k]) > 0.5 * box[k];
             if (!(r2 <= R0 * R0 * (1.0 + 1e-9)) || !outside)
                 return "a check point is outside S0 or inside the box along every periodic axis";
+        }
+    } else if (dim == 2) {
+        // L = 4p points equispaced on the circumcircle (the trapezoidal rule plays
+        // the part of the Gauss grid); each lies outside the box along x or y
+        L = 4 * p;
+        yc.assign(static_cast<size_t>(L) * 3, 0.0);
+        for (int l = 0; l < L; ++l) {
+            const double th = 2.0 * M_PI * l / L;
+            yc[static_cast<size_t>(l) * 3 + 0] = R0 * std::cos(th);
+            yc[static_cast<size_t>(l) * 3 + 1] = R0 * std::sin(th);
         }
     } else {
         std::vector<double> mu, wq;
@@ -574,6 +608,10 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
                 A[static_cast<size_t>(j) * Lf + l] =
                     kernel == 1 ? std::exp(-kappa * ra) / ra - std::exp(-kappa * rb) / rb : 1.0 / ra - 1.0 / rb;
             }
+        } else if (dim == 2) {
+            basis2d(p, y[0] / R0, y[1] / R0, r1.data());
+            basis2d(p, t[0] / R0, t[1] / R0, r2.data());
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + l] = r1[j + 1] - r2[j + 1];
         } else {
             rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
             rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
@@ -673,6 +711,15 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     std::vector<double> xg, wg;
     gauss_legendre(nq, xg, wg);
     box_means.assign(P, 0.0);
+    if (dim == 2) {   // over the rectangle
+        for (int i = 0; i < nq; ++i)
+            for (int j = 0; j < nq; ++j) {
+                basis2d(p, 0.5 * box[0] * xg[i] / R0, 0.5 * box[1] * xg[j] / R0, r1.data());
+                const double w = wg[i] * wg[j] / 4.0;
+                for (int t = 0; t < P; ++t) box_means[t] += w * r1[t];
+            }
+        return std::string();
+    }
     for (int i = 0; i < nq; ++i)
         for (int j = 0; j < nq; ++j)
             for (int k = 0; k < nq; ++k) {
@@ -746,6 +793,7 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
     put(out, static_cast<int32_t>(periodic));
     put(out, static_cast<int32_t>(kernel));
     put(out, kappa);
+    put(out, static_cast<int32_t>(dim));
     put_vec(out, yc);
     put_vec(out, yt);
     put_vec(out, pinv);
@@ -756,7 +804,7 @@ void SystemSetup::serialize(std::vector<unsigned char>& out) const
 
 std::string SystemSetup::deserialize(const unsigned char* data, size_t size, size_t& pos)
 {
-    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0, per = 0, ker = 0;
+    int32_t b = 0, p_ = 0, P_ = 0, L_ = 0, rank_ = 0, nimg = 0, M = 0, per = 0, ker = 0, dm = 0;
     double kap = 0.0;
     bool ok = true;
     for (int k = 0; k < 3; ++k) ok = ok && get(data, size, pos, box[k]);
@@ -764,7 +812,8 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
          get(data, size, pos, thr) && get(data, size, pos, V0) && get(data, size, pos, p_) &&
          get(data, size, pos, P_) && get(data, size, pos, L_) && get(data, size, pos, rank_) &&
          get(data, size, pos, cond) && get(data, size, pos, nimg) && get(data, size, pos, M) &&
-         get(data, size, pos, per) && get(data, size, pos, ker) && get(data, size, pos, kap);
+         get(data, size, pos, per) && get(data, size, pos, ker) && get(data, size, pos, kap) &&
+         get(data, size, pos, dm);
     if (!ok) return "truncated system record";
     if (per != 7 && per != 3 && per != 1) return "bad periodic axes";
     if (per != 7 && b != 0) return "the RBF basis needs three periodic axes";
@@ -773,8 +822,10 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
     for (int k = 0; k < 3; ++k)
         if (!(box[k] > 0.0) || !std::isfinite(box[k])) return "bad box lengths";
     if (b != 0 && b != 1) return "bad basis";
-    if (p_ < 2 || p_ > 40) return "p out of range";
-    if (b == 0 && (P_ != p_ * p_ || M != 0)) return "basis size does not match p";
+    if (dm != 3 && dm != 2) return "bad dimension";
+    if (dm == 2 && (b != 0 || per != 3 || ker != 0 || box[2] != 1.0)) return "bad record of a plane system";
+    if (p_ < 2 || p_ > (dm == 2 ? 128 : 40)) return "p out of range";
+    if (b == 0 && (P_ != (dm == 2 ? 2 * p_ - 1 : p_ * p_) || M != 0)) return "basis size does not match p";
     if (b == 1 && (M < 1 || M > 4096 || P_ != M + 1)) return "bad RBF centre count";
     if (L_ < 1 || L_ > (1 << 20)) return "bad check-point count";
     if (rank_ < 1 || rank_ > P_ - 1) return "bad rank";
@@ -786,6 +837,7 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
     L = L_;
     rank = rank_;
     periodic = per;
+    dim = dm;
     kernel = ker;
     kappa = ker == 1 ? kap : 0.0;
     if (kernel == 1 && !(kappa * R0 <= 64.0)) return "kappa out of range";

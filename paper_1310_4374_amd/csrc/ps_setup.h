@@ -30,6 +30,10 @@ struct Recurrence {
 
 void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 
+// The plane's harmonic polynomials at the scaled point (x, y): out[0] = 1,
+// out[2n-1] = Re w^n, out[2n] = Im w^n, w = x + iy, n = 1..p-1.
+void basis2d(int p, double x, double y, double* out);
+
 // Mean of 1/|y - x| over the box [-d/2, d/2]^3 (divided by its volume): the
 // closed-form potential of a uniform rectangular prism, summed over corners.
 double box_mean_potential(const double box[3], double x, double y, double z);
@@ -73,10 +77,16 @@ struct SystemSetup {
     // axes; no constant basis function to fix: box_means stay zero).
     int kernel = 0;
     double kappa = 0;
+    // Dimension: 3, or 2 for the method in the plane (kernel -log r, x and y
+    // periodic; the basis 1, Re w^n, Im w^n with w = (x + iy)/R0, P = 2p - 1;
+    // L = 4p check points equispaced on the circumcircle; box[2] is held at 1 and
+    // every z at 0, so the 3-D near set, ordering and pair sums apply unchanged).
+    int dim = 3;
     // Returns an empty string on success, or the reason for failure.
     std::string build(const double box[3], int p, double R_b, double lambda, double rcond, int basis = 0,
                       int n_centres = 0, const double* centres = nullptr, int n_check = 0,
-                      const double* check_points = nullptr, int periodic = 7, int kernel = 0, double kappa = 0);
+                      const double* check_points = nullptr, int periodic = 7, int kernel = 0, double kappa = 0,
+                      int dim = 3);
     // The decay surfaces and rows (a function of the periodic axes, box, p and R0 alone).
     void build_decay();
     // Binary form of the set data (little-endian scalars and arrays; the

@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened slab wire]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened slab wire plane]
 """
 import os
 import sys
@@ -196,6 +196,16 @@ def slab():
 def wire():
     """The wire workload (workloads.config_partial("x")) at its sampled particles."""
     _partial("x", "ref_wire.npz")
+
+
+def plane():
+    """The plane workload (workloads.config_plane) at its sampled particles."""
+    from oracle.twod import Plan2D
+    c = W.config_plane()
+    pl = Plan2D(c["box"], c["p"], lam=c["lam"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save("ref_plane.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
 
 
 if __name__ == "__main__":

@@ -35,11 +35,13 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layout_matches_header():
     """The ctypes mirror of ps_params has the C layout (no torch types cross)."""
     assert ctypes.sizeof(_lib.ps_params) == 3 * 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 8 + 8 + 4 + 4 + 4 + 4 + 8 + 4 + 4 + 8 \
-        + 4 + 4 + 8
+        + 4 + 4 + 8 + 4 + 4
     assert _lib.ps_params.n_max.offset == 64
     assert _lib.ps_params.periodic.offset == 120
     assert _lib.ps_params.kernel.offset == 124 and _lib.ps_params.kappa.offset == 128
+    assert _lib.ps_params.dim.offset == 136
     assert ctypes.sizeof(_lib.ps_plan_info) == 112 and _lib.ps_plan_info.kappa.offset == 96
+    assert _lib.ps_plan_info.dim.offset == 108
 
 
 def _params(**kw):
@@ -113,6 +115,28 @@ def test_periodic_axes_checked_on_host():
         assert h.value is None
 
 
+def test_plane_parameters_checked_on_host():
+    """dim other than 0, 2 or 3, and in the plane: the RBF basis, the screened
+    kernel, caller check points, one periodic axis, p above 128, a bad box edge
+    are refused before any device work (box[2] is not read in the plane)."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    cen = (ctypes.c_double * 3)(2.0, 0.0, 0.0)
+    dp = ctypes.cast(cen, ctypes.POINTER(ctypes.c_double))
+    cases = [(dict(dim=1), _lib.PS_E_INVALID), (dict(dim=4), _lib.PS_E_INVALID),
+             (dict(dim=2, basis=1, n_centres=1, centres=dp), _lib.PS_E_UNSUPPORTED),
+             (dict(dim=2, kernel=1, kappa=1.0), _lib.PS_E_UNSUPPORTED),
+             (dict(dim=2, n_check=1, check_points=dp), _lib.PS_E_UNSUPPORTED),
+             (dict(dim=2, periodic=1), _lib.PS_E_UNSUPPORTED),
+             (dict(dim=2, p=129), _lib.PS_E_INVALID), (dict(dim=3, p=41), _lib.PS_E_INVALID)]
+    for kw, status in cases:
+        assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == status, kw
+        assert h.value is None
+    prm = _params(dim=2)
+    prm.box[1] = -1.0
+    assert L.periodic_sum_plan(ctypes.byref(prm), 0, ctypes.byref(h)) == _lib.PS_E_INVALID
+
+
 @pytest.mark.parametrize("kw", [dict(R_b=0.5), dict(R_b=0.0, lambda_=0.9)])
 def test_near_radius_must_exceed_circumradius(kw):
     L = _lib.lib()
@@ -158,11 +182,11 @@ def test_plan_file_with_valid_checksum_but_bad_contents_is_refused(tmp_path):
     whose system record claims p = 99 is refused with PS_E_IO."""
     import struct
     L = _lib.lib()
-    head = b"PSPLAN01" + struct.pack("<Iiid", 3, 1, 256, 1.0)
+    head = b"PSPLAN01" + struct.pack("<Iiid", 4, 1, 256, 1.0)
     prm = struct.pack("<3didd", 1.0, 1.0, 1.0, 99, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
-        + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<id", 0, 0.0)
+        + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<idi", 0, 0.0, 3)
     setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) + struct.pack("<4id", 99, 99 * 99, 10, 5, 1.0) \
-        + struct.pack("<iii", 1, 0, 7) + struct.pack("<id", 0, 0.0)
+        + struct.pack("<iii", 1, 0, 7) + struct.pack("<idi", 0, 0.0, 3)
     body = head + prm + setup
     f = tmp_path / "bad_p.plan"
     f.write_bytes(body + struct.pack("<Q", _fnv1a64(body)))
@@ -180,12 +204,12 @@ def test_plan_file_with_bad_image_list_is_refused(tmp_path):
     p, P, Lc = 2, 4, 6
 
     def plan_file(images):
-        head = b"PSPLAN01" + struct.pack("<Iiid", 3, 1, 256, 1.0)
+        head = b"PSPLAN01" + struct.pack("<Iiid", 4, 1, 256, 1.0)
         prm = struct.pack("<3didd", 1.0, 1.0, 1.0, p, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
-            + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<id", 0, 0.0)
+            + struct.pack("<qqiiii", 100, 0, 0, 0, 0, 7) + struct.pack("<idi", 0, 0.0, 3)
         setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) \
             + struct.pack("<4id", p, P, Lc, P - 1, 1.0) + struct.pack("<iii", len(images), 0, 7) \
-            + struct.pack("<id", 0, 0.0)
+            + struct.pack("<idi", 0, 0.0, 3)
         arrays = struct.pack("<%dd" % (2 * 3 * Lc + (P - 1) * Lc + P), *([0.1] * (2 * 3 * Lc + (P - 1) * Lc + P)))
         arrays += struct.pack("<%di" % (3 * len(images)), *[v for im in images for v in im])
         body = head + prm + setup + arrays

@@ -120,6 +120,17 @@ def config_partial(periodic, n=100_000, nsub=2000):
     return dict(box=d, x=x, q=q, p=16, lam=1.5, periodic=periodic, subset=sub)
 
 
+def config_plane(n=100_000, nsub=2000):
+    """The method in the plane (kernel -log r): N uniform in the unit square,
+    Gaussian charges minus their mean, p = 32, lambda = 1.5.  Positions (N, 2)."""
+    g = rng(9)
+    d = np.array([1.0, 1.0])
+    x = wrap((g.random((n, 2)) - 0.5) * d, d)
+    q = _neutral_gauss(g, n)
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    return dict(box=d, x=x, q=q, p=32, lam=1.5, subset=sub)
+
+
 def config4(nsys=512, nmin=200, nmax=20000):
     g = rng(4)
     systems = []
