@@ -487,15 +487,17 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                 const float4 l = sB[g * 8 + u];
                 dx = __builtin_fmaf(0.5f, s.x, hx) + (lx - l.x);
                 dy = __builtin_fmaf(0.5f, s.y, hy) + (ly - l.y);
-                dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
                 r2 = dx * dx;
                 r2 = __builtin_fmaf(dy, dy, r2);
-                r2 = __builtin_fmaf(dz, dz, r2);
+                if constexpr (KERN != 2) {  // the plane: every z is 0
+                    dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
+                    r2 = __builtin_fmaf(dz, dz, r2);
+                }
             } else {
                 r2 = tt + sB[g * 8 + u].w;
                 r2 = __builtin_fmaf(hx, s.x, r2);
                 r2 = __builtin_fmaf(hy, s.y, r2);
-                r2 = __builtin_fmaf(hz, s.z, r2);
+                if constexpr (KERN != 2) r2 = __builtin_fmaf(hz, s.z, r2);
             }
             float ri = __builtin_amdgcn_rsqf(r2);
             if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
@@ -521,12 +523,12 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                 if (NEAR) {
                     fX = __builtin_fmaf(qr3, dx, fX);
                     fY = __builtin_fmaf(qr3, dy, fY);
-                    fZ = __builtin_fmaf(qr3, dz, fZ);
+                    if constexpr (KERN != 2) fZ = __builtin_fmaf(qr3, dz, fZ);
                 } else {
                     fW += qr3;
                     fX = __builtin_fmaf(qr3, s.x, fX);
                     fY = __builtin_fmaf(qr3, s.y, fY);
-                    fZ = __builtin_fmaf(qr3, s.z, fZ);
+                    if constexpr (KERN != 2) fZ = __builtin_fmaf(qr3, s.z, fZ);
                 }
             }
         }
@@ -686,7 +688,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 // KERN = 1 (screened): r = r^2 u / 2, e = exp(-kappa r), the potential term
 // (q/2) u e = q e/r and the weight (q e/r) u (u + 2 kappa) = 4 q e (1 + kappa r)/r^3.
 // KERN = 2 (the plane's -log r): the potential term -(q/2) log(r^2) and the
-// weight 8 (q/2) / r^2 = 4 q / r^2.
+// weight 2 (q/2) u^2 = 4 q / r^2.
 template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, const double4* __restrict__ sN, double tx,
                                             double ty, double tz, double h2x, double h2y, double h2z, double tt,
@@ -699,14 +701,15 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
         if (NEAR) {
             dx = tx - n.x;
             dy = ty - n.y;
-            dz = tz - n.z;
-            r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            dz = KERN == 2 ? 0.0 : tz - n.z;  // the plane: every z is 0
+            r2 = KERN == 2 ? __builtin_fma(dy, dy, dx * dx) : __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
         } else {
             const double4 f = sF[k];
             dx = f.x;  // -(x - c): the far field accumulates w times these
             dy = f.y;
-            dz = f.z;
-            r2 = __builtin_fma(h2x, f.x, __builtin_fma(h2y, f.y, __builtin_fma(h2z, f.z, tt + f.w)));
+            dz = KERN == 2 ? 0.0 : f.z;
+            r2 = KERN == 2 ? __builtin_fma(h2x, f.x, __builtin_fma(h2y, f.y, tt + f.w))
+                           : __builtin_fma(h2x, f.x, __builtin_fma(h2y, f.y, __builtin_fma(h2z, f.z, tt + f.w)));
         }
         const double y0 = __builtin_amdgcn_rsq(r2);
         double u = y0 * __builtin_fma(-(r2 * y0), y0, 3.0);  // 2/r
@@ -715,7 +718,7 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
         if constexpr (KERN == 2) {
             const bool live = !NEAR || r2 > 0.0;              // K(0) = 0
             qr = live ? -n.w * log(r2) : 0.0;
-            if (FIELD) w = live ? 8.0 * n.w / r2 : 0.0;
+            if (FIELD) w = 2.0 * n.w * (u * u);               // 4 q / r^2 (u = 0 for a masked pair)
         } else if constexpr (KERN == 1) {
             qr = (n.w * u) * exp(-kap * (0.5 * (r2 * u)));        // q e/r
             if (FIELD) w = qr * (u * (u + 2.0 * kap));            // 4 q e (1 + kappa r)/r^3
@@ -829,15 +832,17 @@ __device__ __forceinline__ float pot8_f32(const float4* __restrict__ sA, const f
             const float4 l = sB[u];
             const float dx = __builtin_fmaf(0.5f, s.x, hx) + (lx - l.x);
             const float dy = __builtin_fmaf(0.5f, s.y, hy) + (ly - l.y);
-            const float dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
             r2 = dx * dx;
             r2 = __builtin_fmaf(dy, dy, r2);
-            r2 = __builtin_fmaf(dz, dz, r2);
+            if constexpr (KERN != 2) {  // the plane: every z is 0
+                const float dz = __builtin_fmaf(0.5f, s.z, hz) + (lz - l.z);
+                r2 = __builtin_fmaf(dz, dz, r2);
+            }
         } else {
             r2 = tt + sW[u];
             r2 = __builtin_fmaf(hx, s.x, r2);
             r2 = __builtin_fmaf(hy, s.y, r2);
-            r2 = __builtin_fmaf(hz, s.z, r2);
+            if constexpr (KERN != 2) r2 = __builtin_fmaf(hz, s.z, r2);
         }
         float ri = __builtin_amdgcn_rsqf(r2);
         if (NEAR) ri = r2 > 0.f ? ri : 0.f;  // K(0) = 0
