@@ -170,6 +170,8 @@ typedef struct {
     double  kappa;            /* screening constant (0 for the Coulomb kernel) */
     int32_t kernel;           /* ps_kernel of the plan (every system of a batch shares it) */
     int32_t dim;              /* 3, or 2 for a plan in the plane (every system of a batch shares it) */
+    double  tune_ms;          /* periodic_sum_autotune: median ms per eval of the chosen candidate (0: not tuned) */
+    double  tune_second_ms;   /* the same for the runner-up: the margin the choice rests on */
 } ps_plan_info;
 
 /* Algorithm "set" (Sec. 2.3, steps 1-6) on the host in FP64: circumradius and
@@ -313,12 +315,15 @@ ps_status periodic_sum_eval_batched(ps_plan plan, const int64_t* offsets,
 
 /* Autotuner for the particle pair sums: times each candidate of targets per
  * workgroup {64, 128, 256} x source-split scale {1/2, 1, 2} (relative to the
- * occupancy-based choice) on the given inputs, with HIP events on `stream`,
- * and keeps the fastest in the plan (reported by periodic_sum_plan_info).
+ * occupancy-based choice) on the given inputs, with HIP events on `stream`:
+ * after a warm-up eval, the median of three separately timed evals.  The two
+ * fastest are timed three more times each and the one with the lower median
+ * of its six evals is kept in the plan (periodic_sum_plan_info reports it, and
+ * tune_ms / tune_second_ms give the two medians).
  * offsets: host [nsys+1] as in periodic_sum_eval_batched ({0, n} for a
  * single-system plan); the outputs receive the last candidate's result.
- * Synchronizes the stream.  best_ms (host, may be NULL) receives the best
- * time per eval. */
+ * Synchronizes the stream.  best_ms (host, may be NULL) receives the chosen
+ * candidate's median time per eval. */
 ps_status periodic_sum_autotune(ps_plan plan, const int64_t* offsets,
                                 const double* x, const double* y, const double* z, const double* q,
                                 double* phi, double* ex, double* ey, double* ez, double* best_ms, void* stream);

@@ -45,7 +45,8 @@ class ps_plan_info(ctypes.Structure):
                 ("n_near_last", ctypes.c_int64), ("tile_targets", ctypes.c_int32), ("n_split", ctypes.c_int32),
                 ("nsys", ctypes.c_int32), ("mean_corners", ctypes.c_int32), ("profiled_evals", ctypes.c_int64),
                 ("forward_epoch", ctypes.c_int64), ("periodic", ctypes.c_int32), ("n_rows", ctypes.c_int32),
-                ("kappa", ctypes.c_double), ("kernel", ctypes.c_int32), ("dim", ctypes.c_int32)]
+                ("kappa", ctypes.c_double), ("kernel", ctypes.c_int32), ("dim", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double), ("tune_second_ms", ctypes.c_double)]
 
 
 class ps_select_row(ctypes.Structure):

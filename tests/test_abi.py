@@ -40,8 +40,8 @@ def test_struct_layout_matches_header():
     assert _lib.ps_params.periodic.offset == 120
     assert _lib.ps_params.kernel.offset == 124 and _lib.ps_params.kappa.offset == 128
     assert _lib.ps_params.dim.offset == 136
-    assert ctypes.sizeof(_lib.ps_plan_info) == 112 and _lib.ps_plan_info.kappa.offset == 96
-    assert _lib.ps_plan_info.dim.offset == 108
+    assert ctypes.sizeof(_lib.ps_plan_info) == 128 and _lib.ps_plan_info.kappa.offset == 96
+    assert _lib.ps_plan_info.dim.offset == 108 and _lib.ps_plan_info.tune_second_ms.offset == 120
 
 
 def _params(**kw):
