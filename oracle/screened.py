@@ -91,6 +91,32 @@ class ScreenedPlan:
         return phi, field
 
 
+def energy_gradients_screened(plan, x, q):
+    """E = (1/2) sum_i q_i phi(x_i) for the screened method and its exact gradient,
+    derived as for the Coulomb method (oracle/adjoint.py) with the moments
+    u_t = sum_k q_k K(c_t - x_k) at the centres, w = (A^+)^T u, and
+    psi(z) = sum_k q_k K(z - x_k) + sum_l w_l [K(z - y~_l) - K(z - y_l)]:
+      dE/dx_i = (1/2) q_i grad phi(x_i) + (1/2) q_i sum_{p: (i,p) near} grad psi(x_i + p),
+      dE/dq_i = (1/2) phi(x_i)          + (1/2)     sum_{p: (i,p) near} psi(x_i + p).
+    There is no constant and the charges need not be neutral, so dE/dq is not
+    projected.  Returns (E, dE/dx (N,3), dE/dq (N,))."""
+    x = np.asarray(x, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    phi, field = plan.solve(x, q)
+    E = 0.5 * float(np.sum(q * phi))
+    u = _native.direct_screened(plan.centres, x, q, plan.kappa, grad=False)
+    w = plan.Apinv.T @ u
+    xs, _, base, _ = plan.near(x, q)
+    src = np.concatenate([x, plan.yt, plan.yc])
+    srq = np.concatenate([q, w, -w])
+    psi, gpsi = _native.direct_screened(xs, src, srq, plan.kappa)
+    dpsi = np.zeros(x.shape[0])
+    gsum = np.zeros_like(x)
+    np.add.at(dpsi, base, psi)
+    np.add.at(gsum, base, gpsi)
+    return E, 0.5 * q[:, None] * (-field + gsum), 0.5 * (phi + dpsi)
+
+
 class EwaldScreened:
     """Periodic sum of exp(-kappa r)/r by the split described above."""
 

@@ -192,6 +192,33 @@ class Plan2D:
         return phi, field
 
 
+def energy_gradients2d(plan, x, q):
+    """E = (1/2) sum_i q_i phi(x_i) for the plane's method and its exact gradient,
+    derived as in 3-D (oracle/adjoint.py): moments u_t = sum_k q_k R_t(x_k / R0),
+    t = 2..P, w = (A^+)^T u, psi(z) = sum_k q_k K(z - x_k) + sum_l w_l [K(z - y~_l)
+    - K(z - y_l)] with K = -log r;
+      dE/dx_i = (1/2) q_i grad phi(x_i) + (1/2) q_i sum_{p: (i,p) near} grad psi(x_i + p),
+      dE/dq_i = (1/2) phi(x_i)          + (1/2)     sum_{p: (i,p) near} psi(x_i + p),
+    C1 dropping out for neutral charges and dE/dq projected onto sum dq = 0.
+    Returns (E, dE/dx (N,2), dE/dq (N,))."""
+    x = np.asarray(x, dtype=np.float64)[:, :2]
+    q = np.asarray(q, dtype=np.float64)
+    phi, field = plan.solve(x, q)
+    E = 0.5 * float(np.sum(q * phi))
+    u = basis2d(x[:, 0] / plan.R0, x[:, 1] / plan.R0, plan.p)[1:] @ q
+    w = plan.Apinv.T @ u
+    xs, _, base, _ = plan.near(x, q)
+    src = np.concatenate([x, plan.yt, plan.yc])
+    srq = np.concatenate([q, w, -w])
+    psi, gpsi = _native.direct_log2d(xs, src, srq)
+    dpsi = np.zeros(x.shape[0])
+    gsum = np.zeros_like(x)
+    np.add.at(dpsi, base, psi)
+    np.add.at(gsum, base, gpsi)
+    dq = 0.5 * (phi + dpsi)
+    return E, 0.5 * q[:, None] * (-field + gsum), dq - dq.mean()
+
+
 class EwaldLog2D:
     """Independent Ewald split of the 2-D periodic log sum (conducting boundary,
     zero cell mean).  From -log r = (1/2) int_0^inf (exp(-r^2 t) - exp(-t)) dt / t,

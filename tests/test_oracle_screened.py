@@ -149,3 +149,35 @@ def test_method_is_periodic_and_translation_invariant():
     phi2, f2 = pl.solve(xs, q)
     assert np.linalg.norm(phi2 - phi) / np.linalg.norm(phi) < 1e-5
     assert np.linalg.norm(f2 - f) / np.linalg.norm(f) < 1e-5
+
+
+def _screened_energy(pl, x, q):
+    phi, _ = pl.solve(x, q)
+    return 0.5 * float(q @ phi)
+
+
+def test_screened_adjoint_matches_finite_differences():
+    """The exact gradient of the screened method's energy against central
+    differences (h = 1e-5) in positions and in single charges (any net charge)."""
+    from oracle.screened import energy_gradients_screened
+    R0 = 0.5 * np.linalg.norm(BOX)
+    pl = ScreenedPlan(BOX, 2.0, W.thomson_points(64, 1.5 * R0), 8, lam=1.5)
+    x, q = _cell(30, seed=51)
+    E, dEdx, dEdq = energy_gradients_screened(pl, x, q)
+    assert abs(E - _screened_energy(pl, x, q)) < 1e-14 * abs(E)
+    P = np.array([[i, j, k] for i in (-2, -1, 0, 1, 2) for j in (-2, -1, 0, 1, 2) for k in (-2, -1, 0, 1, 2)]) * BOX
+    d = np.abs(np.linalg.norm(x[:, None, :] + P[None, :, :], axis=2) - pl.R_b).min(axis=1)
+    h = 1e-5
+    for i in np.nonzero(d > 1e-3)[0][:4]:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (_screened_energy(pl, xp, q) - _screened_energy(pl, xm, q)) / (2 * h)
+            assert abs(dEdx[i, k] - fd) < 1e-7 * max(1.0, abs(fd))
+    for i in (0, 7, 19):
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qm[i] -= h
+        fd = (_screened_energy(pl, x, qp) - _screened_energy(pl, x, qm)) / (2 * h)
+        assert abs(dEdq[i] - fd) < 1e-8 * max(1.0, abs(fd))

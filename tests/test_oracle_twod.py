@@ -214,3 +214,37 @@ def test_direct_log_sum_against_numpy():
     want = np.where(live, -0.5 * np.log(np.where(live, r2, 1.0)), 0.0) @ q
     wg = -(np.where(live, 1.0 / np.where(live, r2, 1.0), 0.0)[:, :, None] * d * q[None, :, None]).sum(1)
     assert np.abs(ph - want).max() < 1e-14 and np.abs(gr - wg).max() < 1e-13
+
+
+def _energy2d(pl, x, q):
+    phi, _ = pl.solve(x, q)
+    return 0.5 * float(q @ phi)
+
+
+def test_plane_adjoint_matches_finite_differences():
+    """The exact gradient of the plane method's energy against central
+    differences (h = 1e-5) in positions and in neutral pairs of charges."""
+    from oracle.twod import energy_gradients2d
+    pl = Plan2D(BOX, 20, lam=1.5)
+    x, q = _cell(40, seed=61)
+    E, dEdx, dEdq = energy_gradients2d(pl, x, q)
+    assert abs(E - _energy2d(pl, x, q)) < 1e-14 * abs(E)
+    assert abs(dEdq.sum()) < 1e-12 * np.abs(dEdq).sum()
+    P = np.array([[i * BOX[0], j * BOX[1]] for i in range(-3, 4) for j in range(-3, 4)])
+    d = np.abs(np.linalg.norm(x[:, None, :] + P[None, :, :], axis=2) - pl.R_b).min(axis=1)
+    h = 1e-5
+    for i in np.nonzero(d > 1e-3)[0][:5]:
+        for k in range(2):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (_energy2d(pl, xp, q) - _energy2d(pl, xm, q)) / (2 * h)
+            assert abs(dEdx[i, k] - fd) < 1e-7 * max(1.0, abs(fd))
+    for i, j in ((0, 1), (5, 33), (12, 39)):
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qp[j] -= h
+        qm[i] -= h
+        qm[j] += h
+        fd = (_energy2d(pl, x, qp) - _energy2d(pl, x, qm)) / (2 * h)
+        assert abs((dEdq[i] - dEdq[j]) - fd) < 1e-8 * max(1.0, abs(fd))
