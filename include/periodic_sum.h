@@ -146,8 +146,7 @@ typedef struct {
                              the two axes; C1 from the zero box mean with the closed-form potential of a
                              uniform rectangle.  z and target z pointers may be NULL (they are not read);
                              ez outputs, when given, receive zeros.  Spherical basis (meaning the plane's
-                             harmonic polynomials) only; periodic must be 0, 7 or 3; the exact adjoint is
-                             not available. */
+                             harmonic polynomials) only; periodic must be 0, 7 or 3. */
     int32_t reserved;     /* 0 */
 } ps_params;
 
@@ -256,8 +255,11 @@ ps_status periodic_sum_energy(ps_plan plan, int64_t n,
  *     derived from eqs. (3), (8), (10), (pfx3)-(pfx4) (the paper gives no adjoint).
  *   exact = 0: the physical approximation dE/dx_i = -q_i field_i, dE/dq_i = phi_i.
  * dE/dq is returned projected onto sum dq = 0 (mean removed): the Coulomb energy is
- * only defined for neutral charges.  Screened kernel: exact = 0 only (exact = 1
- * returns PS_E_UNSUPPORTED), and dE/dq = phi without projection (any charges).
+ * only defined for neutral charges (in 3-D and in the plane, whose moments use the
+ * plane's basis and K = -log r).  Screened kernel: u_t = sum_k q_k K(c_t - x_k) at
+ * the centres, K = exp(-kappa r)/r in psi, and dE/dq without projection (any
+ * charges).  With fewer than three periodic axes (slab, wire) only exact = 0 is
+ * available (exact = 1 returns PS_E_UNSUPPORTED).
  * Must follow a periodic_sum_energy (or eval at the
  * particles) with the same inputs on the same stream: it reuses that forward
  * pass's near set, coefficients and outputs kept in the plan.

@@ -1911,10 +1911,6 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     const SysDev& S = pl->tab.sys[0];
     if (exact && S.ndec > 0)
         return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with fewer than three periodic axes (exact = 0 is)");
-    if (exact && pl->kernel == PS_KERNEL_SCREENED)
-        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the screened kernel (exact = 0 is)");
-    if (exact && pl->dim == 2)
-        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available in the plane (exact = 0 is)");
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
@@ -1939,6 +1935,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         J.part = pl->d_adj_part;
         J.ncomp = 4;
         J.bt = bt;
+        J.kappa = pl->kappa;   // the screened kernel's constant (0 otherwise)
         const int64_t ntb = (nb + bt - 1) / bt;
         J.nsplit = static_cast<int>(std::min<int64_t>(split_for(ntb, kItemTarget), ns / kTile + 1));
         if (ntb > pl->adj_tb_cap || static_cast<int64_t>(J.nsplit) * 4 * nb > pl->adj_part_cap ||
@@ -1969,6 +1966,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
             Mj.part = pl->d_mom;
             Mj.ncomp = 1;
             Mj.bt = 256;
+            Mj.kappa = pl->kappa;
             Mj.nsplit = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(kMomBlocks, (n + kTile - 1) / kTile)));
             mom_blocks = Mj.nsplit;
             stride = S.M;
@@ -1989,7 +1987,11 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         HIPCHK(hipStreamSynchronize(st));
         if (S.basis == 1) {
             launch_tblock(static_cast<int64_t>(pl->mom_t.size()), pl->d_mom_job, pl->d_mom_t, st);
-            launch_p2p(0, 256, false, 0, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p, st);
+            launch_p2p(0, 256, false, pl->pair_kern, static_cast<int64_t>(pl->mom_p.size()), pl->d_mom_job, pl->d_mom_p,
+                       st);
+        } else if (S.dim == 2) {
+            mom_blocks = kMomWaves;
+            launch_moments2d(S.P, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sq, pl->d_mom, mom_blocks, st);
         } else {
             mom_blocks = kMomWaves;
             launch_moments(S.P, S.p, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_rec, pl->d_mom, mom_blocks,
@@ -1999,7 +2001,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
                                stride, toff, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az, pl->d_aq,
                                st);
         launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
-        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, 0, static_cast<int64_t>(pl->adj_p.size()),
+        launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, pl->pair_kern, static_cast<int64_t>(pl->adj_p.size()),
                    pl->d_adj_job, pl->d_adj_p, st);
     } else {
         ps_status s = ensure_adjoint_workspace(pl);

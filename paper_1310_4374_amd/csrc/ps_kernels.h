@@ -41,6 +41,9 @@ void launch_far(int lanes, int64_t nitems, int maxP, int maxp, const SysDev* sys
 
 namespace ps {
 void launch_energy(int nsys, const SysDev* sys, const double* sq, const double* osort, double* energy, hipStream_t st);
+// the plane's moments (basis 1, Re w^n, Im w^n)
+void launch_moments2d(int P, const SysDev* sys, const double* sx, const double* sy, const double* sq, double* mom_part,
+                      int mom_blocks, hipStream_t st);
 void launch_moments(int P, int p, const SysDev* sys, const double* sx, const double* sy, const double* sz,
                     const double* sq, const double* rec, double* mom_part, int mom_blocks, hipStream_t st);
 void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,

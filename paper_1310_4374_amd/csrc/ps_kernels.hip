@@ -1717,6 +1717,40 @@ __global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, c
     for (int t = threadIdx.x; t < P; t += 64) part[(int64_t)blockIdx.x * P + t] = acc[t];
 }
 
+// The plane's moments u_t = sum_k q_k R_t(x_k / R0): R_{2n-1} = Re w^n,
+// R_{2n} = Im w^n (w = (x + iy)/R0), reduced across the wave per term;
+// part[block][t] as k_moment.
+__global__ __launch_bounds__(64) void k_moment2d(const SysDev* __restrict__ sys, const double* __restrict__ sx,
+                                                 const double* __restrict__ sy, const double* __restrict__ sq,
+                                                 double* __restrict__ part)
+{
+    extern __shared__ double acc[];  // [P]
+    const SysDev& S = sys[0];
+    const int P = S.P, p = S.p;
+    for (int t = threadIdx.x; t < P; t += 64) acc[t] = 0.0;
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int64_t base = (int64_t)blockIdx.x * 64; base < S.n; base += (int64_t)gridDim.x * 64) {
+        const int64_t i = base + lane;
+        const bool v = i < S.n;
+        const double x = v ? sx[S.n_off + i] * S.inv_R0 : 0.0, y = v ? sy[S.n_off + i] * S.inv_R0 : 0.0;
+        const double q = v ? sq[S.n_off + i] : 0.0;
+        double wr = 1.0, wi = 0.0;
+        for (int n = 1; n < p; ++n) {
+            const double a = wr * x - wi * y, b = wr * y + wi * x;
+            wr = a;
+            wi = b;
+            const double sr = wave_sum(q * wr), si = wave_sum(q * wi);
+            if (lane == 0) {
+                acc[2 * n - 1] += sr;
+                acc[2 * n] += si;
+            }
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < P; t += 64) part[(int64_t)blockIdx.x * P + t] = acc[t];
+}
+
 // u = sum of the moment partials; w = (A^+)^T u; adjoint sources: the sorted
 // particles, then +w_l at the partners y~_l, then -w_l at the check points y_l.
 // (the moment partials hold u_t at part[b * stride + t - toff] for t >= 1)
@@ -1840,6 +1874,11 @@ void launch_moments(int P, int p, const SysDev* sys, const double* sx, const dou
 {
     PS_LAUNCH(k_moment, dim3(mom_blocks), dim3(64), (3 * P + p) * sizeof(double), st, sys, sx, sy, sz, sq, rec,
               mom_part);
+}
+void launch_moments2d(int P, const SysDev* sys, const double* sx, const double* sy, const double* sq, double* mom_part,
+                      int mom_blocks, hipStream_t st)
+{
+    PS_LAUNCH(k_moment2d, dim3(mom_blocks), dim3(64), P * sizeof(double), st, sys, sx, sy, sq, mom_part);
 }
 void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
                             const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,

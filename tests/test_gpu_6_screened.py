@@ -112,8 +112,7 @@ def test_screened_batch_matches_oracle_per_system(ps):
 
 def test_screened_plan_file_and_gradients(ps, tmp_path):
     """A reloaded plan gives bitwise the same sums; the physical gradient is
-    -q field and phi (no projection: any charges); the exact adjoint is refused."""
-    from paper_1310_4374_amd import PeriodicSumError
+    -q field and phi (no projection: any charges)."""
     x, q = W.uniform_box(800, BOX, charges="gauss", seed=97)
     q = q + 0.2
     cen = _centres()
@@ -135,8 +134,26 @@ def test_screened_plan_file_and_gradients(ps, tmp_path):
     assert np.allclose(gx.cpu().numpy(), -q[None, :] * f, rtol=0, atol=1e-12 * np.abs(f).max())
     assert np.allclose(gq.cpu().numpy(), phi0.cpu().numpy(), rtol=0, atol=1e-12 * np.abs(phi0.cpu().numpy()).max())
     assert abs(float(e.item()) - 0.5 * float(q @ phi0.cpu().numpy())) < 1e-10 * abs(float(e.item()))
-    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
-        pl.energy_vjp(X, Q, one, exact=True)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_screened_exact_adjoint_matches_oracle(ps, prec):
+    """The exact gradient of the screened method's energy (moments at the centres,
+    check-point charges w = (A^+)^T u, psi over the near images) against the
+    oracle's, itself pinned to finite differences; no projection of dE/dq."""
+    from oracle.screened import energy_gradients_screened
+    x, q = W.uniform_box(900, BOX, charges="gauss", seed=98)
+    q = q + 0.1
+    cen = _centres()
+    E, dx, dq = energy_gradients_screened(ScreenedPlan(BOX, 2.0, cen, 16, lam=1.5), x, q)
+    pl = ps.Plan(BOX, 16, lam=1.5, precision=prec, n_max=len(q), centres=cen, kernel="screened", kappa=2.0)
+    X, Q = dev(x.T), dev(q)
+    e = pl.energy(X, Q)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(X, Q, one, exact=True)
+    pl.status()
+    assert abs(float(e.item()) / E - 1) <= TOL[prec]
+    assert err(gx.cpu().numpy().T, dx) <= TOL[prec] and err(gq.cpu().numpy(), dq) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])

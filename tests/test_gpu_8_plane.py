@@ -122,8 +122,7 @@ def test_plane_batch(ps):
 
 def test_plane_plan_file_gradient_and_refusals(ps, tmp_path):
     """A reloaded plane plan gives bitwise the same sums; the physical gradient
-    works (-q field, phi projected), the exact adjoint and non-neutral charges are
-    refused."""
+    works (-q field, phi projected); non-neutral charges are refused."""
     from paper_1310_4374_amd import PeriodicSumError
     x, q = _cell(800, 206)
     pl = ps.Plan(BOX, 20, lam=1.5, precision="fp32", n_max=800, dim=2)
@@ -146,11 +145,28 @@ def test_plane_plan_file_gradient_and_refusals(ps, tmp_path):
     ph = phi0.cpu().numpy()
     assert np.allclose(gq.cpu().numpy(), ph - ph.mean(), rtol=0, atol=1e-12 * np.abs(ph).max())
     assert abs(float(e.item()) - 0.5 * float(q @ ph)) < 1e-10 * abs(float(e.item()))
-    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
-        pl.energy_vjp(X, Q, one, exact=True)
     pl.eval(X, dev(q + 0.1))
     with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
         pl.status()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plane_exact_adjoint_matches_oracle(ps, prec):
+    """The exact gradient of the plane method's energy (the plane's moments,
+    check-point charges, psi over the near images) against the oracle's, itself
+    pinned to finite differences; dE/dq projected onto sum dq = 0."""
+    from oracle.twod import energy_gradients2d
+    x, q = _cell(1000, 207)
+    E, dx, dq = energy_gradients2d(Plan2D(BOX, 24, lam=1.5), x, q)
+    pl = ps.Plan(BOX, 24, lam=1.5, precision=prec, n_max=len(q), dim=2)
+    X, Q = dev(x.T), dev(q)
+    e = pl.energy(X, Q)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(X, Q, one, exact=True)
+    pl.status()
+    assert abs(float(e.item()) / E - 1) <= TOL[prec]
+    assert gx.shape == (2, len(q))
+    assert err(gx.cpu().numpy().T, dx) <= TOL[prec] and err(gq.cpu().numpy(), dq) <= TOL[prec]
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
