@@ -182,6 +182,25 @@ class SlabPlan:
     def near(self, x, q):
         return slab_near_set(x, q, self.box, self.R_b)
 
+    def decay_sources(self, w_dec):
+        """The decay rows' adjoint sources for row weights w_dec (oracle/adjoint.py):
+        the plane points, their normal +z (the rows take E_z), a_i = sum_r w_r W_ri
+        and b_i = sum_r w_r (-s|k|) W_ri."""
+        pts, nrm, a, b = [], [], [], []
+        r = 0
+        for s, p_, proj in self.planes:
+            av = np.zeros(len(p_))
+            bv = np.zeros(len(p_))
+            for kk, wv in proj:
+                av += w_dec[r] * wv
+                bv += w_dec[r] * (-s * kk) * wv
+                r += 1
+            pts.append(p_)
+            nrm.append(np.tile([0.0, 0.0, 1.0], (len(p_), 1)))
+            a.append(av)
+            b.append(bv)
+        return np.concatenate(pts), np.concatenate(nrm), np.concatenate(a), np.concatenate(b)
+
     def far_field(self, C, y0):
         Rv, Rg = basis_fn(*(y0.T / self.R0), self.p, grad=True)
         phif = C[1:] @ Rv[1:]

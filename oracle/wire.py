@@ -145,6 +145,18 @@ class WirePlan:
     def near(self, x, q):
         return wire_near_set(x, q, self.box, self.R_b)
 
+    def decay_sources(self, w_dec):
+        """The decay rows' adjoint sources for row weights w_dec (oracle/adjoint.py):
+        the cylinder points, their outward normal (0, cos theta, sin theta) (the
+        rows take E_rho), a_i = sum_r w_r W_ri and b_i = sum_r w_r beta_r W_ri."""
+        a = np.zeros(len(self.pts))
+        b = np.zeros(len(self.pts))
+        for wr, (beta, wv) in zip(w_dec, self.modes):
+            a += wr * wv
+            b += wr * beta * wv
+        nrm = np.stack([np.zeros_like(self.theta), np.cos(self.theta), np.sin(self.theta)], axis=1)
+        return self.pts, nrm, a, b
+
     def rhs(self, xs, qs):
         """The periodicity rows, then -<(dphi_near/drho - beta phi_near) trig> per decay row."""
         phc = _native.direct(np.concatenate([self.yc, self.yt]), xs, qs, grad=False)

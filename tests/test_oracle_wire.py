@@ -187,3 +187,35 @@ def test_periodic_in_x_and_translation_invariant_along_x():
     d = phi2 - phi
     assert _rel(f2, f) < 6e-6
     assert np.linalg.norm(d - d.mean()) / np.linalg.norm(phi - phi.mean()) < 2.5e-5
+
+
+def test_wire_adjoint_matches_finite_differences():
+    """The exact energy gradient with the decay rows' adjoint sources (a charge and
+    a radial dipole at each cylinder point, oracle/adjoint.py) against central
+    differences (h = 1e-5) in positions and in neutral pairs of charges."""
+    from oracle.adjoint import energy_gradients_decay
+    pl = WirePlan(BOX, 8, lam=1.6)
+    x, q = W.uniform_box(30, BOX, charges="gauss", seed=5)
+
+    def energy(xx, qq):
+        phi, _ = pl.solve(xx, qq)
+        return 0.5 * float(qq @ phi)
+
+    E, dEdx, dEdq = energy_gradients_decay(pl, x, q)
+    assert abs(E - energy(x, q)) < 1e-14 * abs(E)
+    h = 1e-5
+    for i in (0, 3, 7):
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (energy(xp, q) - energy(xm, q)) / (2 * h)
+            assert abs(dEdx[i, k] - fd) < 2e-8 * max(1.0, abs(fd))
+    for i, j in ((0, 1), (4, 22)):
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qp[j] -= h
+        qm[i] -= h
+        qm[j] += h
+        fd = (energy(x, qp) - energy(x, qm)) / (2 * h)
+        assert abs((dEdq[i] - dEdq[j]) - fd) < 1e-8 * max(1.0, abs(fd))
