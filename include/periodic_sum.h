@@ -133,7 +133,7 @@ typedef struct {
                              for n = 0, by mx Gauss-Legendre points in x, mx = max(2p + 8,
                              ceil(40 d1 / R0)), times mt equispaced angles, mt = max(4p,
                              ceil(80 pi rho_d / R0)).  With fewer than three axes: spherical basis,
-                             Coulomb kernel; the exact adjoint is not available. */
+                             Coulomb kernel. */
     int32_t kernel;       /* ps_kernel (PS_KERNEL_COULOMB when zero-initialised) */
     double  kappa;        /* PS_KERNEL_SCREENED: the screening constant, 0 < kappa <= 64 / R0 */
     int32_t dim;          /* 0 or 3: three dimensions.  2: the method in the plane (Sec. 1 says it applies to
@@ -258,8 +258,10 @@ ps_status periodic_sum_energy(ps_plan plan, int64_t n,
  * only defined for neutral charges (in 3-D and in the plane, whose moments use the
  * plane's basis and K = -log r).  Screened kernel: u_t = sum_k q_k K(c_t - x_k) at
  * the centres, K = exp(-kappa r)/r in psi, and dE/dq without projection (any
- * charges).  With fewer than three periodic axes (slab, wire) only exact = 0 is
- * available (exact = 1 returns PS_E_UNSUPPORTED).
+ * charges).  With decay rows (slab, wire) w also weights them, and psi gains, at
+ * each decay point y_i with normal n_i, a charge b_i and a dipole -a_i n_i,
+ * a_i = sum_r w_r W_ri, b_i = sum_r w_r c_r W_ri (W_ri the row's quadrature weight
+ * and trigonometric factor at the point, c_r = -s|k| or beta).
  * Must follow a periodic_sum_energy (or eval at the
  * particles) with the same inputs on the same stream: it reuses that forward
  * pass's near set, coefficients and outputs kept in the plan.

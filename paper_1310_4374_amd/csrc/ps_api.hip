@@ -219,6 +219,8 @@ struct ps_plan_s {
     double *d_ax = nullptr, *d_ay = nullptr, *d_az = nullptr, *d_aq = nullptr;
     double *d_adj_tblk = nullptr, *d_adj_part = nullptr, *d_mom = nullptr;
     double *d_dq = nullptr, *d_dx = nullptr, *d_energy = nullptr;
+    // decay rows (slab, wire): their weights, the sources a, b per decay point, psi at the near entries
+    double *d_wdec = nullptr, *d_adj_da = nullptr, *d_adj_db = nullptr, *d_adj_dpart = nullptr;
     TItem* d_adj_t = nullptr;
     PItem* d_adj_p = nullptr;
     PJob* d_adj_job = nullptr;
@@ -1855,6 +1857,13 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_mom_t, 4096 / 256 + 1)
     AL(pl->d_mom_p, (4096 / 256 + 1) * kMomBlocks)
     AL(pl->d_mom_tblk, (4096 / 256 + 1) * 4)
+    AL(pl->d_wdec, std::max(1, S.ndec))
+    const int64_t npts = static_cast<int64_t>(S.nsurf) * S.m2;
+    if (S.ndec > 0) {
+        AL(pl->d_adj_da, npts)
+        AL(pl->d_adj_db, npts)
+        AL(pl->d_adj_dpart, 4 * ncap)
+    }
 #undef AL
     if (e != hipSuccess) return fail(PS_E_NOMEM, "adjoint workspace allocation failed: %s", hipGetErrorString(e));
     pl->adj_ready = true;
@@ -1909,8 +1918,7 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
-    if (exact && S.ndec > 0)
-        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available with fewer than three periodic axes (exact = 0 is)");
+    int64_t nb_dec = 0;   // near entries whose psi includes the decay points' part (slab, wire)
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
@@ -1999,16 +2007,23 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
         }
         launch_adjoint_sources(S.P, S.L, n, pl->d_sys, pl->d_sx, pl->d_sy, pl->d_sz, pl->d_sq, pl->d_mom, mom_blocks,
                                stride, toff, pl->d_pinv, pl->d_chk, pl->chk_tot, pl->d_ax, pl->d_ay, pl->d_az, pl->d_aq,
-                               st);
+                               pl->d_wdec, st);
         launch_tblock(static_cast<int64_t>(pl->adj_t.size()), pl->d_adj_job, pl->d_adj_t, st);
         launch_p2p(pl->precision == PS_FP32_ACC64 ? 1 : 0, bt, true, pl->pair_kern, static_cast<int64_t>(pl->adj_p.size()),
                    pl->d_adj_job, pl->d_adj_p, st);
+        if (S.ndec > 0) {
+            nb_dec = nb;
+            launch_adjoint_decay(static_cast<int64_t>(S.nsurf) * S.m2, nb, pl->d_sys, pl->d_dpts, pl->dec_tot, pl->d_dw,
+                                 pl->d_drows, pl->d_wdec, pl->d_adj_da, pl->d_adj_db, pl->d_nx, pl->d_ny, pl->d_nz,
+                                 pl->d_adj_dpart, st);
+        }
     } else {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
     }
-    launch_adjoint_finish(n, pl->d_sys, pl->d_adj_job, pl->d_inv, pl->d_sq, pl->d_osort, exact ? 1 : 0, pl->d_dq,
-                          pl->d_dx, pl->d_perm, gE, dEdq, dEdx, dEdy, dEdz, st);
+    launch_adjoint_finish(n, pl->d_sys, pl->d_adj_job, pl->d_inv, pl->d_sq, pl->d_osort, exact ? 1 : 0,
+                          nb_dec > 0 ? pl->d_adj_dpart : nullptr, nb_dec, pl->d_dq, pl->d_dx, pl->d_perm, gE, dEdq,
+                          dEdx, dEdy, dEdz, st);
     HIPCHK(hipGetLastError());
     return PS_OK;
 }

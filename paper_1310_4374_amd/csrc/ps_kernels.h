@@ -49,10 +49,15 @@ void launch_moments(int P, int p, const SysDev* sys, const double* sx, const dou
 void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
                             const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,
                             int toff, const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
-                            double* az, double* aq, hipStream_t st);
+                            double* az, double* aq, double* wdec, hipStream_t st);
+// the decay rows' adjoint sources (slab, wire) and their psi at the nb near entries
+void launch_adjoint_decay(int64_t npts, int64_t nb, const SysDev* sys, const double* dpts, int64_t dec_tot,
+                          const double* dw, const double* drows, const double* wdec, double* ad, double* bd,
+                          const double* nx, const double* ny, const double* nz, double* dpart, hipStream_t st);
 void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
-                           const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,
-                           double* oq, double* ox, double* oy, double* oz, hipStream_t st);
+                           const double* osort, int exact, const double* dpart, int64_t dstride, double* dq, double* dx,
+                           const int* perm, const double* gE, double* oq, double* ox, double* oy, double* oz,
+                           hipStream_t st);
 }  // namespace ps
 namespace ps {
 int p2p_blocks_per_cu(int prec, int bt);

@@ -1754,11 +1754,13 @@ __global__ __launch_bounds__(64) void k_moment2d(const SysDev* __restrict__ sys,
 // u = sum of the moment partials; w = (A^+)^T u; adjoint sources: the sorted
 // particles, then +w_l at the partners y~_l, then -w_l at the check points y_l.
 // (the moment partials hold u_t at part[b * stride + t - toff] for t >= 1)
+// The decay rows' weights w_r (rows L..Lf-1) go to wdec.
 __global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ sys, const double* __restrict__ part,
                                                      int nblk, int stride, int toff, const double* __restrict__ pinv,
                                                      const double* __restrict__ chk, int64_t chk_tot,
                                                      double* __restrict__ ax, double* __restrict__ ay,
-                                                     double* __restrict__ az, double* __restrict__ aq)
+                                                     double* __restrict__ az, double* __restrict__ aq,
+                                                     double* __restrict__ wdec)
 {
     extern __shared__ double u[];
     const SysDev& S = sys[0];
@@ -1786,6 +1788,118 @@ __global__ __launch_bounds__(256) void k_adj_weights(const SysDev* __restrict__ 
         az[o2] = cz[l];
         aq[o2] = -w;
     }
+    for (int l = S.L + threadIdx.x; l < S.Lf; l += 256) {
+        double w = 0.0;
+        for (int t = 1; t < P; ++t) w = __builtin_fma(pinv[S.pinv_off + (int64_t)(t - 1) * S.Lf + l], u[t], w);
+        wdec[l - S.L] = w;
+    }
+}
+
+// Adjoint sources of the decay rows (slab, wire): with the row weights w_r,
+// a_i = sum_r w_r W_ri and b_i = sum_r w_r c_r W_ri at decay point i, where
+// W_ri is row r's quadrature weight times its trigonometric factor at the point
+// (as in k_decay_rhs) and c_r = -s|k| (slab plane s) or beta (wire).  One
+// thread per point, rows in order.
+__global__ __launch_bounds__(256) void k_adj_decay_src(const SysDev* __restrict__ sys, const double* __restrict__ dpts,
+                                                       int64_t dec_tot, const double* __restrict__ dw,
+                                                       const double* __restrict__ drows,
+                                                       const double* __restrict__ wdec, double* __restrict__ ad,
+                                                       double* __restrict__ bd)
+{
+    const SysDev& S = sys[0];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)S.nsurf * S.m2) return;
+    const double x = dpts[S.dec_off + i], y = dpts[dec_tot + S.dec_off + i], z = dpts[2 * dec_tot + S.dec_off + i];
+    double a = 0.0, b = 0.0;
+    if (S.periodic == 1) {
+        const double th = atan2(z, y), wi = dw[S.dw_off + i];
+        for (int r = 0; r < S.ndec; ++r) {
+            const double* row = drows + S.drow_off + (int64_t)r * 5;
+            const double tx = row[3] != 0.0 ? sin(row[0] * x) : cos(row[0] * x);
+            const double tt = row[4] != 0.0 ? sin(row[1] * th) : cos(row[1] * th);
+            const double W = wdec[r] * (wi * (tx * tt));
+            a += W;
+            b = __builtin_fma(W, row[2], b);
+        }
+    } else {
+        const int plane = static_cast<int>(i / S.m2);
+        const double wi = dw[S.dw_off + i % S.m2];
+        for (int r = 0; r < S.ndec; ++r) {
+            const double* row = drows + S.drow_off + (int64_t)r * 5;
+            if ((row[3] > 0.0 ? 0 : 1) != plane) continue;
+            const double ph = row[0] * x + row[1] * y;
+            const double W = wdec[r] * (wi * (row[4] != 0.0 ? sin(ph) : cos(ph)));
+            a += W;
+            b = __builtin_fma(W, -row[3] * row[2], b);
+        }
+    }
+    ad[i] = a;
+    bd[i] = b;
+}
+
+// The decay points' part of psi at the near entries: a charge b_i and a dipole
+// -a_i n_i at each decay point y_i (n_i = +z on a slab's planes, the outward
+// radial direction on the wire's cylinder):
+//   psi(z) = sum_i b_i / r + a_i n_i . (y_i - z) / r^3,  r = |z - y_i|,
+// written as psi and the field -grad psi into dpart[4][stride], the layout of a
+// split of the adjoint pair sum.  The decay points stay R0/10 from every near
+// entry.  FP64; one thread per near entry, decay points staged in LDS.
+__global__ __launch_bounds__(256) void k_adj_decay(const SysDev* __restrict__ sys, const double* __restrict__ nx,
+                                                   const double* __restrict__ ny, const double* __restrict__ nz,
+                                                   int64_t nb, const double* __restrict__ dpts, int64_t dec_tot,
+                                                   const double* __restrict__ ad, const double* __restrict__ bd,
+                                                   double* __restrict__ dpart)
+{
+    __shared__ double sy[256][8];  // y, n, a, b
+    const SysDev& S = sys[0];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = e < nb;
+    const double zx = act ? nx[S.near_off + e] : 0.0, zy = act ? ny[S.near_off + e] : 0.0,
+                 zz = act ? nz[S.near_off + e] : 0.0;
+    const int64_t npts = (int64_t)S.nsurf * S.m2;
+    double ps = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int64_t t0 = 0; t0 < npts; t0 += 256) {
+        __syncthreads();
+        const int64_t j = t0 + threadIdx.x;
+        if (j < npts) {
+            const double x = dpts[S.dec_off + j], y = dpts[dec_tot + S.dec_off + j], z = dpts[2 * dec_tot + S.dec_off + j];
+            double nxv = 0.0, nyv = 0.0, nzv = 1.0;
+            if (S.periodic == 1) {
+                const double rho = sqrt(y * y + z * z);
+                nyv = y / rho;
+                nzv = z / rho;
+            }
+            sy[threadIdx.x][0] = x;
+            sy[threadIdx.x][1] = y;
+            sy[threadIdx.x][2] = z;
+            sy[threadIdx.x][3] = nxv;
+            sy[threadIdx.x][4] = nyv;
+            sy[threadIdx.x][5] = nzv;
+            sy[threadIdx.x][6] = ad[j];
+            sy[threadIdx.x][7] = bd[j];
+        }
+        __syncthreads();
+        const int cnt = npts - t0 < 256 ? static_cast<int>(npts - t0) : 256;
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = zx - sy[k][0], dy = zy - sy[k][1], dz = zz - sy[k][2];
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double ri = 1.0 / sqrt(r2), ri3 = ri * ri * ri;
+            const double nd = __builtin_fma(sy[k][5], dz, __builtin_fma(sy[k][4], dy, sy[k][3] * dx));  // n . (z - y)
+            const double a = sy[k][6], b = sy[k][7];
+            ps += b * ri - a * nd * ri3;
+            // grad psi = -b d / r^3 - a (n / r^3 - 3 (n . d) d / r^5)
+            const double c = 3.0 * a * nd * ri3 / r2 - b * ri3;
+            gx += c * dx - a * sy[k][3] * ri3;
+            gy += c * dy - a * sy[k][4] * ri3;
+            gz += c * dz - a * sy[k][5] * ri3;
+        }
+    }
+    if (act) {
+        dpart[e] = ps;
+        dpart[nb + e] = -gx;
+        dpart[2 * nb + e] = -gy;
+        dpart[3 * nb + e] = -gz;
+    }
 }
 
 __global__ void k_copy4(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
@@ -1804,9 +1918,11 @@ __global__ void k_copy4(int64_t n, const double* __restrict__ a, const double* _
 // image order) and form the unprojected gradients in sorted order:
 // dq[i] = (phi_i + sum psi)/2,  dx[k][i] = q_i/2 (grad phi_i + sum grad psi).
 // The pair kernel returned the field of psi, i.e. -grad psi.
+// dpart (may be null): psi and its field from the decay points, [4][dstride].
 __global__ __launch_bounds__(256) void k_adj_gather(const SysDev* __restrict__ sys, const PJob* __restrict__ ajob,
                                                     const int* __restrict__ inv, const double* __restrict__ sq,
                                                     const double* __restrict__ osort, int exact,
+                                                    const double* __restrict__ dpart, int64_t dstride,
                                                     double* __restrict__ dq, double* __restrict__ dx)
 {
     const SysDev& S = sys[0];
@@ -1832,6 +1948,12 @@ __global__ __launch_bounds__(256) void k_adj_gather(const SysDev* __restrict__ s
             fx += P_[J.nt + e];
             fy += P_[2 * J.nt + e];
             fz += P_[3 * J.nt + e];
+        }
+        if (dpart) {
+            ps += dpart[e];
+            fx += dpart[dstride + e];
+            fy += dpart[2 * dstride + e];
+            fz += dpart[3 * dstride + e];
         }
     }
     dq[i] = 0.5 * (o[0] + ps);
@@ -1883,19 +2005,30 @@ void launch_moments2d(int P, const SysDev* sys, const double* sx, const double* 
 void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const double* sx, const double* sy,
                             const double* sz, const double* sq, const double* mom_part, int mom_blocks, int stride,
                             int toff, const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
-                            double* az, double* aq, hipStream_t st)
+                            double* az, double* aq, double* wdec, hipStream_t st)
 {
     PS_LAUNCH(k_copy4, dim3((unsigned)std::min<int64_t>(1024, (n + 255) / 256)), dim3(256), 0, st, n, sx, sy, sz, sq,
               ax, ay, az, aq);
     PS_LAUNCH(k_adj_weights, dim3(1), dim3(256), P * sizeof(double), st, sys, mom_part, mom_blocks, stride, toff, pinv,
-              chk, chk_tot, ax, ay, az, aq);
+              chk, chk_tot, ax, ay, az, aq, wdec);
+}
+void launch_adjoint_decay(int64_t npts, int64_t nb, const SysDev* sys, const double* dpts, int64_t dec_tot,
+                          const double* dw, const double* drows, const double* wdec, double* ad, double* bd,
+                          const double* nx, const double* ny, const double* nz, double* dpart, hipStream_t st)
+{
+    if (npts <= 0 || nb <= 0) return;
+    PS_LAUNCH(k_adj_decay_src, dim3((unsigned)((npts + 255) / 256)), dim3(256), 0, st, sys, dpts, dec_tot, dw, drows,
+              wdec, ad, bd);
+    PS_LAUNCH(k_adj_decay, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sys, nx, ny, nz, nb, dpts, dec_tot, ad,
+              bd, dpart);
 }
 void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
-                           const double* osort, int exact, double* dq, double* dx, const int* perm, const double* gE,
-                           double* oq, double* ox, double* oy, double* oz, hipStream_t st)
+                           const double* osort, int exact, const double* dpart, int64_t dstride, double* dq, double* dx,
+                           const int* perm, const double* gE, double* oq, double* ox, double* oy, double* oz,
+                           hipStream_t st)
 {
-    PS_LAUNCH(k_adj_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sys, ajob, inv, sq, osort, exact, dq,
-              dx);
+    PS_LAUNCH(k_adj_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sys, ajob, inv, sq, osort, exact,
+              dpart, dstride, dq, dx);
     PS_LAUNCH(k_adj_finish, dim3(1), dim3(1024), 0, st, sys, perm, dq, dx, gE, oq, ox, oy, oz);
 }
 

@@ -114,8 +114,7 @@ def test_batch_of_wire_slab_and_three_axis_systems(ps):
 
 def test_wire_plan_file_and_adjoint_modes(ps, tmp_path):
     """A reloaded wire plan gives bitwise the same sums; the physical gradient
-    mode works, the exact adjoint of the decay rows is refused."""
-    from paper_1310_4374_amd import PeriodicSumError
+    mode works."""
     x, q = W.uniform_box(800, np.array(BOX), charges="gauss", seed=176)
     pl = ps.Plan(BOX, 10, lam=1.6, precision="fp32", n_max=800, periodic="x")
     X, Q = dev(x.T), dev(q)
@@ -133,8 +132,6 @@ def test_wire_plan_file_and_adjoint_modes(ps, tmp_path):
     gx, gq = pl.energy_vjp(X, Q, one, exact=False)
     f = field0.cpu().numpy()
     assert np.allclose(gx.cpu().numpy(), -q[None, :] * f, rtol=0, atol=1e-12 * np.abs(f).max())
-    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
-        pl.energy_vjp(X, Q, one, exact=True)
     del e
 
 
@@ -150,3 +147,21 @@ def test_wire_full_size_workload(ps, prec):
     sub = ref["subset"]
     assert pl.info()["n_near_last"] == int(ref["n_near"])
     assert err(phi[sub], ref["phi"]) <= TOL[prec] and err(field[sub], ref["field"]) <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wire_exact_adjoint_matches_oracle(ps, prec):
+    """The exact energy gradient with the decay rows: a charge and a dipole at each
+    decay point join psi (k_adj_decay_src, k_adj_decay), against the oracle's
+    gradient (oracle/adjoint.py, pinned to finite differences)."""
+    from oracle.adjoint import energy_gradients_decay
+    x, q = W.uniform_box(700, np.array(BOX), charges="gauss", seed=77)
+    E, dx, dq = energy_gradients_decay(WirePlan(np.array(BOX), 12, lam=1.6), x, q)
+    pl = ps.Plan(BOX, 12, lam=1.6, precision=prec, n_max=len(q), periodic="x")
+    X, Q = dev(x.T), dev(q)
+    e = pl.energy(X, Q)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(X, Q, one, exact=True)
+    pl.status()
+    assert abs(float(e.item()) / E - 1) <= TOL[prec]
+    assert err(gx.cpu().numpy().T, dx) <= TOL[prec] and err(gq.cpu().numpy(), dq) <= TOL[prec]
