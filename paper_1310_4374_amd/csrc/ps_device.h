@@ -15,6 +15,14 @@ constexpr int kGroup = 32;         // sources per near/far decision
 // error relative to the separation, and its square the cancellation in the
 // expanded r^2 = |t|^2 + |s|^2 - 2 t.s, in units of the rounding.
 constexpr double kFarFactor = 1.5;
+// The plane's -log r turns a relative error of r^2 into an absolute error of the
+// term (the log of the expanded r^2 carries it unscaled), so its FP32 kernels take
+// far groups only beyond 3 rT: ratio 2, cancellation at most 4 roundings.  At the
+// particle counts the plane is used with, blocks are small against the near
+// radius and the share of near groups barely moves.
+constexpr double kFarFactorPlane = 3.0;
+template <int KERN>
+constexpr double far_factor() { return KERN == 2 ? kFarFactorPlane : kFarFactor; }
 // -ln(2)/2: the plane's potential term -log(r) = kLog2Half log2(r^2)
 constexpr double kLog2Half = -0.34657359027997265471;
 // Waves per workgroup of the FP32 check-point sums (k_chk_f32): they share one

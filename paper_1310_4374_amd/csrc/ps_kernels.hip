@@ -468,7 +468,7 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
 // KERN = 2, the plane's -log r (every z is 0): the potential accumulates
 // q log2(r^2), scaled by -ln(2)/2 once at the end, and the field weight is
 // q / r^2; a masked pair gives zero terms, padding (r^2 = 2^120) finite ones
-// times q = 0.
+// times q = 0.  Its far groups start at far_factor<2>() block radii (ps_device.h).
 template <bool NEAR, bool FIELD, int KERN>
 __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
                                             float hy, float hz, float lx, float ly, float lz, float tt, float kap,
@@ -596,7 +596,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
     const bool active = i < J.nt;
     const double* tb = J.tblk + (int64_t)it.tb * 4;
     const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
-    const double far2 = kFarFactor * kFarFactor * rT * rT;
+    const double far2 = far_factor<KERN>() * far_factor<KERN>() * rT * rT;
     double rx = 0.0, ry = 0.0, rz = 0.0;
     if (active) {
         rx = J.tx[i] - cx;
@@ -914,7 +914,7 @@ __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jo
     const bool active = i < J.nt;
     const double* tb = J.tblk + (int64_t)it.tb * 4;
     const double cx = tb[0], cy = tb[1], cz = tb[2], rT = tb[3];
-    const double far2 = kFarFactor * kFarFactor * rT * rT;
+    const double far2 = far_factor<KERN>() * far_factor<KERN>() * rT * rT;
     double rx = 0.0, ry = 0.0, rz = 0.0;
     if (active) {
         rx = J.tx[i] - cx;
