@@ -30,6 +30,10 @@ Parts:
     for K = -log r: harmonic-polynomial basis, check points on the
     circumcircle, the uniform-rectangle box mean; an independent 2-D Ewald
     split, the Jacobi theta-function closed form and brute-force squares;
+  * ``biharmonic`` -- the method for K = r (the biharmonic equation, whose
+    null space Sec. 3 names as the Laplace kernel's): the Almansi basis
+    (harmonics and |u|^2 times harmonics), value and gradient periodicity
+    rows, the closed-form box mean of r; and an independent Ewald-type split;
   * ``pairs.c`` -- FP64 compensated direct sums (eq. (r2)), OpenMP over targets.
 
 Pins (tests/test_oracle_*.py): the basis against an independent assembly from
@@ -56,5 +60,10 @@ translation invariance along x; the 2-D basis against closed forms, harmonicity
 and differences, the rectangle potential against quadrature and its Laplacian,
 the 2-D Ewald split against its parameter, the theta-function closed form and
 brute-force squares of images, and the 2-D method against Ewald (other cells,
-a strong dipole, targets on particles), periodicity and translation invariance.
+a strong dipole, targets on particles), periodicity and translation invariance;
+the biharmonic corner primitive against its third derivative and quadrature,
+its box mean's Laplacian against twice Phi0, the Almansi basis against the far
+expansion of r, the biharmonic split against its parameter, periodicity and
+Delta phi = 2 phi_Coulomb, and the biharmonic method against that split (to
+1e-12), its convergence in p and translation invariance.
 """

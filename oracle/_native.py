@@ -41,6 +41,9 @@ def lib():
         _lib.orc_ewald_screened_real.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, D, D,
                                                  dp, dp, dp, dp]
         _lib.orc_direct_log2d.argtypes = [L, dp, dp, L, dp, dp, dp, L, dp, dp, dp, dp, dp]
+        _lib.orc_direct_dist.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, dp, dp, dp, dp]
+        _lib.orc_ewald_bih_real.argtypes = [L, dp, dp, dp, L, dp, dp, dp, dp, L, dp, dp, dp, D, D,
+                                            dp, dp, dp, dp]
     return _lib
 
 
@@ -156,3 +159,34 @@ def direct_log2d(targets, sources, q, shifts=None, grad=True):
     lib().orc_direct_log2d(n, _p(tx), _p(ty), sx.size, _p(sx), _p(sy), _p(sq), px.size, _p(px), _p(py), _p(phi),
                            *(tuple(_p(a) for a in g) if grad else (null, null)))
     return (phi, np.stack(g, axis=1)) if grad else phi
+
+
+def direct_dist(targets, sources, q, shifts=None, grad=True):
+    """The biharmonic kernel: phi(y) = sum_p sum_j q_j |y - x_j - p| (K(0) = 0) over
+    the given shifts (default: none, the free-space sum), and grad phi."""
+    tx, ty, tz = _cols(targets)
+    sx, sy, sz = _cols(sources)
+    px, py, pz = _cols(np.zeros((1, 3)) if shifts is None else shifts)
+    sq = np.ascontiguousarray(q, dtype=np.float64)
+    n = tx.size
+    phi = np.zeros(n)
+    g = [np.zeros(n) for _ in range(3)] if grad else None
+    null = ctypes.POINTER(ctypes.c_double)()
+    lib().orc_direct_dist(n, _p(tx), _p(ty), _p(tz), sx.size, _p(sx), _p(sy), _p(sz), _p(sq),
+                          px.size, _p(px), _p(py), _p(pz), _p(phi),
+                          *(tuple(_p(a) for a in g) if grad else (null, null, null)))
+    return (phi, np.stack(g, axis=1)) if grad else phi
+
+
+def ewald_bih_real(targets, sources, q, shifts, alpha, rcut):
+    tx, ty, tz = _cols(targets)
+    sx, sy, sz = _cols(sources)
+    px, py, pz = _cols(shifts)
+    sq = np.ascontiguousarray(q, dtype=np.float64)
+    n = tx.size
+    phi = np.zeros(n)
+    g = [np.zeros(n) for _ in range(3)]
+    lib().orc_ewald_bih_real(n, _p(tx), _p(ty), _p(tz), sx.size, _p(sx), _p(sy), _p(sz), _p(sq),
+                             px.size, _p(px), _p(py), _p(pz), float(alpha), float(rcut),
+                             _p(phi), *(_p(a) for a in g))
+    return phi, np.stack(g, axis=1)

@@ -4,7 +4,8 @@
  * TEST INFRASTRUCTURE ONLY: this file belongs to the CPU oracle.  Only the
  * test-suite, the smoke check and the benchmark's CPU-baseline leg may load it.
  *
- * Kernel K(r) = 1/|r|, with K(0) = 0 (paper Sec. 1, eq. (1)): a pair whose
+ * Kernel K(r) = 1/|r| (and, below, exp(-kappa r)/r, -log r in 2-D and r),
+ * with K(0) = 0 (paper Sec. 1, eq. (1)): a pair whose
  * squared distance is exactly zero contributes nothing.  Every sum is a plain
  * loop over all sources with Neumaier-compensated accumulation; OpenMP splits
  * the targets only, so each target's sum has a fixed order.
@@ -262,5 +263,81 @@ void orc_direct_log2d(long nt, const double* tx, const double* ty,
         }
         phi[i] = acc_get(&p);
         if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* The biharmonic kernel K(r) = r (Delta^2 r = -8 pi delta in 3-D), K(0) = 0. */
+/* grad_y K(y - x) = (y - x) / r.                                             */
+
+/* phi(y) = sum_m sum_j q_j |y - x_j - p_m| over a list of shifts p_m (one zero
+ * shift gives the free-space finite sum), and grad phi; gx may be NULL. */
+void orc_direct_dist(long nt, const double* tx, const double* ty, const double* tz,
+                     long ns, const double* sx, const double* sy, const double* sz, const double* sq,
+                     long nimg, const double* px, const double* py, const double* pz,
+                     double* phi, double* gx, double* gy, double* gz)
+{
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nt; ++i) {
+        acc_t p = {0, 0}, ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (long m = 0; m < nimg; ++m) {
+            const double yx = tx[i] - px[m], yy = ty[i] - py[m], yz = tz[i] - pz[m];
+            for (long j = 0; j < ns; ++j) {
+                double dx = yx - sx[j], dy = yy - sy[j], dz = yz - sz[j];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0) continue;
+                double r = sqrt(r2);
+                acc_add(&p, sq[j] * r);
+                if (gx) {
+                    double g = sq[j] / r;
+                    acc_add(&ax, g * dx);
+                    acc_add(&ay, g * dy);
+                    acc_add(&az, g * dz);
+                }
+            }
+        }
+        phi[i] = acc_get(&p);
+        if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
+    }
+}
+
+/* Real-space part of an Ewald split of K(r) = r.  With m = r * g_alpha (the
+ * kernel smoothed by the normalized Gaussian exp(-alpha^2 r^2)), the remainder
+ * r - m = S(r) - 1/(2 alpha^2 r), where
+ *   S(r) = r erfc(alpha r) + erfc(alpha r)/(2 alpha^2 r) - exp(-alpha^2 r^2)/(alpha sqrt(pi))
+ * decays like a Gaussian and
+ *   dS/dr = erfc(alpha r) (1 - 1/(2 alpha^2 r^2)) - exp(-alpha^2 r^2)/(alpha sqrt(pi) r).
+ * This routine sums S over images within rcut (r = 0 skipped). */
+void orc_ewald_bih_real(long nt, const double* tx, const double* ty, const double* tz,
+                        long ns, const double* sx, const double* sy, const double* sz, const double* sq,
+                        long nimg, const double* px, const double* py, const double* pz,
+                        double alpha, double rcut,
+                        double* phi, double* gx, double* gy, double* gz)
+{
+    const double inv_sqrtpi = 0.56418958354775628695;
+    const double rc2 = rcut * rcut, h = 1.0 / (2.0 * alpha * alpha), ea = inv_sqrtpi / alpha;
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nt; ++i) {
+        acc_t p = {0, 0}, ax = {0, 0}, ay = {0, 0}, az = {0, 0};
+        for (long m = 0; m < nimg; ++m) {
+            const double yx = tx[i] - px[m], yy = ty[i] - py[m], yz = tz[i] - pz[m];
+            for (long j = 0; j < ns; ++j) {
+                double dx = yx - sx[j], dy = yy - sy[j], dz = yz - sz[j];
+                double r2 = dx * dx + dy * dy + dz * dz;
+                if (r2 == 0.0 || r2 > rc2) continue;
+                double r = sqrt(r2);
+                double ec = erfc(alpha * r), ex = exp(-alpha * alpha * r2);
+                acc_add(&p, sq[j] * (r * ec + h * ec / r - ea * ex));
+                if (gx) {
+                    double ds = ec * (1.0 - h / r2) - ea * ex / r;
+                    double g = sq[j] * ds / r;   /* grad_y = dS/dr (y - x)/r */
+                    acc_add(&ax, g * dx);
+                    acc_add(&ay, g * dy);
+                    acc_add(&az, g * dz);
+                }
+            }
+        }
+        phi[i] = acc_get(&p);
+        if (gx) { gx[i] = acc_get(&ax); gy[i] = acc_get(&ay); gz[i] = acc_get(&az); }
     }
 }
