@@ -37,6 +37,7 @@ FP64_TFLOPS = 78.6
 FLOP_PER_PAIR = 20         # potential + field: 3 sub, r^2 (mul + 2 FMA), rsqrt, 3 mul, add, 3 FMA
 FLOP_PER_PAIR_SCREENED = 25  # the same plus r = r^2/r, kappa r, exp, the factor e, and 1/r + kappa
 FLOP_PER_PAIR_PLANE = 14     # the plane's -log r: 2 sub, r^2 (mul + FMA), log, reciprocal, q log, add, q/r^2, 2 FMA
+FLOP_PER_PAIR_BIH = 20       # the biharmonic r: 3 sub, r^2 (mul + 2 FMA), rsqrt, r = r^2/r, q r, add, -q/r, 3 FMA
 
 
 def log(*a):
@@ -155,7 +156,8 @@ def main():
     ap.add_argument("--no-cube", action="store_true", help="skip the uniform-cube figures of the default line")
     ap.add_argument("--tile-targets", type=int, default=0, help="targets per workgroup (0: library default)")
     ap.add_argument("--workload", default="clustered",
-                    choices=["clustered", "cube", "screened", "slab", "wire", "plane", "batch", "rocksalt", "bases",
+                    choices=["clustered", "cube", "screened", "slab", "wire", "plane", "biharmonic", "batch",
+                             "rocksalt", "bases",
                              "aspect", "small", "select"],
                     help="clustered (default): the headline solve; the others measure the uniform cube, the "
                          "batched, differentiated and paper-table workloads")
@@ -182,7 +184,7 @@ def main():
         out = {"screened": bench_screened, "batch": bench_batch, "rocksalt": bench_rocksalt, "bases": bench_bases,
                "aspect": bench_aspect, "small": bench_small, "select": bench_select,
                "slab": lambda a: bench_partial(a, "xy"), "wire": lambda a: bench_partial(a, "x"),
-               "plane": bench_plane}[args.workload](args)
+               "plane": bench_plane, "biharmonic": bench_biharmonic}[args.workload](args)
         print(json.dumps(out), flush=True)
         return
     if args.workload == "cube":
@@ -410,6 +412,51 @@ def bench_plane(args):
             "roofline": roofline(args.precision, n, nb, st["pairs"],
                                  "k_p2p_%s<%d,field,plane>" % ("f32" if f32 else "f64", info["tile_targets"]), None,
                                  FLOP_PER_PAIR_PLANE),
+            "stage_ms": st, "set_s": t_set, "accuracy": acc}
+
+
+def bench_biharmonic(args):
+    """The biharmonic kernel r (workloads.config_biharmonic): N = 100,000 uniform
+    in the unit cube, p = 24 (P = 1060, 4L = 4512 fit rows), lambda = 1.5."""
+    import torch
+    import paper_1310_4374_amd as ps
+    import workloads as W
+    c = W.config_biharmonic()
+    n = len(c["q"])
+    dev = torch.device("cuda", 0)
+    x = torch.tensor(np.ascontiguousarray(c["x"].T), device=dev)
+    q = torch.tensor(c["q"], device=dev)
+    t_set = time.perf_counter()
+    plan = ps.Plan(c["box"], c["p"], lam=c["lam"], precision=args.precision, n_max=n, kernel="biharmonic",
+                   tile_targets=args.tile_targets)
+    t_set = time.perf_counter() - t_set
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    field = torch.empty(3, n, dtype=torch.float64, device=dev)
+    steps = max(20, 2 * args.steps)
+    ms, st = timed_solves(plan, x, q, phi, field, steps, max(3, args.warmup))
+    info = plan.info()
+    nb, L = info["n_near_last"], info["L"]
+    pairs_per_step = (n + 2 * L) * nb
+    acc = {}
+    path = os.path.join(ROOT, "tests", "golden", "ref_biharmonic.npz")
+    if os.path.exists(path):
+        ref = np.load(path)
+        sub = ref["subset"]
+        ph, fd = phi.cpu().numpy()[sub], field.cpu().numpy().T[sub]
+        acc["ref_biharmonic"] = {"targets": int(len(sub)), "rel_l2_phi": _rel(ph, ref["phi"]),
+                                 "rel_l2_field": _rel(fd, ref["field"]), "worst_phi": _worst(ph, ref["phi"]),
+                                 "worst_field": _worst(fd, ref["field"])}
+    f32 = args.precision == "fp32"
+    return {"metric": METRIC, "value": pairs_per_step / (ms * 1e-3), "unit": "pair interactions/s",
+            "n_gpus": 1, "steps": steps, "warmup": max(3, args.warmup), "ms_per_step": ms, "solves_per_s": 1e3 / ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if f32 else "f64",
+            "data": "synthetic (seeded uniform positions, Gaussian charges minus their mean)",
+            "config": {"workload": "the biharmonic kernel r, unit cube, N=100000, q~N(0,1)-mean, p=24 (P=1060), "
+                                   "lambda=1.5", "N": n, "p": c["p"], "P": info["P"], "L": L, "n_near": nb,
+                       "pairs_per_solve": pairs_per_step},
+            "roofline": roofline(args.precision, n, nb, st["pairs"],
+                                 "k_p2p_%s<%d,field,biharmonic>" % ("f32" if f32 else "f64", info["tile_targets"]),
+                                 None, FLOP_PER_PAIR_BIH),
             "stage_ms": st, "set_s": t_set, "accuracy": acc}
 
 

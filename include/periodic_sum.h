@@ -86,12 +86,26 @@ typedef enum {
 
 typedef enum {
     PS_KERNEL_COULOMB = 0,  /* K(r) = 1/r, eq. (2) */
-    PS_KERNEL_SCREENED = 1  /* K(r) = exp(-kappa r)/r, the screened Coulomb (Yukawa) kernel: one of the
+    PS_KERNEL_SCREENED = 1, /* K(r) = exp(-kappa r)/r, the screened Coulomb (Yukawa) kernel: one of the
                                "other kernels" the method applies to (Sec. 1).  Its lattice sum converges
                                absolutely, so the charges need not be neutral; Delta - kappa^2 has no nonzero
                                bounded periodic solution, so the fit has no null space: every coefficient of the
                                kernel-at-centres basis (eq. (5)) comes from A^+ f, and there is no constant C1
                                (the mean setting is ignored).  Needs PS_BASIS_RBF, periodic = 7. */
+    PS_KERNEL_BIHARMONIC = 2  /* K(r) = r, the free-space Green's function of the biharmonic operator
+                               (Delta^2 r = -8 pi delta): one of the equations that share the Laplace
+                               kernel's null space, the constants (Sec. 3, null space of A).  Neutral
+                               charges; C1 from the zero box mean (the closed-form mean of r over the
+                               box) or 0.  Basis (Almansi): the p^2 renormalized solid harmonics of
+                               degree <= p-1, then |y/R0|^2 times those of degree <= p-3,
+                               P = p^2 + (p-2)^2; coef holds C1, the harmonics' C_2..C_{p^2}, then
+                               the second set.  The fit has 4L rows: the L value rows, then for
+                               k = x, y, z the L rows asking for the same periodicity of
+                               d/du_k (u = y/R0) at each check pair (values alone do not fix a
+                               biharmonic function), so the check-point sums carry the field.
+                               Outputs: phi = sum q |x - x_j| periodized, E = -grad phi.  Needs
+                               PS_BASIS_SPHERICAL, periodic = 7, dim 3, 3 <= p <= 30; energy_vjp with
+                               exact = 1 is refused (PS_E_UNSUPPORTED). */
 } ps_kernel;
 
 typedef struct {

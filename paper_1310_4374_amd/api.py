@@ -14,7 +14,7 @@ from ._lib import check, lib, ps_params, ps_plan_info, ps_select_row
 _PREC = {"fp64": _lib.PS_FP64, "fp32": _lib.PS_FP32_ACC64, "fp32_acc64": _lib.PS_FP32_ACC64}
 _MEAN = {"zero": _lib.PS_MEAN_ZERO, "none": _lib.PS_MEAN_NONE}
 _PERIODIC = {"xyz": 7, "xy": 3, "x": 1}
-_KERNEL = {"coulomb": 0, "screened": 1}
+_KERNEL = {"coulomb": 0, "screened": 1, "biharmonic": 2}
 
 
 def _host_points(a):
@@ -31,7 +31,8 @@ def _params(box, p, R_b=None, lam=None, precision="fp64", mean="zero", rcond=1e-
             kappa=0.0, dim=3):
     """keep: a list that receives the host arrays the struct points to.
     periodic: "xyz" (three periodic axes), "xy" (a slab, z free) or "x" (a wire, y and z free).
-    kernel: "coulomb" (1/r; -log r in the plane) or "screened" (exp(-kappa r)/r; needs centres).
+    kernel: "coulomb" (1/r; -log r in the plane), "screened" (exp(-kappa r)/r; needs centres) or
+    "biharmonic" (r; spherical basis, three periodic axes).
     dim: 3, or 2 for the method in the plane (box (d1, d2))."""
     prm = ps_params()
     for k in range(len(box) if int(dim) == 2 else 3):
@@ -126,8 +127,9 @@ class Plan:
         circumsphere; None for the Gauss spherical grid.  periodic: "xyz", or
         "xy" for a slab (periodic in x and y, vacuum above and below), or "x" for
         a wire (periodic in x, vacuum around it).
-        kernel: "coulomb" (1/r) or "screened" (exp(-kappa r)/r, any net charge,
-        RBF centres required, no constant term).  dim=2: the method in the plane
+        kernel: "coulomb" (1/r), "screened" (exp(-kappa r)/r, any net charge,
+        RBF centres required, no constant term) or "biharmonic" (r, neutral
+        charges, P = p^2 + (p-2)^2, no exact energy adjoint).  dim=2: the method in the plane
         (box (d1, d2), kernel -log r, positions (2, N), field (2, N))."""
         self.device = torch.device("cuda", device)
         self.dim = int(dim) if int(dim) == 2 else 3

@@ -341,8 +341,12 @@ ps_status check_params(const ps_params* prm)
         return fail(PS_E_UNSUPPORTED, "periodic axes must be 0 or 7 (x, y, z), 3 (x, y) or 1 (x)");
     if (periodic_axes(prm->periodic) != 7 && prm->basis == PS_BASIS_RBF)
         return fail(PS_E_UNSUPPORTED, "the RBF basis needs three periodic axes");
-    if (prm->kernel != PS_KERNEL_COULOMB && prm->kernel != PS_KERNEL_SCREENED)
+    if (prm->kernel != PS_KERNEL_COULOMB && prm->kernel != PS_KERNEL_SCREENED && prm->kernel != PS_KERNEL_BIHARMONIC)
         return fail(PS_E_INVALID, "unknown kernel %d", prm->kernel);
+    if (prm->kernel == PS_KERNEL_BIHARMONIC &&
+        (prm->basis != PS_BASIS_SPHERICAL || periodic_axes(prm->periodic) != 7 || plane || prm->p < 3 || prm->p > 30))
+        return fail(PS_E_UNSUPPORTED, "the biharmonic kernel needs the spherical basis, 3 <= p <= 30, three periodic "
+                                      "axes and three dimensions");
     if (prm->kernel == PS_KERNEL_SCREENED && (prm->basis != PS_BASIS_RBF || periodic_axes(prm->periodic) != 7))
         return fail(PS_E_UNSUPPORTED, "the screened kernel needs the RBF basis and three periodic axes");
     for (int k = 0; k < (plane ? 2 : 3); ++k)
@@ -408,10 +412,18 @@ int check_splits(int64_t ntb_c, int waves, int64_t ntiles_exp, int nsys)
     return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>(kMaxCheckSplit, items), by_tiles)));
 }
 
-// The check-point sums run in FP32 in the FP32 form.  (Running the plane's in
-// FP64 was measured: 0.25 ms more per 1e5-particle solve and no change in the
-// errors against the FP64 oracle, so they stay FP32.)
-bool check_f32(const ps_plan_s* pl) { return pl->precision == PS_FP32_ACC64; }
+// The biharmonic fit has gradient rows: its check-point sums carry the field too
+// and run in the FP64 particle pair kernel in either precision.  (Each term q r
+// is of the size of the near radius and their sum exceeds the result many
+// times over; the check targets' blocks are wide, so the FP32 kernels' far form
+// seldom applies to them, and FP32 rounding of these sums reached the
+// coefficients at 1e-6 of the result.)
+bool check_field(const ps_plan_s* pl) { return pl->kernel == PS_KERNEL_BIHARMONIC; }
+
+// The potential-only check-point sums run in FP32 in the FP32 form.  (Running
+// the plane's in FP64 was measured: 0.25 ms more per 1e5-particle solve and no
+// change in the errors against the FP64 oracle, so they stay FP32.)
+bool check_f32(const ps_plan_s* pl) { return pl->precision == PS_FP32_ACC64 && !check_field(pl); }
 
 // Waves per workgroup of the check-point sums: kChkWaves sharing a 64-target
 // block (FP32), else one per 64 targets of the bt_chk-wide blocks (FP64).
@@ -507,7 +519,7 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     }
     const bool separate = m > 0;
     const int bt = pl->bt;
-    // jobs: check-point sums (potential only), then particle sums, then RBF far
+    // jobs: check-point sums (potential; with the field for the biharmonic kernel), then particle sums, then RBF far
     // fields, then the decay-surface sums (potential and field)
     T.jobs.resize(4 * nsys);
     int64_t pc_off = 0, pp_off = 0, tb_c_off = 0, tb_p_off = 0;
@@ -533,10 +545,10 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
         const double nb_exp = near_expected(su, S.n);
         const int64_t ntiles_exp = static_cast<int64_t>(nb_exp / kTile) + 1;
         C.nsplit = check_splits(ntb_c, check_waves(pl), ntiles_exp, nsys);
-        C.ncomp = 1;
+        C.ncomp = check_field(pl) ? 4 : 1;
         C.bt = pl->bt_chk;
         C.part = pl->d_part_chk + pc_off;
-        pc_off += static_cast<int64_t>(C.nsplit) * C.nt;
+        pc_off += static_cast<int64_t>(C.nsplit) * C.ncomp * C.nt;
         for (int64_t tb = 0; tb < ntb_c; ++tb) {
             T.t_items.push_back(TItem{s, static_cast<int>(tb)});
             for (int sp = 0; sp < C.nsplit; ++sp) T.chk_items.push_back(PItem{s, static_cast<int>(tb), sp, 0});
@@ -747,7 +759,8 @@ bool build_tables(ps_plan_s* pl, const std::vector<int64_t>& n, int64_t m, const
     T.np = T.p_items.size();
     // the same jobs with the partial-sum layout in the static scratch
     // (periodic_sum_eval_noalloc): check partials first, then the particle partials
-    T.scratch_fits = pl->d_scratch && !pl->any_rbf && !pl->any_decay && T.scratch_need <= kScratchDoubles;
+    T.scratch_fits = pl->d_scratch && !pl->any_rbf && !pl->any_decay && !check_field(pl) &&
+                     T.scratch_need <= kScratchDoubles;
     T.jobs_s = T.jobs;
     if (T.scratch_fits) {
         const int64_t pc_tot = T.scratch_need - pp_off;
@@ -843,6 +856,8 @@ void enqueue_get(ps_plan_s* pl, const double* x, const double* y, const double* 
     mark(3);
     if (check_f32(pl))  // step 3 at the check points
         launch_chk_f32(pl->pair_kern, T.nchk, cjobs, pl->d_chk_items, st);
+    else if (check_field(pl))
+        launch_p2p(0, pl->bt_chk, true, pl->pair_kern, T.nchk, cjobs, pl->d_chk_items, st);
     else
         launch_p2p(0, pl->bt_chk, false, pl->pair_kern, T.nchk, cjobs, pl->d_chk_items, st);
     if (T.nd > 0) {  // fewer than three periodic axes: near sums at the decay surfaces, then the decay rows of f
@@ -894,7 +909,7 @@ ps_status init_plan(ps_plan_s* pl, int nsys, const ps_params* prm, int device)
     pl->kernel = prm[0].kernel;
     pl->kappa = prm[0].kernel == PS_KERNEL_SCREENED ? prm[0].kappa : 0.0;
     pl->dim = prm[0].dim == 2 ? 2 : 3;
-    pl->pair_kern = pl->dim == 2 ? 2 : pl->kernel;
+    pl->pair_kern = pl->dim == 2 ? 2 : (pl->kernel == PS_KERNEL_BIHARMONIC ? 3 : pl->kernel);
     if (pl->kernel == PS_KERNEL_SCREENED) pl->mean = PS_MEAN_NONE;   // no constant to fix
     pl->bt = prm[0].tile_targets ? prm[0].tile_targets : (nsys > 1 ? 128 : 256);
     pl->n_split_req = prm[0].n_split;
@@ -1018,7 +1033,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
         S.L = su.L;
         S.nimg = static_cast<int>(su.images.size() / 3);
         S.mean_mode = pl->mean;
-        S.kernel = su.dim == 2 ? 2 : su.kernel;
+        S.kernel = su.dim == 2 ? 2 : (su.kernel == 2 ? 3 : su.kernel);
         S.kappa = su.kappa;
         S.basis = su.basis;
         S.dim = su.dim;
@@ -1191,7 +1206,7 @@ ps_status finish_plan(ps_plan_s* pl, ps_plan* out)
     pl->tblk_chk_cap = tb_c;
     pl->cap_chk = chk_items_cap;
     pl->cap_p = std::max<int64_t>(tb_p * kMaxSplit, 1);
-    pl->part_chk_cap = chk_tot * kMaxCheckSplit + 16;
+    pl->part_chk_cap = chk_tot * kMaxCheckSplit * (check_field(pl) ? 4 : 1) + 16;
     pl->part_p_cap = std::max<int64_t>(4 * nt_sum * 16, 4 * (int64_t)kItemTarget * 256 * 2) + 4 * nt_sum * 8;
     if (pl->n_split_req > 0) pl->part_p_cap = std::max<int64_t>(pl->part_p_cap, 4 * nt_sum * pl->n_split_req);
     hipError_t e = hipSuccess;
@@ -1924,6 +1939,8 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
     int64_t nb_dec = 0;   // near entries whose psi includes the decay points' part (slab, wire)
+    if (exact && pl->kernel == PS_KERNEL_BIHARMONIC)
+        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the biharmonic kernel (exact = 0 works)");
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;

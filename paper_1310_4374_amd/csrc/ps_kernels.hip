@@ -142,17 +142,42 @@ __global__ __launch_bounds__(64) void k_validate_final(const SysDev* __restrict_
 }
 
 // ----------------------------------------------------------------------------
-// spatial ordering: counting sort of particles by Morton-ordered cell, with
-// each cell's entries put back in index order (deterministic result)
+// spatial ordering: counting sort of particles by the Hilbert index of their
+// cell, with each cell's entries put back in index order (deterministic result)
 // ----------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t spread3(uint32_t v)
+// Hilbert index of cell c on the 2^b grid of n axes (3, or 2 in the plane):
+// Skilling's transform of the axes to the transposed index ("Programming the
+// Hilbert curve", 2004), then its bits interleaved from the top.  Consecutive
+// indices are face-adjacent cells, so BT consecutive particles stay compact;
+// the Morton order jumps across the box at its octant boundaries, which left a
+// few target blocks 4-5 times wider than the rest (measured on 1e5 uniform
+// particles in 256-target blocks: largest block radius 0.70 against 0.18, and
+// the sum of the radii cubed, which sets the near-form work, 3.3 against 1.1).
+__device__ __forceinline__ uint32_t hilbert_key(uint32_t c[3], int n, int b)
 {
-    v &= 0x3ffu;
-    v = (v | (v << 16)) & 0x030000FFu;
-    v = (v | (v << 8)) & 0x0300F00Fu;
-    v = (v | (v << 4)) & 0x030C30C3u;
-    v = (v | (v << 2)) & 0x09249249u;
-    return v;
+    if (b == 0) return 0u;
+    const uint32_t M = 1u << (b - 1);
+    for (uint32_t Q = M; Q > 1u; Q >>= 1) {
+        const uint32_t P = Q - 1u;
+        for (int i = 0; i < n; ++i) {
+            if (c[i] & Q) {
+                c[0] ^= P;
+            } else {
+                const uint32_t t = (c[0] ^ c[i]) & P;
+                c[0] ^= t;
+                c[i] ^= t;
+            }
+        }
+    }
+    for (int i = 1; i < n; ++i) c[i] ^= c[i - 1];
+    uint32_t t = 0u;
+    for (uint32_t Q = M; Q > 1u; Q >>= 1)
+        if (c[n - 1] & Q) t ^= Q - 1u;
+    for (int i = 0; i < n; ++i) c[i] ^= t;
+    uint32_t key = 0u;
+    for (int bit = b - 1; bit >= 0; --bit)
+        for (int i = 0; i < n; ++i) key = (key << 1) | ((c[i] >> bit) & 1u);
+    return key;
 }
 
 __global__ __launch_bounds__(256) void k_cell_keys(const SysDev* __restrict__ sys, const CItem* __restrict__ items,
@@ -171,7 +196,7 @@ __global__ __launch_bounds__(256) void k_cell_keys(const SysDev* __restrict__ sy
             u = fmin(fmax(u, 0.0), (double)(S.g[d] - 1));  // also maps NaN to 0
             c[d] = (uint32_t)u;
         }
-        const int key = (int)(spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2));
+        const int key = (int)hilbert_key(c, S.dim == 2 ? 2 : 3, S.gbits);
         keys[g] = key;
         slots[g] = atomicAdd(&cnt[S.cell_off + key], 1);
     }
@@ -469,10 +494,30 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
 // q log2(r^2), scaled by -ln(2)/2 once at the end, and the field weight is
 // q / r^2; a masked pair gives zero terms, padding (r^2 = 2^120) finite ones
 // times q = 0.  Its far groups start at far_factor<2>() block radii (ps_device.h).
+// KERN = 3, the biharmonic r.  Rounding each term q r at FP32 precision would
+// not do: the terms grow with r (and the field terms q (t - s)/r do not decay),
+// and summed over a near set of 1e6 sources the rounding reaches 1e-5 of the
+// result.  So a source farther than kFarFactor
+// block radii from the block centre c (every source of a far group, and such
+// sources inside near groups; the flag sC.w, the same for the whole block, so
+// the branch is uniform) is taken relative to c: with u = s - c, rho = |u|,
+// r = rho sqrt(1 + delta) and delta = (|h|^2 - 2 h.u)/rho^2, it contributes
+// q rho + q rho g, g = sqrt(1 + delta) - 1.  The block adds sum q rho over
+// those sources once, in FP64 (k_p2p_f32), and the pair only q rho g, which is
+// of the size of q |h|.  With y = rsq(1 + delta) and s = (1 + delta) y,
+// g = s - 1 is refined by one Newton step on (1 + g)^2 = 1 + delta, which
+// gives g to a few roundings of itself rather than of 1.  Likewise the field
+// term -q (h - u)/r = q u/rho - q y (h + g u)/rho (1/y = 1 + g): the block adds
+// sum q u/rho once, in FP64, and the pair the rest, of the size of q |h|/rho
+// (y refined by one Newton step).  sC holds (1/rho^2, q rho, -q/rho, 1) per
+// such source.  The other sources of near groups take the potential term
+// q r = q r^2 ri and the field weight -q ri (E = -grad(q r) = -q (t - s)/r); a
+// masked pair (ri = 0) and padding (q = 0) give zero terms.
 template <bool NEAR, bool FIELD, int KERN>
-__device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB, float hx,
-                                            float hy, float hz, float lx, float ly, float lz, float tt, float kap,
-                                            float nk2, double& aP, double& aW, double& aX, double& aY, double& aZ)
+__device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const float4* __restrict__ sB,
+                                            const float4* __restrict__ sC, float hx, float hy, float hz, float lx,
+                                            float ly, float lz, float tt, float kap, float nk2, double& aP,
+                                            double& aW, double& aX, double& aY, double& aZ)
 {
     float fX = 0.f, fY = 0.f, fZ = 0.f, fW = 0.f;
     float p32 = 0.f;
@@ -482,6 +527,27 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const float4 s = sA[g * 8 + u];
+            if constexpr (KERN == 3) {
+                const float4 c = sC[g * 8 + u];
+                if (!NEAR || c.w != 0.f) {
+                    const float dl =
+                        __builtin_fmaf(hz, s.z, __builtin_fmaf(hy, s.y, __builtin_fmaf(hx, s.x, tt))) * c.x;
+                    const float op = 1.f + dl;
+                    const float y = __builtin_amdgcn_rsqf(op);
+                    const float sq = op * y, hy2 = 0.5f * y;
+                    const float res = __builtin_fmaf(sq, sq, -1.f) - dl;
+                    const float gg = __builtin_fmaf(-res, hy2, sq - 1.f);
+                    qv[u] = c.y * gg;
+                    if (FIELD) {  // -q y (h + g u)/rho, with y refined by one Newton step
+                        const float w = c.z * __builtin_fmaf(hy2, __builtin_fmaf(-sq, y, 1.f), y);
+                        const float hg = -0.5f * gg;  // h + g u = h - (g/2) A
+                        fX = __builtin_fmaf(w, __builtin_fmaf(hg, s.x, hx), fX);
+                        fY = __builtin_fmaf(w, __builtin_fmaf(hg, s.y, hy), fY);
+                        fZ = __builtin_fmaf(w, __builtin_fmaf(hg, s.z, hz), fZ);
+                    }
+                    continue;
+                }
+            }
             float dx = 0.f, dy = 0.f, dz = 0.f, r2;
             if (NEAR) {
                 const float4 l = sB[g * 8 + u];
@@ -515,6 +581,9 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                 const float e = __builtin_amdgcn_exp2f((r2 * ri) * nk2);
                 qv[u] = (s.w * ri) * e;
                 if (FIELD) qr3 = qv[u] * (ri * (ri + kap));
+            } else if constexpr (KERN == 3) {
+                qv[u] = s.w * (r2 * ri);
+                if (FIELD) qr3 = -(s.w * ri);
             } else {
                 qv[u] = s.w * ri;
                 if (FIELD) qr3 = qv[u] * (ri * ri);
@@ -536,7 +605,7 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
     }
     aP += (double)p32;
     if (FIELD) {
-        if (NEAR) {
+        if (NEAR || KERN == 3) {  // fX, fY, fZ hold the field itself
             aX += 2.0 * (double)fX;
             aY += 2.0 * (double)fY;
             aZ += 2.0 * (double)fZ;
@@ -588,6 +657,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
     constexpr int PF = kTile / BT;  // sources each thread stages per tile
     __shared__ float4 sA[kTile];
     __shared__ float4 sB[kTile];
+    __shared__ float4 sC[KERN == 3 ? kTile : 1];  // the biharmonic far form: (1/rho^2, q rho, -q/rho)
+    __shared__ double sRed[4][BT / 64];
     __shared__ uint32_t sFar[kTile / kGroup];
     const PItem it = items[blockIdx.x];
     const PJob& J = jobs[it.job];
@@ -613,6 +684,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
     const double* __restrict__ SQ = J.sq;
     // staging: all of a thread's loads of a tile are issued before any is used
     double px[PF], py[PF], pz[PF], pq[PF];
+    // the biharmonic form: sums of q rho and q u/rho over the staged sources that take it (FP64)
+    double cq = 0.0, cvx = 0.0, cvy = 0.0, cvz = 0.0;
     auto fetch = [&](int64_t t) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
@@ -631,17 +704,30 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
             // padding: a source of charge 0 at (2^60, 0, 0) from the centre, which
             // coincides with no target and keeps r^2 finite in FP32
             float4 a = make_float4(-0x1p61f, 0.f, 0.f, 0.f), b = make_float4(0.f, 0.f, 0.f, 0x1p120f);
+            float4 c = make_float4(0x1p-120f, 0.f, 0.f, 0.f);
             bool far = true;
             if (t * kTile + k < sp.ns) {
                 const double ux = px[u] - cx, uy = py[u] - cy, uz = pz[u] - cz;
-                far = ux * ux + uy * uy + uz * uz > far2;
+                const double u2 = ux * ux + uy * uy + uz * uz;
+                far = u2 > far2;
                 const float ax = (float)ux, ay = (float)uy, az = (float)uz;
                 a = make_float4(-2.f * ax, -2.f * ay, -2.f * az, (float)pq[u]);
                 b = make_float4((float)(ux - (double)ax), (float)(uy - (double)ay), (float)(uz - (double)az),
                                 __builtin_fmaf(az, az, __builtin_fmaf(ay, ay, ax * ax)));
+                if constexpr (KERN == 3) {
+                    if (far) {  // rho > 0
+                        const double rho = sqrt(u2), qr = pq[u] * rho, qo = pq[u] / rho;
+                        c = make_float4((float)(1.0 / u2), (float)qr, (float)(-qo), 1.f);
+                        cq += qr;
+                        cvx = __builtin_fma(qo, ux, cvx);
+                        cvy = __builtin_fma(qo, uy, cvy);
+                        cvz = __builtin_fma(qo, uz, cvz);
+                    }
+                }
             }
             sA[k] = a;
             sB[k] = b;
+            if constexpr (KERN == 3) sC[k] = c;
             store_far_bits(sFar, k & ~63, far);
         }
     };
@@ -657,11 +743,30 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 #pragma unroll 1
         for (int gq = 0; gq < kTile / kGroup; ++gq) {
             if ((farm >> gq) & 1)
-                group32_f32<false, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, kap,
-                                                nk2, aP, aW, aX, aY, aZ);
+                group32_f32<false, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, sC + (KERN == 3 ? gq * kGroup : 0),
+                                                hx, hy, hz, lx, ly, lz, tt, kap, nk2, aP, aW, aX, aY, aZ);
             else
-                group32_f32<true, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, hx, hy, hz, lx, ly, lz, tt, kap,
-                                               nk2, aP, aW, aX, aY, aZ);
+                group32_f32<true, FIELD, KERN>(A + gq * kGroup, B + gq * kGroup, sC + (KERN == 3 ? gq * kGroup : 0),
+                                               hx, hy, hz, lx, ly, lz, tt, kap, nk2, aP, aW, aX, aY, aZ);
+        }
+    }
+    if constexpr (KERN == 3) {  // every target of the block gets the sums of q rho and q u/rho, in fixed order
+        cq = wave_sum(cq);
+        cvx = wave_sum(cvx);
+        cvy = wave_sum(cvy);
+        cvz = wave_sum(cvz);
+        if ((threadIdx.x & 63) == 0) {
+            sRed[0][threadIdx.x >> 6] = cq;
+            sRed[1][threadIdx.x >> 6] = cvx;
+            sRed[2][threadIdx.x >> 6] = cvy;
+            sRed[3][threadIdx.x >> 6] = cvz;
+        }
+        __syncthreads();
+        for (int w = 0; w < BT / 64; ++w) {
+            aP += sRed[0][w];
+            aX += 2.0 * sRed[1][w];  // the field is read as 0.5 aX + h aW
+            aY += 2.0 * sRed[2][w];
+            aZ += 2.0 * sRed[3][w];
         }
     }
     if (active) {
@@ -689,6 +794,8 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(p2p_waves_hi
 // (q/2) u e = q e/r and the weight (q e/r) u (u + 2 kappa) = 4 q e (1 + kappa r)/r^3.
 // KERN = 2 (the plane's -log r): the potential term -(q/2) log(r^2) and the
 // weight 2 (q/2) u^2 = 4 q / r^2.  The logarithm is log_pos below.
+// KERN = 3 (the biharmonic r): the potential term (q/2) u r^2 = q r and the
+// weight -4 (q/2) u = 4 (-q/r).
 // log(x) for x > 0: x = m 2^e with m in [sqrt(1/2), sqrt(2)), and
 // log m = 2 atanh(s) = 2 (s + s^3/3 + ... + s^21/21), s = (m - 1)/(m + 1), |s| < 0.172,
 // whose first omitted term is below 2^-55 of the sum; e ln 2 with ln 2 split in
@@ -751,6 +858,9 @@ __device__ __forceinline__ void group32_f64(const double4* __restrict__ sF, cons
         } else if constexpr (KERN == 1) {
             qr = (n.w * u) * exp(-kap * (0.5 * (r2 * u)));        // q e/r
             if (FIELD) w = qr * (u * (u + 2.0 * kap));            // 4 q e (1 + kappa r)/r^3
+        } else if constexpr (KERN == 3) {
+            qr = (n.w * u) * r2;                                  // q r
+            if (FIELD) w = -4.0 * (n.w * u);                      // 4 (-q/r)
         } else {
             qr = n.w * u;                                         // q/r
             if (FIELD) w = qr * (u * u);                          // 4 q/r^3
@@ -1006,7 +1116,9 @@ __global__ __launch_bounds__(64 * WS) void k_chk_f32(const PJob* __restrict__ jo
 // f_l = phi_near(y~_l) - phi_near(y_l) from the split partials (the check job
 // holds the targets in its own order; slot maps a check target to its place):
 // 64 check points per workgroup, 16 lane groups over the splits, combined in
-// fixed order.
+// fixed order.  The biharmonic kernel's check job also carries the field E:
+// its gradient rows f[L + k L + l] = R0 (E_k(y_l) - E_k(y~_l)), the periodicity
+// of d phi_near / du_k (u = y/R0, d/du = -R0 E).
 __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, const PJob* __restrict__ cjobs,
                                               const int* __restrict__ slot, double* __restrict__ fout)
 {
@@ -1015,24 +1127,29 @@ __global__ __launch_bounds__(1024) void k_rhs(const SysDev* __restrict__ sys, co
     const PJob& J = cjobs[blockIdx.y];
     const int g = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int l = blockIdx.x * 64 + lane;
-    double a = 0.0, b = 0.0;
-    if (l < S.L) {
-        const int ia = slot[S.chk_off + l], ib = slot[S.chk_off + S.L + l];
-        for (int s = g; s < J.nsplit; s += 16) {
-            a += J.part[(int64_t)s * J.nt + ia];
-            b += J.part[(int64_t)s * J.nt + ib];
+    const int ncomp = S.kernel == 3 ? 4 : 1;  // uniform over the workgroup
+    for (int c = 0; c < ncomp; ++c) {
+        double a = 0.0, b = 0.0;
+        if (l < S.L) {
+            const int ia = slot[S.chk_off + l], ib = slot[S.chk_off + S.L + l];
+            for (int s = g; s < J.nsplit; s += 16) {
+                const double* P_ = J.part + ((int64_t)s * J.ncomp + c) * J.nt;
+                a += P_[ia];
+                b += P_[ib];
+            }
         }
-    }
-    sa[g][lane] = a;
-    sb[g][lane] = b;
-    __syncthreads();
-    if (g == 0 && l < S.L) {
-        double A = 0.0, B = 0.0;
-        for (int k = 0; k < 16; ++k) {
-            A += sa[k][lane];
-            B += sb[k][lane];
+        if (c > 0) __syncthreads();  // the previous component's reads are done
+        sa[g][lane] = a;
+        sb[g][lane] = b;
+        __syncthreads();
+        if (g == 0 && l < S.L) {
+            double A = 0.0, B = 0.0;
+            for (int k = 0; k < 16; ++k) {
+                A += sa[k][lane];
+                B += sb[k][lane];
+            }
+            fout[S.f_off + (int64_t)c * S.L + l] = c == 0 ? B - A : S.R0 * (A - B);
         }
-        fout[S.f_off + l] = B - A;
     }
 }
 
@@ -1158,6 +1275,30 @@ __device__ double prism_corner(double a, double b, double c)
     return F;
 }
 
+// The biharmonic kernel's box mean Psi0(x) = (1/V0) int_box |y - x| dV takes the
+// corner primitive G with d^3 G/(da db dc) = r = sqrt(a^2 + b^2 + c^2):
+// G = abc r/4 + [ab (a^2 + b^2) ln(c + r) + bc (b^2 + c^2) ln(a + r)
+//     + ca (c^2 + a^2) ln(b + r)]/6 - [a^4 atan(bc/(ar)) + b^4 atan(ca/(br))
+//     + c^4 atan(ab/(cr))]/12
+// (r = (1/4) div(r x) turns the volume integral into face integrals of r (x.n),
+// each of which has a closed form), with the same limits as prism_corner.
+__device__ double dist_corner(double a, double b, double c)
+{
+    const double a2 = a * a, b2 = b * b, c2 = c * c;
+    const double r = sqrt(a2 + b2 + c2);
+    if (r == 0.0) return 0.0;
+    double F = 0.25 * a * b * c * r;
+    double L = 0.0;
+    if (a * b != 0.0) L += a * b * (a2 + b2) * log_c_plus_r(c, r, a2 + b2);
+    if (b * c != 0.0) L += b * c * (b2 + c2) * log_c_plus_r(a, r, b2 + c2);
+    if (c * a != 0.0) L += c * a * (c2 + a2) * log_c_plus_r(b, r, c2 + a2);
+    double T = 0.0;
+    if (a != 0.0) T += a2 * a2 * atan(b * c / (a * r));
+    if (b != 0.0) T += b2 * b2 * atan(c * a / (b * r));
+    if (c != 0.0) T += c2 * c2 * atan(a * b / (c * r));
+    return F + L / 6.0 - T / 12.0;
+}
+
 // The plane's rectangle primitive F with d^2F/du dv = log(u^2 + v^2):
 // F = u v (log(u^2 + v^2) - 3) + u^2 atan(v/u) + v^2 atan(u/v), a term taken as
 // zero where its prefactor vanishes.
@@ -1182,7 +1323,8 @@ __device__ double box_mean_corner(const SysDev& S, int k, double x, double y, do
         return -0.5 * sx * sy * rect_corner(sx * S.half[0] - x, sy * S.half[1] - y) / S.V0;
     }
     const double sx = (k & 1) ? 1.0 : -1.0, sy = (k & 2) ? 1.0 : -1.0, sz = (k & 4) ? 1.0 : -1.0;
-    return sx * sy * sz * prism_corner(sx * S.half[0] - x, sy * S.half[1] - y, sz * S.half[2] - z) / S.V0;
+    const double a = sx * S.half[0] - x, b = sy * S.half[1] - y, c = sz * S.half[2] - z;
+    return sx * sy * sz * (S.kernel == 3 ? dist_corner(a, b, c) : prism_corner(a, b, c)) / S.V0;
 }
 
 // One workgroup per item of the near-size-weighted table (see k_bounds);
@@ -1229,7 +1371,7 @@ __device__ __forceinline__ double mean_corner_term(const SysDev& S, unsigned e, 
     const double gx = (0.5 - (ax - S.mr[0])) * S.box[0];
     const double gy = (0.5 - (ay - S.mr[1])) * S.box[1];
     const double gz = (0.5 - (t - S.mr[2])) * S.box[2];
-    return P.w * W * prism_corner(gx - P.x, gy - P.y, gz - P.z);
+    return P.w * W * (S.kernel == 3 ? dist_corner(gx - P.x, gy - P.y, gz - P.z) : prism_corner(gx - P.x, gy - P.y, gz - P.z));
 }
 
 __device__ __forceinline__ int mask_step(unsigned m, int t)  // bit t minus bit t - 1
@@ -1341,15 +1483,20 @@ __global__ __launch_bounds__(256) void k_c1(const SysDev* __restrict__ sys, cons
 // (r odd), which keeps the loop lengths of the
 // lanes of one round close and each lane's orders increasing, so that the
 // sectoral values (m, +-m) are carried forward from the lane's previous order.
+// The biharmonic basis adds |u|^2 R^_t for degrees below p2 = p - 2 with the
+// coefficients C2[t] (C2 = C + p^2; p2 = 0 otherwise): their sum Q rides on the
+// same recurrence, and phi = P + |u|^2 Q, grad = grad P + |u|^2 grad Q + 2 u Q.
 template <int FL>
-__device__ void far_field_lane(int p, int g, const double* __restrict__ C, const double* __restrict__ A,
-                               const double* __restrict__ B, const double* __restrict__ Cd, double x, double y,
-                               double z, double& phi, double& gx, double& gy, double& gz)
+__device__ void far_field_lane(int p, int p2, int g, const double* __restrict__ C, const double* __restrict__ C2,
+                               const double* __restrict__ A, const double* __restrict__ B,
+                               const double* __restrict__ Cd, double x, double y, double z, double& phi, double& gx,
+                               double& gy, double& gz)
 {
     const double r2 = x * x + y * y + z * z;
     double dA = 1.0, dAx = 0.0, dAy = 0.0, dAz = 0.0;
     double dB = 0.0, dBx = 0.0, dBy = 0.0, dBz = 0.0;
     double P0 = 0.0, X0 = 0.0, Y0 = 0.0, Z0 = 0.0;
+    double Q0 = 0.0, QX = 0.0, QY = 0.0, QZ = 0.0;
     int mc = 0;
     for (int r = 0; r * FL < p; ++r) {
         const int m = r * FL + ((r & 1) ? FL - 1 - g : g);
@@ -1379,6 +1526,13 @@ __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const
                 Y0 = __builtin_fma(ct, v1y, Y0);
                 Z0 = __builtin_fma(ct, v1z, Z0);
             }
+            if (m < p2) {
+                const double c2 = C2[t0];
+                Q0 = __builtin_fma(c2, v1, Q0);
+                QX = __builtin_fma(c2, v1x, QX);
+                QY = __builtin_fma(c2, v1y, QY);
+                QZ = __builtin_fma(c2, v1z, QZ);
+            }
             for (int n = m + 1; n < p; ++n) {
                 const int t = n * n + n + mm;
                 const double a = A[t], b = B[t];
@@ -1391,15 +1545,22 @@ __device__ void far_field_lane(int p, int g, const double* __restrict__ C, const
                 X0 = __builtin_fma(ct, vx, X0);
                 Y0 = __builtin_fma(ct, vy, Y0);
                 Z0 = __builtin_fma(ct, vz, Z0);
+                if (n < p2) {
+                    const double c2 = C2[t];
+                    Q0 = __builtin_fma(c2, v, Q0);
+                    QX = __builtin_fma(c2, vx, QX);
+                    QY = __builtin_fma(c2, vy, QY);
+                    QZ = __builtin_fma(c2, vz, QZ);
+                }
                 v2 = v1; v2x = v1x; v2y = v1y; v2z = v1z;
                 v1 = v; v1x = vx; v1y = vy; v1z = vz;
             }
         }
     }
-    phi = P0;
-    gx = X0;
-    gy = Y0;
-    gz = Z0;
+    phi = __builtin_fma(r2, Q0, P0);
+    gx = __builtin_fma(r2, QX, __builtin_fma(2.0 * x, Q0, X0));
+    gy = __builtin_fma(r2, QY, __builtin_fma(2.0 * y, Q0, Y0));
+    gz = __builtin_fma(r2, QZ, __builtin_fma(2.0 * z, Q0, Z0));
 }
 
 // The plane's far field at the scaled point w = x + iy, lane g of FL: with
@@ -1516,8 +1677,8 @@ __global__ __launch_bounds__(256) void k_far_combine(const SysDev* __restrict__ 
             fy -= gy * S.inv_R0;
         } else {
             double pf, gx, gy, gz;
-            far_field_lane<FL>(p, g, C, A, B, Cd, J.tx[i] * S.inv_R0, J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy,
-                           gz);
+            far_field_lane<FL>(p, S.kernel == 3 ? p - 2 : 0, g, C, C + p * p, A, B, Cd, J.tx[i] * S.inv_R0,
+                               J.ty[i] * S.inv_R0, J.tz[i] * S.inv_R0, pf, gx, gy, gz);
             ph += pf + (g == 0 ? C[0] : 0.0);
             fx -= gx * S.inv_R0;
             fy -= gy * S.inv_R0;
@@ -1613,6 +1774,9 @@ void launch_p2p(int prec, int bt, bool field, int kern, int64_t nitems, const PJ
     P2P_CASE(64, 2)
     P2P_CASE(128, 2)
     P2P_CASE(256, 2)
+    P2P_CASE(64, 3)
+    P2P_CASE(128, 3)
+    P2P_CASE(256, 3)
 #undef P2P_CASE
 }
 void launch_chk_f32(int kern, int64_t nitems, const PJob* jobs, const PItem* items, hipStream_t st)

@@ -456,6 +456,23 @@ void SystemSetup::build_decay()
     n_dec = static_cast<int>(dec_rows.size() / 5);
 }
 
+void bih_eval(const Recurrence& rec, double x, double y, double z, double* out, int dir, double* dout)
+{
+    const int p = rec.p, n1 = p * p, n2 = (p - 2) * (p - 2);
+    const double s2 = x * x + y * y + z * z;
+    if (dir < 0) {
+        rec.eval(x, y, z, out);
+        for (int t = 0; t < n2; ++t) out[n1 + t] = s2 * out[t];
+        return;
+    }
+    const double u[3] = {x, y, z};
+    rec.eval_dir(x, y, z, dir == 0 ? 1.0 : 0.0, dir == 1 ? 1.0 : 0.0, dir == 2 ? 1.0 : 0.0, out, dout);
+    for (int t = 0; t < n2; ++t) {
+        out[n1 + t] = s2 * out[t];
+        dout[n1 + t] = __builtin_fma(s2, dout[t], 2.0 * u[dir] * out[t]);
+    }
+}
+
 std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lambda, double rcond, int basis_,
                                int n_centres, const double* cen, int n_check, const double* chk, int periodic_,
                                int kernel_, double kappa_, int dim_)
@@ -472,9 +489,12 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     }
     if (periodic_ != 7 && periodic_ != 3 && periodic_ != 1) return "periodic axes must be 7 (x, y, z), 3 (x, y) or 1 (x)";
     if (periodic_ != 7 && basis_ != 0) return "the RBF basis needs three periodic axes";
-    if (kernel_ != 0 && kernel_ != 1) return "kernel must be 0 (Coulomb) or 1 (screened)";
+    if (kernel_ != 0 && kernel_ != 1 && kernel_ != 2) return "kernel must be 0 (Coulomb), 1 (screened) or 2 (biharmonic)";
     if (kernel_ == 1 && (basis_ != 1 || periodic_ != 7))
         return "the screened kernel needs the RBF basis and three periodic axes";
+    if (kernel_ == 2 && (basis_ != 0 || periodic_ != 7 || dim_ != 3))
+        return "the biharmonic kernel needs the spherical basis, three periodic axes and three dimensions";
+    if (kernel_ == 2 && (p_ < 3 || p_ > 30)) return "the biharmonic kernel needs 3 <= p <= 30";
     kernel = kernel_;
     kappa = kernel_ == 1 ? kappa_ : 0.0;
     periodic = periodic_;
@@ -486,7 +506,7 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     if (dim == 2) box[2] = 1.0;   // every z is 0: the slab of unit height holds them
     if (dim == 3 && (p_ < 2 || p_ > 40)) return "p must be in [2, 40]";
     p = p_;
-    P = dim == 2 ? 2 * p - 1 : p * p;
+    P = dim == 2 ? 2 * p - 1 : (kernel == 2 ? p * p + (p - 2) * (p - 2) : p * p);
     V0 = box[0] * box[1] * box[2];
     R0 = dim == 2 ? 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1])
                   : 0.5 * std::sqrt(box[0] * box[0] + box[1] * box[1] + box[2] * box[2]);   // step 1
@@ -612,6 +632,15 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
             basis2d(p, y[0] / R0, y[1] / R0, r1.data());
             basis2d(p, t[0] / R0, t[1] / R0, r2.data());
             for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + l] = r1[j + 1] - r2[j + 1];
+        } else if (kernel == 2) {
+            // value row l, then gradient rows L + k L + l: d/du_k B_t(u_l) - d/du_k B_t(u~_l)
+            std::vector<double> d1(P), d2(P);
+            for (int k = 0; k < 3; ++k) {
+                bih_eval(rec, y[0] / R0, y[1] / R0, y[2] / R0, r1.data(), k, d1.data());
+                bih_eval(rec, t[0] / R0, t[1] / R0, t[2] / R0, r2.data(), k, d2.data());
+                for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + L + k * L + l] = d1[j + 1] - d2[j + 1];
+            }
+            for (int j = 0; j < n; ++j) A[static_cast<size_t>(j) * Lf + l] = r1[j + 1] - r2[j + 1];
         } else {
             rec.eval(y[0] / R0, y[1] / R0, y[2] / R0, r1.data());
             rec.eval(t[0] / R0, t[1] / R0, t[2] / R0, r2.data());
@@ -723,7 +752,9 @@ std::string SystemSetup::build(const double bx[3], int p_, double Rb, double lam
     for (int i = 0; i < nq; ++i)
         for (int j = 0; j < nq; ++j)
             for (int k = 0; k < nq; ++k) {
-                rec.eval(0.5 * box[0] * xg[i] / R0, 0.5 * box[1] * xg[j] / R0, 0.5 * box[2] * xg[k] / R0, r1.data());
+                const double u[3] = {0.5 * box[0] * xg[i] / R0, 0.5 * box[1] * xg[j] / R0, 0.5 * box[2] * xg[k] / R0};
+                if (kernel == 2) bih_eval(rec, u[0], u[1], u[2], r1.data());
+                else rec.eval(u[0], u[1], u[2], r1.data());
                 const double w = wg[i] * wg[j] * wg[k] / 8.0;
                 for (int t = 0; t < P; ++t) box_means[t] += w * r1[t];
             }
@@ -817,15 +848,17 @@ std::string SystemSetup::deserialize(const unsigned char* data, size_t size, siz
     if (!ok) return "truncated system record";
     if (per != 7 && per != 3 && per != 1) return "bad periodic axes";
     if (per != 7 && b != 0) return "the RBF basis needs three periodic axes";
-    if (ker != 0 && ker != 1) return "bad kernel";
+    if (ker != 0 && ker != 1 && ker != 2) return "bad kernel";
     if (ker == 1 && (b != 1 || per != 7 || !(kap > 0.0) || !std::isfinite(kap))) return "bad screened-kernel record";
+    if (ker == 2 && (b != 0 || per != 7 || dm != 3 || p_ < 3 || p_ > 30)) return "bad biharmonic-kernel record";
     for (int k = 0; k < 3; ++k)
         if (!(box[k] > 0.0) || !std::isfinite(box[k])) return "bad box lengths";
     if (b != 0 && b != 1) return "bad basis";
     if (dm != 3 && dm != 2) return "bad dimension";
     if (dm == 2 && (b != 0 || per != 3 || ker != 0 || box[2] != 1.0)) return "bad record of a plane system";
     if (p_ < 2 || p_ > (dm == 2 ? 128 : 40)) return "p out of range";
-    if (b == 0 && (P_ != (dm == 2 ? 2 * p_ - 1 : p_ * p_) || M != 0)) return "basis size does not match p";
+    if (b == 0 && (P_ != (dm == 2 ? 2 * p_ - 1 : (ker == 2 ? p_ * p_ + (p_ - 2) * (p_ - 2) : p_ * p_)) || M != 0))
+        return "basis size does not match p";
     if (b == 1 && (M < 1 || M > 4096 || P_ != M + 1)) return "bad RBF centre count";
     if (L_ < 1 || L_ > (1 << 20)) return "bad check-point count";
     if (rank_ < 1 || rank_ > P_ - 1) return "bad rank";

@@ -34,6 +34,10 @@ void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w);
 // out[2n-1] = Re w^n, out[2n] = Im w^n, w = x + iy, n = 1..p-1.
 void basis2d(int p, double x, double y, double* out);
 
+// The biharmonic basis at the scaled point u = (x, y, z): the p^2 harmonics R^_t,
+// then |u|^2 R^_t for t < (p-2)^2.  With dir in 0..2 also d/du_dir of each (dout).
+void bih_eval(const Recurrence& rec, double x, double y, double z, double* out, int dir = -1, double* dout = nullptr);
+
 // Mean of 1/|y - x| over the box [-d/2, d/2]^3 (divided by its volume): the
 // closed-form potential of a uniform rectangular prism, summed over corners.
 double box_mean_potential(const double box[3], double x, double y, double z);
@@ -72,9 +76,14 @@ struct SystemSetup {
     std::vector<double> dec_w;         // [npts] quadrature weights (sum 1), shared by the surfaces
     std::vector<double> dec_rows;      // [n_dec * 5]: slab kx, ky, |k|, s (+1 top, -1 bottom), trig (0 cos, 1 sin);
                                        // wire k, m, beta, trig in x, trig in theta
-    int rows() const { return L + n_dec; }   // rows of the fit (columns of pinv)
+    // rows of the fit (columns of pinv): L periodicity rows of the potential, then
+    // the decay rows (slab, wire) or the 3L gradient rows (biharmonic kernel)
+    int rows() const { return L + (kernel == 2 ? 3 * L : n_dec); }
     // Kernel: 0 Coulomb 1/r; 1 screened exp(-kappa r)/r (RBF basis, three periodic
-    // axes; no constant basis function to fix: box_means stay zero).
+    // axes; no constant basis function to fix: box_means stay zero); 2 the
+    // biharmonic r (spherical basis extended by |u|^2 times the harmonics of
+    // degree <= p-3, P = p^2 + (p-2)^2; after the L value rows, rows L + k L + l
+    // ask for the same periodicity of d/du_k at check pair l, u = y/R0).
     int kernel = 0;
     double kappa = 0;
     // Dimension: 3, or 2 for the method in the plane (kernel -log r, x and y

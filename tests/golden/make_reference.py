@@ -4,7 +4,7 @@ independent Ewald potential for the parameter-choice tests of Table 2.
 Calls only the FP64 CPU oracle (oracle/) on the seeded inputs of workloads/;
 nothing here comes from the HIP library.  The outputs let GPU tests and the
 benchmark compare sampled particles at full size without re-running the slow
-oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened slab wire plane]
+oracle on the GPU machine.  Usage: python tests/golden/make_reference.py cfg2 [cfg2_hard cfg3 cfg3_hard cfg4 cfg5 table2 table3 screened slab wire plane biharmonic]
 """
 import os
 import sys
@@ -206,6 +206,17 @@ def plane():
     sub = c["subset"]
     parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
     _save("ref_plane.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"], n_near=parts["n_near"])
+
+
+def biharmonic():
+    """The biharmonic workload (workloads.config_biharmonic) at its sampled particles."""
+    from oracle.biharmonic import BiharmonicPlan
+    c = W.config_biharmonic()
+    pl = BiharmonicPlan(c["box"], c["p"], lam=c["lam"])
+    sub = c["subset"]
+    parts = pl.solve(c["x"], c["q"], targets=c["x"][sub], return_parts=True)
+    _save("ref_biharmonic.npz", subset=sub, phi=parts["phi"], field=parts["field"], C=parts["C"],
+          n_near=parts["n_near"])
 
 
 if __name__ == "__main__":

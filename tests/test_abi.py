@@ -89,7 +89,7 @@ def test_screened_kernel_parameters_checked_on_host():
     h = ctypes.c_void_p()
     cen = (ctypes.c_double * 3)(2.0, 0.0, 0.0)
     dp = ctypes.cast(cen, ctypes.POINTER(ctypes.c_double))
-    cases = [(dict(kernel=2), _lib.PS_E_INVALID),
+    cases = [(dict(kernel=3), _lib.PS_E_INVALID), (dict(kernel=-1), _lib.PS_E_INVALID),
              (dict(kernel=1, kappa=1.0), _lib.PS_E_UNSUPPORTED),
              (dict(kernel=1, kappa=1.0, basis=1, n_centres=1, centres=dp, periodic=3), _lib.PS_E_UNSUPPORTED),
              (dict(kernel=1, kappa=0.0, basis=1, n_centres=1, centres=dp), _lib.PS_E_INVALID),
@@ -97,6 +97,20 @@ def test_screened_kernel_parameters_checked_on_host():
              (dict(kernel=1, kappa=1e3, basis=1, n_centres=1, centres=dp), _lib.PS_E_INVALID)]
     for kw, status in cases:
         assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == status, kw
+        assert h.value is None
+
+
+def test_biharmonic_kernel_parameters_checked_on_host():
+    """The biharmonic kernel with the RBF basis, fewer than three periodic axes,
+    in the plane or with p outside [3, 30] is refused before any device work."""
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    cen = (ctypes.c_double * 3)(2.0, 0.0, 0.0)
+    dp = ctypes.cast(cen, ctypes.POINTER(ctypes.c_double))
+    cases = [dict(kernel=2, basis=1, n_centres=1, centres=dp), dict(kernel=2, periodic=3), dict(kernel=2, periodic=1),
+             dict(kernel=2, dim=2), dict(kernel=2, p=2), dict(kernel=2, p=31)]
+    for kw in cases:
+        assert L.periodic_sum_plan(ctypes.byref(_params(**kw)), 0, ctypes.byref(h)) == _lib.PS_E_UNSUPPORTED, kw
         assert h.value is None
 
 

@@ -1,0 +1,196 @@
+"""The biharmonic kernel K(r) = r (the equation Sec. 3 names as sharing the
+Laplace kernel's null space): the HIP path against the oracle's method
+(oracle/biharmonic.py), itself pinned to an independent Ewald-type split, the
+Laplacian relation to the Coulomb sum and the box mean's quadrature.
+
+Bars (tests/gpu_common.py): FP64 <= 1e-12, FP32 pairs with FP64 accumulation
+<= 1e-6, on the relative L2 error and on the worst element; near-set sizes exact.
+One reading for FP32 in small systems: each near term q r is of the size of
+the near radius, each field term q (t - s)/r of the size of q, and the results
+are small remainders of their sums, so FP32 rounding of the terms (a few
+roundings each, at random) leaves an error of about 2^-24 sqrt(sum_j (q_j r_ij)^2)
+in phi and 2^-24 sqrt(sum_j q_j^2) in the field.  Where the target blocks span
+a good part of the box (a few thousand particles or fewer) that exceeds 1e-6
+of the result; those tests bound FP32 by max(1e-6, 8 x 2^-24 x kappa), with
+kappa = max_i sqrt(sum_j (q_j r_ij)^2) / max |phi| for phi and
+sqrt(sum_j q_j^2) / max |E| for the field, over the oracle's near set.  The
+full-size workload keeps the 1e-6 bars.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import TOL, dev, err, golden, load_ps, rel
+from oracle.biharmonic import BiharmonicPlan, EwaldBih
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+BOX = (1.0, 1.1, 0.9)
+
+
+@pytest.fixture(scope="module")
+def ps():
+    return load_ps()
+
+
+def _cell(n, seed, box=BOX):
+    g = np.random.default_rng(seed)
+    x = (g.random((n, 3)) - 0.5) * np.array(box)
+    q = g.standard_normal(n)
+    return x, q - q.mean()
+
+
+def _bars(prec, op, x, q, ref, targets=None):
+    """The FP32 bars (phi, field) for a small system (see the module notes)."""
+    if prec == "fp64":
+        return TOL["fp64"], TOL["fp64"]
+    xs, qs, _, _ = op.near(x, q)
+    kp = max(np.sqrt(((qs * np.linalg.norm(t - xs, axis=1)) ** 2).sum())
+             for t in (x if targets is None else targets)) / np.abs(ref[0]).max()
+    kf = np.sqrt((qs * qs).sum()) / np.abs(ref[1]).max()
+    return max(TOL["fp32"], 8 * 2.0 ** -24 * kp), max(TOL["fp32"], 8 * 2.0 ** -24 * kf)
+
+
+def _bih(ps, box, p, x, q, prec, lam=1.6, targets=None, **kw):
+    pl = ps.Plan(box, p, lam=lam, precision=prec, n_max=len(q), m_max=0 if targets is None else len(targets),
+                 kernel="biharmonic", **kw)
+    phi, field = pl.eval(dev(x.T), dev(q), targets=None if targets is None else dev(targets.T))
+    pl.status()
+    return pl, phi.cpu().numpy(), field.cpu().numpy().T
+
+
+def test_biharmonic_tables_match_oracle(ps):
+    """Basis size, 4L fit rows (values, then d/du_x, d/du_y, d/du_z), rank, the
+    pseudo-inverse and the box means of the Almansi basis."""
+    for box, p in ((BOX, 12), ((2.0, 0.7, 1.0), 16), ((1.0, 1.0, 1.0), 20)):
+        op = BiharmonicPlan(box, p, lam=1.6)
+        pl = ps.Plan(box, p, lam=1.6, n_max=10, kernel="biharmonic")
+        inf = pl.info()
+        assert inf["P"] == p * p + (p - 2) ** 2 and inf["L"] == op.L and inf["n_rows"] == 4 * op.L
+        assert inf["rank"] == op.rank == op.P - 1 and abs(inf["cond"] / op.cond - 1) < 1e-9
+        yc, yt, pinv, bm = (t.numpy() for t in pl.tables())
+        np.testing.assert_allclose(yc, op.yc, atol=4e-15 * op.R0)
+        np.testing.assert_allclose(yt, op.yt, atol=4e-15 * op.R0)
+        # two pseudo-inverse algorithms (Householder QR + Jacobi SVD, LAPACK) on a
+        # 4L x (P-1) matrix: their rounding differs by about (P-1) kappa(A) eps,
+        # 2-6e-12 here (kappa 1e2-2.5e2); the outputs keep the 1e-12 bar
+        assert err(pinv, op.Apinv) < 1e-11
+        np.testing.assert_allclose(bm, op.R0mean, atol=1e-14)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_biharmonic_matches_oracle(ps, prec):
+    x, q = _cell(3001, 301)
+    op = BiharmonicPlan(BOX, 16, lam=1.6)
+    ref = op.solve(x, q, return_parts=True)
+    pl, phi, field = _bih(ps, BOX, 16, x, q, prec)
+    e1, e2 = err(phi, ref["phi"]), err(field, ref["field"])
+    b1, b2 = _bars(prec, op, x, q, (ref["phi"], ref["field"]))
+    print(prec, "biharmonic err phi %.3e (bar %.2e) field %.3e (bar %.2e)" % (e1, b1, e2, b2))
+    assert pl.info()["n_near_last"] == ref["n_near"]
+    assert e1 <= b1 and e2 <= b2
+    assert rel(pl.coefficients().numpy(), ref["C"]) < (1e-12 if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n,bt,split", [(2, 0, 0), (63, 64, 0), (257, 128, 3), (1025, 256, 1)])
+def test_biharmonic_ragged_sizes_and_launch_shapes(ps, prec, n, bt, split):
+    x, q = _cell(n, 310 + n)
+    if n == 2:
+        x, q = np.array([[0.1, 0.2, -0.3], [-0.25, 0.05, 0.4]]), np.array([1.0, -1.0])
+    op = BiharmonicPlan(BOX, 12, lam=1.6)
+    ref = op.solve(x, q)
+    _, phi, field = _bih(ps, BOX, 12, x, q, prec, tile_targets=bt, n_split=split)
+    b1, b2 = _bars(prec, op, x, q, ref)
+    assert err(phi, ref[0]) <= b1 and err(field, ref[1]) <= b2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_biharmonic_separate_targets_and_mean_modes(ps, prec):
+    """Targets anywhere in the box, some exactly on particles; C1 = 0 (mean "none")
+    shifts phi by the oracle's constant and leaves the field."""
+    x, q = _cell(1200, 302)
+    g = np.random.default_rng(303)
+    y = (g.random((300, 3)) - 0.5) * np.array(BOX)
+    y[:30] = x[:30]
+    op = BiharmonicPlan(BOX, 14, lam=1.6)
+    ref = op.solve(x, q, targets=y)
+    _, phi, field = _bih(ps, BOX, 14, x, q, prec, targets=y)
+    b1, b2 = _bars(prec, op, x, q, ref, y)
+    assert err(phi, ref[0]) <= b1 and err(field, ref[1]) <= b2
+    ref0 = op.solve(x, q, with_mean=False)
+    _, phi0, field0 = _bih(ps, BOX, 14, x, q, prec, mean="none")
+    b1, b2 = _bars(prec, op, x, q, ref0)
+    assert err(phi0, ref0[0]) <= b1 and err(field0, ref0[1]) <= b2
+
+
+def test_biharmonic_method_accuracy_against_the_split(ps):
+    """FP64 at p = 30, lambda = 2.5 against the independent Ewald-type split."""
+    x, q = _cell(400, 304)
+    pe, fe = EwaldBih(BOX).solve(x, q)
+    _, phi, field = _bih(ps, BOX, 30, x, q, "fp64", lam=2.5)
+    assert err(phi, pe) < 1e-11 and err(field, fe) < 1e-11
+
+
+def test_biharmonic_batch(ps):
+    """One graph launch over three boxes of different shapes and sizes (FP64)."""
+    boxes = [np.array(BOX), np.array([1.2, 1.0, 1.1]), np.array([2.0, 0.7, 1.0])]
+    ns = [900, 700, 500]
+    data = [_cell(n, 320 + k, b) for k, (n, b) in enumerate(zip(ns, boxes))]
+    bp = ps.BatchedPlan([dict(box=b, n_max=n) for b, n in zip(boxes, ns)], p=12, lam=1.6, precision="fp64",
+                        kernel="biharmonic")
+    off = np.concatenate([[0], np.cumsum(ns)])
+    phi, field = bp.eval(dev(np.concatenate([d[0] for d in data]).T), dev(np.concatenate([d[1] for d in data])), off)
+    bp.status()
+    phi, field = phi.cpu().numpy(), field.cpu().numpy().T
+    for k in range(3):
+        ref = BiharmonicPlan(boxes[k], 12, lam=1.6).solve(data[k][0], data[k][1])
+        sl = slice(off[k], off[k + 1])
+        assert err(phi[sl], ref[0]) <= TOL["fp64"] and err(field[sl], ref[1]) <= TOL["fp64"], k
+
+
+def test_biharmonic_plan_file_gradient_and_refusals(ps, tmp_path):
+    """A reloaded plan gives bitwise the same sums; the physical gradient works
+    (-q field, phi projected); the exact adjoint and non-neutral charges are refused."""
+    from paper_1310_4374_amd import PeriodicSumError
+    x, q = _cell(800, 305)
+    pl = ps.Plan(BOX, 12, lam=1.6, precision="fp32", n_max=800, kernel="biharmonic")
+    X, Q = dev(x.T), dev(q)
+    phi0, field0 = pl.eval(X, Q)
+    pl.status()
+    path = tmp_path / "bih.plan"
+    pl.save(path)
+    pl2 = ps.Plan.load(path)
+    assert pl2.info()["kernel"] == 2 and pl2.info()["n_rows"] == 4 * pl2.info()["L"]
+    phi1, field1 = pl2.eval(X, Q)
+    pl2.status()
+    assert torch.equal(phi0, phi1) and torch.equal(field0, field1)
+    e = pl.energy(X, Q)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(X, Q, one, exact=False)
+    f = field0.cpu().numpy()
+    assert np.allclose(gx.cpu().numpy(), -q[None, :] * f, rtol=0, atol=1e-12 * np.abs(f).max())
+    ph = phi0.cpu().numpy()
+    assert np.allclose(gq.cpu().numpy(), ph - ph.mean(), rtol=0, atol=1e-12 * np.abs(ph).max())
+    assert abs(float(e.item()) - 0.5 * float(q @ ph)) < 1e-10 * abs(float(e.item()))
+    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
+        pl.energy_vjp(X, Q, one, exact=True)
+    pl.eval(X, dev(q + 0.1))
+    with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
+        pl.status()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_biharmonic_full_size_workload(ps, prec):
+    """The benchmark's biharmonic workload (N = 100,000 in the unit cube, p = 24,
+    lambda = 1.5, the default launch shape it times): 2,000 sampled particles
+    against the oracle's stored values (tests/golden/ref_biharmonic.npz), near-set size exact."""
+    c = W.config_biharmonic()
+    ref = golden("ref_biharmonic.npz")
+    pl, phi, field = _bih(ps, c["box"], c["p"], c["x"], c["q"], prec, lam=c["lam"])
+    sub = ref["subset"]
+    e1, e2 = err(phi[sub], ref["phi"]), err(field[sub], ref["field"])
+    print(prec, "full-size biharmonic err phi %.3e field %.3e" % (e1, e2))
+    assert pl.info()["n_near_last"] == int(ref["n_near"])
+    assert e1 <= TOL[prec] and e2 <= TOL[prec]

@@ -131,6 +131,17 @@ def config_plane(n=100_000, nsub=2000):
     return dict(box=d, x=x, q=q, p=32, lam=1.5, subset=sub)
 
 
+def config_biharmonic(n=100_000, nsub=2000):
+    """The biharmonic kernel r: N uniform in the unit cube, Gaussian charges
+    minus their mean, p = 24 (P = 24^2 + 22^2 = 1060), lambda = 1.5."""
+    g = rng(10)
+    d = np.array([1.0, 1.0, 1.0])
+    x = wrap((g.random((n, 3)) - 0.5) * d, d)
+    q = _neutral_gauss(g, n)
+    sub = np.sort(g.choice(n, size=min(nsub, n), replace=False))
+    return dict(box=d, x=x, q=q, p=24, lam=1.5, subset=sub)
+
+
 def config4(nsys=512, nmin=200, nmax=20000):
     g = rng(4)
     systems = []
