@@ -2,6 +2,9 @@
  * periodic_sum.h -- C ABI of libperiodic_sum.so, an MI355X (gfx950) implementation
  * of the periodized sum of Gumerov & Duraiswami, "A method to compute periodic sums"
  * (arXiv:1310.4374), for the Coulomb kernel K(r) = 1/|r|, K(0) = 0 (eq. (1)).
+ * Variants (ps_params): periodicity along two axes or one (periodic), the plane
+ * with -log r (dim), the screened Coulomb kernel and the biharmonic kernel r
+ * (kernel), the RBF basis and caller check points (basis, check_points).
  *
  * Problem (Sec. 1, eqs. (1)-(2)): N charges q_i at x_i in the box
  * Omega0 = [-d1/2,d1/2) x [-d2/2,d2/2) x [-d3/2,d3/2), sum q_i = 0, replicated on the
@@ -244,8 +247,9 @@ ps_status periodic_sum_eval(ps_plan plan, int64_t n,
  * reads was written earlier in the same call, so nothing needs clearing.
  * Arguments as periodic_sum_eval with m = 0.
  * Errors: PS_E_INVALID (as periodic_sum_eval, or a batched plan),
- * PS_E_UNSUPPORTED (an RBF-basis plan, or partial sums of this n beyond the
- * array's 8 Mi doubles: 4 n x (source splits) + 2L x (check splits)),
+ * PS_E_UNSUPPORTED (an RBF-basis, slab, wire or biharmonic plan, or partial
+ * sums of this n beyond the array's 8 Mi doubles: 4 n x (source splits) +
+ * 2L x (check splits)),
  * PS_E_HIP. */
 ps_status periodic_sum_eval_noalloc(ps_plan plan, int64_t n,
                                     const double* x, const double* y, const double* z, const double* q,
