@@ -197,6 +197,51 @@ class BiharmonicPlan:
         return phi, -grad
 
 
+def energy_gradients_bih(plan, x, q):
+    """Gradient of E = (1/2) sum_i q_i phi(x_i) computed by the method for K = r,
+    with respect to positions and charges: the derivation of oracle/adjoint.py
+    (eqs. (3), (8), (10)) with this fit's rows.  With u_t = sum_k q_k B_t(x_k)
+    (t >= 2) and w = (A^+)^T u split into the value weights w_l and the gradient
+    weights w_kl (rows L + k L + l), E_ff = (1/2) w^T f is (1/2) sum_j q_j psi(z_j)
+    over the near entries z_j with
+        psi(z) = sum_l w_l [K(y~_l - z) - K(y_l - z)]
+               + sum_l D_l . [grad K(y~_l - z) - grad K(y_l - z)],
+    D_l = R0 (w_xl, w_yl, w_zl), grad K(y - z) = (y - z)/|y - z| taken in y: a
+    charge and a dipole at each check point and partner.  psi joins the base
+    particles' potential in the formulas of oracle/adjoint.py; C1 drops out
+    because the charges are neutral, and dE/dq is projected onto sum dq = 0.
+    Returns (E, dE/dx (N,3), dE/dq (N,))."""
+    x = np.asarray(x, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    parts = plan.solve(x, q, return_parts=True)
+    phi = parts["phi"]
+    E = 0.5 * float(np.sum(q * phi))
+    u = basis_bh(x, plan.p, plan.R0)[1:] @ q                           # (P-1,)
+    w = plan.Apinv.T @ u                                                # (4L,)
+    L = plan.L
+    D = plan.R0 * w[L:].reshape(3, L).T                                 # (L, 3)
+    xs, _, base, _ = plan.near(x, q)
+    src = np.concatenate([x, plan.yt, plan.yc])
+    srq = np.concatenate([q, w[:L], -w[:L]])
+    psi, gpsi = _native.direct_dist(xs, src, srq)
+    for pts, sgn in ((plan.yt, 1.0), (plan.yc, -1.0)):
+        for c0 in range(0, len(xs), 256):
+            d = pts[None, :, :] - xs[c0:c0 + 256, None, :]              # y - z
+            r = np.sqrt((d * d).sum(-1))
+            dd = (d * D[None, :, :]).sum(-1)                            # D . (y - z)
+            psi[c0:c0 + 256] += sgn * (dd / r).sum(1)
+            # grad_z of D.(y - z)/|y - z| is -D/r + (D.(y - z)) (y - z)/r^3
+            g = -D[None, :, :] / r[:, :, None] + (dd / r ** 3)[:, :, None] * d
+            gpsi[c0:c0 + 256] += sgn * g.sum(1)
+    dpsi = np.zeros(x.shape[0])
+    gsum = np.zeros_like(x)
+    np.add.at(dpsi, base, psi)
+    np.add.at(gsum, base, gpsi)
+    dEdx = 0.5 * q[:, None] * (-parts["field"] + gsum)
+    dEdq = 0.5 * (phi + dpsi)
+    return E, dEdx, dEdq - dEdq.mean()
+
+
 class EwaldBih:
     """Ewald-type reference for the periodic sum of K = r (see the module notes)."""
 

@@ -213,3 +213,39 @@ def test_targets_translation_and_coincident_points():
     pt, ft = pl.solve(x, q, targets=y)
     np.testing.assert_allclose(pt[:5], phi[:5], rtol=0, atol=1e-13 * np.abs(phi).max())
     np.testing.assert_allclose(ft[:5], field[:5], rtol=0, atol=1e-13 * np.abs(field).max())
+
+
+def _energy(plan, x, q):
+    return 0.5 * float(q @ plan.solve(x, q)[0])
+
+
+def test_exact_energy_gradient_matches_differences():
+    """The oracle's exact adjoint for K = r (charges and dipoles at the check
+    points and partners) against central differences of its own energy, in
+    positions (particles whose images stay clear of the near-ball sphere) and in
+    neutral pairs of charges."""
+    from oracle.biharmonic import energy_gradients_bih
+    from oracle.geometry import lattice_vectors
+    x, q = _cell(30, 9)
+    pl = BiharmonicPlan(BOX, 12, lam=1.6)
+    E, dx, dq = energy_gradients_bih(pl, x, q)
+    assert abs(E - _energy(pl, x, q)) < 1e-14 * abs(E)
+    P = lattice_vectors(pl.box, pl.R_b)
+    clear = np.abs(np.linalg.norm(x[:, None, :] + P[None, :, :], axis=2) - pl.R_b).min(axis=1) > 1e-3
+    h = 1e-5
+    for i in np.nonzero(clear)[0][:4]:
+        for k in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[i, k] += h
+            xm[i, k] -= h
+            fd = (_energy(pl, xp, q) - _energy(pl, xm, q)) / (2 * h)
+            assert abs(dx[i, k] - fd) < 1e-7 * max(1.0, abs(fd))
+    assert abs(dq.sum()) < 1e-12 * np.abs(dq).sum()
+    for i, j in [(0, 1), (5, 20), (11, 29)]:
+        qp, qm = q.copy(), q.copy()
+        qp[i] += h
+        qp[j] -= h
+        qm[i] -= h
+        qm[j] += h
+        fd = (_energy(pl, x, qp) - _energy(pl, x, qm)) / (2 * h)
+        assert abs((dq[i] - dq[j]) - fd) < 1e-8 * max(1.0, abs(fd))
