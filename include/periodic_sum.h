@@ -107,8 +107,9 @@ typedef enum {
                                d/du_k (u = y/R0) at each check pair (values alone do not fix a
                                biharmonic function), so the check-point sums carry the field.
                                Outputs: phi = sum q |x - x_j| periodized, E = -grad phi.  Needs
-                               PS_BASIS_SPHERICAL, periodic = 7, dim 3, 3 <= p <= 30; energy_vjp with
-                               exact = 1 is refused (PS_E_UNSUPPORTED). */
+                               PS_BASIS_SPHERICAL, periodic = 7, dim 3, 3 <= p <= 30.  energy_vjp
+                               (exact = 1): the gradient rows add a dipole R0 (w_xl, w_yl, w_zl) at
+                               each partner and its negative at each check point to psi. */
 } ps_kernel;
 
 typedef struct {
@@ -279,7 +280,11 @@ ps_status periodic_sum_energy(ps_plan plan, int64_t n,
  * charges).  With decay rows (slab, wire) w also weights them, and psi gains, at
  * each decay point y_i with normal n_i, a charge b_i and a dipole -a_i n_i,
  * a_i = sum_r w_r W_ri, b_i = sum_r w_r c_r W_ri (W_ri the row's quadrature weight
- * and trigonometric factor at the point, c_r = -s|k| or beta).
+ * and trigonometric factor at the point, c_r = -s|k| or beta).  Biharmonic
+ * kernel: u_t over the Almansi basis, K = r in psi, and from the gradient rows
+ * (weights w_kl, rows L + k L + l) a dipole D_l = R0 (w_xl, w_yl, w_zl) at each
+ * partner and -D_l at each check point, whose potential in psi is
+ * D_l . (y - z)/|y - z|.
  * Must follow a periodic_sum_energy (or eval at the
  * particles) with the same inputs on the same stream: it reuses that forward
  * pass's near set, coefficients and outputs kept in the plan.

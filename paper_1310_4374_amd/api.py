@@ -129,7 +129,7 @@ class Plan:
         a wire (periodic in x, vacuum around it).
         kernel: "coulomb" (1/r), "screened" (exp(-kappa r)/r, any net charge,
         RBF centres required, no constant term) or "biharmonic" (r, neutral
-        charges, P = p^2 + (p-2)^2, no exact energy adjoint).  dim=2: the method in the plane
+        charges, P = p^2 + (p-2)^2).  dim=2: the method in the plane
         (box (d1, d2), kernel -log r, positions (2, N), field (2, N))."""
         self.device = torch.device("cuda", device)
         self.dim = int(dim) if int(dim) == 2 else 3

@@ -1877,13 +1877,13 @@ ps_status ensure_adjoint_workspace(ps_plan_s* pl)
     AL(pl->d_mom_t, 4096 / 256 + 1)
     AL(pl->d_mom_p, (4096 / 256 + 1) * kMomBlocks)
     AL(pl->d_mom_tblk, (4096 / 256 + 1) * 4)
-    AL(pl->d_wdec, std::max(1, S.ndec))
+    AL(pl->d_wdec, std::max(1, S.Lf - S.L))   // the weights of the rows after the L value rows
     const int64_t npts = static_cast<int64_t>(S.nsurf) * S.m2;
     if (S.ndec > 0) {
         AL(pl->d_adj_da, npts)
         AL(pl->d_adj_db, npts)
-        AL(pl->d_adj_dpart, 4 * ncap)
     }
+    if (S.ndec > 0 || S.kernel == 3) AL(pl->d_adj_dpart, 4 * ncap)
 #undef AL
     if (e != hipSuccess) return fail(PS_E_NOMEM, "adjoint workspace allocation failed: %s", hipGetErrorString(e));
     pl->adj_ready = true;
@@ -1938,9 +1938,9 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
     HIPCHK(dev_guard.err);
     hipStream_t st = static_cast<hipStream_t>(stream);
     const SysDev& S = pl->tab.sys[0];
-    int64_t nb_dec = 0;   // near entries whose psi includes the decay points' part (slab, wire)
-    if (exact && pl->kernel == PS_KERNEL_BIHARMONIC)
-        return fail(PS_E_UNSUPPORTED, "the exact adjoint is not available for the biharmonic kernel (exact = 0 works)");
+    // near entries whose psi includes the part of the rows after the value rows
+    // (decay points of a slab or wire, check-point dipoles of the biharmonic kernel)
+    int64_t nb_dec = 0;
     if (exact) {
         ps_status s = ensure_adjoint_workspace(pl);
         if (s != PS_OK) return s;
@@ -2038,6 +2038,10 @@ ps_status periodic_sum_energy_vjp(ps_plan pl, int64_t n, const double* x, const 
             launch_adjoint_decay(static_cast<int64_t>(S.nsurf) * S.m2, nb, pl->d_sys, pl->d_dpts, pl->dec_tot, pl->d_dw,
                                  pl->d_drows, pl->d_wdec, pl->d_adj_da, pl->d_adj_db, pl->d_nx, pl->d_ny, pl->d_nz,
                                  pl->d_adj_dpart, st);
+        } else if (S.kernel == 3) {
+            nb_dec = nb;
+            launch_adjoint_dipoles(nb, pl->d_sys, pl->d_nx, pl->d_ny, pl->d_nz, pl->d_chk, pl->chk_tot, pl->d_wdec,
+                                   pl->d_adj_dpart, st);
         }
     } else {
         ps_status s = ensure_adjoint_workspace(pl);

@@ -51,6 +51,11 @@ void launch_adjoint_sources(int P, int L, int64_t n, const SysDev* sys, const do
                             int toff, const double* pinv, const double* chk, int64_t chk_tot, double* ax, double* ay,
                             double* az, double* aq, double* wdec, hipStream_t st);
 // the decay rows' adjoint sources (slab, wire) and their psi at the nb near entries
+// The biharmonic fit's gradient rows in the adjoint: dipoles at the check
+// points and partners (weights wg = the rows' w, 3L), psi and -grad psi at the
+// nb near entries into dpart (4 x nb).
+void launch_adjoint_dipoles(int64_t nb, const SysDev* sys, const double* nx, const double* ny, const double* nz,
+                            const double* chk, int64_t chk_tot, const double* wg, double* dpart, hipStream_t st);
 void launch_adjoint_decay(int64_t npts, int64_t nb, const SysDev* sys, const double* dpts, int64_t dec_tot,
                           const double* dw, const double* drows, const double* wdec, double* ad, double* bd,
                           const double* nx, const double* ny, const double* nz, double* dpart, hipStream_t st);

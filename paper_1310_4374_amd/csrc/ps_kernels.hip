@@ -1851,6 +1851,7 @@ __global__ __launch_bounds__(256) void k_energy(const SysDev* __restrict__ sys, 
 // Partial moments u_t = sum_k q_k R^_t(x_k / R0), t >= 1, over a slice of the
 // particles: one wave per workgroup evaluates the basis recurrence for 64
 // particles at a time and reduces every term across its lanes; part[block][t].
+// The biharmonic basis adds |u|^2 R^_t for degrees below p - 2 at t + p^2.
 // (One wave keeps the LDS at (3P + p) doubles, under 40 KB for p <= 40.)
 __global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, const double* __restrict__ sx,
                                                const double* __restrict__ sy, const double* __restrict__ sz,
@@ -1859,7 +1860,7 @@ __global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, c
 {
     extern __shared__ double lds[];
     const SysDev& S = sys[0];
-    const int P = S.P, p = S.p;
+    const int P = S.P, p = S.p, p2 = S.kernel == 3 ? p - 2 : 0;
     double* A = lds;
     double* B = lds + P;
     double* Cd = lds + 2 * P;
@@ -1877,7 +1878,7 @@ __global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, c
         const bool v = i < S.n;
         const double x = v ? sx[S.n_off + i] * S.inv_R0 : 0.0, y = v ? sy[S.n_off + i] * S.inv_R0 : 0.0,
                      z = v ? sz[S.n_off + i] * S.inv_R0 : 0.0, q = v ? sq[S.n_off + i] : 0.0;
-        const double r2 = x * x + y * y + z * z;
+        const double r2 = x * x + y * y + z * z, qr2 = q * r2;
         double dA = 1.0, dB = 0.0;
         for (int m = 0; m < p; ++m) {
             if (m > 0) {
@@ -1895,11 +1896,19 @@ __global__ __launch_bounds__(64) void k_moment(const SysDev* __restrict__ sys, c
                     const double r = wave_sum(q * v1);
                     if (lane == 0) acc[t0] += r;
                 }
+                if (m < p2) {
+                    const double r = wave_sum(qr2 * v1);
+                    if (lane == 0) acc[p * p + t0] += r;
+                }
                 for (int n = m + 1; n < p; ++n) {
                     const int t = n * n + n + mm;
                     const double vv = -A[t] * z * v1 - B[t] * r2 * v2;
                     const double r = wave_sum(q * vv);
                     if (lane == 0) acc[t] += r;
+                    if (n < p2) {
+                        const double r3 = wave_sum(qr2 * vv);
+                        if (lane == 0) acc[p * p + t] += r3;
+                    }
                     v2 = v1;
                     v1 = vv;
                 }
@@ -2095,6 +2104,60 @@ __global__ __launch_bounds__(256) void k_adj_decay(const SysDev* __restrict__ sy
     }
 }
 
+// The biharmonic fit's gradient rows in the adjoint: with their weights
+// w[k L + l] (k = x, y, z), a dipole D_l = R0 (w[l], w[L + l], w[2L + l]) at each
+// partner y~_l and -D_l at each check point y_l, for K = r:
+//   psi(z) = sum_l D_l . [(y~_l - z)/|y~_l - z| - (y_l - z)/|y_l - z|],
+//   grad psi = sum_l +-[-D_l/r + (D_l . (y - z)) (y - z)/r^3],
+// at every near entry z (FP64, 256 check targets staged in LDS at a time);
+// dpart receives psi and -grad psi as k_adj_decay's.
+__global__ __launch_bounds__(256) void k_adj_dip(const SysDev* __restrict__ sys, const double* __restrict__ nx,
+                                                 const double* __restrict__ ny, const double* __restrict__ nz,
+                                                 int64_t nb, const double* __restrict__ chk, int64_t chk_tot,
+                                                 const double* __restrict__ wg, double* __restrict__ dpart)
+{
+    __shared__ double sy[256][6];  // y, sign x D
+    const SysDev& S = sys[0];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool act = e < nb;
+    const double zx = act ? nx[S.near_off + e] : 0.0, zy = act ? ny[S.near_off + e] : 0.0,
+                 zz = act ? nz[S.near_off + e] : 0.0;
+    const int L = S.L, npts = 2 * L;
+    double ps = 0.0, gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int t0 = 0; t0 < npts; t0 += 256) {
+        __syncthreads();
+        const int j = t0 + threadIdx.x;
+        if (j < npts) {  // check target j: y_l for j < L (sign -), y~_l after (sign +)
+            const int l = j < L ? j : j - L;
+            const double sg = j < L ? -S.R0 : S.R0;
+            sy[threadIdx.x][0] = chk[S.chk_off + j];
+            sy[threadIdx.x][1] = chk[chk_tot + S.chk_off + j];
+            sy[threadIdx.x][2] = chk[2 * chk_tot + S.chk_off + j];
+            sy[threadIdx.x][3] = sg * wg[l];
+            sy[threadIdx.x][4] = sg * wg[L + l];
+            sy[threadIdx.x][5] = sg * wg[2 * L + l];
+        }
+        __syncthreads();
+        const int cnt = npts - t0 < 256 ? npts - t0 : 256;
+        for (int k = 0; k < cnt; ++k) {
+            const double dx = sy[k][0] - zx, dy = sy[k][1] - zy, dz = sy[k][2] - zz;  // y - z
+            const double ri = 1.0 / sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+            const double dd = __builtin_fma(sy[k][5], dz, __builtin_fma(sy[k][4], dy, sy[k][3] * dx)) * ri;
+            ps += dd;
+            const double c = dd * ri * ri;
+            gx += __builtin_fma(c, dx, -sy[k][3] * ri);
+            gy += __builtin_fma(c, dy, -sy[k][4] * ri);
+            gz += __builtin_fma(c, dz, -sy[k][5] * ri);
+        }
+    }
+    if (act) {
+        dpart[e] = ps;
+        dpart[nb + e] = -gx;
+        dpart[2 * nb + e] = -gy;
+        dpart[3 * nb + e] = -gz;
+    }
+}
+
 __global__ void k_copy4(int64_t n, const double* __restrict__ a, const double* __restrict__ b,
                         const double* __restrict__ c, const double* __restrict__ d, double* __restrict__ A,
                         double* __restrict__ B, double* __restrict__ C, double* __restrict__ D)
@@ -2214,6 +2277,13 @@ void launch_adjoint_decay(int64_t npts, int64_t nb, const SysDev* sys, const dou
               wdec, ad, bd);
     PS_LAUNCH(k_adj_decay, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sys, nx, ny, nz, nb, dpts, dec_tot, ad,
               bd, dpart);
+}
+void launch_adjoint_dipoles(int64_t nb, const SysDev* sys, const double* nx, const double* ny, const double* nz,
+                            const double* chk, int64_t chk_tot, const double* wg, double* dpart, hipStream_t st)
+{
+    if (nb <= 0) return;
+    PS_LAUNCH(k_adj_dip, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, sys, nx, ny, nz, nb, chk, chk_tot, wg,
+              dpart);
 }
 void launch_adjoint_finish(int64_t n, const SysDev* sys, const PJob* ajob, const int* inv, const double* sq,
                            const double* osort, int exact, const double* dpart, int64_t dstride, double* dq, double* dx,

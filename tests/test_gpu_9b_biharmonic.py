@@ -152,7 +152,7 @@ def test_biharmonic_batch(ps):
 
 def test_biharmonic_plan_file_gradient_and_refusals(ps, tmp_path):
     """A reloaded plan gives bitwise the same sums; the physical gradient works
-    (-q field, phi projected); the exact adjoint and non-neutral charges are refused."""
+    (-q field, phi projected); non-neutral charges are refused."""
     from paper_1310_4374_amd import PeriodicSumError
     x, q = _cell(800, 305)
     pl = ps.Plan(BOX, 12, lam=1.6, precision="fp32", n_max=800, kernel="biharmonic")
@@ -174,11 +174,32 @@ def test_biharmonic_plan_file_gradient_and_refusals(ps, tmp_path):
     ph = phi0.cpu().numpy()
     assert np.allclose(gq.cpu().numpy(), ph - ph.mean(), rtol=0, atol=1e-12 * np.abs(ph).max())
     assert abs(float(e.item()) - 0.5 * float(q @ ph)) < 1e-10 * abs(float(e.item()))
-    with pytest.raises(PeriodicSumError, match="UNSUPPORTED"):
-        pl.energy_vjp(X, Q, one, exact=True)
     pl.eval(X, dev(q + 0.1))
     with pytest.raises(PeriodicSumError, match="NOT_NEUTRAL"):
         pl.status()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_biharmonic_exact_adjoint_matches_oracle(ps, prec):
+    """The exact gradient of the biharmonic method's energy (moments of the
+    Almansi basis, charges and dipoles at the check points and partners, psi over
+    the near images) against the oracle's, itself pinned to finite differences;
+    dE/dq projected onto sum dq = 0."""
+    from oracle.biharmonic import energy_gradients_bih
+    x, q = _cell(1000, 306)
+    op = BiharmonicPlan(BOX, 14, lam=1.6)
+    E, dx, dq = energy_gradients_bih(op, x, q)
+    pl = ps.Plan(BOX, 14, lam=1.6, precision=prec, n_max=len(q), kernel="biharmonic")
+    X, Q = dev(x.T), dev(q)
+    e = pl.energy(X, Q)
+    one = torch.ones(1, dtype=torch.float64, device="cuda:0")
+    gx, gq = pl.energy_vjp(X, Q, one, exact=True)
+    pl.status()
+    ex, eq = err(gx.cpu().numpy().T, dx), err(gq.cpu().numpy(), dq)
+    b1, b2 = _bars(prec, op, x, q, op.solve(x, q))   # E and dE/dq are potential sums, dE/dx field sums
+    print(prec, "biharmonic adjoint err E %.2e dx %.3e (bar %.2e) dq %.3e (bar %.2e)"
+          % (abs(float(e.item()) / E - 1), ex, b2, eq, b1))
+    assert abs(float(e.item()) / E - 1) <= b1 and ex <= b2 and eq <= b1
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
