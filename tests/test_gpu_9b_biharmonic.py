@@ -125,6 +125,48 @@ def test_biharmonic_separate_targets_and_mean_modes(ps, prec):
     assert err(phi0, ref0[0]) <= b1 and err(field0, ref0[1]) <= b2
 
 
+def test_biharmonic_one_plan_across_counts_and_zero_charges(ps):
+    """One FP32 plan serves 1,500, 400 and 1,500 particles in turn (the work
+    tables are rebuilt per count), then all-zero charges, which give exactly zero
+    potential and field; a particle on a lower face keeps its value."""
+    op = BiharmonicPlan(BOX, 12, lam=1.6)
+    pl = ps.Plan(BOX, 12, lam=1.6, precision="fp32", n_max=1500, kernel="biharmonic")
+    for n, seed in ((1500, 330), (400, 331), (1500, 330)):
+        x, q = _cell(n, seed)
+        x[0] = -0.5 * np.array(BOX)  # on the lower corner: inside [-d/2, d/2)
+        ref = op.solve(x, q)
+        phi, field = pl.eval(dev(x.T), dev(q))
+        pl.status()
+        b1, b2 = _bars("fp32", op, x, q, ref)
+        assert err(phi.cpu().numpy(), ref[0]) <= b1 and err(field.cpu().numpy().T, ref[1]) <= b2, n
+    phi, field = pl.eval(dev(x.T), dev(np.zeros(len(x))))
+    pl.status()
+    assert not torch.any(phi != 0) and not torch.any(field != 0)
+
+
+def test_biharmonic_nearly_coincident_pairs(ps):
+    """Pairs of charges 1e-4 .. 1e-7 apart: the pairs' terms q r vanish with r,
+    their field terms do not; both precisions against the oracle."""
+    g = np.random.default_rng(332)
+    x, q = _cell(1500, 333)
+    pairs = []
+    for sep in np.logspace(-4, -7, 40):
+        c = g.uniform(-0.45, 0.45, size=3) * np.array(BOX)
+        u = g.standard_normal(3)
+        pairs += [c, c + sep * u / np.linalg.norm(u)]
+    xp = np.array(pairs)
+    m = g.uniform(0.5, 1.5, size=len(xp) // 2)
+    X = np.concatenate([x, xp])
+    Q = np.concatenate([q, np.stack([m, -m], axis=1).ravel()])
+    Q -= Q.mean()
+    op = BiharmonicPlan(BOX, 12, lam=1.6)
+    ref = op.solve(X, Q)
+    for prec in ("fp64", "fp32"):
+        _, phi, field = _bih(ps, BOX, 12, X, Q, prec)
+        b1, b2 = _bars(prec, op, X, Q, ref)
+        assert err(phi, ref[0]) <= b1 and err(field, ref[1]) <= b2, prec
+
+
 def test_biharmonic_method_accuracy_against_the_split(ps):
     """FP64 at p = 30, lambda = 2.5 against the independent Ewald-type split."""
     x, q = _cell(400, 304)
