@@ -167,6 +167,39 @@ def test_biharmonic_nearly_coincident_pairs(ps):
         assert err(phi, ref[0]) <= b1 and err(field, ref[1]) <= b2, prec
 
 
+def test_biharmonic_autotune_and_graph_replay(ps):
+    """The autotuner picks a launch shape for a biharmonic plan, and the tuned
+    plan keeps parity; a captured eval replays bitwise (FP32)."""
+    x, q = _cell(4000, 334)
+    op = BiharmonicPlan(BOX, 12, lam=1.6)
+    ref = op.solve(x, q)
+    pl = ps.Plan(BOX, 12, lam=1.6, precision="fp32", n_max=len(q), kernel="biharmonic")
+    X, Q = dev(x.T), dev(q)
+    ms = pl.autotune(X, Q)
+    assert ms > 0 and pl.info()["tune_ms"] > 0
+    phi, field = pl.eval(X, Q)
+    pl.status()
+    b1, b2 = _bars("fp32", op, x, q, ref)
+    assert err(phi.cpu().numpy(), ref[0]) <= b1 and err(field.cpu().numpy().T, ref[1]) <= b2
+    phi_g = torch.empty_like(phi)
+    field_g = torch.empty_like(field)
+    pl.eval(X, Q, out=(phi_g, field_g))
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            pl.eval(X, Q, out=(phi_g, field_g))
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        phi_g.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(phi_g, phi) and torch.equal(field_g, field), rep
+
+
 def test_biharmonic_method_accuracy_against_the_split(ps):
     """FP64 at p = 30, lambda = 2.5 against the independent Ewald-type split."""
     x, q = _cell(400, 304)
