@@ -2141,7 +2141,8 @@ __global__ __launch_bounds__(256) void k_adj_dip(const SysDev* __restrict__ sys,
         const int cnt = npts - t0 < 256 ? npts - t0 : 256;
         for (int k = 0; k < cnt; ++k) {
             const double dx = sy[k][0] - zx, dy = sy[k][1] - zy, dz = sy[k][2] - zz;  // y - z
-            const double ri = 1.0 / sqrt(__builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx)));
+            const double r2 = __builtin_fma(dz, dz, __builtin_fma(dy, dy, dx * dx));
+            const double ri = r2 > 0.0 ? 1.0 / sqrt(r2) : 0.0;  // a coincident point adds nothing, as K(0) = 0
             const double dd = __builtin_fma(sy[k][5], dz, __builtin_fma(sy[k][4], dy, sy[k][3] * dx)) * ri;
             ps += dd;
             const double c = dd * ri * ri;
