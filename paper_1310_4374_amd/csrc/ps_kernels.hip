@@ -508,9 +508,8 @@ __device__ __forceinline__ SourceSplit split_range(const PJob& J, int split)
 // g = s - 1 is refined by one Newton step on (1 + g)^2 = 1 + delta, which
 // gives g to a few roundings of itself rather than of 1.  Likewise the field
 // term -q (h - u)/r = q u/rho - q y (h + g u)/rho (1/y = 1 + g): the block adds
-// sum q u/rho once, in FP64, and the pair the rest, of the size of q |h|/rho
-// (y refined by one Newton step).  sC holds (1/rho^2, q rho, -q/rho, 1) per
-// such source.  The other sources of near groups take the potential term
+// sum q u/rho once, in FP64, and the pair the rest, of the size of q |h|/rho.
+// sC holds (1/rho^2, q rho, -q/rho, 1) per such source.  The other sources of near groups take the potential term
 // q r = q r^2 ri and the field weight -q ri (E = -grad(q r) = -q (t - s)/r); a
 // masked pair (ri = 0) and padding (q = 0) give zero terms.
 template <bool NEAR, bool FIELD, int KERN>
@@ -538,8 +537,8 @@ __device__ __forceinline__ void group32_f32(const float4* __restrict__ sA, const
                     const float res = __builtin_fmaf(sq, sq, -1.f) - dl;
                     const float gg = __builtin_fmaf(-res, hy2, sq - 1.f);
                     qv[u] = c.y * gg;
-                    if (FIELD) {  // -q y (h + g u)/rho, with y refined by one Newton step
-                        const float w = c.z * __builtin_fmaf(hy2, __builtin_fmaf(-sq, y, 1.f), y);
+                    if (FIELD) {  // -q y (h + g u)/rho: a term of the size of q |h|/rho, so y's own rounding is enough
+                        const float w = c.z * y;
                         const float hg = -0.5f * gg;  // h + g u = h - (g/2) A
                         fX = __builtin_fmaf(w, __builtin_fmaf(hg, s.x, hx), fX);
                         fY = __builtin_fmaf(w, __builtin_fmaf(hg, s.y, hy), fY);
