@@ -65,5 +65,6 @@ the biharmonic corner primitive against its third derivative and quadrature,
 its box mean's Laplacian against twice Phi0, the Almansi basis against the far
 expansion of r, the biharmonic split against its parameter, periodicity and
 Delta phi = 2 phi_Coulomb, and the biharmonic method against that split (to
-1e-12), its convergence in p and translation invariance.
+1e-12), its convergence in p and translation invariance, and its exact energy
+gradient against central differences.
 """
