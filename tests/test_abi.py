@@ -238,6 +238,33 @@ def test_plan_file_with_bad_image_list_is_refused(tmp_path):
         assert msg in L.periodic_sum_last_error(), (name, L.periodic_sum_last_error())
 
 
+def test_plan_file_with_bad_biharmonic_record_is_refused(tmp_path):
+    """A checksummed file whose biharmonic system record has the harmonic basis
+    size (p^2 instead of p^2 + (p-2)^2), or fewer than three periodic axes, is
+    refused with PS_E_IO before any device work."""
+    import struct
+    L = _lib.lib()
+    p = 4
+
+    def plan_file(P, periodic):
+        head = b"PSPLAN01" + struct.pack("<Iiid", 4, 1, 256, 1.0)
+        prm = struct.pack("<3didd", 1.0, 1.0, 1.0, p, 1.5, 0.0) + struct.pack("<iid", 0, 0, 1e-13) \
+            + struct.pack("<qqiiii", 100, 0, 0, 0, 0, periodic) + struct.pack("<idi", 2, 0.0, 3)
+        setup = struct.pack("<3di4d", 1.0, 1.0, 1.0, 0, 0.866, 1.5, 2.25, 1.0) \
+            + struct.pack("<4id", p, P, 28, P - 1, 1.0) + struct.pack("<iii", 1, 0, periodic) \
+            + struct.pack("<idi", 2, 0.0, 3)
+        body = head + prm + setup
+        return body + struct.pack("<Q", _fnv1a64(body))
+
+    h = ctypes.c_void_p()
+    for name, P, per, msg in (("harmonic_size", p * p, 7, b"basis size does not match p"),
+                              ("slab", p * p + (p - 2) ** 2, 3, b"bad biharmonic-kernel record")):
+        f = tmp_path / (name + ".plan")
+        f.write_bytes(plan_file(P, per))
+        assert L.periodic_sum_plan_load(str(f).encode(), 0, ctypes.byref(h)) == _lib.PS_E_IO, name
+        assert msg in L.periodic_sum_last_error(), (name, L.periodic_sum_last_error())
+
+
 def _select(prm, tol=1e-6, lambdas=(1.3, 1.5), p_ref=0, n=10, null=None):
     """periodic_sum_select with stand-in particle pointers: every case here is
     rejected by the argument checks, before any device call."""
